@@ -1,0 +1,527 @@
+"""The sampled block matrix product, step by step, in float64 (oracle side).
+
+Test infrastructure only (see the package docstring).
+
+Notation follows the paper: M is m x n, N is n x p, the inner dimension is cut
+into K contiguous blocks with sizes n_k (off[k] .. off[k+1]); M^k, N_k are the
+k-th column block of M and row block of N; M^(i) is column i of M and N_(i)
+row i of N; a_i = ||M^(i)||_2, b_i = ||N_(i)||_2, s_k = sum_{i in k} a_i b_i.
+
+Two sampling modes share one description. An *atom* is a contiguous range of
+the inner dimension; a *stratum* is a contiguous range of atoms that receives
+its own number of draws c_s:
+
+* ``block``      atoms are the K blocks, one stratum, c draws (the block
+                 samplers the paper compares with: probabilities (1.2) or
+                 (1.4), or uniform);
+* ``stratified`` atoms are single inner indices, the K blocks are the
+                 strata, block k gets c_k draws (the paper's Alg. 2 with
+                 within-block probabilities (3.8) or uniform, and block sizes
+                 uniform c/K, (4.2) or (3.9)).
+
+Alg. 1 (probabilities (1.1)) is either mode with K = 1 block of unit atoms.
+"""
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .sampling import (quantize_weights, inclusive_cdf, draw_atoms,
+                       allocate_draws)
+from .rng import TAG_SAMPLE
+
+MODES = ("block", "stratified")
+PROB_RULES = ("uniform", "norm", "exact", "user")
+ALLOC_RULES = ("uniform", "norm", "opt", "user")
+
+
+# ----------------------------------------------------------------------------
+# Partition
+# ----------------------------------------------------------------------------
+
+def check_partition(off, n):
+    """Block offsets 0 = off[0] < off[1] < ... < off[K] = n (Alg. 2 input:
+    sizes n_k >= 1 summing to n)."""
+    off = [int(x) for x in off]
+    if len(off) < 2 or off[0] != 0 or off[-1] != n:
+        raise ValueError("partition must start at 0 and end at n")
+    for a, b in zip(off[:-1], off[1:]):
+        if b <= a:
+            raise ValueError("block sizes must be positive")
+    return off
+
+
+# ----------------------------------------------------------------------------
+# Norms (inputs of (1.1), (1.4), (3.8), (4.2))
+# ----------------------------------------------------------------------------
+
+def column_row_sq(M, N, chunk=8192):
+    """col_sq[i] = ||M^(i)||_2^2 and row_sq[i] = ||N_(i)||_2^2 in float64.
+
+    Each column (row) is promoted to float64 and its squares summed; large
+    inputs are processed a slab of whole columns (rows) at a time, which does
+    not change any single sum.
+    """
+    m, n = M.shape
+    n2, p = N.shape
+    if n2 != n:
+        raise ValueError("inner dimensions differ")
+    col_sq = np.empty(n, dtype=np.float64)
+    row_sq = np.empty(n, dtype=np.float64)
+    for j0 in range(0, n, chunk):
+        blk = np.asarray(M[:, j0:j0 + chunk], dtype=np.float64)
+        col_sq[j0:j0 + chunk] = np.einsum("hi,hi->i", blk, blk)
+        blk = np.asarray(N[j0:j0 + chunk, :], dtype=np.float64)
+        row_sq[j0:j0 + chunk] = np.einsum("if,if->i", blk, blk)
+    return col_sq, row_sq
+
+
+@dataclass
+class BlockStats:
+    """Per-block statistics: ||M^k||_F^2, ||N_k||_F^2 and s_k."""
+    m_sq: np.ndarray
+    n_sq: np.ndarray
+    s: np.ndarray
+
+
+def block_stats(col_sq, row_sq, off):
+    """||M^k||_F^2 = sum of col_sq over block k, ||N_k||_F^2 likewise, and
+    s_k = sum_{i in k} ||M^(i)||_2 ||N_(i)||_2 (the numerator of (4.2) and
+    the denominator of (3.8)). Sums are correctly rounded (math.fsum)."""
+    K = len(off) - 1
+    ab = np.sqrt(col_sq * row_sq)
+    m_sq = np.array([math.fsum(col_sq[off[k]:off[k + 1]]) for k in range(K)])
+    n_sq = np.array([math.fsum(row_sq[off[k]:off[k + 1]]) for k in range(K)])
+    s = np.array([math.fsum(ab[off[k]:off[k + 1]]) for k in range(K)])
+    return BlockStats(m_sq, n_sq, s)
+
+
+def block_product_sq(M, N, off, blocks=None):
+    """||M^k N_k||_F^2 for each block k (or for the listed ``blocks``):
+    the quantity (1.2) and (3.9) need, formed by multiplying the two blocks
+    out in float64."""
+    ks = range(len(off) - 1) if blocks is None else blocks
+    out = []
+    for k in ks:
+        a = np.asarray(M[:, off[k]:off[k + 1]], dtype=np.float64)
+        b = np.asarray(N[off[k]:off[k + 1], :], dtype=np.float64)
+        x = a @ b
+        out.append(float(np.sum(x * x)))
+    return np.array(out)
+
+
+# ----------------------------------------------------------------------------
+# Design: probabilities and draw counts
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Design:
+    """A sampling design: atoms, strata, integer weights and draw counts.
+
+    atom_lo/atom_hi  inner-index range of each atom (A atoms)
+    strat_off        atoms of stratum s are strat_off[s] .. strat_off[s+1]
+    W                quantized weights (Python ints), one per atom
+    cdf              per stratum, the inclusive running sums of its W
+    T                per stratum, the CDF total
+    cs               draws per stratum (sum = c)
+    """
+    mode: str
+    atom_lo: np.ndarray
+    atom_hi: np.ndarray
+    strat_off: list
+    W: list
+    cdf: list
+    T: list
+    cs: list
+    w: np.ndarray = field(default=None)   # float weights before quantizing
+    g: np.ndarray = field(default=None)   # float allocation weights
+
+    @property
+    def c(self):
+        return int(sum(self.cs))
+
+    def p_hat(self):
+        """Sampled probability of each atom within its stratum, W / T."""
+        out = np.zeros(len(self.W))
+        for s in range(len(self.T)):
+            for a in range(self.strat_off[s], self.strat_off[s + 1]):
+                if self.T[s] > 0:
+                    out[a] = float(self.W[a]) / float(self.T[s])
+        return out
+
+
+def atom_weights(mode, prob, off, col_sq, row_sq, stats, blkprod_sq=None,
+                 user_w=None):
+    """Float weights w_a, proportional to the sampling probabilities.
+
+    block mode (atoms = blocks):
+      uniform  w_k = 1                        (uniform block sampling)
+      norm     w_k = ||M^k||_F ||N_k||_F       (1.4)
+      exact    w_k = ||M^k N_k||_F             (1.2)
+    stratified mode (atoms = inner indices):
+      uniform  w_i = 1                        (p_{k_i} = 1/n_k, method UU)
+      norm     w_i = ||M^(i)||_2 ||N_(i)||_2   (3.8); with one block this is
+                                              (1.1), Alg. 1's probabilities
+    user       the caller's weights
+    """
+    K = len(off) - 1
+    n = off[-1]
+    if prob == "user":
+        if user_w is None:
+            raise ValueError("user weights missing")
+        w = np.asarray(user_w, dtype=np.float64).copy()
+        want = K if mode == "block" else n
+        if w.shape != (want,):
+            raise ValueError("user weights have the wrong length")
+        return w
+    if mode == "block":
+        if prob == "uniform":
+            return np.ones(K)
+        if prob == "norm":
+            return np.sqrt(stats.m_sq * stats.n_sq)
+        if prob == "exact":
+            if blkprod_sq is None:
+                raise ValueError("rule 'exact' needs ||M^k N_k||_F^2")
+            return np.sqrt(np.asarray(blkprod_sq, dtype=np.float64))
+    else:
+        if prob == "uniform":
+            return np.ones(n)
+        if prob == "norm":
+            return np.sqrt(col_sq * row_sq)
+    raise ValueError(f"rule {prob!r} not available in {mode} mode")
+
+
+def alloc_weights(alloc, stats, blkprod_sq=None):
+    """Float allocation weights g_k of the strata (stratified mode).
+
+      uniform  g_k = 1                              (c_k = c/K, method UU)
+      norm     g_k = s_k                            (4.2), method ONC
+      opt      g_k = sqrt(max(0, s_k^2 - ||M^k N_k||_F^2))   (3.9), method OPL
+    """
+    K = len(stats.s)
+    if alloc == "uniform":
+        return np.ones(K)
+    if alloc == "norm":
+        return stats.s.copy()
+    if alloc == "opt":
+        if blkprod_sq is None:
+            raise ValueError("rule 'opt' needs ||M^k N_k||_F^2")
+        d = stats.s * stats.s - np.asarray(blkprod_sq, dtype=np.float64)
+        return np.sqrt(np.maximum(d, 0.0))
+    raise ValueError(f"allocation rule {alloc!r} unknown")
+
+
+def make_design(mode, off, c, w, g=None, user_ck=None):
+    """Quantize the weights per stratum, build the CDFs and the draw counts.
+
+    block: one stratum holding the K block atoms, c_1 = c.
+    stratified: stratum k holds the n_k unit atoms of block k; its draw
+    count comes from the allocation weights ``g`` (or ``user_ck``).
+    Quantization is done separately in each stratum (its own maximum).
+    """
+    if mode not in MODES:
+        raise ValueError("unknown mode")
+    K = len(off) - 1
+    if c < 1:
+        raise ValueError("c must be positive")
+    if mode == "block":
+        lo = np.array(off[:-1], dtype=np.int64)
+        hi = np.array(off[1:], dtype=np.int64)
+        strat_off = [0, K]
+    else:
+        n = off[-1]
+        lo = np.arange(n, dtype=np.int64)
+        hi = lo + 1
+        strat_off = list(off)
+    S = len(strat_off) - 1
+    W, cdf, T = [], [], []
+    for s in range(S):
+        Ws = quantize_weights(w[strat_off[s]:strat_off[s + 1]])
+        W.extend(Ws)
+        cs_cdf = inclusive_cdf(Ws)
+        cdf.append(cs_cdf)
+        T.append(cs_cdf[-1] if cs_cdf else 0)
+    if mode == "block":
+        cs = [c if T[0] > 0 else 0]
+    elif user_ck is not None:
+        cs = [int(x) for x in user_ck]
+        if len(cs) != S or sum(cs) != c or min(cs) < 0:
+            raise ValueError("user draw counts must be K non-negative ints "
+                             "summing to c")
+        for s in range(S):
+            if (T[s] > 0) != (cs[s] > 0):
+                raise ValueError("user draw counts must be positive exactly "
+                                 "on the strata with positive weight")
+    else:
+        G = quantize_weights(g)
+        cs = allocate_draws(c, G, T)
+    return Design(mode, lo, hi, strat_off, W, cdf, T, cs,
+                  w=np.asarray(w, dtype=np.float64),
+                  g=None if g is None else np.asarray(g, dtype=np.float64))
+
+
+# ----------------------------------------------------------------------------
+# Sampling (Alg. 1 step 1, applied per stratum as in Alg. 2 step 1)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Draws:
+    """The drawn atoms in concatenation order (stratum-major, draw order).
+
+    atom   global atom index of each draw
+    strat  stratum of each draw
+    scale  1 / sqrt(c_s p_hat) applied to the column of C and row of D
+    lo, width   inner-index range of the drawn atom
+    col_off     column of C where each draw starts; col_off[-1] = L
+    """
+    atom: np.ndarray
+    strat: np.ndarray
+    scale: np.ndarray
+    lo: np.ndarray
+    width: np.ndarray
+    col_off: np.ndarray
+
+    @property
+    def L(self):
+        return int(self.col_off[-1])
+
+
+def draw_scale(c_s, W_a, T_s):
+    """1 / sqrt(c_s p) with p = W_a / T_s, the factor of Alg. 1 step 1(b)
+    (and of (3.2)), in float64: p, c_s p, the square root and the
+    reciprocal are each rounded once."""
+    q = float(W_a) / float(T_s)
+    return 1.0 / math.sqrt(float(c_s) * q)
+
+
+def sample(design, seed, trial=0, tag=TAG_SAMPLE, forced=None):
+    """Draw c_s atoms from each stratum s, independently and with
+    replacement, with probability p_hat = W / T.
+
+    ``forced`` (tests only) replaces the random local atom choices: a list,
+    per stratum, of local atom indices.
+    """
+    atom, strat, scale = [], [], []
+    for s in range(len(design.T)):
+        cnt = design.cs[s]
+        if cnt == 0:
+            continue
+        a0 = design.strat_off[s]
+        if forced is not None:
+            local = list(forced[s])
+        else:
+            local = draw_atoms(design.cdf[s], design.T[s], cnt, seed, trial,
+                               s, tag)
+        for la in local:
+            a = a0 + la
+            if design.W[a] == 0:
+                raise ValueError("forced draw of a zero-weight atom")
+            atom.append(a)
+            strat.append(s)
+            scale.append(draw_scale(cnt, design.W[a], design.T[s]))
+    atom = np.array(atom, dtype=np.int64)
+    lo = design.atom_lo[atom] if len(atom) else np.zeros(0, np.int64)
+    width = (design.atom_hi[atom] - lo) if len(atom) else np.zeros(0, np.int64)
+    col_off = np.concatenate([[0], np.cumsum(width)]).astype(np.int64)
+    return Draws(atom, np.array(strat, dtype=np.int64),
+                 np.array(scale, dtype=np.float64), lo, width, col_off)
+
+
+# ----------------------------------------------------------------------------
+# Sketch and product (Alg. 1 step 1(b); Alg. 2 steps 3-4; (3.2)-(3.3))
+# ----------------------------------------------------------------------------
+
+def sketch(M, N, draws):
+    """C (m x L) and D (L x p): each draw contributes its atom's columns of M
+    and rows of N, multiplied by its scale, placed side by side in draw
+    order (Alg. 2 step 3 concatenates the per-block sketches)."""
+    m, p = M.shape[0], N.shape[1]
+    C = np.zeros((m, draws.L))
+    D = np.zeros((draws.L, p))
+    for t in range(len(draws.atom)):
+        lo, wd, c0 = int(draws.lo[t]), int(draws.width[t]), int(draws.col_off[t])
+        C[:, c0:c0 + wd] = np.asarray(M[:, lo:lo + wd], np.float64) * draws.scale[t]
+        D[c0:c0 + wd, :] = np.asarray(N[lo:lo + wd, :], np.float64) * draws.scale[t]
+    return C, D
+
+
+def sketch_product(C, D):
+    """CD, the estimate of MN (Alg. 2 step 4, (3.3))."""
+    return C @ D
+
+
+def exact_product(M, N):
+    """MN in float64."""
+    return np.asarray(M, np.float64) @ np.asarray(N, np.float64)
+
+
+def judge(MN, CD):
+    """err = ||MN - CD||_F and rel = err / ||MN||_F (rel = 0 when both are 0,
+    +inf when only ||MN||_F is 0)."""
+    d = MN - CD
+    err2 = float(np.sum(d * d))
+    mn2 = float(np.sum(MN * MN))
+    err = math.sqrt(err2)
+    if mn2 == 0.0:
+        rel = 0.0 if err2 == 0.0 else math.inf
+    else:
+        rel = err / math.sqrt(mn2)
+    return err, rel, err2, mn2
+
+
+# ----------------------------------------------------------------------------
+# Closed forms (Lemma 1, Thm 2 proof, Remark 2.2, Remark 2.3)
+# ----------------------------------------------------------------------------
+
+def atom_products_sq(M, N, design):
+    """||X_a||_F^2 for every atom, X_a = M[:, atom] N[atom, :]; for a unit
+    atom this is a_i^2 b_i^2 (the Frobenius norm of an outer product is the
+    product of the two vector norms)."""
+    out = np.empty(len(design.atom_lo))
+    for a, (lo, hi) in enumerate(zip(design.atom_lo, design.atom_hi)):
+        x = np.asarray(M[:, lo:hi], np.float64)
+        y = np.asarray(N[lo:hi, :], np.float64)
+        if hi - lo == 1:
+            out[a] = float(np.sum(x * x)) * float(np.sum(y * y))
+        else:
+            z = x @ y
+            out[a] = float(np.sum(z * z))
+    return out
+
+
+def expected_sq_error(M, N, design):
+    """E ||MN - CD||_F^2 of the design, exactly:
+
+        sum_s (1 / c_s) ( sum_{a in s} ||X_a||_F^2 / p_a - ||sum_{a in s} X_a||_F^2 )
+
+    Summing the per-entry variance (3.7) over all entries (Remark 2.2; the
+    first line of the proof of Thm 2 for unit atoms), with the probabilities
+    p_a = W_a / T_s that are actually sampled.
+    """
+    xa = atom_products_sq(M, N, design)
+    ph = design.p_hat()
+    total = 0.0
+    for s in range(len(design.T)):
+        a0, a1 = design.strat_off[s], design.strat_off[s + 1]
+        lo, hi = int(design.atom_lo[a0]), int(design.atom_hi[a1 - 1])
+        z = np.asarray(M[:, lo:hi], np.float64) @ np.asarray(N[lo:hi, :], np.float64)
+        blk = float(np.sum(z * z))
+        if design.cs[s] == 0:
+            if blk != 0.0 or np.any(xa[a0:a1] != 0.0):
+                raise ValueError("stratum without draws has a nonzero product")
+            continue
+        acc = 0.0
+        for a in range(a0, a1):
+            if xa[a] == 0.0:
+                continue
+            if ph[a] == 0.0:
+                raise ValueError("atom with nonzero product has p = 0 (biased)")
+            acc += xa[a] / ph[a]
+        total += (acc - blk) / design.cs[s]
+    return total
+
+
+def sum_variance_real(col_sq, row_sq, off, blkprod_sq, p, ck):
+    """The sum over entries of the asymptotic variances for real-valued
+    within-block probabilities p (length n) and real block sizes ck (length
+    K): sum_k sum_i a_i^2 b_i^2 / (c_k p_{k_i}) - sum_k ||M^k N_k||_F^2 / c_k
+    (first line of the proof of Thm 2)."""
+    tot = 0.0
+    for k in range(len(off) - 1):
+        sl = slice(off[k], off[k + 1])
+        ab2 = col_sq[sl] * row_sq[sl]
+        pk = p[sl]
+        nz = ab2 > 0
+        tot += (math.fsum(ab2[nz] / pk[nz]) - blkprod_sq[k]) / ck[k]
+    return tot
+
+
+def optimal_value(stats, blkprod_sq, c):
+    """(3.10): the minimum of the summed variance,
+    (1/c) [ sum_k (1 - v_k^2)^(1/2) s_k ]^2 with v_k s_k = ||M^k N_k||_F."""
+    s = stats.s
+    v2 = np.where(s > 0, np.asarray(blkprod_sq) / np.where(s > 0, s * s, 1.0), 0.0)
+    return (math.fsum(np.sqrt(np.maximum(1.0 - v2, 0.0)) * s)) ** 2 / c
+
+
+# ----------------------------------------------------------------------------
+# Whole pipeline
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    design: Design
+    draws: Draws
+    col_sq: np.ndarray
+    row_sq: np.ndarray
+    stats: BlockStats
+    C: np.ndarray
+    D: np.ndarray
+    CD: np.ndarray
+    MN: np.ndarray
+    err: float
+    rel: float
+
+
+def plan(M, N, off, c, mode="block", prob="norm", alloc="norm", user_w=None,
+         user_ck=None, blkprod_sq=None, col_row=None):
+    """Norms -> weights -> design (everything before the random draws)."""
+    n = M.shape[1]
+    off = check_partition(off, n)
+    col_sq, row_sq = col_row if col_row is not None else column_row_sq(M, N)
+    stats = block_stats(col_sq, row_sq, off)
+    need_prod = (prob == "exact") or (mode == "stratified" and alloc == "opt")
+    if need_prod and blkprod_sq is None:
+        blkprod_sq = block_product_sq(M, N, off)
+    w = atom_weights(mode, prob, off, col_sq, row_sq, stats, blkprod_sq, user_w)
+    g = None
+    if mode == "stratified" and alloc != "user":
+        g = alloc_weights(alloc, stats, blkprod_sq)
+    design = make_design(mode, off, c, w, g,
+                         user_ck if (mode == "stratified" and alloc == "user") else None)
+    return design, col_sq, row_sq, stats
+
+
+def run(M, N, off, c, seed=0, trial=0, mode="block", prob="norm",
+        alloc="norm", user_w=None, user_ck=None, blkprod_sq=None):
+    """The full forward path: Alg. 2 (or the block sampler), its product
+    and the judge."""
+    design, col_sq, row_sq, stats = plan(M, N, off, c, mode, prob, alloc,
+                                         user_w, user_ck, blkprod_sq)
+    draws = sample(design, seed, trial)
+    C, D = sketch(M, N, draws)
+    CD = sketch_product(C, D)
+    MN = exact_product(M, N)
+    err, rel, _, _ = judge(MN, CD)
+    return Result(design, draws, col_sq, row_sq, stats, C, D, CD, MN, err, rel)
+
+
+# ----------------------------------------------------------------------------
+# Gradient of the sketch
+# ----------------------------------------------------------------------------
+
+def backward(M, N, draws, G):
+    """Gradients of <G, CD> with respect to M and N, the draws held fixed.
+
+    CD = sum_t scale_t^2 M[:, atom_t] N[atom_t, :] (3.3) is linear in M for
+    fixed N and the other way round, so
+
+        dM[:, atom] = (sum of scale_t^2 over draws t of that atom) G N[atom, :]^T
+        dN[atom, :] = (same factor) M[:, atom]^T G
+
+    and every column of M (row of N) outside the drawn atoms gets zero.
+    """
+    M64 = np.asarray(M, np.float64)
+    N64 = np.asarray(N, np.float64)
+    G64 = np.asarray(G, np.float64)
+    dM = np.zeros_like(M64)
+    dN = np.zeros_like(N64)
+    fac = {}
+    for t in range(len(draws.atom)):
+        key = (int(draws.lo[t]), int(draws.width[t]))
+        fac[key] = fac.get(key, 0.0) + draws.scale[t] ** 2
+    for (lo, wd), f in fac.items():
+        dM[:, lo:lo + wd] = f * (G64 @ N64[lo:lo + wd, :].T)
+        dN[lo:lo + wd, :] = f * (M64[:, lo:lo + wd].T @ G64)
+    return dM, dN
