@@ -1,0 +1,225 @@
+/*
+ * sbmm.h — C ABI of libsbmm: randomized block matrix multiplication by
+ * sampling on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Niu & Li, "Optimal Sampling Algorithms for Block Matrix
+ * Multiplication" (arXiv 2105.04940). The product MN = sum_k M^k N_k over a
+ * partition of the inner dimension into K blocks (eq. 2.3) is estimated by
+ * drawing terms with replacement, rescaling each drawn term by 1/sqrt(c p)
+ * on both factors (Alg. 1), concatenating the drawn columns of M into C and
+ * rows of N into D, and forming CD (Alg. 2, eqs. 3.2-3.3).
+ *
+ * Two sampling modes share the entry points:
+ *   SBMM_MODE_BLOCK       the drawn unit is a whole block; c i.i.d. draws with
+ *                         block probabilities (1.4) "norm", (1.2) "exact",
+ *                         uniform, or user weights.
+ *   SBMM_MODE_STRATIFIED  the paper's Alg. 2: each block is a stratum, the
+ *                         drawn unit is one inner index (a column of M and the
+ *                         matching row of N), block k receives c_k draws with
+ *                         probabilities (3.8) "norm" or 1/n_k "uniform"; c_k
+ *                         comes from c/K "uniform", (4.2) "norm", (3.9) "opt"
+ *                         or the caller.
+ * An "atom" is the drawn unit (a block, or one inner index); a "stratum" is a
+ * group of atoms with its own draw count (the whole problem in block mode,
+ * one block in stratified mode).
+ *
+ * Sampling is bit-reproducible: weights are quantized per stratum to uint64
+ * integers W (W = ceil(w * 2^(B-1-e)), e = floor(log2 max w), B = 63 -
+ * ceil(log2 A_s) for the A_s atoms of the stratum), the per-stratum CDF is an
+ * exact integer running sum with total T, draw j of stratum s reads the
+ * Philox4x64-10 stream with counter (j, s, trial, (1 << 32) | block) and key
+ * (seed, 0), pairs the words into 128-bit words (first word high), maps them
+ * with Lemire's multiply-and-reject to an exactly uniform integer in [0, T),
+ * and takes the first atom whose CDF exceeds it. The rescale uses
+ * p_hat = W / T, the probability actually sampled.
+ *
+ * Layout: every matrix is row-major with a leading dimension (elements
+ * between consecutive rows). M is m x n (ldm >= n), N is n x p (ldn >= p),
+ * C is m x L (ldc >= L), D is L x p (ldd >= p), CD and MN are m x p.
+ *
+ * Ownership: every data pointer is caller-owned device memory unless marked
+ * "host". The library keeps no pointer after a call returns except through
+ * work it has enqueued on the given stream; the caller keeps buffers alive
+ * until that work completes. The handle owns a device workspace that grows
+ * on demand (sbmm_reserve pre-sizes it) and a device status word.
+ *
+ * Errors: every call returns an sbmm_status and never aborts, exits or
+ * throws across the ABI. Arguments are checked on the host before anything
+ * is launched. Conditions only the device can see (non-finite inputs or
+ * weights, a budget below the number of strata that can be sampled) set the
+ * handle's status word; the next synchronizing call (sbmm_plan with a
+ * non-NULL L_host, sbmm_sync, sbmm_run) reports it and clears it. HIP errors
+ * map to SBMM_E_HIP with the HIP text in sbmm_last_error().
+ *
+ * Streams and threads: calls are asynchronous on the given stream unless
+ * documented as synchronizing. Use one handle per host thread.
+ */
+#ifndef SBMM_H
+#define SBMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbmm_handle_s* sbmm_handle;
+typedef void* sbmm_stream; /* a hipStream_t; NULL is the default stream */
+
+typedef enum {
+  SBMM_OK = 0,
+  SBMM_E_ARG = 1,         /* invalid argument (shape, pointer, alignment, partition, enum) */
+  SBMM_E_BUDGET = 2,      /* c too small for the strata that can be sampled */
+  SBMM_E_NONFINITE = 3,   /* NaN/Inf in the inputs or weights */
+  SBMM_E_UNSUPPORTED = 4, /* valid request this build does not implement */
+  SBMM_E_NOMEM = 5,       /* device allocation failed */
+  SBMM_E_HIP = 6,         /* HIP runtime error; text in sbmm_last_error() */
+  SBMM_E_STATE = 7        /* handle used on the wrong device / after destroy */
+} sbmm_status;
+
+typedef enum { SBMM_F64 = 0, SBMM_F32 = 1, SBMM_BF16 = 2, SBMM_F8E4M3 = 3 } sbmm_dtype;
+typedef enum { SBMM_MODE_BLOCK = 0, SBMM_MODE_STRATIFIED = 1 } sbmm_mode;
+typedef enum { SBMM_P_UNIFORM = 0, SBMM_P_NORM = 1, SBMM_P_EXACT = 2, SBMM_P_USER = 3 } sbmm_prob;
+typedef enum { SBMM_ALLOC_UNIFORM = 0, SBMM_ALLOC_NORM = 1, SBMM_ALLOC_OPT = 2, SBMM_ALLOC_USER = 3 } sbmm_alloc;
+
+/* One sampling problem (Alg. 2 input: M, N, the block sizes n_k, c, the
+ * probability rule and, in stratified mode, the block-size rule). */
+typedef struct {
+  int64_t m, n, p;            /* M is m x n, N is n x p; n >= 1, m, p >= 0 */
+  sbmm_dtype in_dtype;        /* dtype of M and N: F64, F32 or BF16 */
+  const void* M; int64_t ldm; /* device, row-major, ldm >= n */
+  const void* N; int64_t ldn; /* device, row-major, ldn >= p */
+  int32_t K;                  /* number of blocks, >= 1 */
+  const int64_t* block_off;   /* host, K+1 offsets: 0 = off[0] < ... < off[K] = n */
+  int64_t c;                  /* total number of draws, >= 1 */
+  sbmm_mode mode;
+  sbmm_prob prob;             /* EXACT: block mode only (equals NORM for unit atoms) */
+  sbmm_alloc alloc;           /* stratified mode only */
+  const double* user_w;       /* device, one weight per atom (K block / n stratified), prob == USER */
+  const int64_t* user_ck;     /* host, K draw counts summing to c, alloc == USER */
+  const double* blkprod_sq;   /* device, K values ||M^k N_k||_F^2 (from sbmm_exact), prob == EXACT or alloc == OPT */
+  uint64_t seed, trial;       /* Philox key word 0 and counter word 2 */
+} sbmm_problem;
+
+/* Sizes derived from a problem (no device work). */
+typedef struct {
+  int64_t atoms;      /* A: K (block) or n (stratified) */
+  int64_t strata;     /* S: 1 (block) or K (stratified) */
+  int64_t max_width;  /* widest atom */
+  int64_t L_max;      /* c * max_width: upper bound of the sketch width L */
+  int64_t L_pad_max;  /* L_max rounded up to the sketch padding (32 columns) */
+} sbmm_sizes;
+
+/* Outputs of the planning step. All device, caller-owned. */
+typedef struct {
+  int32_t* idx;      /* [c]   drawn atom per draw (global atom index), stratum-major then draw order */
+  double* scale;     /* [c]   1 / sqrt(c_s * p_hat) of each draw (Alg. 1 step 1(b)) */
+  int64_t* col_off;  /* [c+1] first column of C (row of D) of each draw; col_off[c] = L */
+  int64_t* ck;       /* [S]   draws per stratum */
+  double* p_hat;     /* [A]   optional (may be NULL): W / T of each atom */
+  int32_t* colmap;   /* [L_pad_max] inner index feeding each sketch column, -1 in the padding */
+  double* colscale;  /* [L_pad_max] scale of each sketch column, 0 in the padding */
+} sbmm_plan_out;
+
+/* ------------------------------------------------------------------------ */
+/* Handle                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Create a handle bound to HIP device `device`. */
+sbmm_status sbmm_create(sbmm_handle* out, int device);
+/* Destroy a handle; waits for nothing (synchronize the streams first). */
+sbmm_status sbmm_destroy(sbmm_handle h);
+/* Static text of a status code. */
+const char* sbmm_status_string(sbmm_status s);
+/* Text of the last error on this handle (empty if none); valid until the next call. */
+const char* sbmm_last_error(sbmm_handle h);
+/* Grow the handle's device workspace to at least `bytes` (synchronizing). */
+sbmm_status sbmm_reserve(sbmm_handle h, size_t bytes);
+/* Wait for `stream`, then report and clear the device status word. */
+sbmm_status sbmm_sync(sbmm_handle h, sbmm_stream stream);
+/* Fill `out` from the problem's shape (host only; validates the problem). */
+sbmm_status sbmm_query_sizes(const sbmm_problem* prob, sbmm_sizes* out);
+
+/* ------------------------------------------------------------------------ */
+/* Steps of the path                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Norm pass: col_sq[i] = ||M^(i)||_2^2, row_sq[i] = ||N_(i)||_2^2 (the
+ * column and row norms behind (1.1), (1.4), (3.8) and (4.2)), and per block
+ * blk[k] = ||M^k||_F^2, blk[K+k] = ||N_k||_F^2, blk[2K+k] = s_k =
+ * sum_{i in k} ||M^(i)||_2 ||N_(i)||_2. All float64, accumulated in float64
+ * in a fixed order (bitwise reproducible). Sizes: col_sq[n], row_sq[n],
+ * blk[3K], device. Sets the status word on a non-finite norm. */
+sbmm_status sbmm_norms(sbmm_handle h, const sbmm_problem* prob, double* col_sq,
+                       double* row_sq, double* blk, sbmm_stream stream);
+
+/* Exact product MN on matrix cores (the reference the sketch is judged
+ * against) with, in the epilogue, mn_sq[0] = ||MN||_F^2 (float64, fixed
+ * order). MN (optional, may be NULL) gets the product in the compute dtype
+ * (F64 for F64 inputs, else F32). blkprod_sq (optional, device [K]) gets
+ * ||M^k N_k||_F^2 per block, the quantity (1.2) and (3.9) need.
+ * mn_sq: device [1], required. */
+sbmm_status sbmm_exact(sbmm_handle h, const sbmm_problem* prob, void* MN,
+                       int64_t ldmn, double* blkprod_sq, double* mn_sq,
+                       sbmm_stream stream);
+
+/* Design and sampling (Alg. 2 inputs p_{k_i} and c_k; Alg. 1 step 1(a)):
+ * weights by the problem's rules from col_sq/row_sq/blk (from sbmm_norms),
+ * integer quantization and per-stratum CDF, draw counts, the c draws, their
+ * scales and the column map of the sketch. If L_host is non-NULL the call
+ * synchronizes, stores the sketch width L and reports the status word;
+ * otherwise it is asynchronous and L stays on the device in col_off[c]. */
+sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* prob,
+                      const double* col_sq, const double* row_sq,
+                      const double* blk, const sbmm_plan_out* out,
+                      int64_t* L_host, sbmm_stream stream);
+
+/* Gather and rescale (Alg. 1 step 1(b), Alg. 2 step 3): C[:, l] = colscale[l]
+ * * M[:, colmap[l]] and D[l, :] = colscale[l] * N[colmap[l], :] for
+ * l < L, zero for L <= l < round_up(L, 32). C is m x L_pad (ldc >=
+ * L_pad_max), D is L_pad x p (ldd >= p), in out_dtype (F64 from F64 inputs;
+ * F32 or BF16 from F32/BF16 inputs). Either of C, D may be NULL. */
+sbmm_status sbmm_sketch(sbmm_handle h, const sbmm_problem* prob,
+                        const sbmm_plan_out* plan, sbmm_dtype out_dtype,
+                        void* C, int64_t ldc, void* D, int64_t ldd,
+                        sbmm_stream stream);
+
+/* Sketched product CD = C D (Alg. 2 step 4, eq. 3.3) on matrix cores over
+ * the inner extent round_up(*L_dev, 32) (read on the device, at most
+ * L_pad_max). dtype is the dtype of C and D: F64 (CD in F64) or F32 / BF16
+ * (CD in F32, float32 accumulation). If MN and err_sq are given, the
+ * epilogue also writes err_sq[0] = ||MN - CD||_F^2 (float64, fixed order).
+ * CD may be NULL when only the error is wanted. */
+sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p,
+                             int64_t L_pad_max, const int64_t* L_dev,
+                             sbmm_dtype dtype, const void* C, int64_t ldc,
+                             const void* D, int64_t ldd, void* CD,
+                             int64_t ldcd, const void* MN, int64_t ldmn,
+                             double* err_sq, sbmm_stream stream);
+
+/* ||X - Y||_F^2 and ||Y||_F^2 of two m x p matrices (F64 or F32) into
+ * out2[0..1] (device, float64, fixed order). */
+sbmm_status sbmm_error(sbmm_handle h, int64_t m, int64_t p, sbmm_dtype dtype,
+                       const void* X, int64_t ldx, const void* Y, int64_t ldy,
+                       double* out2, sbmm_stream stream);
+
+/* The whole forward path, synchronizing: norms, (exact product first when
+ * the rules need ||M^k N_k||_F), plan, sketch, sketched product, exact
+ * product and the error. compute is the dtype of C, D and the sketched
+ * product (F64 for F64 inputs; F32 or BF16 otherwise). C and D (optional)
+ * receive the sketch; CD (required) the estimate; MN (optional) the exact
+ * product. plan (required) receives the draws. err_host / rel_host / L_host
+ * (host, optional) receive ||MN - CD||_F, its ratio to ||MN||_F (0 when
+ * both are 0, +inf when only ||MN||_F is 0) and L. */
+sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* prob, sbmm_dtype compute,
+                     void* C, int64_t ldc, void* D, int64_t ldd, void* CD,
+                     int64_t ldcd, void* MN, int64_t ldmn,
+                     const sbmm_plan_out* plan, double* err_host,
+                     double* rel_host, int64_t* L_host, sbmm_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBMM_H */

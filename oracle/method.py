@@ -370,6 +370,34 @@ def judge(MN, CD):
     return err, rel, err2, mn2
 
 
+def sketch_entries(M, N, draws, rows, cols):
+    """Selected entries of CD straight from (3.3): for each (h, f),
+    sum over draws t of scale_t^2 * sum_{i in atom_t} M[h, i] N[i, f],
+    in float64 (for checks at sizes where CD itself is too large)."""
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    out = np.zeros(len(rows))
+    for t in range(len(draws.atom)):
+        lo, wd = int(draws.lo[t]), int(draws.width[t])
+        a = np.asarray(M[rows, lo:lo + wd], np.float64)
+        b = np.asarray(N[lo:lo + wd, :][:, cols], np.float64).T
+        out += draws.scale[t] ** 2 * np.sum(a * b, axis=1)
+    return out
+
+
+def exact_entries(M, N, rows, cols, chunk=8192):
+    """Selected entries of MN in float64: (MN)[h, f] = sum_i M[h, i] N[i, f]."""
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    out = np.zeros(len(rows))
+    n = M.shape[1]
+    for i0 in range(0, n, chunk):
+        a = np.asarray(M[rows, i0:i0 + chunk], np.float64)
+        b = np.asarray(N[i0:i0 + chunk, :][:, cols], np.float64).T
+        out += np.sum(a * b, axis=1)
+    return out
+
+
 # ----------------------------------------------------------------------------
 # Closed forms (Lemma 1, Thm 2 proof, Remark 2.2, Remark 2.3)
 # ----------------------------------------------------------------------------

@@ -13,10 +13,17 @@ not depend on any floating-point summation order:
 * ``quantize_weights``  - non-negative float weights -> uint64 integers W
                           with a common power-of-two scale;
 * ``inclusive_cdf``     - exact integer running sums of W (total T);
-* ``lemire_uniform``    - Lemire's multiply-and-reject map from 64-bit words
+* ``lemire_uniform``    - Lemire's multiply-and-reject map from random words
                           to an exactly uniform integer in [0, T)
                           (D. Lemire, "Fast random integer generation in an
-                          interval", ACM TOMACS 29(1), 2019);
+                          interval", ACM TOMACS 29(1), 2019), used with
+                          128-bit words (two generator words) so that a
+                          rejection has probability below 2^-64 for any
+                          T < 2^64: the drawn index then depends only on the
+                          high part of the product, which moves by at most
+                          one unit when T moves by a unit, so last-bit
+                          differences in the weights almost never change a
+                          draw;
 * ``search_cdf``        - the atom whose CDF interval holds that integer;
 * ``allocate_draws``    - integer draw counts c_s with sum c and c_s >= 1 on
                           every stratum that can be sampled (Alg. 2 input
@@ -119,16 +126,29 @@ def search_cdf(cdf, r):
     return a
 
 
+WORD_BITS = 128
+
+
+def wide_words(words):
+    """Pairs of consecutive 64-bit words as 128-bit words, the first word of
+    each pair being the high half."""
+    it = iter(words)
+    for hi in it:
+        lo = next(it)
+        yield (int(hi) << 64) | int(lo)
+
+
 def draw_atoms(cdf, T, count, seed, trial, stratum, tag=TAG_SAMPLE):
     """``count`` independent draws from one stratum's integer CDF.
 
     Draw j reads its own Philox word stream (``rng.draw_words``), maps it to
-    an exactly uniform integer r in [0, T) and returns the local atom index
-    whose CDF interval holds r.
+    an exactly uniform integer r in [0, T) with 128-bit words, and returns
+    the local atom index whose CDF interval holds r.
     """
     out = []
     for j in range(count):
-        r = lemire_uniform(draw_words(seed, trial, stratum, j, tag), T)
+        words = wide_words(draw_words(seed, trial, stratum, j, tag))
+        r = lemire_uniform(words, T, word_bits=WORD_BITS)
         out.append(search_cdf(cdf, r))
     return out
 

@@ -1,0 +1,362 @@
+"""Python binding of libsbmm, the MI355X (gfx950) sampled block matrix product.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels. PyTorch tensors provide device memory and the current stream. The
+C entry points are re-exported under the same names (``sbmm_norms``,
+``sbmm_plan``, ...); ``Handle`` bundles them with tensor allocation.
+
+The library must be built (``python -m paper_2105_04940_amd.build``); there is
+no fallback: importing the binding without ``libsbmm.so`` raises.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsbmm.so")
+
+SBMM_OK, SBMM_E_ARG, SBMM_E_BUDGET, SBMM_E_NONFINITE, SBMM_E_UNSUPPORTED, \
+    SBMM_E_NOMEM, SBMM_E_HIP, SBMM_E_STATE = range(8)
+SBMM_F64, SBMM_F32, SBMM_BF16, SBMM_F8E4M3 = range(4)
+MODES = {"block": 0, "stratified": 1}
+PROBS = {"uniform": 0, "norm": 1, "exact": 2, "user": 3}
+ALLOCS = {"uniform": 0, "norm": 1, "opt": 2, "user": 3}
+SKETCH_PAD = 32
+
+# Names of every function the C header declares (checked by the ABI test).
+EXPORTS = (
+    "sbmm_create", "sbmm_destroy", "sbmm_status_string", "sbmm_last_error",
+    "sbmm_reserve", "sbmm_sync", "sbmm_query_sizes", "sbmm_norms",
+    "sbmm_exact", "sbmm_plan", "sbmm_sketch", "sbmm_sketch_gemm",
+    "sbmm_error", "sbmm_run",
+)
+
+
+class SbmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"sbmm status {status}: {msg}")
+        self.status = status
+
+
+class Problem_t(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+        ("in_dtype", ctypes.c_int),
+        ("M", ctypes.c_void_p), ("ldm", ctypes.c_int64),
+        ("N", ctypes.c_void_p), ("ldn", ctypes.c_int64),
+        ("K", ctypes.c_int32), ("block_off", ctypes.c_void_p),
+        ("c", ctypes.c_int64),
+        ("mode", ctypes.c_int), ("prob", ctypes.c_int), ("alloc", ctypes.c_int),
+        ("user_w", ctypes.c_void_p), ("user_ck", ctypes.c_void_p),
+        ("blkprod_sq", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64), ("trial", ctypes.c_uint64),
+    ]
+
+
+class Sizes_t(ctypes.Structure):
+    _fields_ = [("atoms", ctypes.c_int64), ("strata", ctypes.c_int64),
+                ("max_width", ctypes.c_int64), ("L_max", ctypes.c_int64),
+                ("L_pad_max", ctypes.c_int64)]
+
+
+class PlanOut_t(ctypes.Structure):
+    _fields_ = [("idx", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("col_off", ctypes.c_void_p), ("ck", ctypes.c_void_p),
+                ("p_hat", ctypes.c_void_p), ("colmap", ctypes.c_void_p),
+                ("colscale", ctypes.c_void_p)]
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2105_04940_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "sbmm_create": (st, [P(vp), ctypes.c_int]),
+        "sbmm_destroy": (st, [vp]),
+        "sbmm_status_string": (ctypes.c_char_p, [st]),
+        "sbmm_last_error": (ctypes.c_char_p, [vp]),
+        "sbmm_reserve": (st, [vp, ctypes.c_size_t]),
+        "sbmm_sync": (st, [vp, vp]),
+        "sbmm_query_sizes": (st, [P(Problem_t), P(Sizes_t)]),
+        "sbmm_norms": (st, [vp, P(Problem_t), vp, vp, vp, vp]),
+        "sbmm_exact": (st, [vp, P(Problem_t), vp, i64, vp, vp, vp]),
+        "sbmm_plan": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), P(i64), vp]),
+        "sbmm_sketch": (st, [vp, P(Problem_t), P(PlanOut_t), st, vp, i64, vp, i64, vp]),
+        "sbmm_sketch_gemm": (st, [vp, i64, i64, i64, vp, st, vp, i64, vp, i64, vp, i64,
+                                  vp, i64, vp, vp]),
+        "sbmm_error": (st, [vp, i64, i64, st, vp, i64, vp, i64, vp, vp]),
+        "sbmm_run": (st, [vp, P(Problem_t), st, vp, i64, vp, i64, vp, i64, vp, i64,
+                          P(PlanOut_t), P(ctypes.c_double), P(ctypes.c_double), P(i64), vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_code(t):
+    torch = _torch()
+    if t == torch.float64:
+        return SBMM_F64
+    if t == torch.float32:
+        return SBMM_F32
+    if t == torch.bfloat16:
+        return SBMM_BF16
+    raise ValueError(f"unsupported dtype {t}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Problem:
+    """One sampling problem (M, N on the device, block offsets on the host)."""
+    M: object
+    N: object
+    off: object
+    c: int
+    mode: str = "block"
+    prob: str = "norm"
+    alloc: str = "norm"
+    seed: int = 0
+    trial: int = 0
+    user_w: object = None       # device float64 tensor
+    user_ck: object = None      # host int64 sequence
+    blkprod_sq: object = None   # device float64 tensor
+
+    def struct(self):
+        M, N = self.M, self.N
+        if M.dim() != 2 or N.dim() != 2 or M.shape[1] != N.shape[0]:
+            raise ValueError("M must be m x n and N n x p")
+        if M.stride(1) != 1 or N.stride(1) != 1:
+            raise ValueError("M and N must be row-major (unit column stride)")
+        if M.dtype != N.dtype:
+            raise ValueError("M and N must share a dtype")
+        off = np.ascontiguousarray(np.asarray(self.off, dtype=np.int64))
+        ck = (None if self.user_ck is None
+              else np.ascontiguousarray(np.asarray(self.user_ck, dtype=np.int64)))
+        s = Problem_t()
+        s._keep = (off, ck)          # the host arrays live as long as the struct
+        s.m, s.n = M.shape
+        s.p = N.shape[1]
+        s.in_dtype = dtype_code(M.dtype)
+        s.M = M.data_ptr() if M.numel() else None
+        s.ldm = max(M.stride(0), M.shape[1]) if M.shape[0] > 1 else M.shape[1]
+        s.N = N.data_ptr() if N.numel() else None
+        s.ldn = max(N.stride(0), N.shape[1]) if N.shape[0] > 1 else N.shape[1]
+        s.K = len(off) - 1
+        s.block_off = off.ctypes.data
+        s.c = int(self.c)
+        s.mode = MODES[self.mode]
+        s.prob = PROBS[self.prob]
+        s.alloc = ALLOCS[self.alloc]
+        s.user_w = None if self.user_w is None else self.user_w.data_ptr()
+        s.user_ck = None if ck is None else ck.ctypes.data
+        s.blkprod_sq = None if self.blkprod_sq is None else self.blkprod_sq.data_ptr()
+        s.seed = int(self.seed) & (2**64 - 1)
+        s.trial = int(self.trial) & (2**64 - 1)
+        return s
+
+
+def sbmm_query_sizes(problem):
+    s = problem.struct()
+    out = Sizes_t()
+    st = lib().sbmm_query_sizes(ctypes.byref(s), ctypes.byref(out))
+    if st != SBMM_OK:
+        raise SbmmError(st, lib().sbmm_status_string(st).decode())
+    return dict(atoms=out.atoms, strata=out.strata, max_width=out.max_width,
+                L_max=out.L_max, L_pad_max=out.L_pad_max)
+
+
+class Plan:
+    """Device buffers of the planning step."""
+
+    def __init__(self, problem, sizes, device):
+        torch = _torch()
+        c = int(problem.c)
+        kw = dict(device=device)
+        self.idx = torch.empty(c, dtype=torch.int32, **kw)
+        self.scale = torch.empty(c, dtype=torch.float64, **kw)
+        self.col_off = torch.empty(c + 1, dtype=torch.int64, **kw)
+        self.ck = torch.empty(sizes["strata"], dtype=torch.int64, **kw)
+        self.p_hat = torch.empty(sizes["atoms"], dtype=torch.float64, **kw)
+        self.colmap = torch.empty(sizes["L_pad_max"], dtype=torch.int32, **kw)
+        self.colscale = torch.empty(sizes["L_pad_max"], dtype=torch.float64, **kw)
+
+    def struct(self):
+        s = PlanOut_t()
+        s.idx, s.scale, s.col_off, s.ck = (self.idx.data_ptr(), self.scale.data_ptr(),
+                                           self.col_off.data_ptr(), self.ck.data_ptr())
+        s.p_hat = self.p_hat.data_ptr()
+        s.colmap, s.colscale = self.colmap.data_ptr(), self.colscale.data_ptr()
+        self._s = s
+        return s
+
+    @property
+    def L_dev(self):
+        return self.col_off[-1:]
+
+
+class Handle:
+    """A libsbmm handle on one device, with tensor-level helpers."""
+
+    def __init__(self, device=0):
+        self._lib = lib()
+        h = ctypes.c_void_p()
+        st = self._lib.sbmm_create(ctypes.byref(h), int(device))
+        if st != SBMM_OK:
+            raise SbmmError(st, "sbmm_create failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self._lib.sbmm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != SBMM_OK:
+            msg = self._lib.sbmm_last_error(self.h).decode(errors="replace")
+            raise SbmmError(st, f"{self._lib.sbmm_status_string(st).decode()}: {msg}")
+
+    # -- steps --------------------------------------------------------------
+    def norms(self, problem):
+        torch = _torch()
+        s = problem.struct()
+        n, K = s.n, s.K
+        dev = problem.M.device
+        col_sq = torch.empty(n, dtype=torch.float64, device=dev)
+        row_sq = torch.empty(n, dtype=torch.float64, device=dev)
+        blk = torch.empty(3 * K, dtype=torch.float64, device=dev)
+        self._check(self._lib.sbmm_norms(self.h, ctypes.byref(s), _ptr(col_sq), _ptr(row_sq),
+                                         _ptr(blk), _stream()))
+        return col_sq, row_sq, blk
+
+    def exact(self, problem, store=True, blocknorm=False):
+        torch = _torch()
+        s = problem.struct()
+        dev = problem.M.device
+        pd = torch.float64 if problem.M.dtype == torch.float64 else torch.float32
+        MN = torch.empty((s.m, s.p), dtype=pd, device=dev) if store else None
+        bp = torch.empty(s.K, dtype=torch.float64, device=dev) if blocknorm else None
+        mn_sq = torch.empty(1, dtype=torch.float64, device=dev)
+        self._check(self._lib.sbmm_exact(self.h, ctypes.byref(s), _ptr(MN), s.p if store else 0,
+                                         _ptr(bp), _ptr(mn_sq), _stream()))
+        return MN, bp, mn_sq
+
+    def plan(self, problem, col_sq=None, row_sq=None, blk=None, sync=True):
+        s = problem.struct()
+        sizes = sbmm_query_sizes(problem)
+        pl = Plan(problem, sizes, problem.M.device)
+        ps = pl.struct()
+        L = ctypes.c_int64(-1)
+        self._check(self._lib.sbmm_plan(self.h, ctypes.byref(s), _ptr(col_sq), _ptr(row_sq),
+                                        _ptr(blk), ctypes.byref(ps),
+                                        ctypes.byref(L) if sync else None, _stream()))
+        pl.L = L.value if sync else None
+        pl.sizes = sizes
+        return pl
+
+    def sketch(self, problem, plan, out_dtype=None, want_C=True, want_D=True):
+        torch = _torch()
+        s = problem.struct()
+        od = out_dtype or problem.M.dtype
+        Lp = plan.sizes["L_pad_max"]
+        dev = problem.M.device
+        C = torch.empty((s.m, Lp), dtype=od, device=dev) if want_C else None
+        D = torch.empty((Lp, s.p), dtype=od, device=dev) if want_D else None
+        ps = plan.struct()
+        self._check(self._lib.sbmm_sketch(self.h, ctypes.byref(s), ctypes.byref(ps),
+                                          dtype_code(od), _ptr(C), Lp, _ptr(D), s.p, _stream()))
+        return C, D
+
+    def sketch_gemm(self, C, D, plan, MN=None, store=True):
+        torch = _torch()
+        m, Lp = C.shape
+        p = D.shape[1]
+        od = torch.float64 if C.dtype == torch.float64 else torch.float32
+        CD = torch.empty((m, p), dtype=od, device=C.device) if store else None
+        err = torch.empty(1, dtype=torch.float64, device=C.device) if MN is not None else None
+        self._check(self._lib.sbmm_sketch_gemm(
+            self.h, m, p, Lp, _ptr(plan.L_dev), dtype_code(C.dtype), _ptr(C), C.stride(0),
+            _ptr(D), D.stride(0), _ptr(CD), p, _ptr(MN), p if MN is not None else 0,
+            _ptr(err), _stream()))
+        return CD, err
+
+    def error(self, X, Y):
+        torch = _torch()
+        out = torch.empty(2, dtype=torch.float64, device=X.device)
+        self._check(self._lib.sbmm_error(self.h, X.shape[0], X.shape[1], dtype_code(X.dtype),
+                                         _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), _ptr(out),
+                                         _stream()))
+        return out
+
+    def sync(self):
+        self._check(self._lib.sbmm_sync(self.h, _stream()))
+
+    def run(self, problem, compute=None, want_C=True, want_D=True, want_MN=True):
+        """The whole forward path (synchronizing). Returns a dict with C, D
+        (padded to L_pad_max columns / rows), CD, MN, the plan, L, err, rel."""
+        torch = _torch()
+        s = problem.struct()
+        sizes = sbmm_query_sizes(problem)
+        dev = problem.M.device
+        cd = compute or problem.M.dtype
+        pd = torch.float64 if cd == torch.float64 else torch.float32
+        Lp = sizes["L_pad_max"]
+        C = torch.empty((s.m, Lp), dtype=cd, device=dev) if want_C else None
+        D = torch.empty((Lp, s.p), dtype=cd, device=dev) if want_D else None
+        CD = torch.empty((s.m, s.p), dtype=pd, device=dev)
+        MN = torch.empty((s.m, s.p), dtype=pd, device=dev) if want_MN else None
+        pl = Plan(problem, sizes, dev)
+        ps = pl.struct()
+        err = ctypes.c_double()
+        rel = ctypes.c_double()
+        L = ctypes.c_int64()
+        self._check(self._lib.sbmm_run(
+            self.h, ctypes.byref(s), dtype_code(cd), _ptr(C), Lp, _ptr(D), s.p, _ptr(CD), s.p,
+            _ptr(MN), s.p, ctypes.byref(ps), ctypes.byref(err), ctypes.byref(rel),
+            ctypes.byref(L), _stream()))
+        pl.L = L.value
+        pl.sizes = sizes
+        return dict(C=C, D=D, CD=CD, MN=MN, plan=pl, L=L.value, err=err.value, rel=rel.value)
+
+
+def __getattr__(name):
+    # module-level access to the raw C entry points, e.g. sbmm_norms
+    if name in EXPORTS:
+        return getattr(lib(), name)
+    raise AttributeError(name)

@@ -1,0 +1,599 @@
+// C ABI of libsbmm: validation, workspace, stream ordering and status codes
+// around the kernels of the sampled block matrix product.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+struct sbmm_handle_s {
+  int device = 0;
+  char err[512] = {0};
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t* status = nullptr;   // device status word
+};
+
+namespace {
+
+sbmm_status fail(sbmm_handle h, sbmm_status st, const char* fmt, ...) {
+  if (h) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(h->err, sizeof(h->err), fmt, ap);
+    va_end(ap);
+  }
+  return st;
+}
+
+#define HIP_TRY(h, expr)                                                        \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return fail((h), SBMM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// Bump allocator over the handle's workspace. A dry run (base == nullptr)
+// only measures.
+struct Arena {
+  char* base;
+  size_t off = 0;
+  explicit Arena(char* b) : base(b) {}
+  template <typename T> T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (count ? count : 1);
+    return p;
+  }
+};
+
+sbmm_status ensure_ws(sbmm_handle h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return SBMM_OK;
+  HIP_TRY(h, hipSetDevice(h->device));
+  HIP_TRY(h, hipDeviceSynchronize());
+  if (h->ws) {
+    HIP_TRY(h, hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  size_t want = std::max(bytes, (size_t)1 << 20);
+  hipError_t e = hipMalloc(&h->ws, want);
+  if (e != hipSuccess) {
+    h->ws = nullptr;
+    return fail(h, SBMM_E_NOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
+  }
+  h->ws_bytes = want;
+  return SBMM_OK;
+}
+
+sbmm_status check_handle(sbmm_handle h) {
+  if (!h || !h->status) return SBMM_E_STATE;
+  h->err[0] = 0;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+    if (hipSetDevice(h->device) != hipSuccess)
+      return fail(h, SBMM_E_STATE, "cannot select device %d", h->device);
+  }
+  return SBMM_OK;
+}
+
+bool dtype_in_ok(sbmm_dtype t) { return t == SBMM_F64 || t == SBMM_F32 || t == SBMM_BF16; }
+
+// Host-side validation of a problem; fills the derived sizes.
+sbmm_status validate(sbmm_handle h, const sbmm_problem* P, sbmm_sizes* sz, bool blkprod_internal = false) {
+  if (!P) return fail(h, SBMM_E_ARG, "problem is NULL");
+  if (P->n < 1 || P->m < 0 || P->p < 0)
+    return fail(h, SBMM_E_ARG, "shape m=%lld n=%lld p=%lld (need n >= 1, m, p >= 0)",
+                (long long)P->m, (long long)P->n, (long long)P->p);
+  if (P->n > INT32_MAX) return fail(h, SBMM_E_ARG, "n exceeds 2^31 - 1");
+  if (!dtype_in_ok(P->in_dtype)) return fail(h, SBMM_E_ARG, "input dtype %d not supported", (int)P->in_dtype);
+  if (P->m > 0 && (!P->M || P->ldm < P->n))
+    return fail(h, SBMM_E_ARG, "M is NULL or ldm < n");
+  if (P->p > 0 && (!P->N || P->ldn < P->p))
+    return fail(h, SBMM_E_ARG, "N is NULL or ldn < p");
+  if (P->K < 1 || !P->block_off) return fail(h, SBMM_E_ARG, "need K >= 1 and block offsets");
+  if (P->block_off[0] != 0 || P->block_off[P->K] != P->n)
+    return fail(h, SBMM_E_ARG, "block offsets must start at 0 and end at n");
+  int64_t maxw = 0;
+  for (int32_t k = 0; k < P->K; ++k) {
+    const int64_t w = P->block_off[k + 1] - P->block_off[k];
+    if (w < 1) return fail(h, SBMM_E_ARG, "block %d has size %lld (need >= 1)", k, (long long)w);
+    maxw = std::max(maxw, w);
+  }
+  if (P->c < 1 || P->c > INT32_MAX) return fail(h, SBMM_E_ARG, "c = %lld out of range", (long long)P->c);
+  if (P->mode != SBMM_MODE_BLOCK && P->mode != SBMM_MODE_STRATIFIED)
+    return fail(h, SBMM_E_ARG, "unknown mode %d", (int)P->mode);
+  if (P->prob < SBMM_P_UNIFORM || P->prob > SBMM_P_USER)
+    return fail(h, SBMM_E_ARG, "unknown probability rule %d", (int)P->prob);
+  if (P->prob == SBMM_P_USER && !P->user_w) return fail(h, SBMM_E_ARG, "rule USER needs user_w");
+  if (P->mode == SBMM_MODE_BLOCK) {
+    if (P->prob == SBMM_P_EXACT && !P->blkprod_sq && !blkprod_internal)
+      return fail(h, SBMM_E_ARG, "rule EXACT needs blkprod_sq (from sbmm_exact)");
+  } else {
+    if (P->alloc < SBMM_ALLOC_UNIFORM || P->alloc > SBMM_ALLOC_USER)
+      return fail(h, SBMM_E_ARG, "unknown allocation rule %d", (int)P->alloc);
+    if (P->alloc == SBMM_ALLOC_OPT && !P->blkprod_sq && !blkprod_internal)
+      return fail(h, SBMM_E_ARG, "allocation OPT needs blkprod_sq (from sbmm_exact)");
+    if (P->alloc == SBMM_ALLOC_USER) {
+      if (!P->user_ck) return fail(h, SBMM_E_ARG, "allocation USER needs user_ck");
+      int64_t s = 0;
+      for (int32_t k = 0; k < P->K; ++k) {
+        if (P->user_ck[k] < 0) return fail(h, SBMM_E_ARG, "user_ck[%d] < 0", k);
+        s += P->user_ck[k];
+      }
+      if (s != P->c) return fail(h, SBMM_E_ARG, "user_ck sums to %lld, not c = %lld", (long long)s, (long long)P->c);
+    }
+  }
+  if (sz) {
+    const bool blockm = P->mode == SBMM_MODE_BLOCK;
+    sz->atoms = blockm ? P->K : P->n;
+    sz->strata = blockm ? 1 : P->K;
+    sz->max_width = blockm ? maxw : 1;
+    sz->L_max = P->c * sz->max_width;
+    sz->L_pad_max = round_up(sz->L_max, SBMM_SKETCH_PAD);
+  }
+  return SBMM_OK;
+}
+
+// the effective probability rule (EXACT on unit atoms is NORM)
+int eff_prob(const sbmm_problem* P) {
+  if (P->mode == SBMM_MODE_STRATIFIED && P->prob == SBMM_P_EXACT) return SBMM_P_NORM;
+  return P->prob;
+}
+
+bool needs_blkprod(const sbmm_problem* P) {
+  return (P->mode == SBMM_MODE_BLOCK && P->prob == SBMM_P_EXACT) ||
+         (P->mode == SBMM_MODE_STRATIFIED && P->alloc == SBMM_ALLOC_OPT);
+}
+
+sbmm_status status_from_device(sbmm_handle h, int32_t bits) {
+  if (bits & SBMM_DEV_NONFINITE) return fail(h, SBMM_E_NONFINITE, "non-finite input norm or weight");
+  if (bits & SBMM_DEV_BUDGET) return fail(h, SBMM_E_BUDGET, "c is below the number of strata with positive weight");
+  if (bits & SBMM_DEV_USER_CK) return fail(h, SBMM_E_ARG, "user draw counts must be positive exactly on strata with positive weight");
+  if (bits & SBMM_DEV_RNG) return fail(h, SBMM_E_HIP, "sampler exhausted its generator blocks");
+  return SBMM_OK;
+}
+
+sbmm_status read_status(sbmm_handle h, hipStream_t s) {
+  HIP_TRY(h, hipStreamSynchronize(s));
+  int32_t bits = 0;
+  HIP_TRY(h, hipMemcpy(&bits, h->status, sizeof(bits), hipMemcpyDeviceToHost));
+  if (bits) {
+    const int32_t zero = 0;
+    HIP_TRY(h, hipMemcpy(h->status, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  }
+  return status_from_device(h, bits);
+}
+
+// --- internal steps (work on an arena that already has room) --------------
+
+sbmm_status upload_offsets(sbmm_handle h, const sbmm_problem* P, Arena& ar, int64_t** out, hipStream_t s) {
+  int64_t* d = ar.take<int64_t>(P->K + 1);
+  if (ar.base) HIP_TRY(h, hipMemcpyAsync(d, P->block_off, sizeof(int64_t) * (P->K + 1), hipMemcpyHostToDevice, s));
+  *out = d;
+  return SBMM_OK;
+}
+
+sbmm_status do_norms(sbmm_handle h, const sbmm_problem* P, const int64_t* off_dev, double* col_sq,
+                     double* row_sq, double* blk, Arena& ar, hipStream_t s) {
+  int R = 1;
+  const size_t pe = norms_partial_elems(P->in_dtype, P->m, P->n, &R);
+  double* partial = ar.take<double>(pe);
+  if (!ar.base) return SBMM_OK;
+  NormLaunch L{};
+  L.dt = P->in_dtype; L.M = P->M; L.ldm = P->ldm; L.N = P->N; L.ldn = P->ldn;
+  L.m = P->m; L.n = P->n; L.p = P->p; L.K = P->K; L.off_dev = off_dev;
+  L.partial = partial; L.rsplit = R; L.col_sq = col_sq; L.row_sq = row_sq; L.blk = blk;
+  L.status = h->status;
+  HIP_TRY(h, launch_norms(L, s));
+  return SBMM_OK;
+}
+
+sbmm_dtype product_dtype(sbmm_dtype in) { return in == SBMM_F64 ? SBMM_F64 : SBMM_F32; }
+
+// Exact product with optional MN store, block norms and error vs Y.
+sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_dev, void* MN, int64_t ldmn,
+                     const void* Y, int64_t ldy, double* blkprod_sq, double* out2, Arena& ar, hipStream_t s) {
+  if (P->in_dtype == SBMM_BF16) return fail(h, SBMM_E_UNSUPPORTED, "exact product of bf16 inputs is not built");
+  const bool bn = blkprod_sq != nullptr;
+  const int64_t tiles = gemm_tiles(P->in_dtype, P->m, P->p, bn);
+  double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
+  double* blk_part = bn ? ar.take<double>((size_t)P->K * std::max<int64_t>(tiles, 1) * 4) : nullptr;
+  if (!ar.base) return SBMM_OK;
+  if (tiles == 0) {
+    HIP_TRY(h, launch_fill_f64(out2, 2, 0.0, s));
+    if (bn) HIP_TRY(h, launch_fill_f64(blkprod_sq, P->K, 0.0, s));
+    return SBMM_OK;
+  }
+  GemmLaunch G{};
+  G.dt = P->in_dtype; G.A = P->M; G.lda = P->ldm; G.B = P->N; G.ldb = P->ldn;
+  G.m = P->m; G.p = P->p; G.K_host = P->n; G.K_dev = nullptr;
+  G.Cout = MN; G.ldc = ldmn; G.Y = Y; G.ldy = ldy; G.tile_part = tile_part;
+  G.K_blocks = P->K; G.off_dev = off_dev; G.blk_part = blk_part;
+  HIP_TRY(h, launch_gemm(G, s));
+  HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
+  if (bn) HIP_TRY(h, launch_reduce_cols(blk_part, P->K, tiles * 4, blkprod_sq, s));
+  return SBMM_OK;
+}
+
+sbmm_status do_plan(sbmm_handle h, const sbmm_problem* P, const sbmm_sizes& sz, const int64_t* off_dev,
+                    const double* col_sq, const double* row_sq, const double* blk, const sbmm_plan_out* out,
+                    Arena& ar, hipStream_t s) {
+  PlanLaunch L{};
+  L.W = ar.take<uint64_t>(sz.atoms);
+  L.cdf = ar.take<uint64_t>(sz.atoms);
+  L.T = ar.take<uint64_t>(sz.strata);
+  L.draw_off = ar.take<int64_t>(sz.strata + 1);
+  L.width = ar.take<int64_t>(P->c);
+  L.G = ar.take<uint64_t>(sz.strata);
+  L.quota = ar.take<int64_t>(sz.strata);
+  L.rem = ar.take<uint64_t>(sz.strata);
+  L.left = ar.take<int64_t>(1);
+  int64_t* user_ck_dev = nullptr;
+  const bool uck = P->mode == SBMM_MODE_STRATIFIED && P->alloc == SBMM_ALLOC_USER;
+  if (uck) user_ck_dev = ar.take<int64_t>(P->K);
+  if (!ar.base) return SBMM_OK;
+  if (uck) HIP_TRY(h, hipMemcpyAsync(user_ck_dev, P->user_ck, sizeof(int64_t) * P->K, hipMemcpyHostToDevice, s));
+  L.mode = P->mode; L.prob = eff_prob(P); L.alloc = P->alloc;
+  L.n = P->n; L.K = P->K; L.c = P->c; L.A = sz.atoms; L.S = sz.strata;
+  L.off_dev = off_dev; L.col_sq = col_sq; L.row_sq = row_sq; L.blk = blk;
+  L.user_w = P->user_w; L.user_ck_dev = user_ck_dev; L.blkprod_sq = P->blkprod_sq;
+  L.seed = P->seed; L.trial = P->trial;
+  L.idx = out->idx; L.scale = out->scale; L.col_off = out->col_off; L.ck = out->ck;
+  L.p_hat = out->p_hat; L.colmap = out->colmap; L.colscale = out->colscale;
+  L.L_pad_max = sz.L_pad_max; L.status = h->status;
+  HIP_TRY(h, launch_plan(L, s));
+  return SBMM_OK;
+}
+
+bool plan_out_ok(const sbmm_plan_out* o) {
+  return o && o->idx && o->scale && o->col_off && o->ck && o->colmap && o->colscale;
+}
+
+bool sketch_dtype_ok(sbmm_dtype in, sbmm_dtype out) {
+  if (in == SBMM_F64) return out == SBMM_F64;
+  return out == SBMM_F32 || out == SBMM_BF16;
+}
+
+}  // namespace
+
+// ============================================================================
+// Public entry points
+// ============================================================================
+
+extern "C" {
+
+const char* sbmm_status_string(sbmm_status s) {
+  switch (s) {
+    case SBMM_OK: return "ok";
+    case SBMM_E_ARG: return "invalid argument";
+    case SBMM_E_BUDGET: return "sample budget too small";
+    case SBMM_E_NONFINITE: return "non-finite input";
+    case SBMM_E_UNSUPPORTED: return "unsupported";
+    case SBMM_E_NOMEM: return "out of device memory";
+    case SBMM_E_HIP: return "HIP error";
+    case SBMM_E_STATE: return "invalid handle state";
+  }
+  return "unknown status";
+}
+
+sbmm_status sbmm_create(sbmm_handle* out, int device) {
+  if (!out) return SBMM_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SBMM_E_ARG;
+  sbmm_handle h = new (std::nothrow) sbmm_handle_s();
+  if (!h) return SBMM_E_NOMEM;
+  h->device = device;
+  if (hipSetDevice(device) != hipSuccess) { delete h; return SBMM_E_HIP; }
+  if (hipMalloc(&h->status, sizeof(int32_t)) != hipSuccess) { delete h; return SBMM_E_NOMEM; }
+  const int32_t zero = 0;
+  if (hipMemcpy(h->status, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(h->status);
+    delete h;
+    return SBMM_E_HIP;
+  }
+  *out = h;
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_destroy(sbmm_handle h) {
+  if (!h) return SBMM_E_STATE;
+  hipSetDevice(h->device);
+  if (h->ws) hipFree(h->ws);
+  if (h->status) hipFree(h->status);
+  h->status = nullptr;
+  delete h;
+  return SBMM_OK;
+}
+
+const char* sbmm_last_error(sbmm_handle h) { return h ? h->err : "null handle"; }
+
+sbmm_status sbmm_reserve(sbmm_handle h, size_t bytes) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  return ensure_ws(h, bytes);
+}
+
+sbmm_status sbmm_sync(sbmm_handle h, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  return read_status(h, (hipStream_t)stream);
+}
+
+sbmm_status sbmm_query_sizes(const sbmm_problem* prob, sbmm_sizes* out) {
+  if (!out) return SBMM_E_ARG;
+  return validate(nullptr, prob, out, true);   // sizes do not depend on blkprod_sq
+}
+
+sbmm_status sbmm_norms(sbmm_handle h, const sbmm_problem* P, double* col_sq, double* row_sq, double* blk,
+                       sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  sbmm_sizes sz;
+  if ((st = validate(h, P, &sz))) return st;
+  if (!col_sq || !row_sq || !blk) return fail(h, SBMM_E_ARG, "col_sq, row_sq and blk are required");
+  hipStream_t s = (hipStream_t)stream;
+  Arena dry(nullptr);
+  int64_t* off = nullptr;
+  upload_offsets(h, P, dry, &off, s);
+  do_norms(h, P, off, col_sq, row_sq, blk, dry, s);
+  if ((st = ensure_ws(h, dry.off))) return st;
+  Arena ar(h->ws);
+  if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+  return do_norms(h, P, off, col_sq, row_sq, blk, ar, s);
+}
+
+sbmm_status sbmm_exact(sbmm_handle h, const sbmm_problem* P, void* MN, int64_t ldmn, double* blkprod_sq,
+                       double* mn_sq, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  sbmm_sizes sz;
+  if ((st = validate(h, P, &sz))) return st;
+  if (!mn_sq) return fail(h, SBMM_E_ARG, "mn_sq is required");
+  if (MN && ldmn < P->p) return fail(h, SBMM_E_ARG, "ldmn < p");
+  hipStream_t s = (hipStream_t)stream;
+  Arena dry(nullptr);
+  int64_t* off = nullptr;
+  upload_offsets(h, P, dry, &off, s);
+  double* out2 = dry.take<double>(2);
+  if ((st = do_exact(h, P, off, MN, ldmn, nullptr, 0, blkprod_sq, out2, dry, s))) return st;
+  if ((st = ensure_ws(h, dry.off))) return st;
+  Arena ar(h->ws);
+  if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+  out2 = ar.take<double>(2);
+  if ((st = do_exact(h, P, off, MN, ldmn, nullptr, 0, blkprod_sq, out2, ar, s))) return st;
+  HIP_TRY(h, hipMemcpyAsync(mn_sq, out2 + 1, sizeof(double), hipMemcpyDeviceToDevice, s));
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* P, const double* col_sq, const double* row_sq,
+                      const double* blk, const sbmm_plan_out* out, int64_t* L_host, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  sbmm_sizes sz;
+  if ((st = validate(h, P, &sz))) return st;
+  if (!plan_out_ok(out)) return fail(h, SBMM_E_ARG, "plan output buffers missing");
+  const int pr = eff_prob(P);
+  const bool strat = P->mode == SBMM_MODE_STRATIFIED;
+  const bool need_blk = (!strat && pr == SBMM_P_NORM) ||
+                        (strat && (P->alloc == SBMM_ALLOC_NORM || P->alloc == SBMM_ALLOC_OPT));
+  const bool need_colrow = strat && pr == SBMM_P_NORM;
+  if ((need_blk && !blk) || (need_colrow && (!col_sq || !row_sq)))
+    return fail(h, SBMM_E_ARG, "the rule needs the norm-pass outputs");
+  hipStream_t s = (hipStream_t)stream;
+  Arena dry(nullptr);
+  int64_t* off = nullptr;
+  upload_offsets(h, P, dry, &off, s);
+  do_plan(h, P, sz, off, col_sq, row_sq, blk, out, dry, s);
+  if ((st = ensure_ws(h, dry.off))) return st;
+  Arena ar(h->ws);
+  if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+  if ((st = do_plan(h, P, sz, off, col_sq, row_sq, blk, out, ar, s))) return st;
+  if (L_host) {
+    HIP_TRY(h, hipMemcpyAsync(L_host, out->col_off + P->c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    return read_status(h, s);
+  }
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_sketch(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_out* plan, sbmm_dtype out_dtype,
+                        void* C, int64_t ldc, void* D, int64_t ldd, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  sbmm_sizes sz;
+  if ((st = validate(h, P, &sz))) return st;
+  if (!plan || !plan->col_off || !plan->colmap || !plan->colscale) return fail(h, SBMM_E_ARG, "plan buffers missing");
+  if (!sketch_dtype_ok(P->in_dtype, out_dtype)) return fail(h, SBMM_E_ARG, "sketch dtype not allowed for the input dtype");
+  if (C && ldc < sz.L_pad_max) return fail(h, SBMM_E_ARG, "ldc < L_pad_max (%lld)", (long long)sz.L_pad_max);
+  if (D && ldd < P->p) return fail(h, SBMM_E_ARG, "ldd < p");
+  GatherLaunch g{};
+  g.in_dt = P->in_dtype; g.out_dt = out_dtype;
+  g.M = P->M; g.ldm = P->ldm; g.N = P->N; g.ldn = P->ldn; g.m = P->m; g.p = P->p;
+  g.L_dev = plan->col_off + P->c; g.L_pad_max = sz.L_pad_max;
+  g.colmap = plan->colmap; g.colscale = plan->colscale;
+  g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+  HIP_TRY(h, launch_gather(g, (hipStream_t)stream));
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_max, const int64_t* L_dev,
+                             sbmm_dtype dtype, const void* C, int64_t ldc, const void* D, int64_t ldd, void* CD,
+                             int64_t ldcd, const void* MN, int64_t ldmn, double* err_sq, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  if (m < 0 || p < 0 || L_pad_max < 0 || !L_dev) return fail(h, SBMM_E_ARG, "bad sizes or L_dev");
+  if (dtype != SBMM_F64 && dtype != SBMM_F32)
+    return fail(h, SBMM_E_UNSUPPORTED, "sketched product in dtype %d is not built", (int)dtype);
+  if (m > 0 && p > 0 && L_pad_max > 0 && (!C || !D)) return fail(h, SBMM_E_ARG, "C and D are required");
+  if (ldc < L_pad_max || ldd < p) return fail(h, SBMM_E_ARG, "ldc < L_pad_max or ldd < p");
+  if (CD && ldcd < p) return fail(h, SBMM_E_ARG, "ldcd < p");
+  if ((MN != nullptr) != (err_sq != nullptr)) return fail(h, SBMM_E_ARG, "MN and err_sq go together");
+  if (MN && ldmn < p) return fail(h, SBMM_E_ARG, "ldmn < p");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t tiles = gemm_tiles(dtype, m, p, false);
+  Arena dry(nullptr);
+  dry.take<double>(2 * std::max<int64_t>(tiles, 1));
+  dry.take<double>(2);
+  if ((st = ensure_ws(h, dry.off))) return st;
+  Arena ar(h->ws);
+  double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
+  double* out2 = ar.take<double>(2);
+  if (tiles == 0) {
+    if (err_sq) HIP_TRY(h, launch_fill_f64(err_sq, 1, 0.0, s));
+    return SBMM_OK;
+  }
+  GemmLaunch G{};
+  G.dt = dtype; G.A = C; G.lda = ldc; G.B = D; G.ldb = ldd; G.m = m; G.p = p;
+  G.K_host = 0; G.K_dev = L_dev; G.Cout = CD; G.ldc = ldcd; G.Y = MN; G.ldy = ldmn;
+  G.tile_part = err_sq ? tile_part : nullptr;
+  HIP_TRY(h, launch_gemm(G, s));
+  if (err_sq) {
+    HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
+    HIP_TRY(h, hipMemcpyAsync(err_sq, out2, sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_error(sbmm_handle h, int64_t m, int64_t p, sbmm_dtype dtype, const void* X, int64_t ldx,
+                       const void* Y, int64_t ldy, double* out2, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  if (m < 0 || p < 0 || !out2) return fail(h, SBMM_E_ARG, "bad sizes or out2");
+  if (dtype != SBMM_F64 && dtype != SBMM_F32) return fail(h, SBMM_E_ARG, "dtype must be F64 or F32");
+  if (m > 0 && p > 0 && (!X || !Y || ldx < p || ldy < p)) return fail(h, SBMM_E_ARG, "X/Y missing or ld < p");
+  hipStream_t s = (hipStream_t)stream;
+  if (m == 0 || p == 0) {
+    HIP_TRY(h, launch_fill_f64(out2, 2, 0.0, s));
+    return SBMM_OK;
+  }
+  const int64_t np = error_parts(m, p);
+  if ((st = ensure_ws(h, 256 + sizeof(double) * 2 * np))) return st;
+  Arena ar(h->ws);
+  double* part = ar.take<double>(2 * np);
+  HIP_TRY(h, launch_error(dtype, m, p, X, ldx, Y, ldy, part, np, s));
+  HIP_TRY(h, launch_reduce_cols(part, 2, np, out2, s));
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, void* C, int64_t ldc, void* D,
+                     int64_t ldd, void* CD, int64_t ldcd, void* MN, int64_t ldmn, const sbmm_plan_out* plan,
+                     double* err_host, double* rel_host, int64_t* L_host, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  sbmm_sizes sz;
+  if ((st = validate(h, P, &sz, true))) return st;
+  if (!plan_out_ok(plan)) return fail(h, SBMM_E_ARG, "plan output buffers missing");
+  if (!sketch_dtype_ok(P->in_dtype, compute)) return fail(h, SBMM_E_ARG, "compute dtype not allowed for the input dtype");
+  if (compute != SBMM_F64 && compute != SBMM_F32)
+    return fail(h, SBMM_E_UNSUPPORTED, "sketched product in dtype %d is not built", (int)compute);
+  if (P->in_dtype == SBMM_BF16) return fail(h, SBMM_E_UNSUPPORTED, "bf16 inputs are not built in sbmm_run");
+  if ((P->m > 0 && P->p > 0 && !CD) || ldcd < P->p) return fail(h, SBMM_E_ARG, "CD is required with ldcd >= p");
+  if (C && ldc < sz.L_pad_max) return fail(h, SBMM_E_ARG, "ldc < L_pad_max");
+  if (D && ldd < P->p) return fail(h, SBMM_E_ARG, "ldd < p");
+  if (MN && ldmn < P->p) return fail(h, SBMM_E_ARG, "ldmn < p");
+  hipStream_t s = (hipStream_t)stream;
+  const bool bp = needs_blkprod(P);
+  const sbmm_dtype pd = product_dtype(P->in_dtype);
+  const size_t pes = dtype_size(pd), ces = dtype_size(compute);
+
+  for (int pass = 0; pass < 2; ++pass) {
+    Arena ar(pass ? h->ws : nullptr);
+    int64_t* off = nullptr;
+    if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+    double* col_sq = ar.take<double>(P->n);
+    double* row_sq = ar.take<double>(P->n);
+    double* blk = ar.take<double>(3 * (size_t)P->K);
+    double* blkprod = bp ? ar.take<double>(P->K) : nullptr;
+    double* ex2 = ar.take<double>(2);     // exact pass: err^2 (when fused), ||MN||^2
+    double* sk2 = ar.take<double>(2);     // sketch pass: err^2, ||CD||^2
+    void* Cw = C ? C : ar.take<char>(ces * (size_t)std::max<int64_t>(P->m, 1) * sz.L_pad_max);
+    const int64_t ldcw = C ? ldc : sz.L_pad_max;
+    void* Dw = D ? D : ar.take<char>(ces * (size_t)sz.L_pad_max * std::max<int64_t>(P->p, 1));
+    const int64_t lddw = D ? ldd : P->p;
+    void* MNw = MN ? MN : (bp ? ar.take<char>(pes * (size_t)std::max<int64_t>(P->m, 1) * std::max<int64_t>(P->p, 1)) : nullptr);
+    const int64_t ldmnw = MN ? ldmn : P->p;
+    const int64_t tiles_s = gemm_tiles(compute, P->m, P->p, false);
+    double* sk_part = ar.take<double>(2 * std::max<int64_t>(tiles_s, 1));
+    // measure the remaining scratch of the sub-steps on a dry arena
+    if (!pass) {
+      do_norms(h, P, off, col_sq, row_sq, blk, ar, s);
+      Arena sub(nullptr);
+      sub.off = ar.off;
+      do_exact(h, P, off, MNw, ldmnw, nullptr, 0, blkprod, ex2, sub, s);
+      size_t need = sub.off;
+      Arena sub2(nullptr);
+      sub2.off = ar.off;
+      do_plan(h, P, sz, off, col_sq, row_sq, blk, plan, sub2, s);
+      need = std::max(need, sub2.off);
+      if ((st = ensure_ws(h, need))) return st;
+      continue;
+    }
+    const size_t base = ar.off;
+    // 1. norm pass
+    {
+      Arena sub(h->ws);
+      sub.off = base;
+      if ((st = do_norms(h, P, off, col_sq, row_sq, blk, sub, s))) return st;
+    }
+    // 2. exact product first when the rules need ||M^k N_k||_F
+    if (bp) {
+      Arena sub(h->ws);
+      sub.off = base;
+      if ((st = do_exact(h, P, off, MNw, ldmnw, nullptr, 0, blkprod, ex2, sub, s))) return st;
+    }
+    // 3. plan
+    sbmm_problem Q = *P;
+    if (bp) Q.blkprod_sq = blkprod;
+    {
+      Arena sub(h->ws);
+      sub.off = base;
+      if ((st = do_plan(h, &Q, sz, off, col_sq, row_sq, blk, plan, sub, s))) return st;
+    }
+    // 4. sketch
+    {
+      GatherLaunch g{};
+      g.in_dt = P->in_dtype; g.out_dt = compute;
+      g.M = P->M; g.ldm = P->ldm; g.N = P->N; g.ldn = P->ldn; g.m = P->m; g.p = P->p;
+      g.L_dev = plan->col_off + P->c; g.L_pad_max = sz.L_pad_max;
+      g.colmap = plan->colmap; g.colscale = plan->colscale;
+      g.C = Cw; g.ldc = ldcw; g.D = Dw; g.ldd = lddw;
+      HIP_TRY(h, launch_gather(g, s));
+    }
+    // 5. sketched product (with the error when MN is already there)
+    if (tiles_s > 0) {
+      GemmLaunch G{};
+      G.dt = compute; G.A = Cw; G.lda = ldcw; G.B = Dw; G.ldb = lddw; G.m = P->m; G.p = P->p;
+      G.K_host = 0; G.K_dev = plan->col_off + P->c; G.Cout = CD; G.ldc = ldcd;
+      G.Y = bp ? MNw : nullptr; G.ldy = ldmnw; G.tile_part = bp ? sk_part : nullptr;
+      HIP_TRY(h, launch_gemm(G, s));
+      if (bp) HIP_TRY(h, launch_reduce_cols(sk_part, 2, tiles_s, sk2, s));
+    }
+    // 6. exact product with the error against CD
+    if (!bp) {
+      Arena sub(h->ws);
+      sub.off = base;
+      if ((st = do_exact(h, P, off, MNw, ldmnw, CD, ldcd, nullptr, ex2, sub, s))) return st;
+    }
+    // 7. results
+    double hv[4] = {0, 0, 0, 0};
+    int64_t Lh = 0;
+    HIP_TRY(h, hipMemcpyAsync(hv, ex2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (bp && tiles_s > 0) HIP_TRY(h, hipMemcpyAsync(hv + 2, sk2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(&Lh, plan->col_off + P->c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if ((st = read_status(h, s))) return st;
+    const double err2 = bp ? hv[2] : hv[0];
+    const double mn2 = hv[1];
+    const double err = std::sqrt(err2);
+    if (err_host) *err_host = err;
+    if (rel_host) *rel_host = mn2 > 0 ? err / std::sqrt(mn2) : (err2 > 0 ? INFINITY : 0.0);
+    if (L_host) *L_host = Lh;
+  }
+  return SBMM_OK;
+}
+
+}  // extern "C"

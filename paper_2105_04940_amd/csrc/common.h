@@ -1,0 +1,150 @@
+// Internal declarations shared by the libsbmm HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "sbmm.h"
+
+// Device status word bits (set by kernels with plain vector stores; read
+// and cleared by the synchronizing calls).
+enum : int32_t {
+  SBMM_DEV_NONFINITE = 1,   // NaN/Inf in a norm or weight
+  SBMM_DEV_BUDGET = 2,      // c below the number of strata that can be sampled
+  SBMM_DEV_USER_CK = 4,     // user draw counts inconsistent with the weights
+  SBMM_DEV_RNG = 8          // a draw ran out of generator blocks (never expected)
+};
+
+// Sketch columns are padded (with zero columns) to a multiple of this, so
+// the sketched product needs no tail handling along its inner dimension.
+constexpr int64_t SBMM_SKETCH_PAD = 32;
+
+inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+inline int64_t ceil_div(int64_t x, int64_t q) { return (x + q - 1) / q; }
+
+inline size_t dtype_size(sbmm_dtype t) {
+  switch (t) {
+    case SBMM_F64: return 8;
+    case SBMM_F32: return 4;
+    case SBMM_BF16: return 2;
+    case SBMM_F8E4M3: return 1;
+  }
+  return 0;
+}
+
+// ----------------------------------------------------------------------------
+// Device helpers
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t b) {
+  return __uint_as_float(((uint32_t)b) << 16);
+}
+
+// Round-to-nearest-even float -> bf16 bits (NaN kept quiet).
+__device__ __forceinline__ uint16_t float_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+template <typename T> struct Elem;
+template <> struct Elem<double> {
+  __device__ static double to_double(double x) { return x; }
+};
+template <> struct Elem<float> {
+  __device__ static double to_double(float x) { return (double)x; }
+};
+template <> struct Elem<uint16_t> {  // bf16 stored as raw bits
+  __device__ static double to_double(uint16_t x) { return (double)bf16_bits_to_float(x); }
+};
+
+__device__ __forceinline__ double warp_sum_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ----------------------------------------------------------------------------
+// Host-side launch helpers (defined in the .hip files)
+// ----------------------------------------------------------------------------
+
+struct NormLaunch {
+  sbmm_dtype dt;
+  const void* M; int64_t ldm;
+  const void* N; int64_t ldn;
+  int64_t m, n, p;
+  int32_t K;
+  const int64_t* off_dev;   // K+1
+  double* partial;          // [R][n]
+  int rsplit;               // R
+  double* col_sq; double* row_sq; double* blk;
+  int32_t* status;
+};
+size_t norms_partial_elems(sbmm_dtype dt, int64_t m, int64_t n, int* rsplit_out);
+hipError_t launch_norms(const NormLaunch& a, hipStream_t s);
+
+struct PlanLaunch {
+  int mode;                 // sbmm_mode
+  int prob;                 // sbmm_prob
+  int alloc;                // sbmm_alloc
+  int64_t n; int32_t K; int64_t c;
+  int64_t A, S;
+  const int64_t* off_dev;   // K+1
+  const double* col_sq; const double* row_sq; const double* blk;
+  const double* user_w; const int64_t* user_ck_dev; const double* blkprod_sq;
+  uint64_t seed, trial;
+  // workspace
+  uint64_t* W; uint64_t* cdf; uint64_t* T; int64_t* draw_off; int64_t* width;
+  uint64_t* G; int64_t* quota; uint64_t* rem; int64_t* left;
+  // outputs
+  int32_t* idx; double* scale; int64_t* col_off; int64_t* ck; double* p_hat;
+  int32_t* colmap; double* colscale; int64_t L_pad_max;
+  int32_t* status;
+};
+hipError_t launch_plan(const PlanLaunch& a, hipStream_t s);
+
+struct GatherLaunch {
+  sbmm_dtype in_dt, out_dt;
+  const void* M; int64_t ldm;
+  const void* N; int64_t ldn;
+  int64_t m, p;
+  const int64_t* L_dev;
+  int64_t L_pad_max;
+  const int32_t* colmap; const double* colscale;
+  void* C; int64_t ldc;
+  void* D; int64_t ldd;
+};
+hipError_t launch_gather(const GatherLaunch& a, hipStream_t s);
+
+struct GemmLaunch {
+  sbmm_dtype dt;            // F64 or F32 operands
+  const void* A; int64_t lda;   // m x K row-major
+  const void* B; int64_t ldb;   // K x p row-major
+  int64_t m, p;
+  int64_t K_host;           // inner extent if K_dev == nullptr
+  const int64_t* K_dev;     // device inner extent (rounded up to 32 by the kernel)
+  void* Cout; int64_t ldc;  // optional output (F64 for F64, else F32)
+  const void* Y; int64_t ldy;   // optional reference for the error epilogue
+  double* tile_part;        // [tiles][2]: sum (C - Y)^2, sum C^2
+  // block-product norms (optional)
+  int32_t K_blocks; const int64_t* off_dev; double* blk_part;  // [K][tiles*4]
+};
+int64_t gemm_tiles(sbmm_dtype dt, int64_t m, int64_t p, bool blocknorm);
+hipError_t launch_gemm(const GemmLaunch& a, hipStream_t s);
+
+// Fill kernels (used instead of memset so that captured graphs hold only
+// kernel nodes).
+hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
+
+// Sum `rows` x `cols` float64 partials (row-major) over rows in a fixed order
+// into out[cols].
+hipError_t launch_reduce_cols(const double* part, int64_t rows, int64_t cols,
+                              double* out, hipStream_t s);
+
+hipError_t launch_error(sbmm_dtype dt, int64_t m, int64_t p, const void* X,
+                        int64_t ldx, const void* Y, int64_t ldy,
+                        double* part, int64_t nparts, hipStream_t s);
+int64_t error_parts(int64_t m, int64_t p);

@@ -1,0 +1,296 @@
+// Norm pass: squared column norms of M, squared row norms of N and the
+// per-block statistics ||M^k||_F^2, ||N_k||_F^2 and s_k = sum_i a_i b_i that
+// the probability rules (1.1), (1.4), (3.8) and the block sizes (4.2) are
+// built from.
+//
+// Both inputs are row-major and streamed once from HBM with 16-byte loads:
+//  * M (m x n): a wave covers 64 * E consecutive columns of one row (E
+//    elements per 16 bytes), the four waves of a workgroup take rows
+//    round-robin, and the row range is split R ways; each workgroup leaves a
+//    float64 partial per column, summed in split order by the finalize
+//    kernel.
+//  * N (n x p): a group of G lanes (G = 64 for wide rows, fewer for short
+//    rows) reduces one row with cross-lane shuffles.
+// Sums are float64 in a fixed order, so the result is bitwise reproducible.
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kUnroll = 8;
+
+template <typename T> __device__ __forceinline__ void vec_to_double(const uint4& v, double* out);
+template <> __device__ __forceinline__ void vec_to_double<double>(const uint4& v, double* out) {
+  out[0] = __hiloint2double(v.y, v.x);
+  out[1] = __hiloint2double(v.w, v.z);
+}
+template <> __device__ __forceinline__ void vec_to_double<float>(const uint4& v, double* out) {
+  out[0] = (double)__uint_as_float(v.x); out[1] = (double)__uint_as_float(v.y);
+  out[2] = (double)__uint_as_float(v.z); out[3] = (double)__uint_as_float(v.w);
+}
+template <> __device__ __forceinline__ void vec_to_double<uint16_t>(const uint4& v, double* out) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    out[2 * i] = (double)__uint_as_float(w[i] << 16);
+    out[2 * i + 1] = (double)__uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+
+struct NormArgs {
+  const void* M; int64_t ldm;
+  const void* N; int64_t ldn;
+  int64_t m, n, p;
+  int rsplit; int64_t rows_per_split;
+  int64_t mtiles;            // column tiles of M
+  int64_t nblocks_m;         // workgroups on the M part
+  int n_group;               // lanes per row of N
+  int64_t rows_per_wg_n;     // rows of N per workgroup
+  int vec_m, vec_n;          // 16-byte loads allowed (alignment of base and leading dim)
+  double* partial;
+  double* row_sq;
+};
+
+template <typename T>
+__device__ void colsq_part(const NormArgs& a, int64_t bid, double* sm) {
+  constexpr int E = 16 / sizeof(T);
+  constexpr int TC = 64 * E;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t tile = bid % a.mtiles;
+  const int64_t split = bid / a.mtiles;
+  const int64_t j0 = tile * TC + (int64_t)lane * E;
+  const int64_t r0 = split * a.rows_per_split;
+  const int64_t r1 = min(a.m, r0 + a.rows_per_split);
+  const T* M = reinterpret_cast<const T*>(a.M);
+
+  double acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.0;
+
+  const bool full = a.vec_m && (j0 + E <= a.n);
+  if (full) {
+    int64_t r = r0 + wave;
+    for (; r + 4 * (kUnroll - 1) < r1; r += 4 * kUnroll) {
+      uint4 v[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        v[u] = *reinterpret_cast<const uint4*>(M + (r + 4 * u) * a.ldm + j0);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        double x[E];
+        vec_to_double<T>(v[u], x);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = fma(x[e], x[e], acc[e]);
+      }
+    }
+    for (; r < r1; r += 4) {
+      uint4 v = *reinterpret_cast<const uint4*>(M + r * a.ldm + j0);
+      double x[E];
+      vec_to_double<T>(v, x);
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] = fma(x[e], x[e], acc[e]);
+    }
+  } else if (j0 < a.n) {
+    for (int64_t r = r0 + wave; r < r1; r += 4) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (j0 + e < a.n) {
+          double x = Elem<T>::to_double(M[r * a.ldm + j0 + e]);
+          acc[e] = fma(x, x, acc[e]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) sm[wave * TC + lane * E + e] = acc[e];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int c = lane * E + e;
+      double s = sm[c];
+      s += sm[TC + c];
+      s += sm[2 * TC + c];
+      s += sm[3 * TC + c];
+      if (j0 + e < a.n) a.partial[split * a.n + j0 + e] = s;
+    }
+  }
+}
+
+template <typename T>
+__device__ void rowsq_part(const NormArgs& a, int64_t bid) {
+  constexpr int E = 16 / sizeof(T);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int G = a.n_group;
+  const int per_wave = 64 / G;
+  const int grp = lane / G;
+  const int li = lane % G;
+  const T* N = reinterpret_cast<const T*>(a.N);
+  const int64_t row_begin = bid * a.rows_per_wg_n;
+  const int64_t row_end = min(a.n, row_begin + a.rows_per_wg_n);
+  const int64_t nvec = (a.p + E - 1) / E;
+  for (int64_t rb = row_begin + (int64_t)wave * per_wave; rb < row_end; rb += 4 * per_wave) {
+    const int64_t i = rb + grp;
+    double acc = 0.0;
+    if (i < row_end) {
+      const T* row = N + i * a.ldn;
+      int64_t v = li;
+      if (a.vec_n) {
+        for (; v + (int64_t)G * 3 < nvec; v += 4 * (int64_t)G) {
+          uint4 q[4];
+          bool ok[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t c = (v + (int64_t)u * G) * E;
+            ok[u] = c + E <= a.p;
+            if (ok[u]) q[u] = *reinterpret_cast<const uint4*>(row + c);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t c = (v + (int64_t)u * G) * E;
+            if (ok[u]) {
+              double x[E];
+              vec_to_double<T>(q[u], x);
+#pragma unroll
+              for (int e = 0; e < E; ++e) acc = fma(x[e], x[e], acc);
+            } else {
+              for (int e = 0; e < E; ++e)
+                if (c + e < a.p) {
+                  double x = Elem<T>::to_double(row[c + e]);
+                  acc = fma(x, x, acc);
+                }
+            }
+          }
+        }
+      }
+      for (; v < nvec; v += G) {
+        const int64_t c = v * E;
+        if (a.vec_n && c + E <= a.p) {
+          double x[E];
+          vec_to_double<T>(*reinterpret_cast<const uint4*>(row + c), x);
+#pragma unroll
+          for (int e = 0; e < E; ++e) acc = fma(x[e], x[e], acc);
+        } else {
+          for (int e = 0; e < E; ++e)
+            if (c + e < a.p) {
+              double x = Elem<T>::to_double(row[c + e]);
+              acc = fma(x, x, acc);
+            }
+        }
+      }
+    }
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (li == 0 && i < row_end) a.row_sq[i] = acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void norms_kernel(NormArgs a) {
+  __shared__ double sm[4 * 64 * (16 / sizeof(T))];
+  const int64_t bid = blockIdx.x;
+  if (bid < a.nblocks_m)
+    colsq_part<T>(a, bid, sm);
+  else
+    rowsq_part<T>(a, bid - a.nblocks_m);
+}
+
+// One workgroup per block: finish the column sums over the row splits and
+// form the three block statistics.
+__global__ __launch_bounds__(kThreads) void block_stats_kernel(
+    const double* __restrict__ partial, int rsplit, int64_t n,
+    const int64_t* __restrict__ off, int32_t K, double* __restrict__ col_sq,
+    const double* __restrict__ row_sq, double* __restrict__ blk,
+    int32_t* status) {
+  __shared__ double sm[3][kThreads];
+  const int k = blockIdx.x;
+  const int64_t lo = off[k], hi = off[k + 1];
+  double am = 0.0, an = 0.0, as = 0.0;
+  bool bad = false;
+  for (int64_t j = lo + threadIdx.x; j < hi; j += kThreads) {
+    double cs = 0.0;
+    for (int r = 0; r < rsplit; ++r) cs += partial[(int64_t)r * n + j];
+    col_sq[j] = cs;
+    const double rs = row_sq[j];
+    bad |= !isfinite(cs) || !isfinite(rs);
+    am += cs;
+    an += rs;
+    as += sqrt(cs * rs);
+  }
+  if (bad) *status = SBMM_DEV_NONFINITE;
+  sm[0][threadIdx.x] = am;
+  sm[1][threadIdx.x] = an;
+  sm[2][threadIdx.x] = as;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
+      sm[2][threadIdx.x] += sm[2][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    blk[k] = sm[0][0];
+    blk[K + k] = sm[1][0];
+    blk[2 * K + k] = sm[2][0];
+  }
+}
+
+int elems_per_vec(sbmm_dtype dt) { return 16 / (int)dtype_size(dt); }
+
+}  // namespace
+
+// Row splits of M: enough workgroups to fill the chip several times over,
+// but at least 32 rows per split.
+size_t norms_partial_elems(sbmm_dtype dt, int64_t m, int64_t n, int* rsplit_out) {
+  const int64_t tiles = ceil_div(n, 64 * elems_per_vec(dt));
+  int64_t want = ceil_div(4096, tiles > 0 ? tiles : 1);
+  int64_t maxr = m / 32 > 1 ? m / 32 : 1;
+  int64_t R = want < 1 ? 1 : (want > maxr ? maxr : want);
+  if (R > 64) R = 64;
+  *rsplit_out = (int)R;
+  return (size_t)R * (size_t)n;
+}
+
+hipError_t launch_norms(const NormLaunch& L, hipStream_t s) {
+  NormArgs a{};
+  a.M = L.M; a.ldm = L.ldm; a.N = L.N; a.ldn = L.ldn;
+  a.m = L.m; a.n = L.n; a.p = L.p;
+  a.partial = L.partial; a.row_sq = L.row_sq;
+  const int E = elems_per_vec(L.dt);
+  const size_t es = dtype_size(L.dt);
+  a.rsplit = L.rsplit;
+  a.rows_per_split = ceil_div(L.m > 0 ? L.m : 1, L.rsplit);
+  a.mtiles = ceil_div(L.n, 64 * E);
+  a.nblocks_m = L.m > 0 ? a.mtiles * L.rsplit : 0;
+  a.vec_m = ((uintptr_t)L.M % 16 == 0) && ((L.ldm * (int64_t)es) % 16 == 0);
+  a.vec_n = ((uintptr_t)L.N % 16 == 0) && ((L.ldn * (int64_t)es) % 16 == 0);
+  const int64_t nvec = ceil_div(L.p, E);
+  int G = 1;
+  while (G < 64 && G < nvec) G <<= 1;
+  a.n_group = G;
+  const int64_t rows_per_step = 4 * (64 / G);
+  const int64_t steps = L.p > 0 ? std::max<int64_t>(1, ceil_div(L.n, rows_per_step * 4096)) : 0;
+  a.rows_per_wg_n = rows_per_step * std::max<int64_t>(steps, 1);
+  const int64_t nblocks_n = L.p > 0 ? ceil_div(L.n, a.rows_per_wg_n) : 0;
+  if (L.m == 0) launch_fill_f64(L.partial, L.rsplit * L.n, 0.0, s);
+  if (L.p == 0) launch_fill_f64(L.row_sq, L.n, 0.0, s);
+  const int64_t total = a.nblocks_m + nblocks_n;
+  if (total > 0) {
+    dim3 grid((unsigned)total), block(kThreads);
+    switch (L.dt) {
+      case SBMM_F64: hipLaunchKernelGGL(norms_kernel<double>, grid, block, 0, s, a); break;
+      case SBMM_F32: hipLaunchKernelGGL(norms_kernel<float>, grid, block, 0, s, a); break;
+      case SBMM_BF16: hipLaunchKernelGGL(norms_kernel<uint16_t>, grid, block, 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  hipLaunchKernelGGL(block_stats_kernel, dim3(L.K), dim3(kThreads), 0, s,
+                     L.partial, L.m > 0 ? L.rsplit : 1, L.n, L.off_dev, L.K,
+                     L.col_sq, L.row_sq, L.blk, L.status);
+  return hipGetLastError();
+}

@@ -1,0 +1,78 @@
+"""Parity at the full paper-scale block workload (M 4096 x 65536, N 65536 x
+4096 float32, 1024 uneven blocks of 16..112, lognormal(0, 1.5) column / row
+factors), in the launch configuration the benchmark times.
+
+The oracle computes the norms, design and draws at full size, and CD and MN
+on a seeded sample of entries (one by one, from their definitions); the
+norms are compared in full. Indices must be identical; float32 outputs must
+be within 1e-5 (relative Frobenius over the sampled entries).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import method as om
+
+torch = pytest.importorskip("torch")
+import paper_2105_04940_amd as pk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def paper_inputs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    M, N, off = wl.paper_scale()
+    col, row = om.column_row_sq(M, N)
+    Md = torch.from_numpy(M).to(DEV)
+    Nd = torch.from_numpy(N).to(DEV)
+    return M, N, off, Md, Nd, col, row
+
+
+@pytest.fixture(scope="module")
+def h():
+    hd = pk.Handle(0)
+    yield hd
+    hd.close()
+
+
+def test_paper_scale_norms(h, paper_inputs):
+    M, N, off, Md, Nd, col, row = paper_inputs
+    gcol, grow, gblk = h.norms(pk.Problem(Md, Nd, off, 256))
+    torch.cuda.synchronize()
+    assert rel(gcol.cpu().numpy(), col) < 1e-13
+    assert rel(grow.cpu().numpy(), row) < 1e-13
+    st = om.block_stats(col, row, off)
+    b = gblk.cpu().numpy()
+    K = len(off) - 1
+    assert rel(b[:K], st.m_sq) < 1e-13 and rel(b[2 * K:], st.s) < 1e-13
+
+
+@pytest.mark.parametrize("c,prob", [(256, "norm"), (64, "uniform")])
+def test_paper_scale_run(h, paper_inputs, c, prob):
+    M, N, off, Md, Nd, col, row = paper_inputs
+    r = h.run(pk.Problem(Md, Nd, off, c, prob=prob, seed=0, trial=0))
+    design, *_ = om.plan(M, N, off, c, prob=prob, col_row=(col, row))
+    draws = om.sample(design, 0, 0)
+    assert np.array_equal(r["plan"].idx.cpu().numpy(), draws.atom)
+    assert r["L"] == draws.L
+    g = wl.rng(1234)
+    S = 1500
+    rows = g.integers(0, M.shape[0], size=S)
+    cols = g.integers(0, N.shape[1], size=S)
+    cd_o = om.sketch_entries(M, N, draws, rows, cols)
+    mn_o = om.exact_entries(M, N, rows, cols)
+    CD = r["CD"].cpu().numpy()
+    MN = r["MN"].cpu().numpy()
+    assert rel(CD[rows, cols], cd_o) < 1e-5
+    assert rel(MN[rows, cols], mn_o) < 1e-5
+    # the fused error equals the standalone error kernel on the same outputs
+    e2 = h.error(r["CD"], r["MN"]).cpu().numpy()
+    assert abs(r["err"] ** 2 - e2[0]) <= 1e-12 * e2[0]
+    assert abs(r["rel"] - np.sqrt(e2[0] / e2[1])) <= 1e-12 * r["rel"]

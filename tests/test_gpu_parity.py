@@ -1,0 +1,343 @@
+"""Parity of the HIP path with the float64 oracle, element by element, on
+seeded inputs that span several tiles and ragged tails.
+
+Bars: indices, counts and offsets bit-exact; float64 outputs within a
+relative Frobenius error of 1e-12, float32 outputs within 1e-5 (the
+tolerances the method's accuracy targets state); bf16 inputs are compared on
+their exactly promoted values.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import method as om
+
+torch = pytest.importorskip("torch")
+import paper_2105_04940_amd as pk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = pk.Handle(0)
+    yield hd
+    hd.close()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    d = np.linalg.norm(a - b)
+    return d / nb if nb > 0 else d
+
+
+def to_dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV).to(dtype)
+
+
+def host64(t):
+    return t.detach().to("cpu").to(torch.float64).numpy()
+
+
+def oracle_run(Mh, Nh, off, c, **kw):
+    return om.run(Mh, Nh, off, c, **kw)
+
+
+# --------------------------------------------------------------------------
+# norm pass
+# --------------------------------------------------------------------------
+
+NORM_SHAPES = [(1, 7, 1, [0, 3, 7]), (37, 129, 65, [0, 1, 50, 129]),
+               (300, 1000, 200, None), (5, 3000, 3, None), (70, 513, 1030, None)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("shape", NORM_SHAPES)
+def test_norms(h, dtype, shape):
+    m, n, p, off = shape
+    M, N, off2 = wl.random_problem(m, n, p, max(1, n // 40), seed=m + n + p, skew=1.0)
+    off = off or off2
+    Md, Nd = to_dev(M, dtype), to_dev(N, dtype)
+    prob = pk.Problem(Md, Nd, off, c=3)
+    col, row, blk = h.norms(prob)
+    torch.cuda.synchronize()
+    Mh, Nh = host64(Md), host64(Nd)
+    ocol, orow = om.column_row_sq(Mh, Nh)
+    st = om.block_stats(ocol, orow, off)
+    assert rel(host64(col), ocol) < 1e-13
+    assert rel(host64(row), orow) < 1e-13
+    K = len(off) - 1
+    b = host64(blk)
+    assert rel(b[:K], st.m_sq) < 1e-13
+    assert rel(b[K:2 * K], st.n_sq) < 1e-13
+    assert rel(b[2 * K:], st.s) < 1e-13
+
+
+def test_norms_strided_rows(h):
+    # leading dimensions larger than the row length, unaligned for 16-byte loads
+    M, N, off = wl.random_problem(33, 301, 45, 7, seed=5)
+    big_m = to_dev(np.pad(M, ((0, 0), (0, 3))), torch.float32)[:, :301]
+    big_n = to_dev(np.pad(N, ((0, 0), (0, 5))), torch.float32)[:, :45]
+    col, row, blk = h.norms(pk.Problem(big_m, big_n, off, c=2))
+    torch.cuda.synchronize()
+    ocol, orow = om.column_row_sq(M.astype(np.float32).astype(np.float64),
+                                  N.astype(np.float32).astype(np.float64))
+    assert rel(host64(col), ocol) < 1e-13 and rel(host64(row), orow) < 1e-13
+
+
+def test_norms_bitwise_reproducible(h):
+    M, N, off = wl.random_problem(200, 4000, 150, 40, seed=9)
+    prob = pk.Problem(to_dev(M, torch.float32), to_dev(N, torch.float32), off, c=4)
+    a = [t.clone() for t in h.norms(prob)]
+    b = h.norms(prob)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+# --------------------------------------------------------------------------
+# design + sampling with the same weight vector: bit-exact
+# --------------------------------------------------------------------------
+
+def _user_weights(n_atoms, seed, zeros=0.2):
+    g = wl.rng(seed)
+    w = g.lognormal(0, 2, size=n_atoms)
+    w[g.random(n_atoms) < zeros] = 0.0
+    if not np.any(w > 0):
+        w[0] = 1.0
+    return w
+
+
+@pytest.mark.parametrize("K,c,seed", [(64, 16, 0), (1024, 256, 1), (7, 300, 2), (1, 5, 3)])
+def test_plan_block_user_weights_bit_exact(h, K, c, seed):
+    n = K * 3
+    off = wl.equal_blocks(n, K)
+    M = np.zeros((2, n))
+    N = np.zeros((n, 2))
+    w = _user_weights(K, seed)
+    prob = pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), off, c,
+                      prob="user", user_w=to_dev(w, torch.float64), seed=seed * 77 + 1,
+                      trial=seed)
+    pl = h.plan(prob)
+    design = om.make_design("block", off, c, w)
+    draws = om.sample(design, seed * 77 + 1, seed)
+    assert np.array_equal(pl.idx.cpu().numpy(), draws.atom)
+    assert np.array_equal(pl.scale.cpu().numpy(), draws.scale)      # bitwise
+    assert np.array_equal(pl.col_off.cpu().numpy(), draws.col_off)
+    assert pl.L == draws.L
+    assert pl.ck.cpu().tolist() == design.cs
+    assert np.array_equal(pl.p_hat.cpu().numpy(), design.p_hat())
+    cm = pl.colmap.cpu().numpy()
+    cs = pl.colscale.cpu().numpy()
+    exp = np.concatenate([np.arange(lo, lo + wd) for lo, wd in zip(draws.lo, draws.width)])
+    assert np.array_equal(cm[:draws.L], exp)
+    Lp = -(-draws.L // 32) * 32
+    assert np.all(cm[draws.L:Lp] == -1) and np.all(cs[draws.L:Lp] == 0)
+
+
+@pytest.mark.parametrize("alloc", ["uniform", "user"])
+def test_plan_stratified_user_weights_bit_exact(h, alloc):
+    off = [0, 5, 17, 18, 60, 100]
+    n = 100
+    w = _user_weights(n, 11, zeros=0.3)
+    w[17] = 1.0   # block 2 (one atom) must be sampleable
+    c = 40
+    ck = None
+    if alloc == "user":
+        T = [np.any(w[off[k]:off[k + 1]] > 0) for k in range(5)]
+        ck = [8 if t else 0 for t in T]
+        ck[int(np.argmax(T))] += c - sum(ck)
+    M = np.zeros((1, n))
+    N = np.zeros((n, 1))
+    prob = pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), off, c,
+                      mode="stratified", prob="user", alloc=alloc,
+                      user_w=to_dev(w, torch.float64), user_ck=ck, seed=5, trial=9)
+    col, row, blk = h.norms(prob)
+    pl = h.plan(prob, col, row, blk)
+    g = np.ones(5) if alloc == "uniform" else None
+    design = om.make_design("stratified", off, c, w, g=g, user_ck=ck)
+    draws = om.sample(design, 5, 9)
+    assert pl.ck.cpu().tolist() == design.cs
+    assert np.array_equal(pl.idx.cpu().numpy(), draws.atom)
+    assert np.array_equal(pl.scale.cpu().numpy(), draws.scale)
+    assert np.array_equal(pl.col_off.cpu().numpy(), draws.col_off)
+
+
+# --------------------------------------------------------------------------
+# end to end
+# --------------------------------------------------------------------------
+
+def _check_run(h, M, N, off, c, dtype, **kw):
+    Md, Nd = to_dev(M, dtype), to_dev(N, dtype)
+    prob = pk.Problem(Md, Nd, off, c, **kw)
+    r = h.run(prob)
+    Mh, Nh = host64(Md), host64(Nd)
+    okw = {k: v for k, v in kw.items() if k in ("seed", "trial", "mode", "prob", "alloc")}
+    o = oracle_run(Mh, Nh, off, c, **okw)
+    tol = TOL[dtype]
+    idx = r["plan"].idx.cpu().numpy()
+    if not np.array_equal(idx, o.draws.atom):
+        # only a change of the integer weights (from last-bit differences of
+        # the float64 norms) could explain this; report which case it is
+        same_p = np.array_equal(r["plan"].p_hat.cpu().numpy(), o.design.p_hat())
+        pytest.fail(f"indices differ (sampled probabilities identical: {same_p})")
+    assert r["L"] == o.draws.L
+    L = o.draws.L
+    Lp = -(-L // 32) * 32
+    C, D = host64(r["C"]), host64(r["D"])
+    # the scales agree to the last bit when the weights do; the norms (summed
+    # in another order) may move a weight by an ulp
+    ctol = 1e-15 if dtype == torch.float64 else 1e-7
+    assert rel(C[:, :L], o.C) <= ctol
+    assert rel(D[:L], o.D) <= ctol
+    assert np.all(C[:, L:Lp] == 0) and np.all(D[L:Lp] == 0)
+    assert rel(host64(r["CD"]), o.CD) < tol
+    assert rel(host64(r["MN"]), o.MN) < tol
+    if o.err > 0:
+        assert abs(r["err"] - o.err) <= tol * max(o.err, 1e-300) + tol * np.linalg.norm(o.MN)
+        assert abs(r["rel"] - o.rel) <= tol * max(o.rel, 1.0)
+    return r, o
+
+
+def test_tiny_workload_f64(h):
+    M, N, off = wl.tiny(0)
+    r, o = _check_run(h, M, N, off, 16, torch.float64, seed=0)
+    assert r["L"] == 256
+    assert abs(r["rel"] - o.rel) < 1e-12 * o.rel
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(300, 2000, 260, 50, 37), (129, 777, 65, 13, 5),
+                                   (1, 64, 1, 4, 3), (513, 4100, 7, 80, 64)])
+def test_block_norm_ragged(h, dtype, shape):
+    m, n, p, K, c = shape
+    M, N, off = wl.random_problem(m, n, p, K, seed=m * 7 + p, skew=1.2)
+    _check_run(h, M, N, off, c, dtype, seed=3, trial=1)
+
+
+@pytest.mark.parametrize("prob", ["uniform", "exact"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_block_other_rules(h, prob, dtype):
+    M, N, off = wl.random_problem(200, 1500, 170, 30, seed=12, skew=1.0)
+    _check_run(h, M, N, off, 20, dtype, prob=prob, seed=4)
+
+
+@pytest.mark.parametrize("prob,alloc", [("uniform", "uniform"), ("norm", "norm"),
+                                        ("norm", "opt"), ("norm", "uniform")])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_stratified_rules(h, prob, alloc, dtype):
+    M, N, off = wl.random_problem(26, 3000, 28, 6, seed=21, skew=1.5)
+    r, o = _check_run(h, M, N, off, 600, dtype, mode="stratified", prob=prob, alloc=alloc,
+                      seed=8, trial=2)
+    assert r["plan"].ck.cpu().tolist() == o.design.cs
+
+
+def test_block_product_norms(h):
+    for dtype in (torch.float64, torch.float32):
+        M, N, off = wl.random_problem(150, 1300, 140, 17, seed=31, skew=0.8)
+        prob = pk.Problem(to_dev(M, dtype), to_dev(N, dtype), off, c=3)
+        MN, bp, mn_sq = h.exact(prob, store=True, blocknorm=True)
+        torch.cuda.synchronize()
+        Mh, Nh = host64(prob.M), host64(prob.N)
+        ref = om.block_product_sq(Mh, Nh, off)
+        assert rel(host64(bp), ref) < TOL[dtype]
+        MNo = om.exact_product(Mh, Nh)
+        assert rel(host64(MN), MNo) < TOL[dtype]
+        assert abs(mn_sq.item() - float(np.sum(MNo**2))) < TOL[dtype] * float(np.sum(MNo**2))
+
+
+def test_deterministic_single_block(h):
+    M, N, _ = wl.random_problem(90, 300, 70, 1, seed=2)
+    r, o = _check_run(h, M, N, [0, 300], 3, torch.float64, seed=1)
+    assert rel(host64(r["CD"]), host64(r["MN"])) < 1e-12
+    assert r["rel"] < 1e-12
+
+
+def test_unit_strata_deterministic(h):
+    M, N, _ = wl.random_problem(20, 64, 10, 1, seed=3)
+    off = list(range(65))
+    r, o = _check_run(h, M, N, off, 64, torch.float64, mode="stratified", prob="norm",
+                      alloc="uniform")
+    assert r["plan"].ck.cpu().tolist() == [1] * 64
+    assert r["rel"] < 1e-12
+
+
+def test_run_bitwise_reproducible(h):
+    M, N, off = wl.random_problem(260, 3000, 300, 40, seed=4, skew=1.0)
+    prob = pk.Problem(to_dev(M, torch.float32), to_dev(N, torch.float32), off, 32, seed=6)
+    a = h.run(prob)
+    b = h.run(prob)
+    assert torch.equal(a["CD"], b["CD"]) and torch.equal(a["MN"], b["MN"])
+    assert a["err"] == b["err"]
+    prob.trial = 1
+    c = h.run(prob)
+    assert not torch.equal(a["plan"].idx, c["plan"].idx)
+
+
+def test_all_zero_problem(h):
+    M = np.zeros((40, 100))
+    N = np.ones((100, 30))
+    prob = pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), [0, 50, 100], 5)
+    r = h.run(prob)
+    assert r["L"] == 0 and r["err"] == 0.0 and r["rel"] == 0.0
+    assert torch.count_nonzero(r["CD"]).item() == 0
+
+
+def test_empty_outer_dims(h):
+    for m, p in ((0, 5), (5, 0)):
+        M = torch.zeros((m, 40), dtype=torch.float32, device=DEV)
+        N = torch.ones((40, p), dtype=torch.float32, device=DEV)
+        r = h.run(pk.Problem(M, N, [0, 20, 40], 3, prob="uniform"))
+        assert r["err"] == 0.0
+
+
+def test_sketch_gemm_error_epilogue_matches_error_kernel(h):
+    M, N, off = wl.random_problem(300, 2500, 200, 30, seed=7, skew=1.0)
+    prob = pk.Problem(to_dev(M, torch.float32), to_dev(N, torch.float32), off, 24, seed=2)
+    col, row, blk = h.norms(prob)
+    pl = h.plan(prob, col, row, blk)
+    C, D = h.sketch(prob, pl)
+    MN, _, mn_sq = h.exact(prob)
+    CD, err = h.sketch_gemm(C, D, pl, MN=MN)
+    e2 = h.error(CD, MN)
+    torch.cuda.synchronize()
+    assert abs(err.item() - e2[0].item()) <= 1e-12 * e2[0].item()
+    assert abs(mn_sq.item() - e2[1].item()) <= 1e-12 * e2[1].item()
+
+
+# --------------------------------------------------------------------------
+# errors reported through the status word
+# --------------------------------------------------------------------------
+
+def test_nonfinite_input(h):
+    M, N, off = wl.random_problem(50, 200, 40, 5, seed=8)
+    M[3, 17] = np.nan
+    prob = pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), off, 4)
+    with pytest.raises(pk.SbmmError) as ei:
+        h.run(prob)
+    assert ei.value.status == pk.SBMM_E_NONFINITE
+    # the handle recovers
+    M[3, 17] = 0.0
+    h.run(pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), off, 4))
+
+
+def test_budget_below_sampleable_strata(h):
+    M, N, _ = wl.random_problem(10, 60, 8, 1, seed=9)
+    off = [0, 10, 20, 30, 40, 50, 60]
+    M[:, 50:60] = 0.0               # one stratum has zero weight
+    prob = pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), off, 5,
+                      mode="stratified", prob="norm", alloc="norm")
+    r = h.run(prob)                  # 5 draws for 5 sampleable strata: fine
+    assert r["plan"].ck.cpu().tolist() == [1, 1, 1, 1, 1, 0]
+    prob.c = 4
+    with pytest.raises(pk.SbmmError) as ei:
+        h.run(prob)
+    assert ei.value.status == pk.SBMM_E_BUDGET

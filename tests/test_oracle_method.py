@@ -239,6 +239,16 @@ def test_deterministic_stratified_unit_blocks():
     assert _rel(r.CD, r.MN) < 1e-12
 
 
+def test_entry_helpers_match_full_products():
+    M, N, off = wl.random_problem(17, 300, 13, 9, seed=24, skew=1.0)
+    r = om.run(M, N, off, c=7, seed=3)
+    g = wl.rng(25)
+    rows = g.integers(0, 17, size=50)
+    cols = g.integers(0, 13, size=50)
+    assert _rel(om.sketch_entries(M, N, r.draws, rows, cols), r.CD[rows, cols]) < 1e-13
+    assert _rel(om.exact_entries(M, N, rows, cols, chunk=64), (M @ N)[rows, cols]) < 1e-13
+
+
 def test_tiny_workload_runs():
     M, N, off = wl.tiny()
     r = om.run(M, N, off, c=16, seed=0, mode="block", prob="norm")

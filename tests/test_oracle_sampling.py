@@ -10,7 +10,9 @@ import numpy as np
 import pytest
 
 from oracle.sampling import (quantize_weights, inclusive_cdf, lemire_uniform,
-                             search_cdf, draw_atoms, allocate_draws, ceil_log2)
+                             search_cdf, draw_atoms, allocate_draws, ceil_log2,
+                             wide_words)
+from oracle.rng import philox4x64_10, TAG_SAMPLE
 
 
 # --------------------------------------------------------------------------
@@ -167,6 +169,34 @@ def test_draw_frequencies_chi_square():
     exp = np.array([W[a] / T * n for a in nz])
     stat, pval = chisquare(cnt[nz], exp)
     assert pval > 1e-4
+
+
+def test_draw_uses_high_part_of_128_bit_product():
+    # the first draw of (seed 5, trial 2, stratum 1, draw 0) takes the first
+    # two Philox words of block 0 as one 128-bit word, high word first
+    W = quantize_weights([1.0, 2.0, 3.0, 4.0, 0.5])
+    cdf = inclusive_cdf(W)
+    T = cdf[-1]
+    w = philox4x64_10((0, 1, 2, (TAG_SAMPLE << 32) | 0), (5, 0))
+    x = (w[0] << 64) | w[1]
+    assert (x * T) % 2**128 >= (2**128 - T) % T      # accepted (p > 1 - 2^-64)
+    r = (x * T) >> 128
+    assert draw_atoms(cdf, T, 1, seed=5, trial=2, stratum=1) == [search_cdf(cdf, r)]
+    assert list(wide_words([1, 2, 3, 4])) == [(1 << 64) | 2, (3 << 64) | 4]
+
+
+def test_draw_stable_under_unit_change_of_total():
+    # moving one weight by a unit (as last-bit noise in the norms does)
+    # leaves the draws unchanged
+    g = np.random.Generator(np.random.PCG64(4))
+    W = [int(x) for x in g.integers(2**55, 2**56, size=64)]
+    cdf = inclusive_cdf(W)
+    W2 = list(W)
+    W2[10] += 1
+    cdf2 = inclusive_cdf(W2)
+    a = draw_atoms(cdf, cdf[-1], 500, 1, 0, 0)
+    b = draw_atoms(cdf2, cdf2[-1], 500, 1, 0, 0)
+    assert a == b
 
 
 def test_draws_reproducible_and_independent_of_count():
