@@ -195,14 +195,37 @@ sbmm_status do_norms(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
 
 sbmm_dtype product_dtype(sbmm_dtype in) { return in == SBMM_F64 ? SBMM_F64 : SBMM_F32; }
 
+int64_t max_block_width(const sbmm_problem* P) {
+  int64_t w = 0;
+  for (int32_t k = 0; k < P->K; ++k) w = std::max(w, P->block_off[k + 1] - P->block_off[k]);
+  return w;
+}
+
 // Exact product with optional MN store, block norms and error vs Y.
+// Block norms of float32 problems with blocks up to 128 wide come from the
+// Gram-matrix kernel (cheap, separate launch); otherwise the product kernel
+// accumulates them block by block.
 sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_dev, void* MN, int64_t ldmn,
                      const void* Y, int64_t ldy, double* blkprod_sq, double* out2, Arena& ar, hipStream_t s) {
   if (P->in_dtype == SBMM_BF16) return fail(h, SBMM_E_UNSUPPORTED, "exact product of bf16 inputs is not built");
+  const bool gram = blkprod_sq != nullptr && P->in_dtype == SBMM_F32 && max_block_width(P) <= block_gram_max_width();
+  if (gram) {
+    if (ar.base) {
+      if (P->m > 0 && P->p > 0) {
+        HIP_TRY(h, launch_block_gram(reinterpret_cast<const float*>(P->M), P->ldm,
+                                     reinterpret_cast<const float*>(P->N), P->ldn, P->m, P->p, off_dev,
+                                     P->K, blkprod_sq, s));
+      } else {
+        HIP_TRY(h, launch_fill_f64(blkprod_sq, P->K, 0.0, s));
+      }
+    }
+    blkprod_sq = nullptr;   // the product kernel below needs no block bookkeeping
+  }
   const bool bn = blkprod_sq != nullptr;
   const int64_t tiles = gemm_tiles(P->in_dtype, P->m, P->p, bn);
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
   double* blk_part = bn ? ar.take<double>((size_t)P->K * std::max<int64_t>(tiles, 1) * 4) : nullptr;
+  float* stage = ar.take<float>(gemm_stage_bytes(P->in_dtype, P->m, P->p) / sizeof(float));
   if (!ar.base) return SBMM_OK;
   if (tiles == 0) {
     HIP_TRY(h, launch_fill_f64(out2, 2, 0.0, s));
@@ -213,7 +236,7 @@ sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
   G.dt = P->in_dtype; G.A = P->M; G.lda = P->ldm; G.B = P->N; G.ldb = P->ldn;
   G.m = P->m; G.p = P->p; G.K_host = P->n; G.K_dev = nullptr;
   G.Cout = MN; G.ldc = ldmn; G.Y = Y; G.ldy = ldy; G.tile_part = tile_part;
-  G.K_blocks = P->K; G.off_dev = off_dev; G.blk_part = blk_part;
+  G.K_blocks = P->K; G.off_dev = off_dev; G.blk_part = blk_part; G.stage = stage;
   HIP_TRY(h, launch_gemm(G, s));
   HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
   if (bn) HIP_TRY(h, launch_reduce_cols(blk_part, P->K, tiles * 4, blkprod_sq, s));
@@ -436,13 +459,16 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   if (MN && ldmn < p) return fail(h, SBMM_E_ARG, "ldmn < p");
   hipStream_t s = (hipStream_t)stream;
   const int64_t tiles = gemm_tiles(dtype, m, p, false);
+  const size_t stage_elems = gemm_stage_bytes(dtype, m, p) / sizeof(float);
   Arena dry(nullptr);
   dry.take<double>(2 * std::max<int64_t>(tiles, 1));
   dry.take<double>(2);
+  dry.take<float>(stage_elems);
   if ((st = ensure_ws(h, dry.off))) return st;
   Arena ar(h->ws);
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
   double* out2 = ar.take<double>(2);
+  float* stage = ar.take<float>(stage_elems);
   if (tiles == 0) {
     if (err_sq) HIP_TRY(h, launch_fill_f64(err_sq, 1, 0.0, s));
     return SBMM_OK;
@@ -451,6 +477,7 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   G.dt = dtype; G.A = C; G.lda = ldc; G.B = D; G.ldb = ldd; G.m = m; G.p = p;
   G.K_host = 0; G.K_dev = L_dev; G.Cout = CD; G.ldc = ldcd; G.Y = MN; G.ldy = ldmn;
   G.tile_part = err_sq ? tile_part : nullptr;
+  G.stage = stage;
   HIP_TRY(h, launch_gemm(G, s));
   if (err_sq) {
     HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
@@ -519,6 +546,7 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
     const int64_t ldmnw = MN ? ldmn : P->p;
     const int64_t tiles_s = gemm_tiles(compute, P->m, P->p, false);
     double* sk_part = ar.take<double>(2 * std::max<int64_t>(tiles_s, 1));
+    float* sk_stage = ar.take<float>(gemm_stage_bytes(compute, P->m, P->p) / sizeof(float));
     // measure the remaining scratch of the sub-steps on a dry arena
     if (!pass) {
       do_norms(h, P, off, col_sq, row_sq, blk, ar, s);
@@ -570,6 +598,7 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
       G.dt = compute; G.A = Cw; G.lda = ldcw; G.B = Dw; G.ldb = lddw; G.m = P->m; G.p = P->p;
       G.K_host = 0; G.K_dev = plan->col_off + P->c; G.Cout = CD; G.ldc = ldcd;
       G.Y = bp ? MNw : nullptr; G.ldy = ldmnw; G.tile_part = bp ? sk_part : nullptr;
+      G.stage = sk_stage;
       HIP_TRY(h, launch_gemm(G, s));
       if (bp) HIP_TRY(h, launch_reduce_cols(sk_part, 2, tiles_s, sk2, s));
     }

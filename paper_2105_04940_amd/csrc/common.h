@@ -130,9 +130,20 @@ struct GemmLaunch {
   double* tile_part;        // [tiles][2]: sum (C - Y)^2, sum C^2
   // block-product norms (optional)
   int32_t K_blocks; const int64_t* off_dev; double* blk_part;  // [K][tiles*4]
+  // float32 staging of the partial sums of inner extents above 4096 (one
+  // tile-sized slot per workgroup, private to it)
+  float* stage;
 };
+// bytes of the float32 staging buffer launch_gemm needs
+size_t gemm_stage_bytes(sbmm_dtype dt, int64_t m, int64_t p);
 int64_t gemm_tiles(sbmm_dtype dt, int64_t m, int64_t p, bool blocknorm);
 hipError_t launch_gemm(const GemmLaunch& a, hipStream_t s);
+
+// ||M^k N_k||_F^2 per block through the Gram matrices (float32 inputs,
+// blocks at most block_gram_max_width() wide), one workgroup per block.
+hipError_t launch_block_gram(const float* M, int64_t ldm, const float* N, int64_t ldn, int64_t m, int64_t p,
+                             const int64_t* off_dev, int32_t K, double* out, hipStream_t s);
+int64_t block_gram_max_width();
 
 // Fill kernels (used instead of memset so that captured graphs hold only
 // kernel nodes).

@@ -40,6 +40,7 @@ struct GemmArgs {
   int32_t nblk; const int64_t* off; double* blk_part;   // [nblk][tiles*4]
   int64_t tiles_m, tiles_n;
   int vec_a, vec_b;
+  float* stage; int64_t ldstage;   // float32 partial sums of long inner extents
 };
 
 __device__ __forceinline__ int64_t inner_extent(const GemmArgs& g) {
@@ -114,8 +115,25 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_kernel(GemmArgs g) {
     }
 
   f32x4 ra[NA], rb[NB];
+  // Tiles that lie wholly inside both operands (every tile of large aligned
+  // products) load with unpredicated 16-byte loads from per-thread pointers
+  // advanced by one step each time; edge tiles take the predicated path.
+  const bool interior = g.vec_a && g.vec_b && m0 + BM <= g.m && n0 + BN <= g.p;
+  const float* pa = A + (m0 + (tid >> 3)) * g.lda + 4 * (tid & 7);
+  const float* pb = B + (int64_t)(tid / (BN / 4)) * g.ldb + n0 + 4 * (tid % (BN / 4));
+  const int64_t a_q_stride = (int64_t)(kThreads >> 3) * g.lda;          // rows per q step of A
+  const int64_t b_q_stride = (int64_t)(kThreads / (BN / 4)) * g.ldb;    // rows per q step of B
   auto load_tile = [&](int64_t kt) {
     const int64_t k0 = kt * BK;
+    if (interior && k0 + BK <= K) {
+      const float* a0 = pa + k0;
+      const float* b0 = pb + k0 * g.ldb;
+#pragma unroll
+      for (int q = 0; q < NA; ++q) ra[q] = *reinterpret_cast<const f32x4*>(a0 + q * a_q_stride);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rb[q] = *reinterpret_cast<const f32x4*>(b0 + q * b_q_stride);
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int f = tid + kThreads * q;
@@ -296,6 +314,220 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_f32_kernel(GemmArgs g) {
       }
     }
   if (g.tile_part) write_tile_partials(g, e2, n2, sm_red);
+}
+
+// ============================================================================
+// float32, fast path: one accumulator set per wave; every FOLD_K = 4096
+// inner indices the accumulators are added into a float32 staging slot in
+// global memory private to the workgroup, which keeps the rounding error near
+// u (sqrt(FOLD_K) + sqrt(K / FOLD_K)) while leaving the registers to the
+// matrix-core accumulators. Same lane layout as above. Interior tiles run a
+// loop with unpredicated 16-byte loads (the inner-dimension tail, if any, is
+// one predicated step after it); edge tiles run a separate fully predicated
+// loop, so neither loop carries the other's registers.
+// ============================================================================
+template <int WMB, int WNB, int BK>
+struct SgemmTile {
+  static constexpr int BM = 64 * WMB, BN = 64 * WNB;
+  static constexpr int SA = BM + 4, SB = BN + 4;
+  static constexpr int KC = BK / 4;                   // float4 chunks per A row
+  static constexpr int NA = BM * BK / 4 / kThreads;   // float4 loads of A per thread
+  static constexpr int NB = BK * BN / 4 / kThreads;   // float4 loads of B per thread
+  static constexpr int FOLD_TILES = 4096 / BK;
+  static constexpr int NACC = WMB * WNB * 16;
+  float As[2][BK][SA];
+  float Bs[2][BK][SB];
+  double red[8];
+};
+
+template <int WMB, int WNB, int BK, bool EDGE>
+__device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB, BK>& sh,
+                                           int64_t m0, int64_t n0, int64_t K) {
+  using T = SgemmTile<WMB, WNB, BK>;
+  constexpr int BN = T::BN, KC = T::KC, NA = T::NA, NB = T::NB, NACC = T::NACC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int wave_m0 = (wave & 1) * 32 * WMB;
+  const int wave_n0 = (wave >> 1) * 32 * WNB;
+  const float* __restrict__ A = reinterpret_cast<const float*>(g.A);
+  const float* __restrict__ B = reinterpret_cast<const float*>(g.B);
+
+  f32x16 acc[WMB][WNB];
+#pragma unroll
+  for (int b = 0; b < WMB; ++b)
+#pragma unroll
+    for (int c = 0; c < WNB; ++c) acc[b][c] = f32x16{};
+
+  f32x4 ra[NA], rb[NB];
+  // unpredicated loads of a whole step (interior tiles)
+  const float* pa = A + (m0 + tid / KC) * g.lda + 4 * (tid % KC);
+  const float* pb = B + (int64_t)(tid / (BN / 4)) * g.ldb + n0 + 4 * (tid % (BN / 4));
+  const int64_t a_q_stride = (int64_t)(kThreads / KC) * g.lda;
+  const int64_t b_q_stride = (int64_t)(kThreads / (BN / 4)) * g.ldb;
+  auto load_fast = [&](int64_t kt) {
+    const float* a0 = pa + kt * BK;
+    const float* b0 = pb + kt * BK * g.ldb;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) ra[q] = *reinterpret_cast<const f32x4*>(a0 + q * a_q_stride);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) rb[q] = *reinterpret_cast<const f32x4*>(b0 + q * b_q_stride);
+  };
+  // predicated element loads (edge tiles and the inner-dimension tail)
+  auto load_pred = [&](int64_t kt) {
+    const int64_t k0 = kt * BK;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int f = tid + kThreads * q;
+      const int r = f / KC, c4 = f % KC;
+      const int64_t row = m0 + r, col = k0 + 4 * c4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        ra[q][e] = (row < g.m && col + e < K) ? A[row * g.lda + col + e] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int f = tid + kThreads * q;
+      const int kr = f / (BN / 4), c4 = f % (BN / 4);
+      const int64_t krow = k0 + kr, col = n0 + 4 * c4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        rb[q][e] = (krow < K && col + e < g.p) ? B[krow * g.ldb + col + e] : 0.0f;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int f = tid + kThreads * q;
+      const int r = f / KC, c4 = f % KC;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sh.As[buf][4 * c4 + e][r] = ra[q][e];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int f = tid + kThreads * q;
+      const int kr = f / (BN / 4), c4 = f % (BN / 4);
+      *reinterpret_cast<f32x4*>(&sh.Bs[buf][kr][4 * c4]) = rb[q];
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < BK / 2; ++s) {
+      const int k = 2 * s + lh;
+      float av[WMB], bv[WNB];
+      if constexpr (WMB == 4) {
+        const f32x4 t = *reinterpret_cast<const f32x4*>(&sh.As[buf][k][wave_m0 + 4 * lr]);
+        av[0] = t[0]; av[1] = t[1]; av[2] = t[2]; av[3] = t[3];
+      } else {
+        const f32x2 t = *reinterpret_cast<const f32x2*>(&sh.As[buf][k][wave_m0 + 2 * lr]);
+        av[0] = t[0]; av[1] = t[1];
+      }
+      if constexpr (WNB == 2) {
+        const f32x2 t = *reinterpret_cast<const f32x2*>(&sh.Bs[buf][k][wave_n0 + 2 * lr]);
+        bv[0] = t[0]; bv[1] = t[1];
+      } else {
+        const f32x4 t = *reinterpret_cast<const f32x4*>(&sh.Bs[buf][k][wave_n0 + 4 * lr]);
+        bv[0] = t[0]; bv[1] = t[1]; bv[2] = t[2]; bv[3] = t[3];
+      }
+#pragma unroll
+      for (int b = 0; b < WMB; ++b)
+#pragma unroll
+        for (int c = 0; c < WNB; ++c)
+          acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[b], bv[c], acc[b][c], 0, 0, 0);
+    }
+  };
+  // staging slot in lane-major order: [workgroup][wave][accumulator][lane]
+  float* const stg = g.stage + ((int64_t)blockIdx.x * 4 + wave) * (NACC * 64) + lane;
+  int folds = 0;
+  auto fold = [&]() {
+#pragma unroll
+    for (int b = 0; b < WMB; ++b)
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          float* q = stg + ((b * WNB + c) * 16 + v) * 64;
+          *q = folds ? *q + acc[b][c][v] : acc[b][c][v];
+        }
+        acc[b][c] = f32x16{};
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    ++folds;
+  };
+
+  // main loop: whole steps (interior) or every step (edge tiles)
+  const int64_t nkt = EDGE ? (K + BK - 1) / BK : K / BK;
+  if (nkt > 0) {
+    if constexpr (EDGE) load_pred(0); else load_fast(0);
+    store_tile(0);
+  }
+  __syncthreads();
+  // the inner loop holds only loads, LDS traffic and matrix-core steps; the
+  // fold sits between chunks of FOLD_TILES steps
+  int64_t kt = 0;
+  while (true) {
+    const int64_t kend = min(nkt, kt + (int64_t)T::FOLD_TILES);
+    for (; kt < kend; ++kt) {
+      const int cur = (int)(kt & 1);
+      if (kt + 1 < nkt) {
+        if constexpr (EDGE) load_pred(kt + 1); else load_fast(kt + 1);
+      }
+      compute(cur);
+      if (kt + 1 < nkt) store_tile(cur ^ 1);
+      __syncthreads();
+    }
+    if (kt >= nkt || kt * BK >= K) break;
+    fold();
+  }
+  if constexpr (!EDGE) {
+    if (nkt * BK < K) {   // inner-dimension tail of an interior tile
+      load_pred(nkt);
+      store_tile(0);
+      __syncthreads();
+      compute(0);
+    }
+  }
+
+  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < WMB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wave_m0 + WMB * (8 * (v >> 2) + 4 * lh + (v & 3)) + b;
+      if (EDGE && row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) {
+        const int64_t col = n0 + wave_n0 + WNB * lr + c;
+        if (EDGE && col >= g.p) continue;
+        float val = acc[b][c][v];
+        if (folds) val += stg[((b * WNB + c) * 16 + v) * 64];
+        if (Cout) Cout[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (Y) {
+          const double d = dv - (double)Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
+    }
+  if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
+}
+
+template <int WMB, int WNB, int BK, int WG_PER_CU>
+__global__ __launch_bounds__(kThreads, WG_PER_CU) void sgemm_kernel(GemmArgs g) {
+  using T = SgemmTile<WMB, WNB, BK>;
+  __shared__ T sh;
+  int64_t tm, tn;
+  tile_coords(g, tm, tn);
+  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
+  const int64_t K = inner_extent(g);
+  const bool interior = g.vec_a && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p;
+  if (interior)
+    sgemm_body<WMB, WNB, BK, false>(g, sh, m0, n0, K);
+  else
+    sgemm_body<WMB, WNB, BK, true>(g, sh, m0, n0, K);
 }
 
 // ============================================================================
@@ -542,7 +774,7 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
 }
 
 // Tile shapes
-constexpr int F32_WMB = 4, F32_WNB = 2;      // 256 x 128
+constexpr int F32_WMB = 2, F32_WNB = 2, F32_BK = 16, F32_WGS = 2;   // 128 x 128, 2 per CU
 constexpr int F32B_WMB = 2, F32B_WNB = 2;    // 128 x 128 with block norms
 constexpr int F64_WMB = 2, F64_WNB = 2;      // 64 x 64
 
@@ -572,23 +804,35 @@ hipError_t launch_gemm(const GemmLaunch& L, hipStream_t s) {
   g.nblk = L.K_blocks; g.off = L.off_dev; g.blk_part = L.blk_part;
   g.tiles_m = ceil_div(L.m, bm);
   g.tiles_n = ceil_div(L.p, bn);
+  g.stage = L.stage;
+  g.ldstage = 0;
   const size_t es = dtype_size(L.dt);
   const size_t vb = 16;
   g.vec_a = ((uintptr_t)L.A % vb == 0) && ((L.lda * (int64_t)es) % (int64_t)vb == 0);
   g.vec_b = ((uintptr_t)L.B % vb == 0) && ((L.ldb * (int64_t)es) % (int64_t)vb == 0);
   const int64_t tiles = g.tiles_m * g.tiles_n;
   if (tiles == 0) return hipSuccess;
+  // the float32 product folds partial sums into its staging slots once the
+  // inner extent passes 4096; it must always have them
+  if (L.dt == SBMM_F32 && !blocknorm && L.stage == nullptr) return hipErrorInvalidValue;
   dim3 grid((unsigned)tiles), block(kThreads);
   if (L.dt == SBMM_F64) {
     if (blocknorm) hipLaunchKernelGGL((gemm_f64_kernel<F64_WMB, F64_WNB, true>), grid, block, 0, s, g);
     else hipLaunchKernelGGL((gemm_f64_kernel<F64_WMB, F64_WNB, false>), grid, block, 0, s, g);
   } else if (L.dt == SBMM_F32) {
     if (blocknorm) hipLaunchKernelGGL((gemm_f32_kernel<F32B_WMB, F32B_WNB, true>), grid, block, 0, s, g);
-    else hipLaunchKernelGGL((gemm_f32_kernel<F32_WMB, F32_WNB, false>), grid, block, 0, s, g);
+    else hipLaunchKernelGGL((sgemm_kernel<F32_WMB, F32_WNB, F32_BK, F32_WGS>), grid, block, 0, s, g);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+size_t gemm_stage_bytes(sbmm_dtype dt, int64_t m, int64_t p) {
+  if (dt != SBMM_F32) return 0;
+  int64_t bm, bn;
+  tile_shape(dt, false, &bm, &bn);
+  return sizeof(float) * (size_t)(ceil_div(m, bm) * ceil_div(p, bn) * bm * bn);
 }
 
 hipError_t launch_reduce_cols(const double* part, int64_t rows, int64_t cols, double* out, hipStream_t s) {

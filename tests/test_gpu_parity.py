@@ -254,6 +254,18 @@ def test_block_product_norms(h):
         assert abs(mn_sq.item() - float(np.sum(MNo**2))) < TOL[dtype] * float(np.sum(MNo**2))
 
 
+def test_block_product_norms_wide_blocks(h):
+    # blocks wider than the Gram tile take the block-by-block product path
+    M, N, _ = wl.random_problem(140, 700, 90, 1, seed=33, skew=0.5)
+    off = [0, 200, 201, 500, 700]
+    for dtype in (torch.float64, torch.float32):
+        prob = pk.Problem(to_dev(M, dtype), to_dev(N, dtype), off, c=3)
+        _, bp, _ = h.exact(prob, store=False, blocknorm=True)
+        torch.cuda.synchronize()
+        ref = om.block_product_sq(host64(prob.M), host64(prob.N), off)
+        assert rel(host64(bp), ref) < TOL[dtype]
+
+
 def test_deterministic_single_block(h):
     M, N, _ = wl.random_problem(90, 300, 70, 1, seed=2)
     r, o = _check_run(h, M, N, [0, 300], 3, torch.float64, seed=1)
