@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for "
+                         "the HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -128,6 +131,13 @@ def main():
     Md = torch.from_numpy(M).to(dev)
     Nd = torch.from_numpy(N).to(dev)
     h = pk.Handle(0)
+    if args.calibration_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     torch.cuda.synchronize()
 
     timers = {}   # name -> list of (start, end) events

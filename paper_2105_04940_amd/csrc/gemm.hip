@@ -51,12 +51,23 @@ __device__ __forceinline__ int64_t inner_extent(const GemmArgs& g) {
   return g.K_host;
 }
 
-// Map a workgroup to its output tile. Consecutive workgroups walk down a
-// column of tiles so that they share the B panel.
+// Map a workgroup to its output tile. Workgroups are dealt round-robin to
+// the 8 XCDs (each with its own L2), so the launch index is first permuted
+// XCD-major (XCD x gets a contiguous range of logical tiles), and logical
+// tiles are ordered in groups of 8 tile rows walked column by column: the
+// workgroups resident on one XCD at a time then share a few A and B panels.
+constexpr int64_t kXcds = 8, kGroupM = 8;
 __device__ __forceinline__ void tile_coords(const GemmArgs& g, int64_t& tm, int64_t& tn) {
   const int64_t bid = blockIdx.x;
-  tm = bid % g.tiles_m;
-  tn = bid / g.tiles_m;
+  const int64_t tiles = g.tiles_m * g.tiles_n;
+  const int64_t per = tiles / kXcds;
+  const int64_t lg = bid < per * kXcds ? (bid % kXcds) * per + bid / kXcds : bid;
+  const int64_t span = kGroupM * g.tiles_n;
+  const int64_t first = (lg / span) * kGroupM;
+  const int64_t gm = min(g.tiles_m - first, kGroupM);
+  const int64_t r = lg % span;
+  tm = first + r % gm;
+  tn = r / gm;
 }
 
 // Reduce the epilogue partial sums of the workgroup in a fixed order.
