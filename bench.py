@@ -151,6 +151,19 @@ def main():
         timers.setdefault(name, []).append((s, e))
         return out
 
+    def sketch_leg(record, col, row, blk, MN, bp, compute, tag):
+        res = {}
+        for rule in RULES:
+            for c in CS:
+                prob = pk.Problem(Md, Nd, off, c, prob=rule, seed=0, trial=0,
+                                  blkprod_sq=bp if rule == "exact" else None)
+                pl = h.plan(prob, col, row, blk, sync=False)
+                C, D = h.sketch(prob, pl, out_dtype=compute)
+                CD, err = (timed(f"{tag}_c{c}", lambda: h.sketch_gemm(C, D, pl, MN=MN))
+                           if record else h.sketch_gemm(C, D, pl, MN=MN))
+                res[(rule, c)] = (err, pl, CD)
+        return res
+
     def step(record):
         res = {}
         base = pk.Problem(Md, Nd, off, CS[-1])
@@ -184,6 +197,17 @@ def main():
 
     def avg_ms(name):
         return float(np.mean([s.elapsed_time(e) for s, e in timers[name]]))
+
+    # bf16 sketches of the same draws (beside the float32 step, not in it)
+    base = pk.Problem(Md, Nd, off, CS[-1])
+    col, row, blk = h.norms(base)
+    MN, bp, _ = h.exact(base, store=True, blocknorm=True)
+    f32 = sketch_leg(False, col, row, blk, MN, bp, torch.float32, "f32")
+    for _ in range(args.warmup):
+        sketch_leg(False, col, row, blk, MN, bp, torch.bfloat16, "bf16")
+    for _ in range(args.steps):
+        b16 = sketch_leg(True, col, row, blk, MN, bp, torch.bfloat16, "bf16")
+    torch.cuda.synchronize()
 
     mn2v = mn2.item()
     rel_err = {}
@@ -234,6 +258,21 @@ def main():
                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": kernels["norm_pass"]["GB/s"] / HBM_PEAK_GBS, "bytes_per_launch": norm_bytes}
 
+    t_b16 = {c: avg_ms(f"bf16_c{c}") for c in CS}
+    b16_flops = sum(sketch_flops[c] for c in CS) * len(RULES)
+    b16_ms = sum(t_b16[c] for c in CS) * len(RULES)
+    bf16 = {
+        "sketch_gemm_TFLOPs": b16_flops / b16_ms / 1e9,
+        "peak": 2500.0, "unit": "TFLOP/s",
+        "frac": b16_flops / b16_ms / 1e9 / 2500.0,
+        "speedup_vs_f32": sk_total_ms / b16_ms,
+        "per_c": {f"c{c}": {"ms": t_b16[c], "TFLOP/s": sketch_flops[c] / t_b16[c] / 1e9} for c in CS},
+        "rel_err": {f"{r}/c{c}": math.sqrt(b16[(r, c)][0].item() / mn2v) for r in RULES for c in CS},
+        "cd_rel_diff_vs_f32": {f"{r}/c{c}": float(((b16[(r, c)][2] - f32[(r, c)][2]).norm()
+                                                   / f32[(r, c)][2].norm()).item())
+                               for r in RULES for c in CS},
+    }
+
     out = {
         "metric": METRIC,
         "value": step_flops / (ms_per_step * 1e-3) / 1e12,
@@ -262,6 +301,7 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "roofline_norm_pass": norm_roof,
+        "bf16": bf16,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(M, N, off, args.cpu_seconds)

@@ -187,8 +187,9 @@ sbmm_status sbmm_sketch(sbmm_handle h, const sbmm_problem* prob,
 
 /* Sketched product CD = C D (Alg. 2 step 4, eq. 3.3) on matrix cores over
  * the inner extent round_up(*L_dev, 32) (read on the device, at most
- * L_pad_max). dtype is the dtype of C and D: F64 (CD in F64) or F32 / BF16
- * (CD in F32, float32 accumulation). If MN and err_sq are given, the
+ * L_pad_max). dtype is the dtype of C and D: F64 (CD in F64), F32 or BF16
+ * (CD in F32, float32 accumulation; bf16 operands use the bf16 matrix
+ * instructions). If MN and err_sq are given, the
  * epilogue also writes err_sq[0] = ||MN - CD||_F^2 (float64, fixed order).
  * CD may be NULL when only the error is wanted. */
 sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p,

@@ -207,7 +207,8 @@ int64_t max_block_width(const sbmm_problem* P) {
 // accumulates them block by block.
 sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_dev, void* MN, int64_t ldmn,
                      const void* Y, int64_t ldy, double* blkprod_sq, double* out2, Arena& ar, hipStream_t s) {
-  if (P->in_dtype == SBMM_BF16) return fail(h, SBMM_E_UNSUPPORTED, "exact product of bf16 inputs is not built");
+  if (P->in_dtype == SBMM_BF16 && blkprod_sq)
+    return fail(h, SBMM_E_UNSUPPORTED, "block product norms of bf16 inputs are not built");
   const bool gram = blkprod_sq != nullptr && P->in_dtype == SBMM_F32 && max_block_width(P) <= block_gram_max_width();
   if (gram) {
     if (ar.base) {
@@ -450,7 +451,7 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   sbmm_status st = check_handle(h);
   if (st) return st;
   if (m < 0 || p < 0 || L_pad_max < 0 || !L_dev) return fail(h, SBMM_E_ARG, "bad sizes or L_dev");
-  if (dtype != SBMM_F64 && dtype != SBMM_F32)
+  if (dtype != SBMM_F64 && dtype != SBMM_F32 && dtype != SBMM_BF16)
     return fail(h, SBMM_E_UNSUPPORTED, "sketched product in dtype %d is not built", (int)dtype);
   if (m > 0 && p > 0 && L_pad_max > 0 && (!C || !D)) return fail(h, SBMM_E_ARG, "C and D are required");
   if (ldc < L_pad_max || ldd < p) return fail(h, SBMM_E_ARG, "ldc < L_pad_max or ldd < p");
@@ -516,9 +517,8 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
   if ((st = validate(h, P, &sz, true))) return st;
   if (!plan_out_ok(plan)) return fail(h, SBMM_E_ARG, "plan output buffers missing");
   if (!sketch_dtype_ok(P->in_dtype, compute)) return fail(h, SBMM_E_ARG, "compute dtype not allowed for the input dtype");
-  if (compute != SBMM_F64 && compute != SBMM_F32)
+  if (compute != SBMM_F64 && compute != SBMM_F32 && compute != SBMM_BF16)
     return fail(h, SBMM_E_UNSUPPORTED, "sketched product in dtype %d is not built", (int)compute);
-  if (P->in_dtype == SBMM_BF16) return fail(h, SBMM_E_UNSUPPORTED, "bf16 inputs are not built in sbmm_run");
   if ((P->m > 0 && P->p > 0 && !CD) || ldcd < P->p) return fail(h, SBMM_E_ARG, "CD is required with ldcd >= p");
   if (C && ldc < sz.L_pad_max) return fail(h, SBMM_E_ARG, "ldc < L_pad_max");
   if (D && ldd < P->p) return fail(h, SBMM_E_ARG, "ldd < p");

@@ -542,6 +542,213 @@ __global__ __launch_bounds__(kThreads, WG_PER_CU) void sgemm_kernel(GemmArgs g) 
 }
 
 // ============================================================================
+// bf16 operands, float32 accumulation: v_mfma_f32_32x32x16_bf16. Lane
+// (r = lane % 32, h = lane / 32) holds 8 consecutive inner indices 8h..8h+7
+// of A row r and B column r, so both operands sit in LDS with the inner index
+// contiguous: the C tile as loaded ([row][k]) and the D tile transposed
+// ([col][k], two inner indices per 32-bit LDS write). Rows and columns are
+// interleaved across a wave's 32-blocks as in the float32 kernel, and the
+// output layout is the same. bf16 products are exact in float32 and the
+// operand rounding (2^-9) dominates the error, so there is no fold.
+// ============================================================================
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int WMB, int WNB, int BK>
+struct HgemmTile {
+  static constexpr int BM = 64 * WMB, BN = 64 * WNB;
+  static constexpr int SA = BK + 8, SB = BK + 8;        // bf16 elements per LDS row
+  static constexpr int KC = BK / 8;                     // 16-byte chunks per A row
+  static constexpr int NA = BM * KC / kThreads;         // 16-byte loads of A per thread
+  static constexpr int NBP = (BK / 2) * (BN / 8) / kThreads;  // row-pair chunks of B per thread
+  uint16_t As[2][BM][SA];
+  uint16_t Bs[2][BN][SB];
+  double red[8];
+};
+
+template <int WMB, int WNB, int BK, bool EDGE>
+__device__ __forceinline__ void hgemm_body(const GemmArgs& g, HgemmTile<WMB, WNB, BK>& sh,
+                                           int64_t m0, int64_t n0, int64_t K) {
+  using T = HgemmTile<WMB, WNB, BK>;
+  constexpr int BN = T::BN, KC = T::KC, NA = T::NA, NBP = T::NBP;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int wave_m0 = (wave & 1) * 32 * WMB;
+  const int wave_n0 = (wave >> 1) * 32 * WNB;
+  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(g.A);
+  const uint16_t* __restrict__ B = reinterpret_cast<const uint16_t*>(g.B);
+
+  f32x16 acc[WMB][WNB];
+#pragma unroll
+  for (int b = 0; b < WMB; ++b)
+#pragma unroll
+    for (int c = 0; c < WNB; ++c) acc[b][c] = f32x16{};
+
+  uint4 ra[NA], rb0[NBP], rb1[NBP];
+  auto load = [&](int64_t kt) {
+    const int64_t k0 = kt * BK;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int f = tid + kThreads * q;
+      const int i = f / KC, c8 = f % KC;
+      const int64_t row = m0 + i, col = k0 + 8 * c8;
+      if (!EDGE || (row < g.m && col + 8 <= K && g.vec_a)) {
+        ra[q] = *reinterpret_cast<const uint4*>(A + row * g.lda + col);
+      } else {
+        uint16_t t[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = (row < g.m && col + e < K) ? A[row * g.lda + col + e] : 0;
+        ra[q] = make_uint4(t[0] | (uint32_t)t[1] << 16, t[2] | (uint32_t)t[3] << 16,
+                           t[4] | (uint32_t)t[5] << 16, t[6] | (uint32_t)t[7] << 16);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NBP; ++q) {
+      const int f = tid + kThreads * q;
+      const int pr = f / (BN / 8), c8 = f % (BN / 8);
+      const int64_t kr = k0 + 2 * pr, col = n0 + 8 * c8;
+      if (!EDGE || (kr + 1 < K && col + 8 <= g.p && g.vec_b)) {
+        rb0[q] = *reinterpret_cast<const uint4*>(B + kr * g.ldb + col);
+        rb1[q] = *reinterpret_cast<const uint4*>(B + (kr + 1) * g.ldb + col);
+      } else {
+        uint16_t t0[8], t1[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          t0[e] = (kr < K && col + e < g.p) ? B[kr * g.ldb + col + e] : 0;
+          t1[e] = (kr + 1 < K && col + e < g.p) ? B[(kr + 1) * g.ldb + col + e] : 0;
+        }
+        rb0[q] = make_uint4(t0[0] | (uint32_t)t0[1] << 16, t0[2] | (uint32_t)t0[3] << 16,
+                            t0[4] | (uint32_t)t0[5] << 16, t0[6] | (uint32_t)t0[7] << 16);
+        rb1[q] = make_uint4(t1[0] | (uint32_t)t1[1] << 16, t1[2] | (uint32_t)t1[3] << 16,
+                            t1[4] | (uint32_t)t1[5] << 16, t1[6] | (uint32_t)t1[7] << 16);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int f = tid + kThreads * q;
+      const int i = f / KC, c8 = f % KC;
+      *reinterpret_cast<uint4*>(&sh.As[buf][i][8 * c8]) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NBP; ++q) {
+      const int f = tid + kThreads * q;
+      const int pr = f / (BN / 8), c8 = f % (BN / 8);
+      const uint32_t w0[4] = {rb0[q].x, rb0[q].y, rb0[q].z, rb0[q].w};
+      const uint32_t w1[4] = {rb1[q].x, rb1[q].y, rb1[q].z, rb1[q].w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t lo = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+        const uint32_t hi = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+        *reinterpret_cast<uint32_t*>(&sh.Bs[buf][8 * c8 + e][2 * pr]) = lo | (hi << 16);
+      }
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < BK / 16; ++s) {
+      bf16x8 av[WMB], bv[WNB];
+#pragma unroll
+      for (int b = 0; b < WMB; ++b)
+        av[b] = *reinterpret_cast<const bf16x8*>(&sh.As[buf][wave_m0 + WMB * lr + b][16 * s + 8 * lh]);
+#pragma unroll
+      for (int c = 0; c < WNB; ++c)
+        bv[c] = *reinterpret_cast<const bf16x8*>(&sh.Bs[buf][wave_n0 + WNB * lr + c][16 * s + 8 * lh]);
+#pragma unroll
+      for (int b = 0; b < WMB; ++b)
+#pragma unroll
+        for (int c = 0; c < WNB; ++c)
+          acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[b], bv[c], acc[b][c], 0, 0, 0);
+    }
+  };
+
+  const int64_t nkt = EDGE ? (K + BK - 1) / BK : K / BK;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nkt) load(kt + 1);
+    compute(cur);
+    if (kt + 1 < nkt) store(cur ^ 1);
+    __syncthreads();
+  }
+  if constexpr (!EDGE) {
+    if (nkt * BK < K) {   // inner-dimension tail: one predicated step
+      {
+        const int64_t k0 = nkt * BK;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+          const int f = tid + kThreads * q;
+          const int i = f / KC, c8 = f % KC;
+          const int64_t row = m0 + i, col = k0 + 8 * c8;
+          uint16_t t[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) t[e] = (col + e < K) ? A[row * g.lda + col + e] : 0;
+          ra[q] = make_uint4(t[0] | (uint32_t)t[1] << 16, t[2] | (uint32_t)t[3] << 16,
+                             t[4] | (uint32_t)t[5] << 16, t[6] | (uint32_t)t[7] << 16);
+        }
+#pragma unroll
+        for (int q = 0; q < NBP; ++q) {
+          const int f = tid + kThreads * q;
+          const int pr = f / (BN / 8), c8 = f % (BN / 8);
+          const int64_t kr = k0 + 2 * pr, col = n0 + 8 * c8;
+          const uint4 z = make_uint4(0, 0, 0, 0);
+          rb0[q] = kr < K ? *reinterpret_cast<const uint4*>(B + kr * g.ldb + col) : z;
+          rb1[q] = kr + 1 < K ? *reinterpret_cast<const uint4*>(B + (kr + 1) * g.ldb + col) : z;
+        }
+      }
+      store(0);
+      __syncthreads();
+      compute(0);
+    }
+  }
+
+  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < WMB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wave_m0 + WMB * (8 * (v >> 2) + 4 * lh + (v & 3)) + b;
+      if (EDGE && row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) {
+        const int64_t col = n0 + wave_n0 + WNB * lr + c;
+        if (EDGE && col >= g.p) continue;
+        const float val = acc[b][c][v];
+        if (Cout) Cout[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (Y) {
+          const double d = dv - (double)Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
+}
+
+template <int WMB, int WNB, int BK, int WG_PER_CU>
+__global__ __launch_bounds__(kThreads, WG_PER_CU) void hgemm_kernel(GemmArgs g) {
+  using T = HgemmTile<WMB, WNB, BK>;
+  __shared__ T sh;
+  int64_t tm, tn;
+  tile_coords(g, tm, tn);
+  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
+  const int64_t K = inner_extent(g);
+  const bool interior = g.vec_a && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p;
+  if (interior)
+    hgemm_body<WMB, WNB, BK, false>(g, sh, m0, n0, K);
+  else
+    hgemm_body<WMB, WNB, BK, true>(g, sh, m0, n0, K);
+}
+
+// ============================================================================
 // float64: v_mfma_f64_16x16x4_f64. A wave owns (16 WMB) x (16 WNB); lane
 // (r = lane % 16, q = lane / 16) feeds row r with inner index 4s + q.
 // ============================================================================
@@ -788,9 +995,11 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
 constexpr int F32_WMB = 2, F32_WNB = 2, F32_BK = 16, F32_WGS = 2;   // 128 x 128, 2 per CU
 constexpr int F32B_WMB = 2, F32B_WNB = 2;    // 128 x 128 with block norms
 constexpr int F64_WMB = 2, F64_WNB = 2;      // 64 x 64
+constexpr int BF16_WMB = 2, BF16_WNB = 2, BF16_BK = 64, BF16_WGS = 2;   // 128 x 128
 
 void tile_shape(sbmm_dtype dt, bool blocknorm, int64_t* bm, int64_t* bn) {
   if (dt == SBMM_F64) { *bm = 32 * F64_WMB; *bn = 32 * F64_WNB; return; }
+  if (dt == SBMM_BF16) { *bm = 64 * BF16_WMB; *bn = 64 * BF16_WNB; return; }
   if (blocknorm) { *bm = 64 * F32B_WMB; *bn = 64 * F32B_WNB; return; }
   *bm = 64 * F32_WMB; *bn = 64 * F32_WNB;
 }
@@ -833,6 +1042,8 @@ hipError_t launch_gemm(const GemmLaunch& L, hipStream_t s) {
   } else if (L.dt == SBMM_F32) {
     if (blocknorm) hipLaunchKernelGGL((gemm_f32_kernel<F32B_WMB, F32B_WNB, true>), grid, block, 0, s, g);
     else hipLaunchKernelGGL((sgemm_kernel<F32_WMB, F32_WNB, F32_BK, F32_WGS>), grid, block, 0, s, g);
+  } else if (L.dt == SBMM_BF16) {
+    hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS>), grid, block, 0, s, g);
   } else {
     return hipErrorInvalidValue;
   }

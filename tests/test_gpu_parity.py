@@ -353,3 +353,37 @@ def test_budget_below_sampleable_strata(h):
     with pytest.raises(pk.SbmmError) as ei:
         h.run(prob)
     assert ei.value.status == pk.SBMM_E_BUDGET
+
+
+# --------------------------------------------------------------------------
+# bf16 sketch (float32 accumulation)
+# --------------------------------------------------------------------------
+
+def _bf16_round(x):
+    """float64 -> float32 -> bf16 (round to nearest even each time), back to
+    float64: the rounding the gather applies to the scaled sketch."""
+    return torch.from_numpy(np.asarray(x, np.float64)).to(torch.float32).to(
+        torch.bfloat16).to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("in_dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("shape", [(300, 2000, 260, 50, 37), (513, 4100, 129, 80, 64)])
+def test_bf16_sketch(h, in_dtype, shape):
+    m, n, p, K, c = shape
+    M, N, off = wl.random_problem(m, n, p, K, seed=m + 3 * p, skew=1.0)
+    Md, Nd = to_dev(M, in_dtype), to_dev(N, in_dtype)
+    r = h.run(pk.Problem(Md, Nd, off, c, seed=2), compute=torch.bfloat16)
+    Mh, Nh = host64(Md), host64(Nd)
+    o = om.run(Mh, Nh, off, c, seed=2)
+    assert np.array_equal(r["plan"].idx.cpu().numpy(), o.draws.atom)
+    L = o.draws.L
+    Cq, Dq = _bf16_round(o.C), _bf16_round(o.D)
+    C, D = host64(r["C"]), host64(r["D"])
+    assert np.array_equal(C[:, :L], Cq) and np.array_equal(D[:L], Dq)
+    # float32 accumulation of the bf16 operands
+    assert rel(host64(r["CD"]), Cq @ Dq) < 1e-5
+    assert rel(host64(r["MN"]), o.MN) < 1e-5
+    # the operand rounding itself: reported, bounded by a few bf16 units
+    arith = rel(host64(r["CD"]), o.CD)
+    print(f"bf16 sketch vs float64 sketch: {arith:.2e}")
+    assert arith < 2e-2
