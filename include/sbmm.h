@@ -219,6 +219,21 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* prob, sbmm_dtype compute
                      const sbmm_plan_out* plan, double* err_host,
                      double* rel_host, int64_t* L_host, sbmm_stream stream);
 
+/* Gradient of <G, CD> with respect to M and N, the draws and p held fixed
+ * (CD is bilinear in M and N, eq. 3.3): dC = G D^T and dD = C^T G on matrix
+ * cores (bf16) or in a float64-accumulating kernel (F32 / F64), then
+ * dM[:, i] = sum of scale_l dC[:, l] over the sketch columns l fed by column
+ * i, dN[i, :] likewise from dD, in draw order; columns of M / rows of N that
+ * no draw touched get 0. plan, C (m x L, ldc), D (L x p, ldd) come from the
+ * forward (sbmm_plan / sbmm_sketch in dtype `compute`); L is the sketch width
+ * (host; at most L_pad_max). G is m x p (ldg) in F64 for F64 compute, else
+ * F32 (converted to bf16 inside for bf16 compute). dM (m x n, lddm) and dN
+ * (n x p, lddn) are written in full in the problem's input dtype. */
+sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* prob, const sbmm_plan_out* plan, int64_t L,
+                          sbmm_dtype compute, const void* C, int64_t ldc, const void* D, int64_t ldd,
+                          const void* G, int64_t ldg, void* dM, int64_t lddm, void* dN, int64_t lddn,
+                          sbmm_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

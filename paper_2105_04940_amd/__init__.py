@@ -30,7 +30,7 @@ EXPORTS = (
     "sbmm_create", "sbmm_destroy", "sbmm_status_string", "sbmm_last_error",
     "sbmm_reserve", "sbmm_sync", "sbmm_query_sizes", "sbmm_norms",
     "sbmm_exact", "sbmm_plan", "sbmm_sketch", "sbmm_sketch_gemm",
-    "sbmm_error", "sbmm_run",
+    "sbmm_error", "sbmm_run", "sbmm_backward",
 )
 
 
@@ -92,6 +92,8 @@ def load_library(path=LIB_PATH):
         "sbmm_error": (st, [vp, i64, i64, st, vp, i64, vp, i64, vp, vp]),
         "sbmm_run": (st, [vp, P(Problem_t), st, vp, i64, vp, i64, vp, i64, vp, i64,
                           P(PlanOut_t), P(ctypes.c_double), P(ctypes.c_double), P(i64), vp]),
+        "sbmm_backward": (st, [vp, P(Problem_t), P(PlanOut_t), i64, st, vp, i64, vp, i64, vp, i64,
+                               vp, i64, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -324,6 +326,26 @@ class Handle:
                                          _stream()))
         return out
 
+    def backward(self, problem, plan, C, D, G, L=None):
+        """dM, dN of <G, CD> with the draws of `plan` held fixed (C, D from
+        the forward in the compute dtype; G float64 for float64 compute, else
+        float32). Returns tensors in the dtype of M and N."""
+        torch = _torch()
+        s = problem.struct()
+        ps = plan.struct()
+        if L is None:
+            L = plan.L if plan.L is not None else plan.sizes["L_pad_max"]
+        want = torch.float64 if C.dtype == torch.float64 else torch.float32
+        if G.dtype != want or G.stride(1) != 1:
+            raise ValueError(f"G must be a row-major {want} tensor")
+        dM = torch.empty((s.m, s.n), dtype=problem.M.dtype, device=problem.M.device)
+        dN = torch.empty((s.n, s.p), dtype=problem.N.dtype, device=problem.N.device)
+        self._check(self._lib.sbmm_backward(
+            self.h, ctypes.byref(s), ctypes.byref(ps), int(L), dtype_code(C.dtype),
+            _ptr(C), C.stride(0), _ptr(D), D.stride(0), _ptr(G), G.stride(0),
+            _ptr(dM), s.n, _ptr(dN), s.p, _stream()))
+        return dM, dN
+
     def sync(self):
         self._check(self._lib.sbmm_sync(self.h, _stream()))
 
@@ -355,7 +377,58 @@ class Handle:
         return dict(C=C, D=D, CD=CD, MN=MN, plan=pl, L=L.value, err=err.value, rel=rel.value)
 
 
+_handles = {}
+
+
+def default_handle(device):
+    """One library handle per device index, created on first use."""
+    import torch
+    idx = torch.device(device).index or 0
+    if idx not in _handles:
+        _handles[idx] = Handle(idx)
+    return _handles[idx]
+
+
+def _sampled_matmul_class():
+    import torch
+
+    class SampledMatmul(torch.autograd.Function):
+        """Y ~ X W by sampling blocks of the inner dimension (block mode):
+        forward = norm pass, design and draws, gather of C and D, sketched
+        product CD; backward = sbmm_backward with the forward's draws (p is
+        held fixed). Arguments: X (m x n), W (n x p), block offsets, c, seed,
+        trial, probability rule ("norm", "uniform", "exact" or "user" with
+        user weights), compute dtype of the sketch (None = input dtype)."""
+
+        @staticmethod
+        def forward(ctx, X, W, off, c, seed=0, trial=0, prob="norm", compute=None, user_w=None):
+            h = default_handle(X.device)
+            problem = Problem(X.detach(), W.detach(), off, c, prob=prob, seed=seed, trial=trial,
+                              user_w=user_w)
+            if prob == "exact":
+                _, problem.blkprod_sq, _ = h.exact(problem, store=False, blocknorm=True)
+            col, row, blk = h.norms(problem)
+            plan = h.plan(problem, col, row, blk, sync=True)
+            C, D = h.sketch(problem, plan, out_dtype=compute or X.dtype)
+            CD, _ = h.sketch_gemm(C, D, plan)
+            ctx.save_for_backward(C, D)
+            ctx.problem, ctx.plan, ctx.h = problem, plan, h
+            return CD
+
+        @staticmethod
+        def backward(ctx, G):
+            C, D = ctx.saved_tensors
+            dM, dN = ctx.h.backward(ctx.problem, ctx.plan, C, D, G.contiguous())
+            return dM, dN, None, None, None, None, None, None, None
+
+    return SampledMatmul
+
+
 def __getattr__(name):
+    if name == "SampledMatmul":
+        cls = _sampled_matmul_class()
+        globals()["SampledMatmul"] = cls
+        return cls
     # module-level access to the raw C entry points, e.g. sbmm_norms
     if name in EXPORTS:
         return getattr(lib(), name)

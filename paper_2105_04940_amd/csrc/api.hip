@@ -359,7 +359,7 @@ sbmm_status sbmm_norms(sbmm_handle h, const sbmm_problem* P, double* col_sq, dou
   sbmm_status st = check_handle(h);
   if (st) return st;
   sbmm_sizes sz;
-  if ((st = validate(h, P, &sz))) return st;
+  if ((st = validate(h, P, &sz, true))) return st;
   if (!col_sq || !row_sq || !blk) return fail(h, SBMM_E_ARG, "col_sq, row_sq and blk are required");
   hipStream_t s = (hipStream_t)stream;
   Arena dry(nullptr);
@@ -377,7 +377,7 @@ sbmm_status sbmm_exact(sbmm_handle h, const sbmm_problem* P, void* MN, int64_t l
   sbmm_status st = check_handle(h);
   if (st) return st;
   sbmm_sizes sz;
-  if ((st = validate(h, P, &sz))) return st;
+  if ((st = validate(h, P, &sz, true))) return st;
   if (!mn_sq) return fail(h, SBMM_E_ARG, "mn_sq is required");
   if (MN && ldmn < P->p) return fail(h, SBMM_E_ARG, "ldmn < p");
   hipStream_t s = (hipStream_t)stream;
@@ -430,7 +430,7 @@ sbmm_status sbmm_sketch(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_ou
   sbmm_status st = check_handle(h);
   if (st) return st;
   sbmm_sizes sz;
-  if ((st = validate(h, P, &sz))) return st;
+  if ((st = validate(h, P, &sz, true))) return st;
   if (!plan || !plan->col_off || !plan->colmap || !plan->colscale) return fail(h, SBMM_E_ARG, "plan buffers missing");
   if (!sketch_dtype_ok(P->in_dtype, out_dtype)) return fail(h, SBMM_E_ARG, "sketch dtype not allowed for the input dtype");
   if (C && ldc < sz.L_pad_max) return fail(h, SBMM_E_ARG, "ldc < L_pad_max (%lld)", (long long)sz.L_pad_max);
@@ -621,6 +621,73 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
     if (err_host) *err_host = err;
     if (rel_host) *rel_host = mn2 > 0 ? err / std::sqrt(mn2) : (err2 > 0 ? INFINITY : 0.0);
     if (L_host) *L_host = Lh;
+  }
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_out* plan, int64_t L,
+                          sbmm_dtype compute, const void* C, int64_t ldc, const void* D, int64_t ldd,
+                          const void* G, int64_t ldg, void* dM, int64_t lddm, void* dN, int64_t lddn,
+                          sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  sbmm_sizes sz;
+  if ((st = validate(h, P, &sz, true))) return st;
+  if (!plan || !plan->idx || !plan->scale || !plan->col_off) return fail(h, SBMM_E_ARG, "plan buffers missing");
+  if (!sketch_dtype_ok(P->in_dtype, compute)) return fail(h, SBMM_E_ARG, "compute dtype not allowed for the input dtype");
+  if (L < 0 || L > sz.L_pad_max) return fail(h, SBMM_E_ARG, "L must lie in [0, L_pad_max]");
+  const int64_t m = P->m, n = P->n, p = P->p;
+  if ((m > 0 && !dM) || (p > 0 && !dN)) return fail(h, SBMM_E_ARG, "dM and dN are required");
+  if ((dM && lddm < n) || (dN && lddn < p)) return fail(h, SBMM_E_ARG, "lddm < n or lddn < p");
+  if (L > 0 && m > 0 && p > 0) {
+    if (!C || !D || !G) return fail(h, SBMM_E_ARG, "C, D and G are required");
+    if (ldc < L || ldd < p || ldg < p) return fail(h, SBMM_E_ARG, "ldc < L, ldd < p or ldg < p");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const sbmm_dtype gd = compute == SBMM_F64 ? SBMM_F64 : SBMM_F32;   // dtype of G, dC, dD
+  const size_t ges = dtype_size(gd);
+  for (int pass = 0; pass < 2; ++pass) {
+    Arena ar(pass ? h->ws : nullptr);
+    int64_t* off = nullptr;
+    if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+    int32_t* cnt = ar.take<int32_t>(sz.atoms);
+    int32_t* rank = ar.take<int32_t>(P->c);
+    int64_t* aoff = ar.take<int64_t>(sz.atoms + 1);
+    int32_t* list = ar.take<int32_t>(P->c);
+    char* dC = ar.take<char>(ges * (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(L, 1));
+    char* dD = ar.take<char>(ges * (size_t)std::max<int64_t>(L, 1) * std::max<int64_t>(p, 1));
+    uint16_t* G16 = compute == SBMM_BF16 ? ar.take<uint16_t>((size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(p, 1)) : nullptr;
+    if (!pass) {
+      if ((st = ensure_ws(h, ar.off))) return st;
+      continue;
+    }
+    HIP_TRY(h, launch_draw_lists(plan->idx, P->c, sz.atoms, cnt, rank, aoff, list, s));
+    if (L > 0 && m > 0 && p > 0) {
+      if (compute == SBMM_BF16) {
+        HIP_TRY(h, launch_to_bf16(reinterpret_cast<const float*>(G), m, p, ldg, G16, s));
+        GemmLaunch g1{};   // dC = G D^T  (m x L, inner p)
+        g1.dt = SBMM_BF16; g1.A = G16; g1.lda = p; g1.B = D; g1.ldb = ldd; g1.b_trans = true;
+        g1.m = m; g1.p = L; g1.K_host = p; g1.Cout = dC; g1.ldc = L;
+        HIP_TRY(h, launch_gemm(g1, s));
+        GemmLaunch g2{};   // dD = C^T G  (L x p, inner m)
+        g2.dt = SBMM_BF16; g2.A = C; g2.lda = ldc; g2.a_trans = true; g2.B = G16; g2.ldb = p;
+        g2.m = L; g2.p = p; g2.K_host = m; g2.Cout = dD; g2.ldc = p;
+        HIP_TRY(h, launch_gemm(g2, s));
+      } else {
+        HIP_TRY(h, launch_gemm_strided(gd, G, ldg, 1, D, 1, ldd, dC, L, m, L, p, s));
+        HIP_TRY(h, launch_gemm_strided(gd, C, 1, ldc, G, ldg, 1, dD, p, L, p, m, s));
+      }
+    } else {
+      if (m > 0 && L > 0) HIP_TRY(h, launch_fill_f64(reinterpret_cast<double*>(dC), (int64_t)(ges * m * L / 8), 0.0, s));
+      if (p > 0 && L > 0) HIP_TRY(h, launch_fill_f64(reinterpret_cast<double*>(dD), (int64_t)(ges * L * p / 8), 0.0, s));
+    }
+    BackwardScatter b{};
+    b.mode = P->mode; b.off_dev = off; b.K = P->K; b.aoff = aoff; b.list = list;
+    b.scale = plan->scale; b.col_off = plan->col_off; b.m = m; b.n = n; b.p = p;
+    b.grad_dt = gd; b.out_dt = P->in_dtype; b.dC = dC; b.lddc = std::max<int64_t>(L, 1);
+    b.dD = dD; b.lddd = std::max<int64_t>(p, 1); b.dM = dM; b.lddm = lddm; b.dN = dN; b.lddn = lddn;
+    b.L = L; b.status = h->status;
+    HIP_TRY(h, launch_scatter(b, s));
   }
   return SBMM_OK;
 }

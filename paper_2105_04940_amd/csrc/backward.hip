@@ -1,0 +1,243 @@
+// Gradient of the sketched product with the draws held fixed.
+//
+// CD = C D with C[:, l] = scale_l M[:, colmap[l]] and D[l, :] = scale_l
+// N[colmap[l], :] (eq. 3.3), so for an upstream gradient G = dL/d(CD):
+//     dC = G D^T,   dD = C^T G,
+//     dM[:, i] = sum over sketch columns l with colmap[l] = i of scale_l dC[:, l],
+//     dN[i, :] = sum over the same l of scale_l dD[l, :],
+// and every column of M (row of N) that no draw touched gets zero. The two
+// products run on the matrix-core kernels; the sums run here, per inner
+// index, over the draws of its atom in draw order (no atomics, bitwise
+// reproducible).
+//
+// The per-atom draw lists are a counting sort of the draws by atom that keeps
+// draw order within an atom.
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// One workgroup: per-atom counts and offsets, and the draws of each atom in
+// ascending draw order.
+__global__ __launch_bounds__(kThreads) void draw_lists_kernel(const int32_t* __restrict__ idx, int64_t c,
+                                                              int64_t A, int32_t* __restrict__ cnt,
+                                                              int32_t* __restrict__ rank,
+                                                              int64_t* __restrict__ aoff,
+                                                              int32_t* __restrict__ list) {
+  __shared__ int64_t sm[kThreads];
+  for (int64_t a = threadIdx.x; a < A; a += kThreads) cnt[a] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int64_t t = 0; t < c; ++t) {
+      const int32_t a = idx[t];
+      rank[t] = a >= 0 ? cnt[a]++ : -1;
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the counts (each thread owns a contiguous run)
+  const int64_t per = (A + kThreads - 1) / kThreads;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min(A, b0 + per);
+  int64_t local = 0;
+  for (int64_t a = b0; a < b1; ++a) local += cnt[a];
+  sm[threadIdx.x] = local;
+  __syncthreads();
+  for (int o = 1; o < kThreads; o <<= 1) {
+    const int64_t add = (int)threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
+    __syncthreads();
+    sm[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t run = sm[threadIdx.x] - local;
+  for (int64_t a = b0; a < b1; ++a) {
+    aoff[a] = run;
+    run += cnt[a];
+  }
+  if (threadIdx.x == kThreads - 1) aoff[A] = sm[kThreads - 1];
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < c; t += kThreads)
+    if (rank[t] >= 0) list[aoff[idx[t]] + rank[t]] = (int32_t)t;
+}
+
+struct ScatterArgs {
+  int mode;
+  const int64_t* off;      // block offsets (block mode: atom -> columns)
+  int32_t K;
+  const int64_t* aoff; const int32_t* list;
+  const double* scale; const int64_t* col_off;
+  int64_t m, n, p;
+  int64_t L;               // columns of dC / rows of dD
+  int32_t* status;
+};
+
+__device__ __forceinline__ void atom_of(const ScatterArgs& a, int64_t i, int64_t& atom, int64_t& j) {
+  if (a.mode == SBMM_MODE_BLOCK) {
+    int64_t lo = 0, hi = a.K;            // last block with off[k] <= i
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (a.off[mid] <= i) lo = mid; else hi = mid;
+    }
+    atom = lo;
+    j = i - a.off[lo];
+  } else {
+    atom = i;
+    j = 0;
+  }
+}
+
+template <typename T> __device__ __forceinline__ void put(T* p, int64_t i, double v);
+template <> __device__ __forceinline__ void put<double>(double* p, int64_t i, double v) { p[i] = v; }
+template <> __device__ __forceinline__ void put<float>(float* p, int64_t i, double v) { p[i] = (float)v; }
+template <> __device__ __forceinline__ void put<uint16_t>(uint16_t* p, int64_t i, double v) {
+  p[i] = float_to_bf16_bits((float)v);
+}
+
+// dM[h, i] for a 256-column x 16-row block; dC is m x ldc (float or double)
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kThreads) void scatter_cols_kernel(ScatterArgs a, const Tin* __restrict__ dC,
+                                                                int64_t lddc, Tout* __restrict__ dM,
+                                                                int64_t lddm, int64_t ctiles) {
+  const int64_t i = (blockIdx.x % ctiles) * kThreads + threadIdx.x;
+  const int64_t h0 = (blockIdx.x / ctiles) * 16;
+  if (i >= a.n) return;
+  int64_t atom, j;
+  atom_of(a, i, atom, j);
+  const int64_t q0 = a.aoff[atom], q1 = a.aoff[atom + 1];
+  const int64_t h1 = min(a.m, h0 + 16);
+  for (int64_t h = h0; h < h1; ++h) {
+    double s = 0.0;
+    for (int64_t q = q0; q < q1; ++q) {
+      const int32_t t = a.list[q];
+      const int64_t l = a.col_off[t] + j;
+      if (l >= a.L) { *a.status = SBMM_DEV_USER_CK; continue; }   // L below the sketch width
+      s += a.scale[t] * (double)dC[h * lddc + l];
+    }
+    put<Tout>(dM, h * lddm + i, s);
+  }
+}
+
+// dN[i, f]: one wave per inner index, lanes across f; dD is L x lddd
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kThreads) void scatter_rows_kernel(ScatterArgs a, const Tin* __restrict__ dD,
+                                                                int64_t lddd, Tout* __restrict__ dN,
+                                                                int64_t lddn) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= a.n) return;
+  int64_t atom, j;
+  atom_of(a, i, atom, j);
+  const int64_t q0 = a.aoff[atom], q1 = a.aoff[atom + 1];
+  for (int64_t f = lane; f < a.p; f += 64) {
+    double s = 0.0;
+    for (int64_t q = q0; q < q1; ++q) {
+      const int32_t t = a.list[q];
+      const int64_t l = a.col_off[t] + j;
+      if (l >= a.L) { *a.status = SBMM_DEV_USER_CK; continue; }
+      s += a.scale[t] * (double)dD[l * lddd + f];
+    }
+    put<Tout>(dN, i * lddn + f, s);
+  }
+}
+
+// C[i][j] = sum_k A(i, k) B(k, j) with arbitrary element strides, 16 x 16
+// output tile per workgroup, float64 accumulation (small problems).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gemm_strided_kernel(const T* __restrict__ A, int64_t ars, int64_t aks,
+                                                                const T* __restrict__ B, int64_t bks, int64_t bjs,
+                                                                T* __restrict__ C, int64_t ldc, int64_t M,
+                                                                int64_t Nc, int64_t K, int64_t tiles_m) {
+  __shared__ T As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t i = (blockIdx.x % tiles_m) * 16 + ty;
+  const int64_t j = (blockIdx.x / tiles_m) * 16 + tx;
+  double acc = 0.0;
+  for (int64_t k0 = 0; k0 < K; k0 += 16) {
+    As[ty][tx] = (i < M && k0 + tx < K) ? A[i * ars + (k0 + tx) * aks] : T(0);
+    Bs[ty][tx] = (k0 + ty < K && j < Nc) ? B[(k0 + ty) * bks + j * bjs] : T(0);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc += (double)As[ty][kk] * (double)Bs[kk][tx];
+    __syncthreads();
+  }
+  if (i < M && j < Nc) C[i * ldc + j] = (T)acc;
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, int64_t rows, int64_t cols, int64_t ldx,
+                               uint16_t* __restrict__ y) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / cols, c = e % cols;
+    y[e] = float_to_bf16_bits(x[r * ldx + c]);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_to_bf16(const float* x, int64_t rows, int64_t cols, int64_t ldx, uint16_t* y,
+                          hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>(ceil_div(rows * cols, 256), 8192);
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, rows, cols, ldx, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_draw_lists(const int32_t* idx, int64_t c, int64_t A, int32_t* cnt, int32_t* rank,
+                             int64_t* aoff, int32_t* list, hipStream_t s) {
+  hipLaunchKernelGGL(draw_lists_kernel, dim3(1), dim3(kThreads), 0, s, idx, c, A, cnt, rank, aoff, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const BackwardScatter& b, hipStream_t s) {
+  ScatterArgs a{};
+  a.mode = b.mode; a.off = b.off_dev; a.K = b.K; a.aoff = b.aoff; a.list = b.list;
+  a.scale = b.scale; a.col_off = b.col_off; a.m = b.m; a.n = b.n; a.p = b.p;
+  a.L = b.L; a.status = b.status;
+  const int64_t ctiles = ceil_div(b.n, kThreads);
+  const dim3 gc((unsigned)(ctiles * ceil_div(std::max<int64_t>(b.m, 1), 16)));
+  const dim3 gr((unsigned)ceil_div(b.n, 4));
+  if (b.m > 0 && b.dM) {
+    if (b.grad_dt == SBMM_F64) {
+      hipLaunchKernelGGL((scatter_cols_kernel<double, double>), gc, dim3(kThreads), 0, s, a,
+                         (const double*)b.dC, b.lddc, (double*)b.dM, b.lddm, ctiles);
+    } else if (b.out_dt == SBMM_F32) {
+      hipLaunchKernelGGL((scatter_cols_kernel<float, float>), gc, dim3(kThreads), 0, s, a,
+                         (const float*)b.dC, b.lddc, (float*)b.dM, b.lddm, ctiles);
+    } else {
+      hipLaunchKernelGGL((scatter_cols_kernel<float, uint16_t>), gc, dim3(kThreads), 0, s, a,
+                         (const float*)b.dC, b.lddc, (uint16_t*)b.dM, b.lddm, ctiles);
+    }
+  }
+  if (b.p > 0 && b.dN) {
+    if (b.grad_dt == SBMM_F64) {
+      hipLaunchKernelGGL((scatter_rows_kernel<double, double>), gr, dim3(kThreads), 0, s, a,
+                         (const double*)b.dD, b.lddd, (double*)b.dN, b.lddn);
+    } else if (b.out_dt == SBMM_F32) {
+      hipLaunchKernelGGL((scatter_rows_kernel<float, float>), gr, dim3(kThreads), 0, s, a,
+                         (const float*)b.dD, b.lddd, (float*)b.dN, b.lddn);
+    } else {
+      hipLaunchKernelGGL((scatter_rows_kernel<float, uint16_t>), gr, dim3(kThreads), 0, s, a,
+                         (const float*)b.dD, b.lddd, (uint16_t*)b.dN, b.lddn);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_strided(sbmm_dtype dt, const void* A, int64_t ars, int64_t aks, const void* B,
+                               int64_t bks, int64_t bjs, void* C, int64_t ldc, int64_t M, int64_t Nc,
+                               int64_t K, hipStream_t s) {
+  if (M <= 0 || Nc <= 0) return hipSuccess;
+  const int64_t tm = ceil_div(M, 16), tn = ceil_div(Nc, 16);
+  const dim3 grid((unsigned)(tm * tn));
+  if (dt == SBMM_F64)
+    hipLaunchKernelGGL(gemm_strided_kernel<double>, grid, dim3(kThreads), 0, s, (const double*)A, ars, aks,
+                       (const double*)B, bks, bjs, (double*)C, ldc, M, Nc, K, tm);
+  else if (dt == SBMM_F32)
+    hipLaunchKernelGGL(gemm_strided_kernel<float>, grid, dim3(kThreads), 0, s, (const float*)A, ars, aks,
+                       (const float*)B, bks, bjs, (float*)C, ldc, M, Nc, K, tm);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}

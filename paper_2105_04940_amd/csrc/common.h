@@ -133,6 +133,8 @@ struct GemmLaunch {
   // float32 staging of the partial sums of inner extents above 4096 (one
   // tile-sized slot per workgroup, private to it)
   float* stage;
+  // bf16 only: A given as K x M (a_trans) / B given as N x K (b_trans)
+  bool a_trans, b_trans;
 };
 // bytes of the float32 staging buffer launch_gemm needs
 size_t gemm_stage_bytes(sbmm_dtype dt, int64_t m, int64_t p);
@@ -144,6 +146,27 @@ hipError_t launch_gemm(const GemmLaunch& a, hipStream_t s);
 hipError_t launch_block_gram(const float* M, int64_t ldm, const float* N, int64_t ldn, int64_t m, int64_t p,
                              const int64_t* off_dev, int32_t K, double* out, hipStream_t s);
 int64_t block_gram_max_width();
+
+// Backward of the sketch: per-atom draw lists and the scatter of dC / dD
+// into dM / dN.
+hipError_t launch_draw_lists(const int32_t* idx, int64_t c, int64_t A, int32_t* cnt, int32_t* rank,
+                             int64_t* aoff, int32_t* list, hipStream_t s);
+struct BackwardScatter {
+  int mode; const int64_t* off_dev; int32_t K;
+  const int64_t* aoff; const int32_t* list; const double* scale; const int64_t* col_off;
+  int64_t m, n, p;
+  sbmm_dtype grad_dt;   // dtype of dC / dD (F64 or F32)
+  sbmm_dtype out_dt;    // dtype of dM / dN
+  const void* dC; int64_t lddc; const void* dD; int64_t lddd;
+  void* dM; int64_t lddm; void* dN; int64_t lddn;
+  int64_t L; int32_t* status;
+};
+hipError_t launch_scatter(const BackwardScatter& b, hipStream_t s);
+hipError_t launch_gemm_strided(sbmm_dtype dt, const void* A, int64_t ars, int64_t aks, const void* B,
+                               int64_t bks, int64_t bjs, void* C, int64_t ldc, int64_t M, int64_t Nc,
+                               int64_t K, hipStream_t s);
+hipError_t launch_to_bf16(const float* x, int64_t rows, int64_t cols, int64_t ldx, uint16_t* y,
+                          hipStream_t s);
 
 // Fill kernels (used instead of memset so that captured graphs hold only
 // kernel nodes).

@@ -560,12 +560,16 @@ struct HgemmTile {
   static constexpr int KC = BK / 8;                     // 16-byte chunks per A row
   static constexpr int NA = BM * KC / kThreads;         // 16-byte loads of A per thread
   static constexpr int NBP = (BK / 2) * (BN / 8) / kThreads;  // row-pair chunks of B per thread
+  static constexpr int NAP = (BK / 2) * (BM / 8) / kThreads;  // row-pair chunks of A (transposed A)
+  static constexpr int NBK = BN * KC / kThreads;               // 16-byte runs of B (transposed B)
   uint16_t As[2][BM][SA];
   uint16_t Bs[2][BN][SB];
   double red[8];
 };
 
-template <int WMB, int WNB, int BK, bool EDGE>
+// AT: A is given as K x M (A[i][k] at A + k lda + i); BT: B is given as
+// N x K (B[k][j] at B + j ldb + k). The LDS layouts stay [row][k] / [col][k].
+template <int WMB, int WNB, int BK, bool EDGE, bool AT, bool BT>
 __device__ __forceinline__ void hgemm_body(const GemmArgs& g, HgemmTile<WMB, WNB, BK>& sh,
                                            int64_t m0, int64_t n0, int64_t K) {
   using T = HgemmTile<WMB, WNB, BK>;
@@ -583,64 +587,101 @@ __device__ __forceinline__ void hgemm_body(const GemmArgs& g, HgemmTile<WMB, WNB
 #pragma unroll
     for (int c = 0; c < WNB; ++c) acc[b][c] = f32x16{};
 
-  uint4 ra[NA], rb0[NBP], rb1[NBP];
+  // Each operand tile is gathered either as 16-byte runs along k (stored
+  // directly) or as pairs of k-rows of 8 consecutive rows/columns (stored
+  // transposed, two k per 32-bit write).
+  constexpr int RA = NA > T::NAP ? NA : T::NAP;       // registers for either A layout
+  constexpr int RB = NBP > T::NBK ? NBP : T::NBK;     // registers for either B layout
+  uint4 ra0[RA], ra1[RA], rb0[RB], rb1[RB];
+  auto pack8 = [](const uint16_t* t) {
+    return make_uint4(t[0] | (uint32_t)t[1] << 16, t[2] | (uint32_t)t[3] << 16,
+                      t[4] | (uint32_t)t[5] << 16, t[6] | (uint32_t)t[7] << 16);
+  };
+  // 16-byte run along k of row r (k contiguous, leading dimension ld)
+  auto run_k = [&](const uint16_t* X, int64_t ld, int64_t r, int64_t rmax, int64_t k, bool vec) {
+    if (!EDGE || (r < rmax && k + 8 <= K && vec)) return *reinterpret_cast<const uint4*>(X + r * ld + k);
+    uint16_t t[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = (r < rmax && k + e < K) ? X[r * ld + k + e] : 0;
+    return pack8(t);
+  };
+  // 8 consecutive rows/columns c..c+7 of k-row kr (index contiguous)
+  auto run_i = [&](const uint16_t* X, int64_t ld, int64_t kr, int64_t c, int64_t cmax, bool vec) {
+    if (!EDGE || (kr < K && c + 8 <= cmax && vec)) return *reinterpret_cast<const uint4*>(X + kr * ld + c);
+    uint16_t t[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = (kr < K && c + e < cmax) ? X[kr * ld + c + e] : 0;
+    return pack8(t);
+  };
   auto load = [&](int64_t kt) {
     const int64_t k0 = kt * BK;
+    if constexpr (!AT) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int f = tid + kThreads * q;
-      const int i = f / KC, c8 = f % KC;
-      const int64_t row = m0 + i, col = k0 + 8 * c8;
-      if (!EDGE || (row < g.m && col + 8 <= K && g.vec_a)) {
-        ra[q] = *reinterpret_cast<const uint4*>(A + row * g.lda + col);
-      } else {
-        uint16_t t[8];
+      for (int q = 0; q < NA; ++q) {
+        const int f = tid + kThreads * q;
+        ra0[q] = run_k(A, g.lda, m0 + f / KC, g.m, k0 + 8 * (f % KC), g.vec_a);
+      }
+    } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) t[e] = (row < g.m && col + e < K) ? A[row * g.lda + col + e] : 0;
-        ra[q] = make_uint4(t[0] | (uint32_t)t[1] << 16, t[2] | (uint32_t)t[3] << 16,
-                           t[4] | (uint32_t)t[5] << 16, t[6] | (uint32_t)t[7] << 16);
+      for (int q = 0; q < T::NAP; ++q) {
+        const int f = tid + kThreads * q;
+        const int pr = f / (T::BM / 8), c8 = f % (T::BM / 8);
+        ra0[q] = run_i(A, g.lda, k0 + 2 * pr, m0 + 8 * c8, g.m, g.vec_a);
+        ra1[q] = run_i(A, g.lda, k0 + 2 * pr + 1, m0 + 8 * c8, g.m, g.vec_a);
       }
     }
+    if constexpr (BT) {
 #pragma unroll
-    for (int q = 0; q < NBP; ++q) {
-      const int f = tid + kThreads * q;
-      const int pr = f / (BN / 8), c8 = f % (BN / 8);
-      const int64_t kr = k0 + 2 * pr, col = n0 + 8 * c8;
-      if (!EDGE || (kr + 1 < K && col + 8 <= g.p && g.vec_b)) {
-        rb0[q] = *reinterpret_cast<const uint4*>(B + kr * g.ldb + col);
-        rb1[q] = *reinterpret_cast<const uint4*>(B + (kr + 1) * g.ldb + col);
-      } else {
-        uint16_t t0[8], t1[8];
+      for (int q = 0; q < T::NBK; ++q) {
+        const int f = tid + kThreads * q;
+        rb0[q] = run_k(B, g.ldb, n0 + f / KC, g.p, k0 + 8 * (f % KC), g.vec_b);
+      }
+    } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          t0[e] = (kr < K && col + e < g.p) ? B[kr * g.ldb + col + e] : 0;
-          t1[e] = (kr + 1 < K && col + e < g.p) ? B[(kr + 1) * g.ldb + col + e] : 0;
-        }
-        rb0[q] = make_uint4(t0[0] | (uint32_t)t0[1] << 16, t0[2] | (uint32_t)t0[3] << 16,
-                            t0[4] | (uint32_t)t0[5] << 16, t0[6] | (uint32_t)t0[7] << 16);
-        rb1[q] = make_uint4(t1[0] | (uint32_t)t1[1] << 16, t1[2] | (uint32_t)t1[3] << 16,
-                            t1[4] | (uint32_t)t1[5] << 16, t1[6] | (uint32_t)t1[7] << 16);
+      for (int q = 0; q < NBP; ++q) {
+        const int f = tid + kThreads * q;
+        const int pr = f / (BN / 8), c8 = f % (BN / 8);
+        rb0[q] = run_i(B, g.ldb, k0 + 2 * pr, n0 + 8 * c8, g.p, g.vec_b);
+        rb1[q] = run_i(B, g.ldb, k0 + 2 * pr + 1, n0 + 8 * c8, g.p, g.vec_b);
       }
     }
   };
-  auto store = [&](int buf) {
+  // write 8 rows/columns x 2 k of a transposed pair into an LDS [row][k] tile
+  auto store_pair = [](uint16_t (*X)[T::SA], int c0, int k, const uint4& a0, const uint4& a1) {
+    const uint32_t w0[4] = {a0.x, a0.y, a0.z, a0.w};
+    const uint32_t w1[4] = {a1.x, a1.y, a1.z, a1.w};
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int f = tid + kThreads * q;
-      const int i = f / KC, c8 = f % KC;
-      *reinterpret_cast<uint4*>(&sh.As[buf][i][8 * c8]) = ra[q];
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t lo = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+      const uint32_t hi = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+      *reinterpret_cast<uint32_t*>(&X[c0 + e][k]) = lo | (hi << 16);
     }
+  };
+  auto store = [&](int buf) {
+    if constexpr (!AT) {
 #pragma unroll
-    for (int q = 0; q < NBP; ++q) {
-      const int f = tid + kThreads * q;
-      const int pr = f / (BN / 8), c8 = f % (BN / 8);
-      const uint32_t w0[4] = {rb0[q].x, rb0[q].y, rb0[q].z, rb0[q].w};
-      const uint32_t w1[4] = {rb1[q].x, rb1[q].y, rb1[q].z, rb1[q].w};
+      for (int q = 0; q < NA; ++q) {
+        const int f = tid + kThreads * q;
+        *reinterpret_cast<uint4*>(&sh.As[buf][f / KC][8 * (f % KC)]) = ra0[q];
+      }
+    } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t lo = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-        const uint32_t hi = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-        *reinterpret_cast<uint32_t*>(&sh.Bs[buf][8 * c8 + e][2 * pr]) = lo | (hi << 16);
+      for (int q = 0; q < T::NAP; ++q) {
+        const int f = tid + kThreads * q;
+        store_pair(sh.As[buf], 8 * (f % (T::BM / 8)), 2 * (f / (T::BM / 8)), ra0[q], ra1[q]);
+      }
+    }
+    if constexpr (BT) {
+#pragma unroll
+      for (int q = 0; q < T::NBK; ++q) {
+        const int f = tid + kThreads * q;
+        *reinterpret_cast<uint4*>(&sh.Bs[buf][f / KC][8 * (f % KC)]) = rb0[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NBP; ++q) {
+        const int f = tid + kThreads * q;
+        store_pair(sh.Bs[buf], 8 * (f % (BN / 8)), 2 * (f / (BN / 8)), rb0[q], rb1[q]);
       }
     }
   };
@@ -662,7 +703,9 @@ __device__ __forceinline__ void hgemm_body(const GemmArgs& g, HgemmTile<WMB, WNB
     }
   };
 
-  const int64_t nkt = EDGE ? (K + BK - 1) / BK : K / BK;
+  // interior tiles of products whose inner extent is a multiple of BK run
+  // unpredicated; anything else takes the predicated loads
+  const int64_t nkt = (K + BK - 1) / BK;
   if (nkt > 0) {
     load(0);
     store(0);
@@ -675,37 +718,6 @@ __device__ __forceinline__ void hgemm_body(const GemmArgs& g, HgemmTile<WMB, WNB
     if (kt + 1 < nkt) store(cur ^ 1);
     __syncthreads();
   }
-  if constexpr (!EDGE) {
-    if (nkt * BK < K) {   // inner-dimension tail: one predicated step
-      {
-        const int64_t k0 = nkt * BK;
-#pragma unroll
-        for (int q = 0; q < NA; ++q) {
-          const int f = tid + kThreads * q;
-          const int i = f / KC, c8 = f % KC;
-          const int64_t row = m0 + i, col = k0 + 8 * c8;
-          uint16_t t[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) t[e] = (col + e < K) ? A[row * g.lda + col + e] : 0;
-          ra[q] = make_uint4(t[0] | (uint32_t)t[1] << 16, t[2] | (uint32_t)t[3] << 16,
-                             t[4] | (uint32_t)t[5] << 16, t[6] | (uint32_t)t[7] << 16);
-        }
-#pragma unroll
-        for (int q = 0; q < NBP; ++q) {
-          const int f = tid + kThreads * q;
-          const int pr = f / (BN / 8), c8 = f % (BN / 8);
-          const int64_t kr = k0 + 2 * pr, col = n0 + 8 * c8;
-          const uint4 z = make_uint4(0, 0, 0, 0);
-          rb0[q] = kr < K ? *reinterpret_cast<const uint4*>(B + kr * g.ldb + col) : z;
-          rb1[q] = kr + 1 < K ? *reinterpret_cast<const uint4*>(B + (kr + 1) * g.ldb + col) : z;
-        }
-      }
-      store(0);
-      __syncthreads();
-      compute(0);
-    }
-  }
-
   float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
   const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
   double e2 = 0.0, n2 = 0.0;
@@ -733,7 +745,7 @@ __device__ __forceinline__ void hgemm_body(const GemmArgs& g, HgemmTile<WMB, WNB
   if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
 }
 
-template <int WMB, int WNB, int BK, int WG_PER_CU>
+template <int WMB, int WNB, int BK, int WG_PER_CU, bool AT = false, bool BT = false>
 __global__ __launch_bounds__(kThreads, WG_PER_CU) void hgemm_kernel(GemmArgs g) {
   using T = HgemmTile<WMB, WNB, BK>;
   __shared__ T sh;
@@ -741,11 +753,11 @@ __global__ __launch_bounds__(kThreads, WG_PER_CU) void hgemm_kernel(GemmArgs g) 
   tile_coords(g, tm, tn);
   const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
   const int64_t K = inner_extent(g);
-  const bool interior = g.vec_a && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p;
+  const bool interior = g.vec_a && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p && K % BK == 0;
   if (interior)
-    hgemm_body<WMB, WNB, BK, false>(g, sh, m0, n0, K);
+    hgemm_body<WMB, WNB, BK, false, AT, BT>(g, sh, m0, n0, K);
   else
-    hgemm_body<WMB, WNB, BK, true>(g, sh, m0, n0, K);
+    hgemm_body<WMB, WNB, BK, true, AT, BT>(g, sh, m0, n0, K);
 }
 
 // ============================================================================
@@ -1043,7 +1055,14 @@ hipError_t launch_gemm(const GemmLaunch& L, hipStream_t s) {
     if (blocknorm) hipLaunchKernelGGL((gemm_f32_kernel<F32B_WMB, F32B_WNB, true>), grid, block, 0, s, g);
     else hipLaunchKernelGGL((sgemm_kernel<F32_WMB, F32_WNB, F32_BK, F32_WGS>), grid, block, 0, s, g);
   } else if (L.dt == SBMM_BF16) {
-    hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS>), grid, block, 0, s, g);
+    if (L.a_trans && L.b_trans)
+      hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, true, true>), grid, block, 0, s, g);
+    else if (L.a_trans)
+      hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, true, false>), grid, block, 0, s, g);
+    else if (L.b_trans)
+      hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, false, true>), grid, block, 0, s, g);
+    else
+      hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS>), grid, block, 0, s, g);
   } else {
     return hipErrorInvalidValue;
   }

@@ -89,8 +89,6 @@ def test_sizes_block_and_stratified():
     dict(c=0),                               # no draws
     dict(c=2**31),                           # too many draws
     dict(prob="user"),                       # user weights missing
-    dict(prob="exact"),                      # block norms missing
-    dict(mode="stratified", alloc="opt"),    # block norms missing
     dict(mode="stratified", alloc="user"),   # counts missing
     dict(mode="stratified", alloc="user", user_ck=[1, 1]),      # sum != c
     dict(mode="stratified", alloc="user", user_ck=[4, -1]),     # negative

@@ -387,3 +387,101 @@ def test_bf16_sketch(h, in_dtype, shape):
     arith = rel(host64(r["CD"]), o.CD)
     print(f"bf16 sketch vs float64 sketch: {arith:.2e}")
     assert arith < 2e-2
+
+
+def test_plan_rejects_missing_block_norms(h):
+    M, N, off = wl.random_problem(10, 60, 8, 3, seed=40)
+    for kw in (dict(prob="exact"), dict(mode="stratified", alloc="opt")):
+        prob = pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), off, 4, **kw)
+        col, row, blk = h.norms(prob)
+        with pytest.raises(pk.SbmmError) as ei:
+            h.plan(prob, col, row, blk)
+        assert ei.value.status == pk.SBMM_E_ARG
+
+
+# --------------------------------------------------------------------------
+# backward (draws and p held fixed)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode,off", [("block", None), ("stratified", None)])
+def test_backward_f64_matches_oracle(h, mode, off):
+    # the finite-difference case: 64 x 256 x 64, 8 blocks of 32, c = 4
+    M, N, _ = wl.random_problem(64, 256, 64, 8, seed=41)
+    off = wl.equal_blocks(256, 8)
+    c = 4 if mode == "block" else 16
+    Md = to_dev(M, torch.float64).requires_grad_(True)
+    Nd = to_dev(N, torch.float64).requires_grad_(True)
+    G = wl.rng(42).standard_normal((64, 64))
+    kw = dict(mode=mode, prob="norm", alloc="norm", seed=3)
+    prob = pk.Problem(Md.detach(), Nd.detach(), off, c, **kw)
+    col, row, blk = h.norms(prob)
+    pl = h.plan(prob, col, row, blk)
+    C, D = h.sketch(prob, pl)
+    CD, _ = h.sketch_gemm(C, D, pl)
+    dM, dN = h.backward(prob, pl, C, D, to_dev(G, torch.float64))
+    o = om.run(M, N, off, c, **kw)
+    assert np.array_equal(pl.idx.cpu().numpy(), o.draws.atom)
+    odM, odN = om.backward(M, N, o.draws, G)
+    assert rel(host64(dM), odM) < 1e-12 and rel(host64(dN), odN) < 1e-12
+    # columns of M / rows of N outside the drawn atoms get exactly zero
+    hit = np.zeros(256, bool)
+    for lo, w in zip(o.draws.lo, o.draws.width):
+        hit[lo:lo + w] = True
+    assert np.all(host64(dM)[:, ~hit] == 0) and np.all(host64(dN)[~hit] == 0)
+
+
+def test_backward_finite_differences_autograd(h):
+    # fixed user weights keep the draws and p fixed, so <G, CD> is bilinear
+    # in (M, N) and central differences are exact up to rounding
+    M, N, _ = wl.random_problem(64, 256, 64, 8, seed=43)
+    off = wl.equal_blocks(256, 8)
+    w = to_dev(wl.rng(44).uniform(0.5, 2.0, size=8), torch.float64)
+    G = to_dev(wl.rng(45).standard_normal((64, 64)), torch.float64)
+    SM = pk.SampledMatmul
+    X = to_dev(M, torch.float64).requires_grad_(True)
+    W = to_dev(N, torch.float64).requires_grad_(True)
+    Y = SM.apply(X, W, off, 4, 7, 0, "user", None, w)
+    (Y * G).sum().backward()
+    g = wl.rng(46)
+    for _ in range(3):
+        dx = to_dev(g.standard_normal(M.shape), torch.float64)
+        dw = to_dev(g.standard_normal(N.shape), torch.float64)
+        eps = 1e-3
+        with torch.no_grad():
+            fp = (SM.apply(X + eps * dx, W + eps * dw, off, 4, 7, 0, "user", None, w) * G).sum()
+            fm = (SM.apply(X - eps * dx, W - eps * dw, off, 4, 7, 0, "user", None, w) * G).sum()
+        fd = ((fp - fm) / (2 * eps)).item()
+        an = ((X.grad * dx).sum() + (W.grad * dw).sum()).item()
+        assert abs(fd - an) <= 1e-8 * max(1.0, abs(an))
+
+
+def test_backward_bf16_linear_layer(h):
+    # the differentiable linear layer at a reduced size: X 1024 x 4096,
+    # W 4096 x 2048 (bf16), 128 blocks of 32, c = 32
+    X, W, G = wl.linear_layer(1024, 4096, 2048, seed=47)
+    off = wl.equal_blocks(4096, 128)
+    Xd = to_dev(X, torch.bfloat16).requires_grad_(True)
+    Wd = to_dev(W, torch.bfloat16).requires_grad_(True)
+    Gd = to_dev(G, torch.float32)
+    Y = pk.SampledMatmul.apply(Xd, Wd, off, 32, 5, 0, "norm", None, None)
+    Y.backward(Gd)
+    Xh, Wh = host64(Xd), host64(Wd)
+    o = om.run(Xh, Wh, off, 32, seed=5, prob="norm")
+    ctx_idx = np.array(o.draws.atom)
+    # reference from the same bf16 operands the kernels multiply: the scaled
+    # sketch rounded to bf16 and G rounded to bf16
+    Cq, Dq = _bf16_round(o.C), _bf16_round(o.D)
+    Gq = _bf16_round(G.astype(np.float64))
+    dC = Gq @ Dq.T
+    dD = Cq.T @ Gq
+    dX = np.zeros_like(Xh)
+    dW = np.zeros_like(Wh)
+    for t in range(len(o.draws.atom)):
+        lo, wd, c0 = int(o.draws.lo[t]), int(o.draws.width[t]), int(o.draws.col_off[t])
+        dX[:, lo:lo + wd] += o.draws.scale[t] * dC[:, c0:c0 + wd]
+        dW[lo:lo + wd] += o.draws.scale[t] * dD[c0:c0 + wd]
+    # bf16 outputs: within a few bf16 units of the float64 reference
+    assert rel(host64(Xd.grad), dX) < 1e-2 and rel(host64(Wd.grad), dW) < 1e-2
+    # and an unbiased estimate of the exact gradient G W^T (reported)
+    exact = G.astype(np.float64) @ Wh.T
+    print("bf16 sampled dX vs exact-product gradient:", rel(host64(Xd.grad), exact))
