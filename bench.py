@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-linear-layer", action="store_true",
+                    help="skip the bf16 linear-layer forward/backward leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -110,6 +112,75 @@ def cpu_baseline(M, N, off, target_s):
                    f"M[:{r}, :] (x{n}) and N[:, :{r}], rule norm, c=256, L={res.draws.L}; "
                    f"{dt:.1f} s"),
         "seconds": dt,
+    }
+
+
+def linear_layer_leg(h, pk, wl, torch, steps, warmup):
+    """The differentiable linear layer Y ~ X W (bf16, 512 blocks of 32,
+    c = 128): forward (norms, plan, gather, sketched product) and backward
+    (dC = G D^T, dD = C^T G and the scatter into dX, dW), beside the dense
+    backward G W^T, X^T G with torch's bf16 matmul for context."""
+    dev = "cuda:0"
+    X, W, G = wl.linear_layer()
+    off = wl.equal_blocks(X.shape[1], 512)
+    Xd = torch.from_numpy(X).to(dev).to(torch.bfloat16)
+    Wd = torch.from_numpy(W).to(dev).to(torch.bfloat16)
+    Gd = torch.from_numpy(G).to(dev)
+    del X, W, G
+    b, d_in = Xd.shape
+    d_out = Wd.shape[1]
+    c = 128
+    prob = pk.Problem(Xd, Wd, off, c, seed=11)
+
+    def fwd():
+        col, row, blk = h.norms(prob)
+        pl = h.plan(prob, col, row, blk, sync=False)
+        C, D = h.sketch(prob, pl, out_dtype=torch.bfloat16)
+        Y, _ = h.sketch_gemm(C, D, pl)
+        return pl, C, D, Y
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    fw, bw = [], []
+    for it in range(warmup + steps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        pl, C, D, Y = fwd()
+        e1.record()
+        dX, dW = h.backward(prob, pl, C, D, Gd)
+        e2.record()
+        if it >= warmup:
+            fw.append((e0, e1))
+            bw.append((e1, e2))
+    L = int(pl.col_off[-1].item())
+    # dense backward in bf16 for context (transposed operands made contiguous)
+    G16 = Gd.to(torch.bfloat16)
+    Wt = Wd.t().contiguous()
+    Xt = Xd.t().contiguous()
+    dense = []
+    for it in range(warmup + steps):
+        e0, e1 = ev(), ev()
+        e0.record()
+        torch.mm(G16, Wt)
+        torch.mm(Xt, G16)
+        e1.record()
+        if it >= warmup:
+            dense.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = lambda ev_list: float(np.mean([s.elapsed_time(e) for s, e in ev_list]))
+    t_f, t_b, t_d = ms(fw), ms(bw), ms(dense)
+    bwd_flops = 2 * (2.0 * b * d_out * L)
+    return {
+        "workload": (f"linear layer X {b}x{d_in}, W {d_in}x{d_out} bf16, 512 blocks of 32, "
+                     f"c={c}, G {b}x{d_out} float32"),
+        "L": L,
+        "forward_ms": t_f,
+        "backward_ms": t_b,
+        "backward_TFLOPs": bwd_flops / t_b / 1e9,
+        "backward_frac_bf16_peak": bwd_flops / t_b / 1e9 / 2500.0,
+        "dense_backward_ms_torch_bf16": t_d,
+        "backward_speedup_vs_dense": t_d / t_b,
     }
 
 
@@ -303,6 +374,10 @@ def main():
         "roofline_norm_pass": norm_roof,
         "bf16": bf16,
     }
+    if not args.no_linear_layer:
+        del Md, Nd, MN, res, f32, b16
+        torch.cuda.empty_cache()
+        out["linear_layer"] = linear_layer_leg(h, pk, wl, torch, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(M, N, off, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -4,15 +4,19 @@
 //  * the exact product MN that the estimate is judged against, optionally
 //    with ||M^k N_k||_F^2 per block (the quantity (1.2) and (3.9) need).
 // Both operands are row-major with the inner dimension along A's rows and
-// down B's columns. Each workgroup (4 waves, 2 x 2) owns one output tile and
-// walks the inner dimension in 32-wide (float32) or 16-wide (float64) steps
-// through double-buffered LDS, prefetching the next step into registers
-// while the matrix cores work on the current one.
+// down B's columns (the bf16 kernel also takes either operand transposed,
+// for the backward products). Each workgroup (4 waves, 2 x 2) owns one
+// output tile and walks the inner dimension through double-buffered LDS,
+// prefetching the next step into registers while the matrix cores work on
+// the current one.
 //
-// float32 accumulation is two-level: the matrix-core accumulators are
-// folded into a second register set every 256 inner indices (and at block
-// boundaries), which keeps the rounding error near u (sqrt(256) +
-// sqrt(K/256)) instead of u sqrt(K).
+// float32 accumulation is two-level. The plain float32 product (sgemm)
+// folds its matrix-core accumulators into a float32 staging slot per lane in
+// global memory every 4096 inner indices, so the inner loop keeps a single
+// accumulator set; the product with per-block norms (gemm_f32) folds into a
+// second register set every 256 inner indices and at block boundaries. The
+// rounding error then grows like u (sqrt(F) + sqrt(K/F)) for fold period F
+// instead of u sqrt(K).
 //
 // The epilogue optionally stores the tile and adds float64 partial sums of
 // (C - Y)^2 and C^2 for the error ||MN - CD||_F; partials are reduced in a

@@ -1,0 +1,77 @@
+"""The differentiable linear layer at full size: X 8192 x 16384 and W 16384 x
+8192 in bf16 (X ~ N(0,1), W ~ N(0, 0.01^2)), 512 blocks of 32, c = 128,
+upstream gradient G 8192 x 8192 ~ N(0,1), through SampledMatmul.
+
+The oracle draws from its own norms; the gradients are checked on a seeded
+sample of columns of dX and rows of dW against float64 products of the same
+bf16-rounded operands (the scaled sketch and G), and every untouched column /
+row must be exactly zero."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import method as om
+
+torch = pytest.importorskip("torch")
+import paper_2105_04940_amd as pk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def bf16_round(x):
+    return torch.from_numpy(np.ascontiguousarray(x, np.float64)).to(torch.float32).to(
+        torch.bfloat16).to(torch.float64).numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def test_linear_layer_full_size():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    X, W, G = wl.linear_layer()
+    off = wl.equal_blocks(X.shape[1], 512)
+    Xd = torch.from_numpy(X).to(DEV).to(torch.bfloat16).requires_grad_(True)
+    Wd = torch.from_numpy(W).to(DEV).to(torch.bfloat16).requires_grad_(True)
+    Gd = torch.from_numpy(G).to(DEV)
+    Y = pk.SampledMatmul.apply(Xd, Wd, off, 128, 11, 0, "norm", None, None)
+    gpu_idx = Y.grad_fn.plan.idx.cpu().numpy()
+    Y.backward(Gd)
+    torch.cuda.synchronize()
+    Xh = Xd.detach().float().cpu().numpy().astype(np.float64)
+    Wh = Wd.detach().float().cpu().numpy().astype(np.float64)
+    design, col, row, st = om.plan(Xh, Wh, off, 128, prob="norm")
+    draws = om.sample(design, 11, 0)
+    assert draws.L == 4096
+    assert np.array_equal(gpu_idx, draws.atom)
+    dX = Xd.grad.float().cpu().numpy()
+    dW = Wd.grad.float().cpu().numpy()
+    hit = np.zeros(X.shape[1], bool)
+    for lo, w in zip(draws.lo, draws.width):
+        hit[lo:lo + w] = True
+    assert np.all(dX[:, ~hit] == 0) and np.all(dW[~hit] == 0)
+    Gq = bf16_round(G)
+    g = wl.rng(5)
+    cols = g.choice(np.nonzero(hit)[0], size=12, replace=False)
+    # the draws feeding each sampled inner index, with their sketch positions
+    ref_x, ref_w, got_x, got_w = [], [], [], []
+    for i in cols:
+        sx = np.zeros(G.shape[0])
+        sw = np.zeros(G.shape[1])
+        for t in range(len(draws.atom)):
+            lo, wd, c0 = int(draws.lo[t]), int(draws.width[t]), int(draws.col_off[t])
+            if lo <= i < lo + wd:
+                s = draws.scale[t]
+                d_row = bf16_round(s * Wh[i, :])        # row of D fed by i
+                c_col = bf16_round(s * Xh[:, i])        # column of C fed by i
+                sx += s * (Gq @ d_row)
+                sw += s * (c_col @ Gq)
+        ref_x.append(sx)
+        ref_w.append(sw)
+        got_x.append(dX[:, i])
+        got_w.append(dW[i, :])
+    # bf16 outputs: a few bf16 units of the float64 reference
+    assert rel(np.array(got_x), np.array(ref_x)) < 1e-2
+    assert rel(np.array(got_w), np.array(ref_w)) < 1e-2
