@@ -49,11 +49,20 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-linear-layer", action="store_true",
                     help="skip the bf16 linear-layer forward/backward leg")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 512-problem batched leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for "
                          "the HBM byte counters of a profiler run)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarize two rocprofv3 counter_collection.csv files (FETCH_SIZE, "
+                         "WRITE_SIZE) of a --calibration-copy run into profiles/hbm_traffic.json "
+                         "and exit (no GPU use)")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_CSV", "COMMAND"),
+                    help="print a markdown kernel-time table from a rocprofv3 kernel_trace.csv "
+                         "(float32 products split into exact and sketched) and exit (no GPU use)")
     return ap.parse_args()
 
 
@@ -80,37 +89,146 @@ def traffic_from_profile(kernel_key, src_hash, launches_flops):
     return ent.get("bytes_per_launch")
 
 
+CAL_BYTES = 256 << 20   # the --calibration-copy size
+
+
+def pmc_summary(fetch_csv, write_csv, command):
+    """HBM bytes per launch of the float32 products from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for
+    the plain 256 MiB copy. A float32 product launched right after the
+    block-Gram kernel is the exact MN; the others are sketched products."""
+    import csv
+
+    def rows(path, counter):
+        out = []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]),
+                                float(r["Counter_Value"]) * 1024.0))
+        out.sort()
+        return out
+
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rs = rows(path, counter)
+        copies = [v for _, name, grid, v in rs if "copyBuffer" in name and v > CAL_BYTES / 8]
+        if not copies:
+            raise SystemExit(f"{path}: no calibration copy found")
+        factor = CAL_BYTES / copies[0]
+        groups = {"sketch_gemm": [], "exact_gemm": []}
+        prev = ""
+        for _, name, grid, v in rs:
+            if "sgemm_kernel" in name:
+                groups["exact_gemm" if "block_gram" in prev else "sketch_gemm"].append(v * factor)
+            if "copyBuffer" not in name:
+                prev = name
+        res[counter] = (factor, {k: (float(np.mean(v)) if v else None, len(v))
+                                 for k, v in groups.items()})
+    gh = source_hash("gemm.hip", "gemm_common.h")
+    out = {"command": command, "calibration": {
+        "copy_bytes": CAL_BYTES, "fetch_factor": res["FETCH_SIZE"][0],
+        "write_factor": res["WRITE_SIZE"][0]}}
+    for key in ("sketch_gemm", "exact_gemm"):
+        f, nf = res["FETCH_SIZE"][1][key]
+        w, nw = res["WRITE_SIZE"][1][key]
+        if f is None or w is None:
+            continue
+        out[key] = {"source_hash": gh, "fetch_bytes": f, "write_bytes": w,
+                    "bytes_per_launch": f + w, "launches": [nf, nw]}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def _short(name):
+    name = name.replace("(anonymous namespace)::", "")
+    depth, out = 0, []
+    for ch in name:             # drop the argument list
+        if ch == "(" and depth == 0 and out:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).replace("void ", "")
+
+
+def trace_summary(trace_csv, command):
+    """Kernel-time table from a rocprofv3 kernel trace; a float32 product
+    launched right after the block-Gram kernel is the exact MN, the others
+    are sketched products."""
+    import csv
+    with open(trace_csv) as fh:
+        recs = sorted(csv.DictReader(fh), key=lambda r: int(r["Dispatch_Id"]))
+    stats = {}
+    prev = ""
+    for r in recs:
+        name = _short(r["Kernel_Name"])
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        key = name
+        if "sgemm_kernel" in name:
+            key = name + (" — exact MN" if "block_gram" in prev else " — sketched CD")
+        stats.setdefault(key, []).append(us)
+        if "copyBuffer" not in name:
+            prev = name
+    total = sum(sum(v) for v in stats.values())
+    print(f"Command (repository root, one MI355X):\n\n```\n{command}\n```\n")
+    print("| kernel | calls | avg (us) | min (us) | max (us) | total (ms) | % |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for k, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| `{k}` | {len(v)} | {np.mean(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
+              f"{sum(v) / 1e3:.2f} | {100 * sum(v) / total:.1f} |")
+
+
 def cpu_baseline(M, N, off, target_s):
-    """The float64 oracle, as it stands, on a bounded slab of the same
-    workload: the first r rows of M and columns of N with the full inner
-    dimension, rule norm, c = 256. r grows until the run takes about
-    ``target_s`` seconds."""
+    """The float64 oracle, as it stands, on the same step: norms, exact MN,
+    per-block ||M^k N_k||_F^2, then for each (rule, c) the design, draws,
+    sketch, CD and its error. If the whole step would take much longer than
+    ``target_s`` seconds, a slab of M's first r rows and N's first r columns
+    (full inner dimension) stands in, r sized from a timed probe. The value is
+    the step's algorithmic flops (as on the GPU) per second."""
     from oracle import method as om
     try:
         from threadpoolctl import threadpool_info
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    r = 256
-    while True:
-        Ms = M[:r, :]
-        Ns = N[:, :r]
-        t0 = time.perf_counter()
-        res = om.run(Ms, Ns, off, 256, seed=0, prob="norm")
-        dt = time.perf_counter() - t0
-        if dt >= target_s / 2 or r >= M.shape[0]:
-            break
-        r = min(M.shape[0], r * 2)
     n = M.shape[1]
-    flops = 2.0 * r * n * r + 2.0 * r * r * res.draws.L
+    r = M.shape[0]
+    # probe: one exact product on a 512-row slab predicts the step time
+    t0 = time.perf_counter()
+    om.exact_product(M[:512, :], N[:, :512])
+    probe = time.perf_counter() - t0
+    # the step costs about 8 such products (MN, the per-block products, the
+    # sketches); it scales with r^2
+    r = int(min(r, max(256, 128 * math.floor(512 * math.sqrt(target_s / (8 * probe)) / 128))))
+    Ms, Ns = M[:r, :], N[:, :r]
+    t0 = time.perf_counter()
+    col, row = om.column_row_sq(Ms, Ns)
+    MN = om.exact_product(Ms, Ns)
+    bp = om.block_product_sq(Ms, Ns, off)
+    flops = 2.0 * r * n * r
+    Ls = []
+    for rule in RULES:
+        for c in CS:
+            design, *_ = om.plan(Ms, Ns, off, c, prob=rule, col_row=(col, row),
+                                 blkprod_sq=bp if rule == "exact" else None)
+            draws = om.sample(design, 0, 0)
+            C, D = om.sketch(Ms, Ns, draws)
+            CD = om.sketch_product(C, D)
+            om.judge(MN, CD)
+            flops += 2.0 * r * r * draws.L
+            Ls.append(draws.L)
+    dt = time.perf_counter() - t0
     return {
         "value": flops / dt / 1e12,
         "unit": "TFLOP/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"oracle norm pass, design, draws, sketch, CD and exact MN in float64 on "
-                   f"M[:{r}, :] (x{n}) and N[:, :{r}], rule norm, c=256, L={res.draws.L}; "
-                   f"{dt:.1f} s"),
+        "sample": (f"one whole step of the oracle in float64 (norms, exact MN, per-block "
+                   f"norms, 9 x (design, draws, sketch, CD, error), L = {Ls}) on M[:{r}, :] "
+                   f"(x{n}) and N[:, :{r}]; {dt:.1f} s"),
         "seconds": dt,
     }
 
@@ -184,8 +302,77 @@ def linear_layer_leg(h, pk, wl, torch, steps, warmup):
     }
 
 
+def batched_leg(h, pk, wl, torch, steps, warmup):
+    """512 independent problems (m, p in [256, 2048], n in [4096, 32768],
+    blocks of 8..128, c in [16, 256], inputs written on the device) as one
+    batched pass: grouped norm pass, per-problem plans, grouped exact and
+    sketched products. Tuned once, then timed eagerly and as a graph."""
+    items, mats = wl.batched_device_inputs(512)
+    probs = [dict(M=M, N=N, off=it["off"], c=it["c"], prob="norm", seed=0, trial=t)
+             for t, (it, (M, N)) in enumerate(zip(items, mats))]
+    b = pk.Batch(h, probs)
+    tuning = b.tune(reps=2)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    eager_ms = timed(b.run)
+    b.capture()
+    graph_ms = timed(b.replay)
+    L = b.L.cpu().numpy()
+    e2 = b.err2_mn2.cpu().numpy()
+    rel = np.sqrt(e2[0::2] / e2[1::2])
+    m = np.array([it["m"] for it in items], np.float64)
+    n = np.array([it["n"] for it in items], np.float64)
+    p = np.array([it["p"] for it in items], np.float64)
+    exact_flops = float(np.sum(2 * m * n * p))
+    sketch_flops = float(np.sum(2 * m * p * L))
+    norm_bytes = float(np.sum((m * n + n * p) * 4))
+    best = [tuning["ms"][g][2 * tuning["cfg"][g] + tuning["lpt"][g]] for g in range(2)]
+    out = {
+        "workload": ("512 independent block-sampling problems: m, p uniform in [256, 2048], n uniform in "
+                     "[4096, 32768], uneven blocks of 8..128, c uniform in [16, 256], rule (1.4), float32 "
+                     "inputs from the counter-based stream written on the device; one pass = grouped norm "
+                     "pass + per-problem plans + grouped exact MN + grouped sketched CD (gather fused) + "
+                     "per-problem errors"),
+        "pass_ms_eager": eager_ms,
+        "pass_ms_graph": graph_ms,
+        "TFLOPs_graph": (exact_flops + sketch_flops) / graph_ms / 1e9,
+        "exact_TFLOPs": exact_flops / best[0] / 1e9,
+        "sketch_TFLOPs": sketch_flops / best[1] / 1e9,
+        "frac_fp32_peak_sketch": sketch_flops / best[1] / 1e9 / FP32_PEAK_TFLOPS,
+        "exact_flops": exact_flops, "sketch_flops": sketch_flops, "norm_bytes": norm_bytes,
+        "tuning": tuning,
+        "rel_err": {"mean": float(rel.mean()), "min": float(rel.min()), "max": float(rel.max())},
+        "L_total": int(L.sum()),
+    }
+    b.close()
+    del mats, probs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
+    if args.trace_summary:
+        trace_summary(*args.trace_summary)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1],
+                    "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o run -- python bench.py "
+                    "--steps 1 --warmup 0 --no-cpu-baseline --no-linear-layer --calibration-copy")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the path "
               "runs on one MI355X; multi-GPU sharding is a design note, not built.",
@@ -312,7 +499,7 @@ def main():
 
     # dominant kernel of the step by time: the sketched products (one kernel,
     # 9 launches) or the exact product with block norms (one launch)
-    gh = source_hash("gemm.hip", "common.h")
+    gh = source_hash("gemm.hip", "gemm_common.h")
     if sk_total_ms >= t_exact:
         dom = "sketch_gemm"
         achieved = sketch_tflops
@@ -378,6 +565,9 @@ def main():
         del Md, Nd, MN, res, f32, b16
         torch.cuda.empty_cache()
         out["linear_layer"] = linear_layer_leg(h, pk, wl, torch, args.steps, args.warmup)
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        out["batched"] = batched_leg(h, pk, wl, torch, max(2, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(M, N, off, args.cpu_seconds)
     print(json.dumps(out), flush=True)

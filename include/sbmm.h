@@ -234,6 +234,89 @@ sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* prob, const sbmm_pl
                           const void* G, int64_t ldg, void* dM, int64_t lddm, void* dN, int64_t lddn,
                           sbmm_stream stream);
 
+
+/* ------------------------------------------------------------------------ */
+/* Many independent problems in one pass                                     */
+/* ------------------------------------------------------------------------ */
+
+/* One problem of a batch: block mode, float32 inputs and products, rule
+ * UNIFORM or NORM (1.4). All of Alg. 1 / the block sampler runs for it: norm
+ * pass, design, draws (Philox key `seed`, counter word 2 `trial`), the
+ * sketched product CD (the drawn columns of M and rows of N are read in
+ * place, scaled as the gather would write them) and the exact MN it is
+ * judged against. m, n, p >= 1. M (m x n, ldm >= n) and N (n x p, ldn >= p)
+ * are device, row-major; CD and MN (m x p, ldcd / ldmn >= p) are device
+ * outputs. block_off is host (K + 1 offsets, read during sbmm_batch_create
+ * only). Every pointer is kept by the batch: the buffers must stay valid
+ * until sbmm_batch_destroy, and their contents may change between runs. */
+typedef struct {
+  int64_t m, n, p;
+  const float* M; int64_t ldm;
+  const float* N; int64_t ldn;
+  int32_t K; const int64_t* block_off;
+  int64_t c;
+  sbmm_prob prob;
+  uint64_t seed, trial;
+  float* CD; int64_t ldcd;
+  float* MN; int64_t ldmn;
+} sbmm_batch_item;
+
+/* Per-problem results of a batch run (device, caller-owned, kept by the
+ * batch like the items' buffers). err2_mn2 [2T] (required): ||MN_t - CD_t||_F^2
+ * and ||MN_t||_F^2 of problem t at 2t, 2t + 1. L [T] (optional): sketch width
+ * of each problem. idx [sum of c_t] (optional): the drawn blocks, problem t
+ * starting at sum_{u<t} c_u. */
+typedef struct {
+  double* err2_mn2;
+  int64_t* L;
+  int32_t* idx;
+} sbmm_batch_outputs;
+
+typedef struct sbmm_batch_s* sbmm_batch;
+
+/* Tile configuration of the two grouped products (exact MN, sketched CD)
+ * and whether their work lists start with the longest inner extents. cfg
+ * indexes the tile shapes 128x128, 64x128, 128x64, 64x64. The timings are
+ * filled by sbmm_batch_tune: ms[g][2 cfg + lpt] for product g (0 exact, 1
+ * sketch), -1 where not measured. */
+typedef struct {
+  int32_t cfg[2];
+  int32_t lpt[2];
+  float ms[2][8];
+} sbmm_batch_tuning;
+
+/* Validate T problems, allocate the batch's device memory (owned by the
+ * batch) and upload its argument tables; synchronizing. The starting
+ * configuration is 128x128 tiles with longest-first work lists. */
+sbmm_status sbmm_batch_create(sbmm_handle h, int32_t T, const sbmm_batch_item* items,
+                              const sbmm_batch_outputs* out, sbmm_batch* batch);
+sbmm_status sbmm_batch_destroy(sbmm_batch batch);
+
+/* Enqueue one pass over every problem: grouped norm pass, one-workgroup-per-
+ * problem plans, grouped exact product, grouped sketched product with the
+ * error in its epilogue, per-problem reduction. Asynchronous; makes no
+ * allocation, host synchronization or memset, so it can be captured. Device
+ * status (non-finite norms) is reported by sbmm_sync. */
+sbmm_status sbmm_batch_run(sbmm_handle h, sbmm_batch batch, sbmm_stream stream);
+
+/* Capture sbmm_batch_run into a HIP graph held by the batch (replacing any
+ * previous one), on a stream of the library's own; sbmm_batch_replay
+ * launches it on `stream`. A later sbmm_batch_tune / _set_tuning drops the
+ * graph. */
+sbmm_status sbmm_batch_capture(sbmm_handle h, sbmm_batch batch);
+sbmm_status sbmm_batch_replay(sbmm_handle h, sbmm_batch batch, sbmm_stream stream);
+
+/* Autotuner: run the pass once, then time each tile configuration and work
+ * order of the two grouped products on this batch (`reps` launches each,
+ * HIP events on `stream`), keep the fastest and report all timings in
+ * *out (optional). Synchronizing. Results do not depend on the
+ * configuration (same accumulation order per output element). */
+sbmm_status sbmm_batch_tune(sbmm_handle h, sbmm_batch batch, int32_t reps, sbmm_batch_tuning* out,
+                            sbmm_stream stream);
+/* Apply a stored configuration (e.g. from an earlier tuning of the same
+ * shapes); synchronizing. */
+sbmm_status sbmm_batch_set_tuning(sbmm_handle h, sbmm_batch batch, const sbmm_batch_tuning* t);
+
 #ifdef __cplusplus
 }
 #endif

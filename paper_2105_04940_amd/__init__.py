@@ -31,7 +31,10 @@ EXPORTS = (
     "sbmm_reserve", "sbmm_sync", "sbmm_query_sizes", "sbmm_norms",
     "sbmm_exact", "sbmm_plan", "sbmm_sketch", "sbmm_sketch_gemm",
     "sbmm_error", "sbmm_run", "sbmm_backward",
+    "sbmm_batch_create", "sbmm_batch_destroy", "sbmm_batch_run", "sbmm_batch_capture",
+    "sbmm_batch_replay", "sbmm_batch_tune", "sbmm_batch_set_tuning",
 )
+BATCH_TILES = ((128, 128), (64, 128), (128, 64), (64, 64))
 
 
 class SbmmError(RuntimeError):
@@ -68,6 +71,28 @@ class PlanOut_t(ctypes.Structure):
                 ("colscale", ctypes.c_void_p)]
 
 
+class BatchItem_t(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+        ("M", ctypes.c_void_p), ("ldm", ctypes.c_int64),
+        ("N", ctypes.c_void_p), ("ldn", ctypes.c_int64),
+        ("K", ctypes.c_int32), ("block_off", ctypes.c_void_p),
+        ("c", ctypes.c_int64), ("prob", ctypes.c_int),
+        ("seed", ctypes.c_uint64), ("trial", ctypes.c_uint64),
+        ("CD", ctypes.c_void_p), ("ldcd", ctypes.c_int64),
+        ("MN", ctypes.c_void_p), ("ldmn", ctypes.c_int64),
+    ]
+
+
+class BatchOutputs_t(ctypes.Structure):
+    _fields_ = [("err2_mn2", ctypes.c_void_p), ("L", ctypes.c_void_p), ("idx", ctypes.c_void_p)]
+
+
+class BatchTuning_t(ctypes.Structure):
+    _fields_ = [("cfg", ctypes.c_int32 * 2), ("lpt", ctypes.c_int32 * 2),
+                ("ms", (ctypes.c_float * 8) * 2)]
+
+
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with "
@@ -94,6 +119,13 @@ def load_library(path=LIB_PATH):
                           P(PlanOut_t), P(ctypes.c_double), P(ctypes.c_double), P(i64), vp]),
         "sbmm_backward": (st, [vp, P(Problem_t), P(PlanOut_t), i64, st, vp, i64, vp, i64, vp, i64,
                                vp, i64, vp, i64, vp]),
+        "sbmm_batch_create": (st, [vp, i32, P(BatchItem_t), P(BatchOutputs_t), P(vp)]),
+        "sbmm_batch_destroy": (st, [vp]),
+        "sbmm_batch_run": (st, [vp, vp, vp]),
+        "sbmm_batch_capture": (st, [vp, vp]),
+        "sbmm_batch_replay": (st, [vp, vp, vp]),
+        "sbmm_batch_tune": (st, [vp, vp, i32, P(BatchTuning_t), vp]),
+        "sbmm_batch_set_tuning": (st, [vp, vp, P(BatchTuning_t)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -375,6 +407,110 @@ class Handle:
         pl.L = L.value
         pl.sizes = sizes
         return dict(C=C, D=D, CD=CD, MN=MN, plan=pl, L=L.value, err=err.value, rel=rel.value)
+
+
+class Batch:
+    """Many independent block-mode problems run as one pass (sbmm_batch_*).
+
+    ``problems`` is a list of dicts with keys M, N (float32 device tensors,
+    row-major, any leading dimension), off (block offsets), c, and optional
+    prob ("norm" / "uniform"), seed, trial. The batch allocates CD and MN per
+    problem, the per-problem (err^2, ||MN||^2) pairs, the sketch widths and
+    the draws, and keeps every pointer: run(), capture() / replay() and tune()
+    take no arguments beyond the stream (torch's current one)."""
+
+    def __init__(self, handle, problems):
+        torch = _torch()
+        self.handle = handle
+        self._lib = handle._lib
+        self.problems = problems
+        T = len(problems)
+        dev = problems[0]["M"].device
+        self.CD, self.MN, self._offs = [], [], []
+        items = (BatchItem_t * T)()
+        for t, pr in enumerate(problems):
+            M, N = pr["M"], pr["N"]
+            if M.dtype != torch.float32 or N.dtype != torch.float32:
+                raise ValueError("batches take float32 M and N")
+            if M.stride(1) != 1 or N.stride(1) != 1:
+                raise ValueError("M and N must be row-major")
+            m, n = M.shape
+            p = N.shape[1]
+            off = np.ascontiguousarray(np.asarray(pr["off"], dtype=np.int64))
+            self._offs.append(off)
+            CD = torch.empty((m, p), dtype=torch.float32, device=dev)
+            MN = torch.empty((m, p), dtype=torch.float32, device=dev)
+            self.CD.append(CD)
+            self.MN.append(MN)
+            it = items[t]
+            it.m, it.n, it.p = m, n, p
+            it.M, it.ldm = M.data_ptr(), M.stride(0)
+            it.N, it.ldn = N.data_ptr(), N.stride(0)
+            it.K = len(off) - 1
+            it.block_off = off.ctypes.data
+            it.c = int(pr["c"])
+            it.prob = PROBS[pr.get("prob", "norm")]
+            it.seed = int(pr.get("seed", 0))
+            it.trial = int(pr.get("trial", 0))
+            it.CD, it.ldcd = CD.data_ptr(), p
+            it.MN, it.ldmn = MN.data_ptr(), p
+        self.cs = [int(pr["c"]) for pr in problems]
+        self.err2_mn2 = torch.zeros(2 * T, dtype=torch.float64, device=dev)
+        self.L = torch.zeros(T, dtype=torch.int64, device=dev)
+        self.idx = torch.zeros(sum(self.cs), dtype=torch.int32, device=dev)
+        outs = BatchOutputs_t(self.err2_mn2.data_ptr(), self.L.data_ptr(), self.idx.data_ptr())
+        b = ctypes.c_void_p()
+        handle._check(self._lib.sbmm_batch_create(handle.h, T, items, ctypes.byref(outs),
+                                                  ctypes.byref(b)))
+        self.b = b
+
+    def run(self):
+        self.handle._check(self._lib.sbmm_batch_run(self.handle.h, self.b, _stream()))
+
+    def capture(self):
+        self.handle._check(self._lib.sbmm_batch_capture(self.handle.h, self.b))
+
+    def replay(self):
+        self.handle._check(self._lib.sbmm_batch_replay(self.handle.h, self.b, _stream()))
+
+    def tune(self, reps=3):
+        """Time every tile configuration and work order of the two grouped
+        products and keep the fastest; returns the tuning record as a dict."""
+        t = BatchTuning_t()
+        self.handle._check(self._lib.sbmm_batch_tune(self.handle.h, self.b, reps, ctypes.byref(t),
+                                                     _stream()))
+        return self._tuning_dict(t)
+
+    def set_tuning(self, d):
+        t = BatchTuning_t()
+        for g in range(2):
+            t.cfg[g] = d["cfg"][g]
+            t.lpt[g] = d["lpt"][g]
+            for i in range(8):
+                t.ms[g][i] = d.get("ms", [[-1.0] * 8] * 2)[g][i]
+        self.handle._check(self._lib.sbmm_batch_set_tuning(self.handle.h, self.b, ctypes.byref(t)))
+
+    @staticmethod
+    def _tuning_dict(t):
+        return {"cfg": [t.cfg[0], t.cfg[1]], "lpt": [t.lpt[0], t.lpt[1]],
+                "tiles": [list(BATCH_TILES[t.cfg[0]]), list(BATCH_TILES[t.cfg[1]])],
+                "ms": [[t.ms[g][i] for i in range(8)] for g in range(2)]}
+
+    def draws(self, t):
+        """The drawn blocks of problem t (device tensor view)."""
+        a = sum(self.cs[:t])
+        return self.idx[a:a + self.cs[t]]
+
+    def close(self):
+        if getattr(self, "b", None):
+            self._lib.sbmm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _handles = {}

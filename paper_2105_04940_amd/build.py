@@ -70,5 +70,23 @@ def build(verbose=False, jobs=None):
     return LIB_PATH
 
 
+WORKLOAD_SRC = os.path.join(ROOT, "workloads", "gen.hip")
+WORKLOAD_LIB = os.path.join(ROOT, "workloads", "libsbmm_workload.so")
+
+
+def build_workload(verbose=False):
+    """The device-side input generator (workloads/gen.hip), a library of its
+    own: it generates test and benchmark inputs and is not part of libsbmm."""
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           WORKLOAD_SRC, "-o", WORKLOAD_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(WORKLOAD_LIB + ".tmp", WORKLOAD_LIB)
+    return WORKLOAD_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    print(build_workload(verbose="-v" in sys.argv))

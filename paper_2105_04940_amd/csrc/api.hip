@@ -8,34 +8,9 @@
 #include <new>
 #include <vector>
 
-#include "common.h"
-
-struct sbmm_handle_s {
-  int device = 0;
-  char err[512] = {0};
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  int32_t* status = nullptr;   // device status word
-};
+#include "api_internal.h"
 
 namespace {
-
-sbmm_status fail(sbmm_handle h, sbmm_status st, const char* fmt, ...) {
-  if (h) {
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(h->err, sizeof(h->err), fmt, ap);
-    va_end(ap);
-  }
-  return st;
-}
-
-#define HIP_TRY(h, expr)                                                        \
-  do {                                                                          \
-    hipError_t e_ = (expr);                                                     \
-    if (e_ != hipSuccess)                                                       \
-      return fail((h), SBMM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));     \
-  } while (0)
 
 // Bump allocator over the handle's workspace. A dry run (base == nullptr)
 // only measures.
@@ -67,17 +42,6 @@ sbmm_status ensure_ws(sbmm_handle h, size_t bytes) {
     return fail(h, SBMM_E_NOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
   }
   h->ws_bytes = want;
-  return SBMM_OK;
-}
-
-sbmm_status check_handle(sbmm_handle h) {
-  if (!h || !h->status) return SBMM_E_STATE;
-  h->err[0] = 0;
-  int cur = -1;
-  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
-    if (hipSetDevice(h->device) != hipSuccess)
-      return fail(h, SBMM_E_STATE, "cannot select device %d", h->device);
-  }
   return SBMM_OK;
 }
 
@@ -148,25 +112,6 @@ int eff_prob(const sbmm_problem* P) {
 bool needs_blkprod(const sbmm_problem* P) {
   return (P->mode == SBMM_MODE_BLOCK && P->prob == SBMM_P_EXACT) ||
          (P->mode == SBMM_MODE_STRATIFIED && P->alloc == SBMM_ALLOC_OPT);
-}
-
-sbmm_status status_from_device(sbmm_handle h, int32_t bits) {
-  if (bits & SBMM_DEV_NONFINITE) return fail(h, SBMM_E_NONFINITE, "non-finite input norm or weight");
-  if (bits & SBMM_DEV_BUDGET) return fail(h, SBMM_E_BUDGET, "c is below the number of strata with positive weight");
-  if (bits & SBMM_DEV_USER_CK) return fail(h, SBMM_E_ARG, "user draw counts must be positive exactly on strata with positive weight");
-  if (bits & SBMM_DEV_RNG) return fail(h, SBMM_E_HIP, "sampler exhausted its generator blocks");
-  return SBMM_OK;
-}
-
-sbmm_status read_status(sbmm_handle h, hipStream_t s) {
-  HIP_TRY(h, hipStreamSynchronize(s));
-  int32_t bits = 0;
-  HIP_TRY(h, hipMemcpy(&bits, h->status, sizeof(bits), hipMemcpyDeviceToHost));
-  if (bits) {
-    const int32_t zero = 0;
-    HIP_TRY(h, hipMemcpy(h->status, &zero, sizeof(zero), hipMemcpyHostToDevice));
-  }
-  return status_from_device(h, bits);
 }
 
 // --- internal steps (work on an arena that already has room) --------------
@@ -317,7 +262,7 @@ sbmm_status sbmm_create(sbmm_handle* out, int device) {
   if (hipMalloc(&h->status, sizeof(int32_t)) != hipSuccess) { delete h; return SBMM_E_NOMEM; }
   const int32_t zero = 0;
   if (hipMemcpy(h->status, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(h->status);
+    (void)hipFree(h->status);
     delete h;
     return SBMM_E_HIP;
   }
@@ -327,9 +272,10 @@ sbmm_status sbmm_create(sbmm_handle* out, int device) {
 
 sbmm_status sbmm_destroy(sbmm_handle h) {
   if (!h) return SBMM_E_STATE;
-  hipSetDevice(h->device);
-  if (h->ws) hipFree(h->ws);
-  if (h->status) hipFree(h->status);
+  // teardown is best effort: the handle is gone whatever these return
+  (void)hipSetDevice(h->device);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->status) (void)hipFree(h->status);
   h->status = nullptr;
   delete h;
   return SBMM_OK;

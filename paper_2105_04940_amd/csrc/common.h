@@ -84,6 +84,17 @@ struct NormLaunch {
 };
 size_t norms_partial_elems(sbmm_dtype dt, int64_t m, int64_t n, int* rsplit_out);
 hipError_t launch_norms(const NormLaunch& a, hipStream_t s);
+// Batched norm pass: per problem, build_batch_norm_args writes the argument
+// blocks (batch_norm_args_bytes / batch_stats_args_bytes bytes) of a
+// NormLaunch (m, n, p >= 1) and returns its workgroup count; the caller
+// uploads them with the prefix sums of workgroups (wg_off) and of blocks
+// (blk_off), count + 1 entries each.
+size_t batch_norm_args_bytes();
+size_t batch_stats_args_bytes();
+int64_t build_batch_norm_args(const NormLaunch& L, void* norm_out, void* stats_out);
+hipError_t launch_batch_norms(sbmm_dtype dt, const void* norm_args, const int64_t* wg_off, int64_t total_wg,
+                              const void* stats_args, const int64_t* blk_off, int64_t total_blk,
+                              int32_t count, hipStream_t s);
 
 struct PlanLaunch {
   int mode;                 // sbmm_mode
@@ -104,6 +115,8 @@ struct PlanLaunch {
   int32_t* status;
 };
 hipError_t launch_plan(const PlanLaunch& a, hipStream_t s);
+// block-mode plans of many problems, one workgroup each (plans in device memory)
+hipError_t launch_batch_plan(const PlanLaunch* plans_dev, int32_t count, hipStream_t s);
 
 struct GatherLaunch {
   sbmm_dtype in_dt, out_dt;
@@ -135,11 +148,41 @@ struct GemmLaunch {
   float* stage;
   // bf16 only: A given as K x M (a_trans) / B given as N x K (b_trans)
   bool a_trans, b_trans;
+  // grouped float32 only: read the sketch in place from A = M, B = N
+  const int32_t* colmap; const double* colscale;
 };
 // bytes of the float32 staging buffer launch_gemm needs
 size_t gemm_stage_bytes(sbmm_dtype dt, int64_t m, int64_t p);
 int64_t gemm_tiles(sbmm_dtype dt, int64_t m, int64_t p, bool blocknorm);
 hipError_t launch_gemm(const GemmLaunch& a, hipStream_t s);
+// Many float32 products in one launch, one workgroup per (problem, tile)
+// item (see gemm.hip). The per problem argument blocks (grouped_gemm_args_bytes
+// each, built on the host by build_grouped_gemm_args for tile configuration
+// cfg) and the work list live in device memory; `stage` holds items * bm * bn
+// floats (one staging slot per item).
+struct GroupedLaunch {
+  const void* probs;
+  const int32_t* item_prob; const int32_t* item_tile; const int64_t* part_base;
+  int64_t items, nparts;
+  float* stage;
+  int cfg;
+  bool gather;
+};
+int grouped_cfg_count();
+void grouped_cfg_shape(int cfg, int64_t* bm, int64_t* bn, int* wg_per_cu);
+size_t grouped_gemm_args_bytes();
+void build_grouped_gemm_args(const GemmLaunch& L, int cfg, void* out);
+hipError_t launch_grouped_gemm(const GroupedLaunch& L, hipStream_t s);
+// Per problem t: out[2t] = its sketched tiles' error partials summed,
+// out[2t+1] = its exact tiles' squared-norm partials summed (fixed order);
+// L[t] = *col_end[t] when L is not null.
+hipError_t launch_grouped_reduce(const double* sk_part, int64_t sk_nparts, const int64_t* sk_base,
+                                 const double* ex_part, int64_t ex_nparts, const int64_t* ex_base,
+                                 const int64_t* const* col_end, int32_t count, double* out, int64_t* L,
+                                 hipStream_t s);
+// bf16 products (launch_gemm forwards SBMM_BF16 here) and their tile shape
+hipError_t launch_hgemm(const GemmLaunch& a, hipStream_t s);
+void hgemm_tile_shape(int64_t* bm, int64_t* bn);
 
 // ||M^k N_k||_F^2 per block through the Gram matrices (float32 inputs,
 // blocks at most block_gram_max_width() wide), one workgroup per block.

@@ -23,71 +23,13 @@
 // fixed order by a second kernel, so every result is bitwise reproducible.
 #include "common.h"
 
+#include <cstring>
+
+#include "gemm_common.h"
+
 namespace {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-constexpr int kThreads = 256;
-
-struct GemmArgs {
-  const void* A; int64_t lda;
-  const void* B; int64_t ldb;
-  int64_t m, p;
-  int64_t K_host; const int64_t* K_dev;
-  void* C; int64_t ldc;
-  const void* Y; int64_t ldy;
-  double* tile_part;            // [2][tiles]
-  int32_t nblk; const int64_t* off; double* blk_part;   // [nblk][tiles*4]
-  int64_t tiles_m, tiles_n;
-  int vec_a, vec_b;
-  float* stage; int64_t ldstage;   // float32 partial sums of long inner extents
-};
-
-__device__ __forceinline__ int64_t inner_extent(const GemmArgs& g) {
-  if (g.K_dev) {
-    const int64_t L = *g.K_dev;
-    return (L + SBMM_SKETCH_PAD - 1) / SBMM_SKETCH_PAD * SBMM_SKETCH_PAD;
-  }
-  return g.K_host;
-}
-
-// Map a workgroup to its output tile. Workgroups are dealt round-robin to
-// the 8 XCDs (each with its own L2), so the launch index is first permuted
-// XCD-major (XCD x gets a contiguous range of logical tiles), and logical
-// tiles are ordered in groups of 8 tile rows walked column by column: the
-// workgroups resident on one XCD at a time then share a few A and B panels.
-constexpr int64_t kXcds = 8, kGroupM = 8;
-__device__ __forceinline__ void tile_coords(const GemmArgs& g, int64_t& tm, int64_t& tn) {
-  const int64_t bid = blockIdx.x;
-  const int64_t tiles = g.tiles_m * g.tiles_n;
-  const int64_t per = tiles / kXcds;
-  const int64_t lg = bid < per * kXcds ? (bid % kXcds) * per + bid / kXcds : bid;
-  const int64_t span = kGroupM * g.tiles_n;
-  const int64_t first = (lg / span) * kGroupM;
-  const int64_t gm = min(g.tiles_m - first, kGroupM);
-  const int64_t r = lg % span;
-  tm = first + r % gm;
-  tn = r / gm;
-}
-
-// Reduce the epilogue partial sums of the workgroup in a fixed order.
-__device__ void write_tile_partials(const GemmArgs& g, double e2, double n2, double* sm) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  e2 = warp_sum_f64(e2);
-  n2 = warp_sum_f64(n2);
-  if (lane == 0) { sm[wave] = e2; sm[4 + wave] = n2; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t tiles = g.tiles_m * g.tiles_n;
-    const int64_t t = blockIdx.x;
-    g.tile_part[t] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
-    g.tile_part[tiles + t] = ((sm[4] + sm[5]) + sm[6]) + sm[7];
-  }
-}
+using namespace gemm_detail;
 
 // ============================================================================
 // float32: v_mfma_f32_32x32x2_f32. A wave owns (32 WMB) x (32 WNB); lane
@@ -355,9 +297,10 @@ struct SgemmTile {
   double red[8];
 };
 
-template <int WMB, int WNB, int BK, bool EDGE>
+template <int WMB, int WNB, int BK, bool EDGE, bool GATHER = false>
 __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB, BK>& sh,
-                                           int64_t m0, int64_t n0, int64_t K) {
+                                           int64_t m0, int64_t n0, int64_t K, int64_t slot,
+                                           int64_t part, int64_t nparts) {
   using T = SgemmTile<WMB, WNB, BK>;
   constexpr int BN = T::BN, KC = T::KC, NA = T::NA, NB = T::NB, NACC = T::NACC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -409,13 +352,60 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
         rb[q][e] = (krow < K && col + e < g.p) ? B[krow * g.ldb + col + e] : 0.0f;
     }
   };
-  auto store_tile = [&](int buf) {
+  // gathered loads (sketch read in place): a lane keeps one inner index of A
+  // (16 lanes cover 16 consecutive sketch columns of a row) and reads the
+  // drawn column of M; B rows are rows colmap[k] of N. Each value is
+  // (float)(x * scale) with the product in float64, as the gather writes it.
+  constexpr int GR = kThreads / BK;                 // A rows per pass
+  auto load_gather = [&](int64_t kt) {
+    const int64_t k0 = kt * BK;
+    {
+      const int kk = tid % BK;
+      const int64_t k = k0 + kk;
+      const int32_t j = (!EDGE || k < K) ? g.colmap[k] : -1;
+      const double sc = j >= 0 ? g.colscale[k] : 0.0;
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
+      for (int q = 0; q < 4 * NA; ++q) {
+        const int64_t row = m0 + tid / BK + GR * q;
+        float v = 0.0f;
+        if (j >= 0 && (!EDGE || row < g.m)) v = (float)((double)A[row * g.lda + j] * sc);
+        ra[q / 4][q % 4] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
       const int f = tid + kThreads * q;
-      const int r = f / KC, c4 = f % KC;
+      const int kr = f / (BN / 4), c4 = f % (BN / 4);
+      const int64_t krow = k0 + kr, col = n0 + 4 * c4;
+      const int32_t j = (!EDGE || krow < K) ? g.colmap[krow] : -1;
+      if (j < 0) {
+        rb[q] = f32x4{};
+        continue;
+      }
+      const double sc = g.colscale[krow];
+      const float* src = B + (int64_t)j * g.ldb + col;
+      if (!EDGE) {
+        const f32x4 x = *reinterpret_cast<const f32x4*>(src);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) sh.As[buf][4 * c4 + e][r] = ra[q][e];
+        for (int e = 0; e < 4; ++e) rb[q][e] = (float)((double)x[e] * sc);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[q][e] = col + e < g.p ? (float)((double)src[e] * sc) : 0.0f;
+      }
+    }
+  };
+  auto store_tile = [&](int buf) {
+    if constexpr (GATHER) {
+#pragma unroll
+      for (int q = 0; q < 4 * NA; ++q) sh.As[buf][tid % BK][tid / BK + GR * q] = ra[q / 4][q % 4];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int f = tid + kThreads * q;
+        const int r = f / KC, c4 = f % KC;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sh.As[buf][4 * c4 + e][r] = ra[q][e];
+      }
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -432,16 +422,20 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
       if constexpr (WMB == 4) {
         const f32x4 t = *reinterpret_cast<const f32x4*>(&sh.As[buf][k][wave_m0 + 4 * lr]);
         av[0] = t[0]; av[1] = t[1]; av[2] = t[2]; av[3] = t[3];
-      } else {
+      } else if constexpr (WMB == 2) {
         const f32x2 t = *reinterpret_cast<const f32x2*>(&sh.As[buf][k][wave_m0 + 2 * lr]);
         av[0] = t[0]; av[1] = t[1];
+      } else {
+        av[0] = sh.As[buf][k][wave_m0 + lr];
       }
       if constexpr (WNB == 2) {
         const f32x2 t = *reinterpret_cast<const f32x2*>(&sh.Bs[buf][k][wave_n0 + 2 * lr]);
         bv[0] = t[0]; bv[1] = t[1];
-      } else {
+      } else if constexpr (WNB == 4) {
         const f32x4 t = *reinterpret_cast<const f32x4*>(&sh.Bs[buf][k][wave_n0 + 4 * lr]);
         bv[0] = t[0]; bv[1] = t[1]; bv[2] = t[2]; bv[3] = t[3];
+      } else {
+        bv[0] = sh.Bs[buf][k][wave_n0 + lr];
       }
 #pragma unroll
       for (int b = 0; b < WMB; ++b)
@@ -451,7 +445,7 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
     }
   };
   // staging slot in lane-major order: [workgroup][wave][accumulator][lane]
-  float* const stg = g.stage + ((int64_t)blockIdx.x * 4 + wave) * (NACC * 64) + lane;
+  float* const stg = g.stage + (slot * 4 + wave) * (NACC * 64) + lane;
   int folds = 0;
   auto fold = [&]() {
 #pragma unroll
@@ -471,8 +465,13 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
 
   // main loop: whole steps (interior) or every step (edge tiles)
   const int64_t nkt = EDGE ? (K + BK - 1) / BK : K / BK;
+  auto load = [&](int64_t kt) {
+    if constexpr (GATHER) load_gather(kt);
+    else if constexpr (EDGE) load_pred(kt);
+    else load_fast(kt);
+  };
   if (nkt > 0) {
-    if constexpr (EDGE) load_pred(0); else load_fast(0);
+    load(0);
     store_tile(0);
   }
   __syncthreads();
@@ -483,9 +482,7 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
     const int64_t kend = min(nkt, kt + (int64_t)T::FOLD_TILES);
     for (; kt < kend; ++kt) {
       const int cur = (int)(kt & 1);
-      if (kt + 1 < nkt) {
-        if constexpr (EDGE) load_pred(kt + 1); else load_fast(kt + 1);
-      }
+      if (kt + 1 < nkt) load(kt + 1);
       compute(cur);
       if (kt + 1 < nkt) store_tile(cur ^ 1);
       __syncthreads();
@@ -493,7 +490,7 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
     if (kt >= nkt || kt * BK >= K) break;
     fold();
   }
-  if constexpr (!EDGE) {
+  if constexpr (!EDGE && !GATHER) {
     if (nkt * BK < K) {   // inner-dimension tail of an interior tile
       load_pred(nkt);
       store_tile(0);
@@ -527,7 +524,7 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
       }
       if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
     }
-  if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
+  if (g.tile_part) write_tile_partials_at(g, e2, n2, sh.red, part, nparts);
 }
 
 template <int WMB, int WNB, int BK, int WG_PER_CU>
@@ -539,229 +536,79 @@ __global__ __launch_bounds__(kThreads, WG_PER_CU) void sgemm_kernel(GemmArgs g) 
   const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
   const int64_t K = inner_extent(g);
   const bool interior = g.vec_a && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p;
+  const int64_t tiles = g.tiles_m * g.tiles_n;
   if (interior)
-    sgemm_body<WMB, WNB, BK, false>(g, sh, m0, n0, K);
+    sgemm_body<WMB, WNB, BK, false>(g, sh, m0, n0, K, blockIdx.x, blockIdx.x, tiles);
   else
-    sgemm_body<WMB, WNB, BK, true>(g, sh, m0, n0, K);
+    sgemm_body<WMB, WNB, BK, true>(g, sh, m0, n0, K, blockIdx.x, blockIdx.x, tiles);
 }
 
 // ============================================================================
-// bf16 operands, float32 accumulation: v_mfma_f32_32x32x16_bf16. Lane
-// (r = lane % 32, h = lane / 32) holds 8 consecutive inner indices 8h..8h+7
-// of A row r and B column r, so both operands sit in LDS with the inner index
-// contiguous: the C tile as loaded ([row][k]) and the D tile transposed
-// ([col][k], two inner indices per 32-bit LDS write). Rows and columns are
-// interleaved across a wave's 32-blocks as in the float32 kernel, and the
-// output layout is the same. bf16 products are exact in float32 and the
-// operand rounding (2^-9) dominates the error, so there is no fold.
+// Many independent float32 products in one launch. The host lists the work
+// items (problem, tile) in the order they should start (longest inner extent
+// first) and workgroup i takes item i; the hardware dispatches workgroups in
+// index order as compute units free up, so short products fill in behind
+// long ones. A workgroup runs exactly one tile: there is no loop over items
+// around the barriers of the tile body (with thread-0-only blocks on such a
+// loop's back edge, the compiler can split the loop so that the other lanes
+// re-enter the next item before thread 0 has fetched it). The float32
+// staging slot and the error partials are indexed by the item.
 // ============================================================================
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-template <int WMB, int WNB, int BK>
-struct HgemmTile {
-  static constexpr int BM = 64 * WMB, BN = 64 * WNB;
-  static constexpr int SA = BK + 8, SB = BK + 8;        // bf16 elements per LDS row
-  static constexpr int KC = BK / 8;                     // 16-byte chunks per A row
-  static constexpr int NA = BM * KC / kThreads;         // 16-byte loads of A per thread
-  static constexpr int NBP = (BK / 2) * (BN / 8) / kThreads;  // row-pair chunks of B per thread
-  static constexpr int NAP = (BK / 2) * (BM / 8) / kThreads;  // row-pair chunks of A (transposed A)
-  static constexpr int NBK = BN * KC / kThreads;               // 16-byte runs of B (transposed B)
-  uint16_t As[2][BM][SA];
-  uint16_t Bs[2][BN][SB];
-  double red[8];
+struct GroupedArgs {
+  const GemmArgs* probs;       // per problem
+  const int32_t* item_prob;    // per work item: problem
+  const int32_t* item_tile;    // per work item: tile of the problem (row-major over its tiles)
+  const int64_t* part_base;    // per problem: first partial slot
+  int64_t items;
+  int64_t nparts;
 };
 
-// AT: A is given as K x M (A[i][k] at A + k lda + i); BT: B is given as
-// N x K (B[k][j] at B + j ldb + k). The LDS layouts stay [row][k] / [col][k].
-template <int WMB, int WNB, int BK, bool EDGE, bool AT, bool BT>
-__device__ __forceinline__ void hgemm_body(const GemmArgs& g, HgemmTile<WMB, WNB, BK>& sh,
-                                           int64_t m0, int64_t n0, int64_t K) {
-  using T = HgemmTile<WMB, WNB, BK>;
-  constexpr int BN = T::BN, KC = T::KC, NA = T::NA, NBP = T::NBP;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 31, lh = lane >> 5;
-  const int wave_m0 = (wave & 1) * 32 * WMB;
-  const int wave_n0 = (wave >> 1) * 32 * WNB;
-  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(g.A);
-  const uint16_t* __restrict__ B = reinterpret_cast<const uint16_t*>(g.B);
-
-  f32x16 acc[WMB][WNB];
-#pragma unroll
-  for (int b = 0; b < WMB; ++b)
-#pragma unroll
-    for (int c = 0; c < WNB; ++c) acc[b][c] = f32x16{};
-
-  // Each operand tile is gathered either as 16-byte runs along k (stored
-  // directly) or as pairs of k-rows of 8 consecutive rows/columns (stored
-  // transposed, two k per 32-bit write).
-  constexpr int RA = NA > T::NAP ? NA : T::NAP;       // registers for either A layout
-  constexpr int RB = NBP > T::NBK ? NBP : T::NBK;     // registers for either B layout
-  uint4 ra0[RA], ra1[RA], rb0[RB], rb1[RB];
-  auto pack8 = [](const uint16_t* t) {
-    return make_uint4(t[0] | (uint32_t)t[1] << 16, t[2] | (uint32_t)t[3] << 16,
-                      t[4] | (uint32_t)t[5] << 16, t[6] | (uint32_t)t[7] << 16);
-  };
-  // 16-byte run along k of row r (k contiguous, leading dimension ld)
-  auto run_k = [&](const uint16_t* X, int64_t ld, int64_t r, int64_t rmax, int64_t k, bool vec) {
-    if (!EDGE || (r < rmax && k + 8 <= K && vec)) return *reinterpret_cast<const uint4*>(X + r * ld + k);
-    uint16_t t[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) t[e] = (r < rmax && k + e < K) ? X[r * ld + k + e] : 0;
-    return pack8(t);
-  };
-  // 8 consecutive rows/columns c..c+7 of k-row kr (index contiguous)
-  auto run_i = [&](const uint16_t* X, int64_t ld, int64_t kr, int64_t c, int64_t cmax, bool vec) {
-    if (!EDGE || (kr < K && c + 8 <= cmax && vec)) return *reinterpret_cast<const uint4*>(X + kr * ld + c);
-    uint16_t t[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) t[e] = (kr < K && c + e < cmax) ? X[kr * ld + c + e] : 0;
-    return pack8(t);
-  };
-  auto load = [&](int64_t kt) {
-    const int64_t k0 = kt * BK;
-    if constexpr (!AT) {
-#pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        const int f = tid + kThreads * q;
-        ra0[q] = run_k(A, g.lda, m0 + f / KC, g.m, k0 + 8 * (f % KC), g.vec_a);
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < T::NAP; ++q) {
-        const int f = tid + kThreads * q;
-        const int pr = f / (T::BM / 8), c8 = f % (T::BM / 8);
-        ra0[q] = run_i(A, g.lda, k0 + 2 * pr, m0 + 8 * c8, g.m, g.vec_a);
-        ra1[q] = run_i(A, g.lda, k0 + 2 * pr + 1, m0 + 8 * c8, g.m, g.vec_a);
-      }
-    }
-    if constexpr (BT) {
-#pragma unroll
-      for (int q = 0; q < T::NBK; ++q) {
-        const int f = tid + kThreads * q;
-        rb0[q] = run_k(B, g.ldb, n0 + f / KC, g.p, k0 + 8 * (f % KC), g.vec_b);
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NBP; ++q) {
-        const int f = tid + kThreads * q;
-        const int pr = f / (BN / 8), c8 = f % (BN / 8);
-        rb0[q] = run_i(B, g.ldb, k0 + 2 * pr, n0 + 8 * c8, g.p, g.vec_b);
-        rb1[q] = run_i(B, g.ldb, k0 + 2 * pr + 1, n0 + 8 * c8, g.p, g.vec_b);
-      }
-    }
-  };
-  // write 8 rows/columns x 2 k of a transposed pair into an LDS [row][k] tile
-  auto store_pair = [](uint16_t (*X)[T::SA], int c0, int k, const uint4& a0, const uint4& a1) {
-    const uint32_t w0[4] = {a0.x, a0.y, a0.z, a0.w};
-    const uint32_t w1[4] = {a1.x, a1.y, a1.z, a1.w};
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint32_t lo = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-      const uint32_t hi = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-      *reinterpret_cast<uint32_t*>(&X[c0 + e][k]) = lo | (hi << 16);
-    }
-  };
-  auto store = [&](int buf) {
-    if constexpr (!AT) {
-#pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        const int f = tid + kThreads * q;
-        *reinterpret_cast<uint4*>(&sh.As[buf][f / KC][8 * (f % KC)]) = ra0[q];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < T::NAP; ++q) {
-        const int f = tid + kThreads * q;
-        store_pair(sh.As[buf], 8 * (f % (T::BM / 8)), 2 * (f / (T::BM / 8)), ra0[q], ra1[q]);
-      }
-    }
-    if constexpr (BT) {
-#pragma unroll
-      for (int q = 0; q < T::NBK; ++q) {
-        const int f = tid + kThreads * q;
-        *reinterpret_cast<uint4*>(&sh.Bs[buf][f / KC][8 * (f % KC)]) = rb0[q];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NBP; ++q) {
-        const int f = tid + kThreads * q;
-        store_pair(sh.Bs[buf], 8 * (f % (BN / 8)), 2 * (f / (BN / 8)), rb0[q], rb1[q]);
-      }
-    }
-  };
-  auto compute = [&](int buf) {
-#pragma unroll
-    for (int s = 0; s < BK / 16; ++s) {
-      bf16x8 av[WMB], bv[WNB];
-#pragma unroll
-      for (int b = 0; b < WMB; ++b)
-        av[b] = *reinterpret_cast<const bf16x8*>(&sh.As[buf][wave_m0 + WMB * lr + b][16 * s + 8 * lh]);
-#pragma unroll
-      for (int c = 0; c < WNB; ++c)
-        bv[c] = *reinterpret_cast<const bf16x8*>(&sh.Bs[buf][wave_n0 + WNB * lr + c][16 * s + 8 * lh]);
-#pragma unroll
-      for (int b = 0; b < WMB; ++b)
-#pragma unroll
-        for (int c = 0; c < WNB; ++c)
-          acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[b], bv[c], acc[b][c], 0, 0, 0);
-    }
-  };
-
-  // interior tiles of products whose inner extent is a multiple of BK run
-  // unpredicated; anything else takes the predicated loads
-  const int64_t nkt = (K + BK - 1) / BK;
-  if (nkt > 0) {
-    load(0);
-    store(0);
-  }
-  __syncthreads();
-  for (int64_t kt = 0; kt < nkt; ++kt) {
-    const int cur = (int)(kt & 1);
-    if (kt + 1 < nkt) load(kt + 1);
-    compute(cur);
-    if (kt + 1 < nkt) store(cur ^ 1);
-    __syncthreads();
-  }
-  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
-  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
-  double e2 = 0.0, n2 = 0.0;
-#pragma unroll
-  for (int b = 0; b < WMB; ++b)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = m0 + wave_m0 + WMB * (8 * (v >> 2) + 4 * lh + (v & 3)) + b;
-      if (EDGE && row >= g.m) continue;
-#pragma unroll
-      for (int c = 0; c < WNB; ++c) {
-        const int64_t col = n0 + wave_n0 + WNB * lr + c;
-        if (EDGE && col >= g.p) continue;
-        const float val = acc[b][c][v];
-        if (Cout) Cout[row * g.ldc + col] = val;
-        const double dv = (double)val;
-        if (Y) {
-          const double d = dv - (double)Y[row * g.ldy + col];
-          e2 = fma(d, d, e2);
-        }
-        n2 = fma(dv, dv, n2);
-      }
-      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
-  if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
+template <int WMB, int WNB, int BK, int WG_PER_CU, bool GATHER>
+__global__ __launch_bounds__(kThreads, WG_PER_CU) void sgemm_grouped_kernel(GroupedArgs ga) {
+  using T = SgemmTile<WMB, WNB, BK>;
+  __shared__ T sh;
+  const int64_t it = blockIdx.x;
+  const int32_t pi = ga.item_prob[it];
+  const int64_t local = ga.item_tile[it];
+  const GemmArgs& g = ga.probs[pi];
+  const int64_t m0 = (local / g.tiles_n) * T::BM, n0 = (local % g.tiles_n) * T::BN;
+  const int64_t K = inner_extent(g);
+  const bool interior = (GATHER || g.vec_a) && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p;
+  const int64_t part = ga.part_base[pi] + local;
+  if (interior)
+    sgemm_body<WMB, WNB, BK, false, GATHER>(g, sh, m0, n0, K, it, part, ga.nparts);
+  else
+    sgemm_body<WMB, WNB, BK, true, GATHER>(g, sh, m0, n0, K, it, part, ga.nparts);
 }
 
-template <int WMB, int WNB, int BK, int WG_PER_CU, bool AT = false, bool BT = false>
-__global__ __launch_bounds__(kThreads, WG_PER_CU) void hgemm_kernel(GemmArgs g) {
-  using T = HgemmTile<WMB, WNB, BK>;
-  __shared__ T sh;
-  int64_t tm, tn;
-  tile_coords(g, tm, tn);
-  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
-  const int64_t K = inner_extent(g);
-  const bool interior = g.vec_a && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p && K % BK == 0;
-  if (interior)
-    hgemm_body<WMB, WNB, BK, false, AT, BT>(g, sh, m0, n0, K);
-  else
-    hgemm_body<WMB, WNB, BK, true, AT, BT>(g, sh, m0, n0, K);
+// Per problem t: out[2t] = sum of the error partials of its sketched tiles,
+// out[2t+1] = sum of the squared-norm partials of its exact tiles (one
+// workgroup per problem, fixed order); L[t] = *col_end[t].
+__global__ __launch_bounds__(kThreads) void grouped_reduce_kernel(
+    const double* __restrict__ sk_part, int64_t sk_nparts, const int64_t* __restrict__ sk_base,
+    const double* __restrict__ ex_part, int64_t ex_nparts, const int64_t* __restrict__ ex_base,
+    const int64_t* const* __restrict__ col_end, double* __restrict__ out, int64_t* __restrict__ L) {
+  __shared__ double sm[2][kThreads];
+  const int t = blockIdx.x;
+  double e2 = 0.0, n2 = 0.0;
+  for (int64_t i = sk_base[t] + threadIdx.x; i < sk_base[t + 1]; i += kThreads) e2 += sk_part[i];
+  for (int64_t i = ex_base[t] + threadIdx.x; i < ex_base[t + 1]; i += kThreads) n2 += ex_part[ex_nparts + i];
+  sm[0][threadIdx.x] = e2;
+  sm[1][threadIdx.x] = n2;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + o];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * t] = sm[0][0];
+    out[2 * t + 1] = sm[1][0];
+    if (L) L[t] = *col_end[t];
+  }
+  (void)sk_nparts;
 }
 
 // ============================================================================
@@ -1011,11 +858,10 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
 constexpr int F32_WMB = 2, F32_WNB = 2, F32_BK = 16, F32_WGS = 2;   // 128 x 128, 2 per CU
 constexpr int F32B_WMB = 2, F32B_WNB = 2;    // 128 x 128 with block norms
 constexpr int F64_WMB = 2, F64_WNB = 2;      // 64 x 64
-constexpr int BF16_WMB = 2, BF16_WNB = 2, BF16_BK = 64, BF16_WGS = 2;   // 128 x 128
 
 void tile_shape(sbmm_dtype dt, bool blocknorm, int64_t* bm, int64_t* bn) {
   if (dt == SBMM_F64) { *bm = 32 * F64_WMB; *bn = 32 * F64_WNB; return; }
-  if (dt == SBMM_BF16) { *bm = 64 * BF16_WMB; *bn = 64 * BF16_WNB; return; }
+  if (dt == SBMM_BF16) { hgemm_tile_shape(bm, bn); return; }
   if (blocknorm) { *bm = 64 * F32B_WMB; *bn = 64 * F32B_WNB; return; }
   *bm = 64 * F32_WMB; *bn = 64 * F32_WNB;
 }
@@ -1029,23 +875,11 @@ int64_t gemm_tiles(sbmm_dtype dt, int64_t m, int64_t p, bool blocknorm) {
 }
 
 hipError_t launch_gemm(const GemmLaunch& L, hipStream_t s) {
+  if (L.dt == SBMM_BF16) return launch_hgemm(L, s);
   const bool blocknorm = L.blk_part != nullptr;
   int64_t bm, bn;
   tile_shape(L.dt, blocknorm, &bm, &bn);
-  GemmArgs g{};
-  g.A = L.A; g.lda = L.lda; g.B = L.B; g.ldb = L.ldb;
-  g.m = L.m; g.p = L.p; g.K_host = L.K_host; g.K_dev = L.K_dev;
-  g.C = L.Cout; g.ldc = L.ldc; g.Y = L.Y; g.ldy = L.ldy;
-  g.tile_part = L.tile_part;
-  g.nblk = L.K_blocks; g.off = L.off_dev; g.blk_part = L.blk_part;
-  g.tiles_m = ceil_div(L.m, bm);
-  g.tiles_n = ceil_div(L.p, bn);
-  g.stage = L.stage;
-  g.ldstage = 0;
-  const size_t es = dtype_size(L.dt);
-  const size_t vb = 16;
-  g.vec_a = ((uintptr_t)L.A % vb == 0) && ((L.lda * (int64_t)es) % (int64_t)vb == 0);
-  g.vec_b = ((uintptr_t)L.B % vb == 0) && ((L.ldb * (int64_t)es) % (int64_t)vb == 0);
+  const GemmArgs g = make_gemm_args(L, bm, bn);
   const int64_t tiles = g.tiles_m * g.tiles_n;
   if (tiles == 0) return hipSuccess;
   // the float32 product folds partial sums into its staging slots once the
@@ -1058,18 +892,67 @@ hipError_t launch_gemm(const GemmLaunch& L, hipStream_t s) {
   } else if (L.dt == SBMM_F32) {
     if (blocknorm) hipLaunchKernelGGL((gemm_f32_kernel<F32B_WMB, F32B_WNB, true>), grid, block, 0, s, g);
     else hipLaunchKernelGGL((sgemm_kernel<F32_WMB, F32_WNB, F32_BK, F32_WGS>), grid, block, 0, s, g);
-  } else if (L.dt == SBMM_BF16) {
-    if (L.a_trans && L.b_trans)
-      hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, true, true>), grid, block, 0, s, g);
-    else if (L.a_trans)
-      hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, true, false>), grid, block, 0, s, g);
-    else if (L.b_trans)
-      hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, false, true>), grid, block, 0, s, g);
-    else
-      hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS>), grid, block, 0, s, g);
   } else {
     return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Grouped float32 products: tile configurations the tuner chooses from.
+// ----------------------------------------------------------------------------
+namespace {
+struct GroupedCfg { int bm, bn, wg_per_cu; };
+constexpr GroupedCfg kGroupedCfgs[] = {{128, 128, 2}, {64, 128, 2}, {128, 64, 2}, {64, 64, 4}};
+constexpr int kGroupedCfgCount = sizeof(kGroupedCfgs) / sizeof(kGroupedCfgs[0]);
+
+template <bool GATHER>
+void launch_grouped_cfg(int cfg, dim3 grid, const GroupedArgs& ga, hipStream_t s) {
+  const dim3 block(kThreads);
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((sgemm_grouped_kernel<2, 2, F32_BK, 2, GATHER>), grid, block, 0, s, ga); break;
+    case 1: hipLaunchKernelGGL((sgemm_grouped_kernel<1, 2, F32_BK, 2, GATHER>), grid, block, 0, s, ga); break;
+    case 2: hipLaunchKernelGGL((sgemm_grouped_kernel<2, 1, F32_BK, 2, GATHER>), grid, block, 0, s, ga); break;
+    default: hipLaunchKernelGGL((sgemm_grouped_kernel<1, 1, F32_BK, 4, GATHER>), grid, block, 0, s, ga); break;
+  }
+}
+}  // namespace
+
+int grouped_cfg_count() { return kGroupedCfgCount; }
+
+void grouped_cfg_shape(int cfg, int64_t* bm, int64_t* bn, int* wg_per_cu) {
+  const GroupedCfg& c = kGroupedCfgs[cfg < 0 || cfg >= kGroupedCfgCount ? 0 : cfg];
+  *bm = c.bm; *bn = c.bn; *wg_per_cu = c.wg_per_cu;
+}
+
+size_t grouped_gemm_args_bytes() { return sizeof(GemmArgs); }
+
+void build_grouped_gemm_args(const GemmLaunch& L, int cfg, void* out) {
+  int64_t bm, bn;
+  int w;
+  grouped_cfg_shape(cfg, &bm, &bn, &w);
+  const GemmArgs g = make_gemm_args(L, bm, bn);
+  std::memcpy(out, &g, sizeof(g));
+}
+
+hipError_t launch_grouped_gemm(const GroupedLaunch& L, hipStream_t s) {
+  if (L.items <= 0) return hipSuccess;
+  if (L.stage == nullptr) return hipErrorInvalidValue;
+  GroupedArgs ga{reinterpret_cast<const GemmArgs*>(L.probs), L.item_prob, L.item_tile, L.part_base,
+                 L.items, L.nparts};
+  const dim3 grid((unsigned)L.items);
+  if (L.gather) launch_grouped_cfg<true>(L.cfg, grid, ga, s);
+  else launch_grouped_cfg<false>(L.cfg, grid, ga, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_grouped_reduce(const double* sk_part, int64_t sk_nparts, const int64_t* sk_base,
+                                 const double* ex_part, int64_t ex_nparts, const int64_t* ex_base,
+                                 const int64_t* const* col_end, int32_t count, double* out, int64_t* L,
+                                 hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grouped_reduce_kernel, dim3((unsigned)count), dim3(kThreads), 0, s, sk_part, sk_nparts,
+                     sk_base, ex_part, ex_nparts, ex_base, col_end, out, L);
   return hipGetLastError();
 }
 

@@ -1,0 +1,103 @@
+// Shared pieces of the matrix-core product kernels: the argument block, the
+// XCD-aware tile order and the fixed-order reduction of the error partials.
+#pragma once
+#include "common.h"
+
+namespace gemm_detail {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kThreads = 256;
+
+struct GemmArgs {
+  const void* A; int64_t lda;
+  const void* B; int64_t ldb;
+  int64_t m, p;
+  int64_t K_host; const int64_t* K_dev;
+  void* C; int64_t ldc;
+  const void* Y; int64_t ldy;
+  double* tile_part;            // [2][tiles]
+  int32_t nblk; const int64_t* off; double* blk_part;   // [nblk][tiles*4]
+  int64_t tiles_m, tiles_n;
+  int vec_a, vec_b;
+  float* stage; int64_t ldstage;   // float32 partial sums of long inner extents
+  // sketch read in place (gather fused into the product): A column k is
+  // colscale[k] * M[:, colmap[k]] and B row k is colscale[k] * N[colmap[k], :]
+  // (colmap < 0: zero), with A = M and B = N
+  const int32_t* colmap; const double* colscale;
+};
+
+__device__ inline __attribute__((always_inline)) int64_t inner_extent(const GemmArgs& g) {
+  if (g.K_dev) {
+    const int64_t L = *g.K_dev;
+    return (L + SBMM_SKETCH_PAD - 1) / SBMM_SKETCH_PAD * SBMM_SKETCH_PAD;
+  }
+  return g.K_host;
+}
+
+// Map a workgroup to its output tile. Workgroups are dealt round-robin to
+// the 8 XCDs (each with its own L2), so the launch index is first permuted
+// XCD-major (XCD x gets a contiguous range of logical tiles), and logical
+// tiles are ordered in groups of 8 tile rows walked column by column: the
+// workgroups resident on one XCD at a time then share a few A and B panels.
+constexpr int64_t kXcds = 8, kGroupM = 8;
+__device__ inline __attribute__((always_inline)) void tile_coords(const GemmArgs& g, int64_t& tm, int64_t& tn) {
+  const int64_t bid = blockIdx.x;
+  const int64_t tiles = g.tiles_m * g.tiles_n;
+  const int64_t per = tiles / kXcds;
+  const int64_t lg = bid < per * kXcds ? (bid % kXcds) * per + bid / kXcds : bid;
+  const int64_t span = kGroupM * g.tiles_n;
+  const int64_t first = (lg / span) * kGroupM;
+  const int64_t gm = min(g.tiles_m - first, kGroupM);
+  const int64_t r = lg % span;
+  tm = first + r % gm;
+  tn = r / gm;
+}
+
+// Reduce the epilogue partial sums of the workgroup in a fixed order into
+// slot `part` of the [2][nparts] partials.
+__device__ inline void write_tile_partials_at(const GemmArgs& g, double e2, double n2, double* sm,
+                                              int64_t part, int64_t nparts) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  e2 = warp_sum_f64(e2);
+  n2 = warp_sum_f64(n2);
+  if (lane == 0) { sm[wave] = e2; sm[4 + wave] = n2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    g.tile_part[part] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
+    g.tile_part[nparts + part] = ((sm[4] + sm[5]) + sm[6]) + sm[7];
+  }
+}
+
+// One launch per product: the partial slot is the workgroup index.
+__device__ inline void write_tile_partials(const GemmArgs& g, double e2, double n2, double* sm) {
+  write_tile_partials_at(g, e2, n2, sm, blockIdx.x, g.tiles_m * g.tiles_n);
+}
+
+
+// Argument block of one launch with tiles of bm x bn.
+inline GemmArgs make_gemm_args(const GemmLaunch& L, int64_t bm, int64_t bn) {
+  GemmArgs g{};
+  g.A = L.A; g.lda = L.lda; g.B = L.B; g.ldb = L.ldb;
+  g.m = L.m; g.p = L.p; g.K_host = L.K_host; g.K_dev = L.K_dev;
+  g.C = L.Cout; g.ldc = L.ldc; g.Y = L.Y; g.ldy = L.ldy;
+  g.tile_part = L.tile_part;
+  g.nblk = L.K_blocks; g.off = L.off_dev; g.blk_part = L.blk_part;
+  g.tiles_m = ceil_div(L.m, bm);
+  g.tiles_n = ceil_div(L.p, bn);
+  g.stage = L.stage;
+  g.ldstage = 0;
+  g.colmap = L.colmap;
+  g.colscale = L.colscale;
+  const int64_t es = (int64_t)dtype_size(L.dt);
+  const int64_t vb = 16;
+  g.vec_a = ((uintptr_t)L.A % vb == 0) && ((L.lda * es) % vb == 0);
+  g.vec_b = ((uintptr_t)L.B % vb == 0) && ((L.ldb * es) % vb == 0);
+  return g;
+}
+
+}  // namespace gemm_detail

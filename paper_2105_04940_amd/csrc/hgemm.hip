@@ -1,0 +1,252 @@
+// bf16 matrix-core product (sketched product of a bf16 sketch, and the two
+// products of the backward, which take one operand transposed). The tile
+// order, argument block and error epilogue are those of the float32 product.
+#include "gemm_common.h"
+
+namespace {
+
+using namespace gemm_detail;
+
+// ============================================================================
+// bf16 operands, float32 accumulation: v_mfma_f32_32x32x16_bf16. Lane
+// (r = lane % 32, h = lane / 32) holds 8 consecutive inner indices 8h..8h+7
+// of A row r and B column r, so both operands sit in LDS with the inner index
+// contiguous: the C tile as loaded ([row][k]) and the D tile transposed
+// ([col][k], two inner indices per 32-bit LDS write). Rows and columns are
+// interleaved across a wave's 32-blocks as in the float32 kernel, and the
+// output layout is the same. bf16 products are exact in float32 and the
+// operand rounding (2^-9) dominates the error, so there is no fold.
+// ============================================================================
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int WMB, int WNB, int BK>
+struct HgemmTile {
+  static constexpr int BM = 64 * WMB, BN = 64 * WNB;
+  static constexpr int SA = BK + 8, SB = BK + 8;        // bf16 elements per LDS row
+  static constexpr int KC = BK / 8;                     // 16-byte chunks per A row
+  static constexpr int NA = BM * KC / kThreads;         // 16-byte loads of A per thread
+  static constexpr int NBP = (BK / 2) * (BN / 8) / kThreads;  // row-pair chunks of B per thread
+  static constexpr int NAP = (BK / 2) * (BM / 8) / kThreads;  // row-pair chunks of A (transposed A)
+  static constexpr int NBK = BN * KC / kThreads;               // 16-byte runs of B (transposed B)
+  uint16_t As[2][BM][SA];
+  uint16_t Bs[2][BN][SB];
+  double red[8];
+};
+
+// AT: A is given as K x M (A[i][k] at A + k lda + i); BT: B is given as
+// N x K (B[k][j] at B + j ldb + k). The LDS layouts stay [row][k] / [col][k].
+template <int WMB, int WNB, int BK, bool EDGE, bool AT, bool BT>
+__device__ __forceinline__ void hgemm_body(const GemmArgs& g, HgemmTile<WMB, WNB, BK>& sh,
+                                           int64_t m0, int64_t n0, int64_t K) {
+  using T = HgemmTile<WMB, WNB, BK>;
+  constexpr int BN = T::BN, KC = T::KC, NA = T::NA, NBP = T::NBP;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int wave_m0 = (wave & 1) * 32 * WMB;
+  const int wave_n0 = (wave >> 1) * 32 * WNB;
+  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(g.A);
+  const uint16_t* __restrict__ B = reinterpret_cast<const uint16_t*>(g.B);
+
+  f32x16 acc[WMB][WNB];
+#pragma unroll
+  for (int b = 0; b < WMB; ++b)
+#pragma unroll
+    for (int c = 0; c < WNB; ++c) acc[b][c] = f32x16{};
+
+  // Each operand tile is gathered either as 16-byte runs along k (stored
+  // directly) or as pairs of k-rows of 8 consecutive rows/columns (stored
+  // transposed, two k per 32-bit write).
+  constexpr int RA = NA > T::NAP ? NA : T::NAP;       // registers for either A layout
+  constexpr int RB = NBP > T::NBK ? NBP : T::NBK;     // registers for either B layout
+  uint4 ra0[RA], ra1[RA], rb0[RB], rb1[RB];
+  auto pack8 = [](const uint16_t* t) {
+    return make_uint4(t[0] | (uint32_t)t[1] << 16, t[2] | (uint32_t)t[3] << 16,
+                      t[4] | (uint32_t)t[5] << 16, t[6] | (uint32_t)t[7] << 16);
+  };
+  // 16-byte run along k of row r (k contiguous, leading dimension ld)
+  auto run_k = [&](const uint16_t* X, int64_t ld, int64_t r, int64_t rmax, int64_t k, bool vec) {
+    if (!EDGE || (r < rmax && k + 8 <= K && vec)) return *reinterpret_cast<const uint4*>(X + r * ld + k);
+    uint16_t t[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = (r < rmax && k + e < K) ? X[r * ld + k + e] : 0;
+    return pack8(t);
+  };
+  // 8 consecutive rows/columns c..c+7 of k-row kr (index contiguous)
+  auto run_i = [&](const uint16_t* X, int64_t ld, int64_t kr, int64_t c, int64_t cmax, bool vec) {
+    if (!EDGE || (kr < K && c + 8 <= cmax && vec)) return *reinterpret_cast<const uint4*>(X + kr * ld + c);
+    uint16_t t[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = (kr < K && c + e < cmax) ? X[kr * ld + c + e] : 0;
+    return pack8(t);
+  };
+  auto load = [&](int64_t kt) {
+    const int64_t k0 = kt * BK;
+    if constexpr (!AT) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int f = tid + kThreads * q;
+        ra0[q] = run_k(A, g.lda, m0 + f / KC, g.m, k0 + 8 * (f % KC), g.vec_a);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < T::NAP; ++q) {
+        const int f = tid + kThreads * q;
+        const int pr = f / (T::BM / 8), c8 = f % (T::BM / 8);
+        ra0[q] = run_i(A, g.lda, k0 + 2 * pr, m0 + 8 * c8, g.m, g.vec_a);
+        ra1[q] = run_i(A, g.lda, k0 + 2 * pr + 1, m0 + 8 * c8, g.m, g.vec_a);
+      }
+    }
+    if constexpr (BT) {
+#pragma unroll
+      for (int q = 0; q < T::NBK; ++q) {
+        const int f = tid + kThreads * q;
+        rb0[q] = run_k(B, g.ldb, n0 + f / KC, g.p, k0 + 8 * (f % KC), g.vec_b);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NBP; ++q) {
+        const int f = tid + kThreads * q;
+        const int pr = f / (BN / 8), c8 = f % (BN / 8);
+        rb0[q] = run_i(B, g.ldb, k0 + 2 * pr, n0 + 8 * c8, g.p, g.vec_b);
+        rb1[q] = run_i(B, g.ldb, k0 + 2 * pr + 1, n0 + 8 * c8, g.p, g.vec_b);
+      }
+    }
+  };
+  // write 8 rows/columns x 2 k of a transposed pair into an LDS [row][k] tile
+  auto store_pair = [](uint16_t (*X)[T::SA], int c0, int k, const uint4& a0, const uint4& a1) {
+    const uint32_t w0[4] = {a0.x, a0.y, a0.z, a0.w};
+    const uint32_t w1[4] = {a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t lo = (w0[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+      const uint32_t hi = (w1[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+      *reinterpret_cast<uint32_t*>(&X[c0 + e][k]) = lo | (hi << 16);
+    }
+  };
+  auto store = [&](int buf) {
+    if constexpr (!AT) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int f = tid + kThreads * q;
+        *reinterpret_cast<uint4*>(&sh.As[buf][f / KC][8 * (f % KC)]) = ra0[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < T::NAP; ++q) {
+        const int f = tid + kThreads * q;
+        store_pair(sh.As[buf], 8 * (f % (T::BM / 8)), 2 * (f / (T::BM / 8)), ra0[q], ra1[q]);
+      }
+    }
+    if constexpr (BT) {
+#pragma unroll
+      for (int q = 0; q < T::NBK; ++q) {
+        const int f = tid + kThreads * q;
+        *reinterpret_cast<uint4*>(&sh.Bs[buf][f / KC][8 * (f % KC)]) = rb0[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NBP; ++q) {
+        const int f = tid + kThreads * q;
+        store_pair(sh.Bs[buf], 8 * (f % (BN / 8)), 2 * (f / (BN / 8)), rb0[q], rb1[q]);
+      }
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < BK / 16; ++s) {
+      bf16x8 av[WMB], bv[WNB];
+#pragma unroll
+      for (int b = 0; b < WMB; ++b)
+        av[b] = *reinterpret_cast<const bf16x8*>(&sh.As[buf][wave_m0 + WMB * lr + b][16 * s + 8 * lh]);
+#pragma unroll
+      for (int c = 0; c < WNB; ++c)
+        bv[c] = *reinterpret_cast<const bf16x8*>(&sh.Bs[buf][wave_n0 + WNB * lr + c][16 * s + 8 * lh]);
+#pragma unroll
+      for (int b = 0; b < WMB; ++b)
+#pragma unroll
+        for (int c = 0; c < WNB; ++c)
+          acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[b], bv[c], acc[b][c], 0, 0, 0);
+    }
+  };
+
+  // interior tiles of products whose inner extent is a multiple of BK run
+  // unpredicated; anything else takes the predicated loads
+  const int64_t nkt = (K + BK - 1) / BK;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nkt) load(kt + 1);
+    compute(cur);
+    if (kt + 1 < nkt) store(cur ^ 1);
+    __syncthreads();
+  }
+  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < WMB; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wave_m0 + WMB * (8 * (v >> 2) + 4 * lh + (v & 3)) + b;
+      if (EDGE && row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) {
+        const int64_t col = n0 + wave_n0 + WNB * lr + c;
+        if (EDGE && col >= g.p) continue;
+        const float val = acc[b][c][v];
+        if (Cout) Cout[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (Y) {
+          const double d = dv - (double)Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
+}
+
+template <int WMB, int WNB, int BK, int WG_PER_CU, bool AT = false, bool BT = false>
+__global__ __launch_bounds__(kThreads, WG_PER_CU) void hgemm_kernel(GemmArgs g) {
+  using T = HgemmTile<WMB, WNB, BK>;
+  __shared__ T sh;
+  int64_t tm, tn;
+  tile_coords(g, tm, tn);
+  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
+  const int64_t K = inner_extent(g);
+  const bool interior = g.vec_a && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p && K % BK == 0;
+  if (interior)
+    hgemm_body<WMB, WNB, BK, false, AT, BT>(g, sh, m0, n0, K);
+  else
+    hgemm_body<WMB, WNB, BK, true, AT, BT>(g, sh, m0, n0, K);
+}
+
+
+constexpr int BF16_WMB = 2, BF16_WNB = 2, BF16_BK = 64, BF16_WGS = 2;   // 128 x 128
+
+}  // namespace
+
+void hgemm_tile_shape(int64_t* bm, int64_t* bn) { *bm = 64 * BF16_WMB; *bn = 64 * BF16_WNB; }
+
+hipError_t launch_hgemm(const GemmLaunch& L, hipStream_t s) {
+  int64_t bm, bn;
+  hgemm_tile_shape(&bm, &bn);
+  const GemmArgs g = make_gemm_args(L, bm, bn);
+  const int64_t tiles = g.tiles_m * g.tiles_n;
+  if (tiles == 0) return hipSuccess;
+  dim3 grid((unsigned)tiles), block(kThreads);
+  if (L.a_trans && L.b_trans)
+    hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, true, true>), grid, block, 0, s, g);
+  else if (L.a_trans)
+    hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, true, false>), grid, block, 0, s, g);
+  else if (L.b_trans)
+    hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS, false, true>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((hgemm_kernel<BF16_WMB, BF16_WNB, BF16_BK, BF16_WGS>), grid, block, 0, s, g);
+  return hipGetLastError();
+}

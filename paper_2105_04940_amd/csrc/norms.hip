@@ -13,6 +13,7 @@
 //    rows) reduces one row with cross-lane shuffles.
 // Sums are float64 in a fixed order, so the result is bitwise reproducible.
 #include <algorithm>
+#include <cstring>
 
 #include "common.h"
 
@@ -198,15 +199,26 @@ __global__ __launch_bounds__(kThreads) void norms_kernel(NormArgs a) {
     rowsq_part<T>(a, bid - a.nblocks_m);
 }
 
+struct StatsArgs {
+  const double* partial; int rsplit; int64_t n;
+  const int64_t* off; int32_t K;
+  double* col_sq; const double* row_sq; double* blk;
+  int32_t* status;
+};
+
 // One workgroup per block: finish the column sums over the row splits and
 // form the three block statistics.
-__global__ __launch_bounds__(kThreads) void block_stats_kernel(
-    const double* __restrict__ partial, int rsplit, int64_t n,
-    const int64_t* __restrict__ off, int32_t K, double* __restrict__ col_sq,
-    const double* __restrict__ row_sq, double* __restrict__ blk,
-    int32_t* status) {
+__device__ void block_stats_body(const StatsArgs& s, int k) {
+  const double* __restrict__ partial = s.partial;
+  const int rsplit = s.rsplit;
+  const int64_t n = s.n;
+  const int64_t* __restrict__ off = s.off;
+  const int32_t K = s.K;
+  double* __restrict__ col_sq = s.col_sq;
+  const double* __restrict__ row_sq = s.row_sq;
+  double* __restrict__ blk = s.blk;
+  int32_t* status = s.status;
   __shared__ double sm[3][kThreads];
-  const int k = blockIdx.x;
   const int64_t lo = off[k], hi = off[k + 1];
   double am = 0.0, an = 0.0, as = 0.0;
   bool bad = false;
@@ -240,23 +252,46 @@ __global__ __launch_bounds__(kThreads) void block_stats_kernel(
   }
 }
 
-int elems_per_vec(sbmm_dtype dt) { return 16 / (int)dtype_size(dt); }
+__global__ __launch_bounds__(kThreads) void block_stats_kernel(StatsArgs s) { block_stats_body(s, blockIdx.x); }
 
-}  // namespace
-
-// Row splits of M: enough workgroups to fill the chip several times over,
-// but at least 32 rows per split.
-size_t norms_partial_elems(sbmm_dtype dt, int64_t m, int64_t n, int* rsplit_out) {
-  const int64_t tiles = ceil_div(n, 64 * elems_per_vec(dt));
-  int64_t want = ceil_div(4096, tiles > 0 ? tiles : 1);
-  int64_t maxr = m / 32 > 1 ? m / 32 : 1;
-  int64_t R = want < 1 ? 1 : (want > maxr ? maxr : want);
-  if (R > 64) R = 64;
-  *rsplit_out = (int)R;
-  return (size_t)R * (size_t)n;
+// Last t with off[t] <= x (off ascending, off[0] = 0 <= x).
+__device__ __forceinline__ int32_t find_problem(const int64_t* __restrict__ off, int32_t T, int64_t x) {
+  int32_t lo = 0, hi = T;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
 }
 
-hipError_t launch_norms(const NormLaunch& L, hipStream_t s) {
+// Norm pass of many problems in one launch: workgroup b belongs to the
+// problem t with wg_off[t] <= b < wg_off[t+1] and runs that problem's
+// workgroup b - wg_off[t].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void batch_norms_kernel(const NormArgs* __restrict__ args,
+                                                               const int64_t* __restrict__ wg_off, int32_t count) {
+  __shared__ double sm[4 * 64 * (16 / sizeof(T))];
+  const int64_t bid = blockIdx.x;
+  const int32_t t = find_problem(wg_off, count, bid);
+  const NormArgs& a = args[t];
+  const int64_t local = bid - wg_off[t];
+  if (local < a.nblocks_m)
+    colsq_part<T>(a, local, sm);
+  else
+    rowsq_part<T>(a, local - a.nblocks_m);
+}
+
+__global__ __launch_bounds__(kThreads) void batch_stats_kernel(const StatsArgs* __restrict__ args,
+                                                               const int64_t* __restrict__ blk_off, int32_t count) {
+  const int64_t bid = blockIdx.x;
+  const int32_t t = find_problem(blk_off, count, bid);
+  block_stats_body(args[t], (int)(bid - blk_off[t]));
+}
+
+int elems_per_vec(sbmm_dtype dt) { return 16 / (int)dtype_size(dt); }
+
+// Argument block of one problem's norm pass; returns its workgroup count.
+int64_t make_norm_args(const NormLaunch& L, NormArgs* out) {
   NormArgs a{};
   a.M = L.M; a.ldm = L.ldm; a.N = L.N; a.ldn = L.ldn;
   a.m = L.m; a.n = L.n; a.p = L.p;
@@ -277,9 +312,34 @@ hipError_t launch_norms(const NormLaunch& L, hipStream_t s) {
   const int64_t steps = L.p > 0 ? std::max<int64_t>(1, ceil_div(L.n, rows_per_step * 4096)) : 0;
   a.rows_per_wg_n = rows_per_step * std::max<int64_t>(steps, 1);
   const int64_t nblocks_n = L.p > 0 ? ceil_div(L.n, a.rows_per_wg_n) : 0;
-  if (L.m == 0) launch_fill_f64(L.partial, L.rsplit * L.n, 0.0, s);
-  if (L.p == 0) launch_fill_f64(L.row_sq, L.n, 0.0, s);
-  const int64_t total = a.nblocks_m + nblocks_n;
+  *out = a;
+  return a.nblocks_m + nblocks_n;
+}
+
+StatsArgs make_stats_args(const NormLaunch& L) {
+  return StatsArgs{L.partial, L.m > 0 ? L.rsplit : 1, L.n, L.off_dev, L.K, L.col_sq, L.row_sq, L.blk, L.status};
+}
+
+}  // namespace
+
+// Row splits of M: enough workgroups to fill the chip several times over,
+// but at least 32 rows per split.
+size_t norms_partial_elems(sbmm_dtype dt, int64_t m, int64_t n, int* rsplit_out) {
+  const int64_t tiles = ceil_div(n, 64 * elems_per_vec(dt));
+  int64_t want = ceil_div(4096, tiles > 0 ? tiles : 1);
+  int64_t maxr = m / 32 > 1 ? m / 32 : 1;
+  int64_t R = want < 1 ? 1 : (want > maxr ? maxr : want);
+  if (R > 64) R = 64;
+  *rsplit_out = (int)R;
+  return (size_t)R * (size_t)n;
+}
+
+hipError_t launch_norms(const NormLaunch& L, hipStream_t s) {
+  NormArgs a;
+  const int64_t total = make_norm_args(L, &a);
+  hipError_t e = hipSuccess;
+  if (L.m == 0 && (e = launch_fill_f64(L.partial, L.rsplit * L.n, 0.0, s)) != hipSuccess) return e;
+  if (L.p == 0 && (e = launch_fill_f64(L.row_sq, L.n, 0.0, s)) != hipSuccess) return e;
   if (total > 0) {
     dim3 grid((unsigned)total), block(kThreads);
     switch (L.dt) {
@@ -289,8 +349,41 @@ hipError_t launch_norms(const NormLaunch& L, hipStream_t s) {
       default: return hipErrorInvalidValue;
     }
   }
-  hipLaunchKernelGGL(block_stats_kernel, dim3(L.K), dim3(kThreads), 0, s,
-                     L.partial, L.m > 0 ? L.rsplit : 1, L.n, L.off_dev, L.K,
-                     L.col_sq, L.row_sq, L.blk, L.status);
+  hipLaunchKernelGGL(block_stats_kernel, dim3(L.K), dim3(kThreads), 0, s, make_stats_args(L));
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Batched form: host-built argument blocks, uploaded once by the caller.
+// ----------------------------------------------------------------------------
+size_t batch_norm_args_bytes() { return sizeof(NormArgs); }
+size_t batch_stats_args_bytes() { return sizeof(StatsArgs); }
+
+int64_t build_batch_norm_args(const NormLaunch& L, void* norm_out, void* stats_out) {
+  NormArgs a;
+  const int64_t wg = make_norm_args(L, &a);
+  std::memcpy(norm_out, &a, sizeof(a));
+  const StatsArgs st = make_stats_args(L);
+  std::memcpy(stats_out, &st, sizeof(st));
+  return wg;
+}
+
+hipError_t launch_batch_norms(sbmm_dtype dt, const void* norm_args, const int64_t* wg_off, int64_t total_wg,
+                              const void* stats_args, const int64_t* blk_off, int64_t total_blk,
+                              int32_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const NormArgs* na = reinterpret_cast<const NormArgs*>(norm_args);
+  if (total_wg > 0) {
+    dim3 grid((unsigned)total_wg), block(kThreads);
+    switch (dt) {
+      case SBMM_F64: hipLaunchKernelGGL(batch_norms_kernel<double>, grid, block, 0, s, na, wg_off, count); break;
+      case SBMM_F32: hipLaunchKernelGGL(batch_norms_kernel<float>, grid, block, 0, s, na, wg_off, count); break;
+      case SBMM_BF16: hipLaunchKernelGGL(batch_norms_kernel<uint16_t>, grid, block, 0, s, na, wg_off, count); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (total_blk > 0)
+    hipLaunchKernelGGL(batch_stats_kernel, dim3((unsigned)total_blk), dim3(kThreads), 0, s,
+                       reinterpret_cast<const StatsArgs*>(stats_args), blk_off, count);
   return hipGetLastError();
 }

@@ -138,10 +138,9 @@ __device__ uint64_t block_excl_scan(uint64_t v, uint64_t* sm, uint64_t* total) {
 }
 
 // One workgroup per stratum: weights, maximum, quantization, CDF.
-__global__ __launch_bounds__(kThreads) void design_kernel(PlanLaunch a) {
+__device__ void design_body(const PlanLaunch& a, int64_t s) {
   __shared__ double smd[kThreads];
   __shared__ uint64_t smu[kThreads];
-  const int64_t s = blockIdx.x;
   const int64_t a0 = strat_begin(a, s), a1 = strat_begin(a, s + 1);
   const int64_t As = a1 - a0;
   double mx = 0.0;
@@ -177,6 +176,8 @@ __global__ __launch_bounds__(kThreads) void design_kernel(PlanLaunch a) {
       a.p_hat[i] = total > 0 ? (double)a.W[i] / (double)total : 0.0;
   }
 }
+
+__global__ __launch_bounds__(kThreads) void design_kernel(PlanLaunch a) { design_body(a, blockIdx.x); }
 
 // 128-bit helpers for the apportionment.
 struct U128 { uint64_t hi, lo; };
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void alloc_kernel(PlanLaunch a) {
 }
 
 // Block mode: the single stratum gets all c draws (none if every weight is 0).
-__global__ void alloc_block_kernel(PlanLaunch a) {
+__device__ __forceinline__ void alloc_block_body(const PlanLaunch& a) {
   if (threadIdx.x == 0) {
     const int64_t cnt = a.T[0] > 0 ? a.c : 0;
     a.ck[0] = cnt;
@@ -337,11 +338,11 @@ __global__ void alloc_block_kernel(PlanLaunch a) {
   }
 }
 
-// One thread per draw.
-__global__ __launch_bounds__(kThreads) void sample_kernel(PlanLaunch a) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+__global__ void alloc_block_kernel(PlanLaunch a) { alloc_block_body(a); }
+
+// Draw t (t < c).
+__device__ void sample_one(const PlanLaunch& a, int64_t t) {
   const int64_t total = a.draw_off[a.S];
-  if (t >= a.c) return;
   if (t >= total) {   // no draws (budget error or all-zero weights)
     a.idx[t] = -1; a.scale[t] = 0.0; a.width[t] = 0;
     return;
@@ -389,8 +390,14 @@ __global__ __launch_bounds__(kThreads) void sample_kernel(PlanLaunch a) {
   a.width[t] = a.mode == SBMM_MODE_BLOCK ? a.off_dev[atom + 1] - a.off_dev[atom] : 1;
 }
 
+// One thread per draw.
+__global__ __launch_bounds__(kThreads) void sample_kernel(PlanLaunch a) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t < a.c) sample_one(a, t);
+}
+
 // Exclusive scan of the draw widths into col_off (single workgroup).
-__global__ __launch_bounds__(kThreads) void offsets_kernel(PlanLaunch a) {
+__device__ void offsets_body(const PlanLaunch& a) {
   __shared__ uint64_t smu[kThreads];
   const int64_t c = a.c;
   const int64_t per = (c + kThreads - 1) / kThreads;
@@ -406,11 +413,11 @@ __global__ __launch_bounds__(kThreads) void offsets_kernel(PlanLaunch a) {
   if (threadIdx.x == 0) a.col_off[c] = (int64_t)tot;
 }
 
-// Column map of the sketch: one thread per draw fills its columns; the
-// first workgroup also writes the zero padding up to the next multiple of 32.
-__global__ __launch_bounds__(kThreads) void colmap_kernel(PlanLaunch a) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t < a.c) {
+__global__ __launch_bounds__(kThreads) void offsets_kernel(PlanLaunch a) { offsets_body(a); }
+
+// Columns of the sketch fed by draw t.
+__device__ __forceinline__ void colmap_one(const PlanLaunch& a, int64_t t) {
+  {
     const int64_t w = a.width[t];
     const int64_t c0 = a.col_off[t];
     if (w > 0) {
@@ -423,7 +430,11 @@ __global__ __launch_bounds__(kThreads) void colmap_kernel(PlanLaunch a) {
       }
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x < SBMM_SKETCH_PAD) {
+}
+
+// Zero padding of the column map up to the next multiple of 32.
+__device__ __forceinline__ void colmap_pad(const PlanLaunch& a) {
+  if (threadIdx.x < SBMM_SKETCH_PAD) {
     const int64_t L = a.col_off[a.c];
     const int64_t Lp = (L + SBMM_SKETCH_PAD - 1) / SBMM_SKETCH_PAD * SBMM_SKETCH_PAD;
     const int64_t l = L + threadIdx.x;
@@ -434,7 +445,38 @@ __global__ __launch_bounds__(kThreads) void colmap_kernel(PlanLaunch a) {
   }
 }
 
+// Column map of the sketch: one thread per draw fills its columns; the
+// first workgroup also writes the padding.
+__global__ __launch_bounds__(kThreads) void colmap_kernel(PlanLaunch a) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t < a.c) colmap_one(a, t);
+  if (blockIdx.x == 0) colmap_pad(a);
+}
+
+// Many independent block-mode problems: one workgroup runs the whole plan of
+// problem blockIdx.x (design, allocation, draws, offsets, column map), with
+// workgroup barriers between the steps.
+__global__ __launch_bounds__(kThreads) void batch_plan_kernel(const PlanLaunch* __restrict__ plans) {
+  const PlanLaunch& a = plans[blockIdx.x];
+  design_body(a, 0);
+  __syncthreads();
+  alloc_block_body(a);
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < a.c; t += kThreads) sample_one(a, t);
+  __syncthreads();
+  offsets_body(a);
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < a.c; t += kThreads) colmap_one(a, t);
+  colmap_pad(a);
+}
+
 }  // namespace
+
+hipError_t launch_batch_plan(const PlanLaunch* plans_dev, int32_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_plan_kernel, dim3((unsigned)count), dim3(kThreads), 0, s, plans_dev);
+  return hipGetLastError();
+}
 
 hipError_t launch_plan(const PlanLaunch& a, hipStream_t s) {
   hipLaunchKernelGGL(design_kernel, dim3((unsigned)a.S), dim3(kThreads), 0, s, a);

@@ -1,0 +1,284 @@
+"""Parity of the batched path (many independent block-mode problems per
+pass: grouped norm pass, one-workgroup plans, grouped exact and
+sketched products with the gather fused in, per-problem reduction) with the
+float64 oracle run problem by problem.
+
+Bars as for a single problem: draws bit-exact, float32 outputs within 1e-5
+relative Frobenius. Beyond parity: results do not depend on the tile
+configuration or work order the tuner picks, a captured graph replays to the
+eager results, and the full 512-problem workload (inputs written on the
+device from the counter-based stream the host can regenerate) matches the
+oracle on sampled problems and entries.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import method as om
+
+torch = pytest.importorskip("torch")
+import paper_2105_04940_amd as pk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = pk.Handle(0)
+    yield hd
+    hd.close()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def padded(x, ld):
+    """Device float32 copy of x with leading dimension ld >= x.shape[1]."""
+    buf = torch.zeros((x.shape[0], ld), dtype=torch.float32, device=DEV)
+    buf[:, :x.shape[1]] = torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(DEV)
+    return buf[:, :x.shape[1]]
+
+
+# problems with ragged tiles in every direction, blocks of 8..128, both
+# rules, a problem smaller than one tile, one with c above K, aligned and
+# unaligned leading dimensions
+SMALL = [
+    dict(m=300, n=3000, p=260, lo=8, hi=128, c=40, prob="norm", ldm=3000, ldn=260, skew=1.0),
+    dict(m=128, n=4096, p=128, lo=32, hi=32, c=16, prob="uniform", ldm=4096, ldn=128, skew=0.0),
+    dict(m=77, n=1500, p=45, lo=8, hi=64, c=64, prob="norm", ldm=1501, ldn=47, skew=1.5),
+    dict(m=520, n=5000, p=700, lo=16, hi=112, c=100, prob="norm", ldm=5004, ldn=704, skew=1.5),
+    dict(m=1, n=200, p=3, lo=8, hi=16, c=5, prob="uniform", ldm=200, ldn=3, skew=0.0),
+    dict(m=257, n=700, p=129, lo=100, hi=128, c=300, prob="norm", ldm=700, ldn=132, skew=0.5),
+]
+
+
+@pytest.fixture(scope="module")
+def small_batch(h):
+    probs, host = [], []
+    for t, d in enumerate(SMALL):
+        g = wl.rng(100 + t)
+        M = g.standard_normal((d["m"], d["n"])).astype(np.float32)
+        N = g.standard_normal((d["n"], d["p"])).astype(np.float32)
+        if d["skew"] > 0:
+            M *= g.lognormal(0.0, d["skew"], size=d["n"]).astype(np.float32)[None, :]
+            N *= g.lognormal(0.0, d["skew"], size=d["n"]).astype(np.float32)[:, None]
+        K = max(1, round(d["n"] / ((d["lo"] + d["hi"]) / 2)))
+        off = wl.uneven_blocks(d["n"], K, d["lo"], d["hi"], 7 + t)
+        probs.append(dict(M=padded(M, d["ldm"]), N=padded(N, d["ldn"]), off=off, c=d["c"],
+                          prob=d["prob"], seed=0, trial=t))
+        host.append((M, N, off))
+    b = pk.Batch(h, probs)
+    yield b, probs, host
+    b.close()
+
+
+def oracle_problem(M, N, off, c, prob, trial):
+    Mh = M.astype(np.float64)
+    Nh = N.astype(np.float64)
+    return om.run(Mh, Nh, off, c, seed=0, trial=trial, prob=prob)
+
+
+def check_against_oracle(b, probs, host, t, o):
+    idx = b.draws(t).cpu().numpy()
+    assert np.array_equal(idx, o.draws.atom), t
+    assert int(b.L[t].item()) == o.draws.L
+    assert rel(b.CD[t].cpu().numpy(), o.CD) < 1e-5, t
+    assert rel(b.MN[t].cpu().numpy(), o.MN) < 1e-5, t
+    e2, mn2 = b.err2_mn2[2 * t].item(), b.err2_mn2[2 * t + 1].item()
+    mn_norm = float(np.linalg.norm(o.MN))
+    assert abs(mn2 - mn_norm ** 2) <= 1e-5 * mn_norm ** 2
+    assert abs(np.sqrt(e2) - o.err) <= 1e-5 * max(o.err, mn_norm)
+
+
+def test_small_batch_matches_oracle(small_batch):
+    b, probs, host = small_batch
+    b.run()
+    torch.cuda.synchronize()
+    for t, (M, N, off) in enumerate(host):
+        o = oracle_problem(M, N, off, probs[t]["c"], probs[t]["prob"], t)
+        check_against_oracle(b, probs, host, t, o)
+
+
+def _snapshot(b):
+    return ([x.clone() for x in b.CD], [x.clone() for x in b.MN], b.err2_mn2.clone(), b.L.clone(),
+            b.idx.clone())
+
+
+def _same(s1, s2, exact_sums=True):
+    """CD, MN, L and the draws bit for bit; the per-problem squared norms
+    bit for bit too when the tiling is the same, else to float64 rounding
+    (they are sums of per-tile partials, and the tiling sets the grouping)."""
+    for a, c in zip(s1[0] + s1[1], s2[0] + s2[1]):
+        if not torch.equal(a, c):
+            return False
+    if not (torch.equal(s1[3], s2[3]) and torch.equal(s1[4], s2[4])):
+        return False
+    if exact_sums:
+        return torch.equal(s1[2], s2[2])
+    return bool(torch.allclose(s1[2], s2[2], rtol=1e-12, atol=0.0))
+
+
+def _clear(b):
+    for x in b.CD + b.MN:
+        x.fill_(float("nan"))
+    b.err2_mn2.zero_()
+    b.L.zero_()
+    b.idx.zero_()
+
+
+def test_results_do_not_depend_on_tiles_or_order(small_batch):
+    b, *_ = small_batch
+    b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
+    b.run()
+    ref = _snapshot(b)
+    for cfg_ex in range(4):
+        for cfg_sk in range(4):
+            for lpt in (0, 1):
+                _clear(b)
+                b.set_tuning({"cfg": [cfg_ex, cfg_sk], "lpt": [lpt, 1 - lpt]})
+                b.run()
+                torch.cuda.synchronize()
+                assert _same(ref, _snapshot(b), exact_sums=False), (cfg_ex, cfg_sk, lpt)
+
+
+def test_tuner_picks_a_measured_configuration(small_batch):
+    b, probs, host = small_batch
+    t = b.tune(reps=2)
+    for g in range(2):
+        ms = t["ms"][g]
+        assert all(v > 0 for v in ms)
+        assert ms[2 * t["cfg"][g] + t["lpt"][g]] == min(ms)
+    _clear(b)
+    b.run()
+    torch.cuda.synchronize()
+    o = oracle_problem(*host[3], probs[3]["c"], probs[3]["prob"], 3)
+    check_against_oracle(b, probs, host, 3, o)
+
+
+def test_graph_replays_match_eager(small_batch):
+    b, *_ = small_batch
+    b.set_tuning({"cfg": [1, 2], "lpt": [1, 0]})
+    b.run()
+    torch.cuda.synchronize()
+    ref = _snapshot(b)
+    b.capture()
+    x = torch.randn(512, 512, device=DEV)
+    for rep in range(3):
+        _clear(b)
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        assert _same(ref, _snapshot(b)), rep
+        # the program's own eager work between replays
+        y = x @ x
+        b.run()
+        torch.cuda.synchronize()
+        assert _same(ref, _snapshot(b)), rep
+        assert torch.isfinite(y).all()
+
+
+def test_graph_sees_new_inputs(small_batch):
+    # the graph holds pointers, not values: new contents of M give new results
+    b, probs, host = small_batch
+    b.capture()
+    M0 = probs[0]["M"]
+    saved = M0.clone()
+    M0.mul_(2.0)
+    b.replay()
+    torch.cuda.synchronize()
+    o = oracle_problem(host[0][0] * np.float32(2.0), host[0][1], host[0][2], probs[0]["c"], probs[0]["prob"], 0)
+    check_against_oracle(b, probs, host, 0, o)
+    M0.copy_(saved)
+    b.replay()
+    torch.cuda.synchronize()
+
+
+def test_batch_rejects_bad_items(h):
+    M = torch.zeros((4, 10), dtype=torch.float32, device=DEV)
+    N = torch.zeros((10, 3), dtype=torch.float32, device=DEV)
+    for bad in (dict(off=[0, 4, 9]), dict(off=[0, 4, 10], c=0), dict(off=[0, 4, 10], prob="exact"),
+                dict(off=[0, 0, 10])):
+        pr = dict(M=M, N=N, off=[0, 4, 10], c=3)
+        pr.update(bad)
+        with pytest.raises(pk.SbmmError) as e:
+            pk.Batch(h, [pr])
+        assert e.value.status == pk.SBMM_E_ARG
+
+
+def test_batch_all_zero_problem(h):
+    M = torch.zeros((40, 100), dtype=torch.float32, device=DEV)
+    N = torch.zeros((100, 30), dtype=torch.float32, device=DEV)
+    b = pk.Batch(h, [dict(M=M, N=N, off=list(range(0, 101, 10)), c=5)])
+    b.run()
+    torch.cuda.synchronize()
+    assert int(b.L[0].item()) == 0
+    assert torch.count_nonzero(b.CD[0]).item() == 0 and torch.count_nonzero(b.MN[0]).item() == 0
+    assert b.err2_mn2.abs().sum().item() == 0.0
+    b.close()
+
+
+def test_device_fill_matches_host_stream():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    for rows, cols, ld, seed, stream in ((7, 13, 13, 3, 5), (300, 257, 260, 3, 1), (1, 1, 4, 0, 0)):
+        buf = torch.zeros((rows, ld), dtype=torch.float32, device=DEV)
+        x = buf[:, :cols]
+        wl.device_fill(x, seed, stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), wl.philox_matrix(rows, cols, seed, stream))
+        assert torch.count_nonzero(buf[:, cols:]).item() == 0
+
+
+# --------------------------------------------------------------------------
+# the full batched workload: 512 problems, inputs written on the device
+# --------------------------------------------------------------------------
+
+def make_full_batch(h, T=512):
+    items, mats = wl.batched_device_inputs(T)
+    probs = [dict(M=M, N=N, off=it["off"], c=it["c"], prob="norm", seed=0, trial=t)
+             for t, (it, (M, N)) in enumerate(zip(items, mats))]
+    return items, probs, pk.Batch(h, probs)
+
+
+@pytest.mark.slow
+def test_full_batched_workload_sampled(h):
+    items, probs, b = make_full_batch(h)
+    b.tune(reps=1)
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    g = wl.rng(99)
+    e2 = b.err2_mn2.cpu().numpy()
+    CDs = b.CD
+    MNs = b.MN
+    # every problem: the fused error equals ||MN - CD||^2 of the stored outputs
+    for t in range(len(items)):
+        d = (MNs[t].double() - CDs[t].double()).pow(2).sum().item()
+        assert abs(e2[2 * t] - d) <= 1e-9 * max(d, 1e-300), t
+        assert abs(e2[2 * t + 1] - MNs[t].double().pow(2).sum().item()) <= 1e-9 * e2[2 * t + 1], t
+    # sampled problems against the oracle on regenerated host inputs
+    for t in (0, 1, 2, 3, 255, 511) + tuple(int(x) for x in g.choice(np.arange(4, 511), 4, replace=False)):
+        it = items[t]
+        sm, sn = wl.batched_item_streams(t)
+        M = wl.philox_matrix(it["m"], it["n"], wl.INPUT_SEED, sm)
+        N = wl.philox_matrix(it["n"], it["p"], wl.INPUT_SEED, sn)
+        assert np.array_equal(probs[t]["M"][:4].cpu().numpy(), M[:4])
+        Mh, Nh = M.astype(np.float64), N.astype(np.float64)
+        design, *_ = om.plan(Mh, Nh, it["off"], it["c"], prob="norm")
+        draws = om.sample(design, 0, t)
+        assert np.array_equal(b.draws(t).cpu().numpy(), draws.atom), t
+        assert int(b.L[t].item()) == draws.L, t
+        rows = g.integers(0, it["m"], size=300)
+        cols = g.integers(0, it["p"], size=300)
+        cd = CDs[t].cpu().numpy()[rows, cols]
+        mn = MNs[t].cpu().numpy()[rows, cols]
+        assert rel(cd, om.sketch_entries(Mh, Nh, draws, rows, cols)) < 1e-5, t
+        assert rel(mn, om.exact_entries(Mh, Nh, rows, cols)) < 1e-5, t
+    b.close()

@@ -18,7 +18,11 @@ and the block-sampling settings this project measures):
                   i.i.d. N(0, S1) or multivariate t_1 located at the all-ones
                   vector with scale S1, rows of N likewise with S2, where
                   S1 = (0.7^|i-j|) (m x m) and S2 = (2 * 0.7^|i-j|) (p x p).
-* ``batched``     per-trial sizes of the 512-problem batched workload.
+* ``batched``     per-trial sizes of the 512-problem batched workload; its
+                  matrices come from a counter-based stream (``philox_matrix``
+                  on the host, ``device_fill`` on the GPU, bit-identical) so
+                  that 87 GB of inputs can be written in place on the device
+                  and any trial regenerated on the host.
 * ``linear``      the activations / weights / upstream gradient of the
                   differentiable linear layer.
 """
@@ -28,8 +32,13 @@ import numpy as np
 __all__ = [
     "rng", "gaussian", "uneven_blocks", "equal_blocks", "tiny",
     "paper_scale", "paper_scale_factors", "case_data", "batched_sizes",
-    "linear_layer", "random_problem",
+    "linear_layer", "random_problem", "philox_matrix", "device_fill",
+    "INPUT_SEED", "batched_item_streams", "batched_device_inputs",
 ]
+
+INPUT_SEED = 3          # key word 0 of the batched workload's input streams
+_TAG_INPUT = 3
+_UNIT_SCALE = np.float32(float.fromhex("0x1.bb67aep-16"))   # float32(1/sqrt((2^32-1)/3))
 
 
 def rng(seed):
@@ -180,3 +189,82 @@ def random_problem(m, n, p, K, seed, dtype=np.float64, lo=None, hi=None,
         lo, hi = 1, n
     off = uneven_blocks(n, K, lo, hi, seed + 1000003)
     return M.astype(dtype), N.astype(dtype), off
+
+
+def batched_item_streams(t):
+    """Stream ids of trial t's M and N in the batched workload."""
+    return 2 * t, 2 * t + 1
+
+
+def philox_matrix(rows, cols, seed, stream, scale=1.0):
+    """rows x cols float32: element q = r * cols + c from 64-bit word q % 4
+    of the Philox4x64-10 block with key (seed, 0) and counter
+    (q // 4, stream, 0, 3 * 2^32) (NumPy's Philox, which advances its
+    counter before each block, so it starts one below); the four 16-bit
+    pieces of the word are summed, centred and scaled to unit variance
+    (Irwin-Hall of four uniforms), then multiplied by ``scale`` in float32
+    (skipped for 1). The same bits as workloads/gen.hip on the device."""
+    total = rows * cols
+    nblk = (total + 3) // 4
+    ctr = (0 | (stream << 64) | (0 << 128) | ((_TAG_INPUT << 32) << 192)) - 1
+    ctr %= 1 << 256
+    start = np.array([(ctr >> (64 * i)) & ((1 << 64) - 1) for i in range(4)], dtype=np.uint64)
+    bg = np.random.Philox(counter=start, key=np.array([seed, 0], dtype=np.uint64))
+    w = bg.random_raw(4 * nblk)[:total]
+    m16 = np.uint64(0xffff)
+    s = (w & m16) + ((w >> np.uint64(16)) & m16) + ((w >> np.uint64(32)) & m16) + (w >> np.uint64(48))
+    x = (s.astype(np.int64) - 131070).astype(np.float32) * _UNIT_SCALE
+    if scale != 1.0:
+        x = x * np.float32(scale)
+    return x.reshape(rows, cols)
+
+
+_wl_lib = None
+
+
+def device_fill(x, seed, stream, scale=1.0):
+    """Fill the float32 device tensor x (2-D, row-major, any leading
+    dimension; memory between rows is not touched) with the stream
+    ``philox_matrix`` describes, on torch's current stream."""
+    import ctypes
+    import os
+    import torch
+    global _wl_lib
+    if _wl_lib is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsbmm_workload.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: run paper_2105_04940_amd.build.build_workload()")
+        lib = ctypes.CDLL(path)
+        lib.sbmm_workload_fill.restype = ctypes.c_int
+        lib.sbmm_workload_fill.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_uint64, ctypes.c_uint64, ctypes.c_float, ctypes.c_void_p]
+        _wl_lib = lib
+    if x.dtype != torch.float32 or x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("device_fill takes a row-major 2-D float32 tensor")
+    rows, cols = x.shape
+    ld = x.stride(0)
+    err = _wl_lib.sbmm_workload_fill(ctypes.c_void_p(x.data_ptr()), rows, cols, ld, seed, stream,
+                                     float(scale), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if err != 0:
+        raise RuntimeError(f"sbmm_workload_fill failed with hipError {err}")
+
+
+def batched_device_inputs(T=512, seed=11, device="cuda:0"):
+    """The batched workload on the device: per trial t (sizes from
+    ``batched_sizes``) M_t and N_t written in place by ``device_fill`` from
+    streams ``batched_item_streams(t)`` of INPUT_SEED, each with its leading
+    dimension rounded up to a multiple of 4 floats (16-byte rows). Returns
+    the size dicts and a list of (M_t, N_t) tensor views."""
+    import torch
+    items = batched_sizes(T, seed=seed)
+    mats = []
+    for t, it in enumerate(items):
+        sm, sn = batched_item_streams(t)
+        Mb = torch.empty((it["m"], (it["n"] + 3) // 4 * 4), dtype=torch.float32, device=device)
+        Nb = torch.empty((it["n"], (it["p"] + 3) // 4 * 4), dtype=torch.float32, device=device)
+        M = Mb[:, :it["n"]]
+        N = Nb[:, :it["p"]]
+        device_fill(M, INPUT_SEED, sm)
+        device_fill(N, INPUT_SEED, sn)
+        mats.append((M, N))
+    return items, mats
