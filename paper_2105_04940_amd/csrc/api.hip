@@ -405,17 +405,22 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   if ((MN != nullptr) != (err_sq != nullptr)) return fail(h, SBMM_E_ARG, "MN and err_sq go together");
   if (MN && ldmn < p) return fail(h, SBMM_E_ARG, "ldmn < p");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t tiles = gemm_tiles(dtype, m, p, false);
+  // bf16 runs in the inner-index-contiguous form: D^T (p x L_pad) first
+  const bool bf = dtype == SBMM_BF16;
+  const int64_t tiles = bf ? gemm_tiles_tn(m, p) : gemm_tiles(dtype, m, p, false);
   const size_t stage_elems = gemm_stage_bytes(dtype, m, p) / sizeof(float);
+  const size_t dt_elems = bf ? (size_t)std::max<int64_t>(p, 1) * std::max<int64_t>(L_pad_max, 1) : 0;
   Arena dry(nullptr);
   dry.take<double>(2 * std::max<int64_t>(tiles, 1));
   dry.take<double>(2);
   dry.take<float>(stage_elems);
+  dry.take<uint16_t>(dt_elems);
   if ((st = ensure_ws(h, dry.off))) return st;
   Arena ar(h->ws);
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
   double* out2 = ar.take<double>(2);
   float* stage = ar.take<float>(stage_elems);
+  uint16_t* Dt = ar.take<uint16_t>(dt_elems);
   if (tiles == 0) {
     if (err_sq) HIP_TRY(h, launch_fill_f64(err_sq, 1, 0.0, s));
     return SBMM_OK;
@@ -425,6 +430,10 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   G.K_host = 0; G.K_dev = L_dev; G.Cout = CD; G.ldc = ldcd; G.Y = MN; G.ldy = ldmn;
   G.tile_part = err_sq ? tile_part : nullptr;
   G.stage = stage;
+  if (bf) {
+    HIP_TRY(h, launch_transpose_bf16(SBMM_BF16, D, L_pad_max, p, ldd, L_dev, Dt, L_pad_max, s));
+    G.B = Dt; G.ldb = L_pad_max; G.b_trans = true;
+  }
   HIP_TRY(h, launch_gemm(G, s));
   if (err_sq) {
     HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
@@ -602,7 +611,11 @@ sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_
     int32_t* list = ar.take<int32_t>(P->c);
     char* dC = ar.take<char>(ges * (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(L, 1));
     char* dD = ar.take<char>(ges * (size_t)std::max<int64_t>(L, 1) * std::max<int64_t>(p, 1));
-    uint16_t* G16 = compute == SBMM_BF16 ? ar.take<uint16_t>((size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(p, 1)) : nullptr;
+    const bool bf = compute == SBMM_BF16;
+    const size_t mp = (size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(p, 1);
+    uint16_t* G16 = bf ? ar.take<uint16_t>(mp) : nullptr;                 // G, m x p
+    uint16_t* G16t = bf ? ar.take<uint16_t>(mp) : nullptr;                // G^T, p x m
+    uint16_t* Ct = bf ? ar.take<uint16_t>((size_t)std::max<int64_t>(L, 1) * std::max<int64_t>(m, 1)) : nullptr;  // C^T, L x m
     if (!pass) {
       if ((st = ensure_ws(h, ar.off))) return st;
       continue;
@@ -615,8 +628,11 @@ sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_
         g1.dt = SBMM_BF16; g1.A = G16; g1.lda = p; g1.B = D; g1.ldb = ldd; g1.b_trans = true;
         g1.m = m; g1.p = L; g1.K_host = p; g1.Cout = dC; g1.ldc = L;
         HIP_TRY(h, launch_gemm(g1, s));
-        GemmLaunch g2{};   // dD = C^T G  (L x p, inner m)
-        g2.dt = SBMM_BF16; g2.A = C; g2.lda = ldc; g2.a_trans = true; g2.B = G16; g2.ldb = p;
+        // dD = C^T G  (L x p, inner m) from C^T (L x m) and G^T (p x m)
+        HIP_TRY(h, launch_transpose_bf16(SBMM_F32, G, m, p, ldg, nullptr, G16t, m, s));
+        HIP_TRY(h, launch_transpose_bf16(SBMM_BF16, C, m, L, ldc, nullptr, Ct, m, s));
+        GemmLaunch g2{};
+        g2.dt = SBMM_BF16; g2.A = Ct; g2.lda = m; g2.B = G16t; g2.ldb = m; g2.b_trans = true;
         g2.m = L; g2.p = p; g2.K_host = m; g2.Cout = dD; g2.ldc = p;
         HIP_TRY(h, launch_gemm(g2, s));
       } else {

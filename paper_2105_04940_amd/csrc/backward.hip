@@ -174,7 +174,54 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t rows, int64_
   }
 }
 
+// y (cols x rows, leading dimension ldy) = bf16 of x^T (x rows x cols,
+// float32 or bf16, leading dimension ldx), through 64 x 64 LDS tiles: reads
+// and writes are both along contiguous rows. With rows_dev, only the first
+// round_up(*rows_dev, 32) rows of x are transposed (the rest of the grid
+// exits).
+template <typename Tin>
+__global__ __launch_bounds__(256) void transpose_bf16_kernel(const Tin* __restrict__ x, int64_t rows, int64_t cols,
+                                                             int64_t ldx, const int64_t* __restrict__ rows_dev,
+                                                             uint16_t* __restrict__ y, int64_t ldy) {
+  __shared__ uint16_t t[64][66];
+  const int64_t tiles_c = (cols + 63) / 64;
+  const int64_t r0 = (int64_t)(blockIdx.x / tiles_c) * 64, c0 = (int64_t)(blockIdx.x % tiles_c) * 64;
+  int64_t nrows = rows;
+  if (rows_dev) nrows = min(rows, (*rows_dev + SBMM_SKETCH_PAD - 1) / SBMM_SKETCH_PAD * SBMM_SKETCH_PAD);
+  if (r0 >= nrows) return;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    uint16_t v = 0;
+    if (r < nrows && c < cols) {
+      if constexpr (sizeof(Tin) == 4) v = float_to_bf16_bits(x[r * ldx + c]);
+      else v = x[r * ldx + c];
+    }
+    t[i][tx] = v;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < cols && r < nrows) y[c * ldy + r] = t[tx][i];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_transpose_bf16(sbmm_dtype src_dt, const void* x, int64_t rows, int64_t cols, int64_t ldx,
+                                 const int64_t* rows_dev, uint16_t* y, int64_t ldy, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const dim3 grid((unsigned)(ceil_div(rows, 64) * ceil_div(cols, 64)));
+  if (src_dt == SBMM_F32)
+    hipLaunchKernelGGL(transpose_bf16_kernel<float>, grid, dim3(256), 0, s, reinterpret_cast<const float*>(x), rows,
+                       cols, ldx, rows_dev, y, ldy);
+  else if (src_dt == SBMM_BF16)
+    hipLaunchKernelGGL(transpose_bf16_kernel<uint16_t>, grid, dim3(256), 0, s, reinterpret_cast<const uint16_t*>(x),
+                       rows, cols, ldx, rows_dev, y, ldy);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 hipError_t launch_to_bf16(const float* x, int64_t rows, int64_t cols, int64_t ldx, uint16_t* y,
                           hipStream_t s) {

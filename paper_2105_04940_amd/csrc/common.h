@@ -154,6 +154,8 @@ struct GemmLaunch {
 // bytes of the float32 staging buffer launch_gemm needs
 size_t gemm_stage_bytes(sbmm_dtype dt, int64_t m, int64_t p);
 int64_t gemm_tiles(sbmm_dtype dt, int64_t m, int64_t p, bool blocknorm);
+// tiles of a bf16 product in the inner-index-contiguous form (B given as N x K)
+int64_t gemm_tiles_tn(int64_t m, int64_t p);
 hipError_t launch_gemm(const GemmLaunch& a, hipStream_t s);
 // Many float32 products in one launch, one workgroup per (problem, tile)
 // item (see gemm.hip). The per problem argument blocks (grouped_gemm_args_bytes
@@ -210,6 +212,10 @@ hipError_t launch_gemm_strided(sbmm_dtype dt, const void* A, int64_t ars, int64_
                                int64_t K, hipStream_t s);
 hipError_t launch_to_bf16(const float* x, int64_t rows, int64_t cols, int64_t ldx, uint16_t* y,
                           hipStream_t s);
+// y (cols x rows, ldy) = bf16(x^T) for x rows x cols (ldx) in F32 or BF16;
+// with rows_dev only the first round_up(*rows_dev, 32) rows are transposed.
+hipError_t launch_transpose_bf16(sbmm_dtype src_dt, const void* x, int64_t rows, int64_t cols, int64_t ldx,
+                                 const int64_t* rows_dev, uint16_t* y, int64_t ldy, hipStream_t s);
 
 // Fill kernels (used instead of memset so that captured graphs hold only
 // kernel nodes).

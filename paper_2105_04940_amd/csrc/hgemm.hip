@@ -227,14 +227,170 @@ __global__ __launch_bounds__(kThreads, WG_PER_CU) void hgemm_kernel(GemmArgs g) 
 }
 
 
+// ============================================================================
+// "TN" form: A is M x K and B is N x K, both row-major with the inner index
+// contiguous (every bf16 product of the path is brought to this form). A
+// workgroup owns a 256 x 256 tile; each of its four waves a 128 x 128 quarter
+// as 4 x 4 blocks of v_mfma_f32_32x32x16_bf16, so every 16-byte fragment read
+// from LDS feeds four matrix instructions. One k-step is 64 wide: 32 KB of A
+// and 32 KB of B, double-buffered (128 KB of LDS, one workgroup per CU),
+// loaded as 16-byte chunks (8 consecutive k) whose position within their
+// 128-byte LDS row is XOR-swizzled by the row index (chunk c of row r at
+// c ^ (r & 7)): the 8 lanes of each read phase then hit 8 different chunk
+// positions, and rows need no padding.
+// ============================================================================
+struct TnTile {
+  static constexpr int BM = 256, BN = 256, BK = 64, KC = BK / 8;
+  static constexpr int NL = BM * KC / kThreads;     // 16-byte chunks of A (and of B) per thread
+  uint4 As[2][BM * KC];
+  uint4 Bs[2][BN * KC];
+  double red[8];
+};
+
+__device__ __forceinline__ int tn_slot(int row, int chunk) { return row * TnTile::KC + (chunk ^ (row & 7)); }
+
+template <bool EDGE>
+__device__ __forceinline__ void hgemm_tn_body(const GemmArgs& g, TnTile& sh, int64_t m0, int64_t n0, int64_t K) {
+  constexpr int BK = TnTile::BK, KC = TnTile::KC, NL = TnTile::NL;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 128;
+  const uint16_t* __restrict__ A = reinterpret_cast<const uint16_t*>(g.A);
+  const uint16_t* __restrict__ B = reinterpret_cast<const uint16_t*>(g.B);
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[b][c] = f32x16{};
+
+  // chunk f = tid + 256 q of a tile: row f / 8, k-chunk f % 8
+  uint4 ra[NL], rb[NL];
+  // interior tiles: whole 16-byte chunks, zero past K (K is a multiple of 8)
+  auto load_one = [&](const uint16_t* X, int64_t ld, int64_t r, int64_t rmax, int64_t k, bool vec) -> uint4 {
+    if (!EDGE) return k < K ? *reinterpret_cast<const uint4*>(X + r * ld + k) : make_uint4(0, 0, 0, 0);
+    if (r < rmax && k + 8 <= K && vec) return *reinterpret_cast<const uint4*>(X + r * ld + k);
+    uint16_t t[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = (r < rmax && k + e < K) ? X[r * ld + k + e] : 0;
+    return make_uint4(t[0] | (uint32_t)t[1] << 16, t[2] | (uint32_t)t[3] << 16, t[4] | (uint32_t)t[5] << 16,
+                      t[6] | (uint32_t)t[7] << 16);
+  };
+  auto load = [&](int64_t kt) {
+    const int64_t k0 = kt * BK;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int f = tid + kThreads * q;
+      ra[q] = load_one(A, g.lda, m0 + f / KC, g.m, k0 + 8 * (f % KC), g.vec_a);
+      rb[q] = load_one(B, g.ldb, n0 + f / KC, g.p, k0 + 8 * (f % KC), g.vec_b);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int f = tid + kThreads * q;
+      sh.As[buf][tn_slot(f / KC, f % KC)] = ra[q];
+      sh.Bs[buf][tn_slot(f / KC, f % KC)] = rb[q];
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < BK / 16; ++s) {
+      bf16x8 av[4], bv[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const uint4 v = sh.As[buf][tn_slot(wm0 + 32 * b + lr, 2 * s + lh)];
+        av[b] = __builtin_bit_cast(bf16x8, v);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const uint4 v = sh.Bs[buf][tn_slot(wn0 + 32 * c + lr, 2 * s + lh)];
+        bv[c] = __builtin_bit_cast(bf16x8, v);
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[b], bv[c], acc[b][c], 0, 0, 0);
+    }
+  };
+
+  const int64_t nkt = (K + BK - 1) / BK;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nkt) load(kt + 1);
+    compute(cur);
+    if (kt + 1 < nkt) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
+      if (EDGE && row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t col = n0 + wn0 + 32 * c + lr;
+        if (EDGE && col >= g.p) continue;
+        const float val = acc[b][c][v];
+        if (Cout) Cout[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (Y) {
+          const double d = dv - (double)Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
+}
+
+__global__ __launch_bounds__(kThreads, 1) void hgemm_tn_kernel(GemmArgs g) {
+  __shared__ TnTile sh;
+  int64_t tm, tn;
+  tile_coords(g, tm, tn);
+  const int64_t m0 = tm * TnTile::BM, n0 = tn * TnTile::BN;
+  const int64_t K = inner_extent(g);
+  const bool interior = g.vec_a && g.vec_b && m0 + TnTile::BM <= g.m && n0 + TnTile::BN <= g.p && K % 8 == 0;
+  if (interior)
+    hgemm_tn_body<false>(g, sh, m0, n0, K);
+  else
+    hgemm_tn_body<true>(g, sh, m0, n0, K);
+}
+
+
 constexpr int BF16_WMB = 2, BF16_WNB = 2, BF16_BK = 64, BF16_WGS = 2;   // 128 x 128
 
 }  // namespace
 
 void hgemm_tile_shape(int64_t* bm, int64_t* bn) { *bm = 64 * BF16_WMB; *bn = 64 * BF16_WNB; }
 
+void hgemm_tn_tile_shape(int64_t* bm, int64_t* bn) { *bm = TnTile::BM; *bn = TnTile::BN; }
+
+int64_t gemm_tiles_tn(int64_t m, int64_t p) { return ceil_div(m, TnTile::BM) * ceil_div(p, TnTile::BN); }
+
 hipError_t launch_hgemm(const GemmLaunch& L, hipStream_t s) {
   int64_t bm, bn;
+  if (L.b_trans && !L.a_trans) {
+    // both operands inner-index contiguous: the 256 x 256 kernel
+    hgemm_tn_tile_shape(&bm, &bn);
+    const GemmArgs g = make_gemm_args(L, bm, bn);
+    const int64_t tiles = g.tiles_m * g.tiles_n;
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(hgemm_tn_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
+    return hipGetLastError();
+  }
   hgemm_tile_shape(&bm, &bn);
   const GemmArgs g = make_gemm_args(L, bm, bn);
   const int64_t tiles = g.tiles_m * g.tiles_n;
