@@ -370,8 +370,9 @@ def main():
         return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1],
-                    "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -d <dir> -o run -- python bench.py "
-                    "--steps 1 --warmup 0 --no-cpu-baseline --no-linear-layer --calibration-copy")
+                    "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o run -- "
+                    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-linear-layer --no-batched "
+                    "--calibration-copy")
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the path "
@@ -422,6 +423,19 @@ def main():
                 res[(rule, c)] = (err, pl, CD)
         return res
 
+    def mx_leg(record, col, row, blk, MN, bp):
+        res = {}
+        for rule in RULES:
+            for c in CS:
+                prob = pk.Problem(Md, Nd, off, c, prob=rule, seed=0, trial=0,
+                                  blkprod_sq=bp if rule == "exact" else None)
+                pl = h.plan(prob, col, row, blk, sync=False)
+                C8, Cs, Dt8, Ds = h.sketch_mx(prob, pl)
+                CD, err = (timed(f"mx_c{c}", lambda: h.sketch_gemm_mx(C8, Cs, Dt8, Ds, pl, MN=MN))
+                           if record else h.sketch_gemm_mx(C8, Cs, Dt8, Ds, pl, MN=MN))
+                res[(rule, c)] = (err, pl, CD)
+        return res
+
     def step(record):
         res = {}
         base = pk.Problem(Md, Nd, off, CS[-1])
@@ -465,6 +479,12 @@ def main():
         sketch_leg(False, col, row, blk, MN, bp, torch.bfloat16, "bf16")
     for _ in range(args.steps):
         b16 = sketch_leg(True, col, row, blk, MN, bp, torch.bfloat16, "bf16")
+    torch.cuda.synchronize()
+    # MX E4M3 sketches of the same draws
+    for _ in range(args.warmup):
+        mx_leg(False, col, row, blk, MN, bp)
+    for _ in range(args.steps):
+        mx8 = mx_leg(True, col, row, blk, MN, bp)
     torch.cuda.synchronize()
 
     mn2v = mn2.item()
@@ -530,6 +550,21 @@ def main():
                                                    / f32[(r, c)][2].norm()).item())
                                for r in RULES for c in CS},
     }
+    t_mx = {c: avg_ms(f"mx_c{c}") for c in CS}
+    mx_ms = sum(t_mx[c] for c in CS) * len(RULES)
+    mx = {
+        "format": "OCP MX E4M3 (E8M0 scale per 32 sketch columns), float32 accumulation",
+        "sketch_gemm_TFLOPs": b16_flops / mx_ms / 1e9,
+        "peak": 5000.0, "unit": "TFLOP/s",
+        "frac": b16_flops / mx_ms / 1e9 / 5000.0,
+        "speedup_vs_f32": sk_total_ms / mx_ms,
+        "speedup_vs_bf16": b16_ms / mx_ms,
+        "per_c": {f"c{c}": {"ms": t_mx[c], "TFLOP/s": sketch_flops[c] / t_mx[c] / 1e9} for c in CS},
+        "rel_err": {f"{r}/c{c}": math.sqrt(mx8[(r, c)][0].item() / mn2v) for r in RULES for c in CS},
+        "cd_rel_diff_vs_f32": {f"{r}/c{c}": float(((mx8[(r, c)][2] - f32[(r, c)][2]).norm()
+                                                   / f32[(r, c)][2].norm()).item())
+                               for r in RULES for c in CS},
+    }
 
     out = {
         "metric": METRIC,
@@ -560,9 +595,10 @@ def main():
         "roofline": roofline,
         "roofline_norm_pass": norm_roof,
         "bf16": bf16,
+        "mx_e4m3": mx,
     }
     if not args.no_linear_layer:
-        del Md, Nd, MN, res, f32, b16
+        del Md, Nd, MN, res, f32, b16, mx8
         torch.cuda.empty_cache()
         out["linear_layer"] = linear_layer_leg(h, pk, wl, torch, args.steps, args.warmup)
     if not args.no_batched:

@@ -199,6 +199,32 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p,
                              int64_t ldcd, const void* MN, int64_t ldmn,
                              double* err_sq, sbmm_stream stream);
 
+/* The sketch in OCP MX E4M3 (8-bit floats with a shared power-of-two E8M0
+ * scale per 32 consecutive sketch columns; float32 inputs): the float32 sketch
+ * values C[:, l], D[l, :] of sbmm_sketch are grouped in blocks of 32 along l;
+ * a block's scale is 2^X with X = floor(log2 max|x|) - 8 (the byte X + 127;
+ * 1 for an all-zero block) and its elements are x / 2^X clamped to +-448 and
+ * rounded to the nearest E4M3 (ties to even). C (m x L_pad bytes, ldc) with
+ * scales Cs (m x L_pad/32 bytes, ldcs, blocks of one row); D is written
+ * transposed: Dt (p x L_pad bytes, lddt) with scales Ds (p x L_pad/32, ldds,
+ * blocks of one column of D). ldc, lddt >= L_pad_max and multiples of 16;
+ * ldcs, ldds >= round_up(L_pad_max / 32, 4) and multiples of 4; C, Dt 16-byte
+ * and Cs, Ds 4-byte aligned. Either the C or the D pair may be NULL. The
+ * scales of the blocks past L_pad up to a multiple of 4 blocks are written as
+ * 1 (the product reads scales four at a time). */
+sbmm_status sbmm_sketch_mx(sbmm_handle h, const sbmm_problem* prob, const sbmm_plan_out* plan, void* C, int64_t ldc,
+                           void* Cs, int64_t ldcs, void* Dt, int64_t lddt, void* Ds, int64_t ldds,
+                           sbmm_stream stream);
+
+/* Sketched product CD = C D of an MX E4M3 sketch (from sbmm_sketch_mx) on the
+ * block-scaled matrix instruction with float32 accumulation, over the inner
+ * extent round_up(*L_dev, 32); CD (m x p, float32) and the optional error
+ * against MN as in sbmm_sketch_gemm. */
+sbmm_status sbmm_sketch_gemm_mx(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_max, const int64_t* L_dev,
+                                const void* C, int64_t ldc, const void* Cs, int64_t ldcs, const void* Dt,
+                                int64_t lddt, const void* Ds, int64_t ldds, float* CD, int64_t ldcd,
+                                const float* MN, int64_t ldmn, double* err_sq, sbmm_stream stream);
+
 /* ||X - Y||_F^2 and ||Y||_F^2 of two m x p matrices (F64 or F32) into
  * out2[0..1] (device, float64, fixed order). */
 sbmm_status sbmm_error(sbmm_handle h, int64_t m, int64_t p, sbmm_dtype dtype,

@@ -33,6 +33,7 @@ EXPORTS = (
     "sbmm_error", "sbmm_run", "sbmm_backward",
     "sbmm_batch_create", "sbmm_batch_destroy", "sbmm_batch_run", "sbmm_batch_capture",
     "sbmm_batch_replay", "sbmm_batch_tune", "sbmm_batch_set_tuning",
+    "sbmm_sketch_mx", "sbmm_sketch_gemm_mx",
 )
 BATCH_TILES = ((128, 128), (64, 128), (128, 64), (64, 64))
 
@@ -126,6 +127,9 @@ def load_library(path=LIB_PATH):
         "sbmm_batch_replay": (st, [vp, vp, vp]),
         "sbmm_batch_tune": (st, [vp, vp, i32, P(BatchTuning_t), vp]),
         "sbmm_batch_set_tuning": (st, [vp, vp, P(BatchTuning_t)]),
+        "sbmm_sketch_mx": (st, [vp, P(Problem_t), P(PlanOut_t), vp, i64, vp, i64, vp, i64, vp, i64, vp]),
+        "sbmm_sketch_gemm_mx": (st, [vp, i64, i64, i64, vp, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                                     vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -347,6 +351,36 @@ class Handle:
         self._check(self._lib.sbmm_sketch_gemm(
             self.h, m, p, Lp, _ptr(plan.L_dev), dtype_code(C.dtype), _ptr(C), C.stride(0),
             _ptr(D), D.stride(0), _ptr(CD), p, _ptr(MN), p if MN is not None else 0,
+            _ptr(err), _stream()))
+        return CD, err
+
+    def sketch_mx(self, problem, plan):
+        """The sketch in MX E4M3: (C, Cs, Dt, Ds) uint8 tensors: C m x L_pad_max
+        codes, Cs m x nsc scale bytes, Dt (D transposed) p x L_pad_max codes,
+        Ds p x nsc scale bytes, nsc = round_up(L_pad_max / 32, 4)."""
+        torch = _torch()
+        s = problem.struct()
+        Lp = plan.sizes["L_pad_max"]
+        nsc = (Lp // 32 + 3) // 4 * 4
+        dev = problem.M.device
+        C = torch.empty((s.m, Lp), dtype=torch.uint8, device=dev)
+        Cs = torch.empty((s.m, nsc), dtype=torch.uint8, device=dev)
+        Dt = torch.empty((s.p, Lp), dtype=torch.uint8, device=dev)
+        Ds = torch.empty((s.p, nsc), dtype=torch.uint8, device=dev)
+        ps = plan.struct()
+        self._check(self._lib.sbmm_sketch_mx(self.h, ctypes.byref(s), ctypes.byref(ps), _ptr(C), Lp, _ptr(Cs),
+                                             nsc, _ptr(Dt), Lp, _ptr(Ds), nsc, _stream()))
+        return C, Cs, Dt, Ds
+
+    def sketch_gemm_mx(self, C, Cs, Dt, Ds, plan, MN=None, store=True):
+        torch = _torch()
+        m, Lp = C.shape
+        p = Dt.shape[0]
+        CD = torch.empty((m, p), dtype=torch.float32, device=C.device) if store else None
+        err = torch.empty(1, dtype=torch.float64, device=C.device) if MN is not None else None
+        self._check(self._lib.sbmm_sketch_gemm_mx(
+            self.h, m, p, Lp, _ptr(plan.L_dev), _ptr(C), C.stride(0), _ptr(Cs), Cs.stride(0), _ptr(Dt),
+            Dt.stride(0), _ptr(Ds), Ds.stride(0), _ptr(CD), p, _ptr(MN), p if MN is not None else 0,
             _ptr(err), _stream()))
         return CD, err
 

@@ -442,6 +442,78 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   return SBMM_OK;
 }
 
+sbmm_status sbmm_sketch_mx(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_out* plan, void* C, int64_t ldc,
+                           void* Cs, int64_t ldcs, void* Dt, int64_t lddt, void* Ds, int64_t ldds,
+                           sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  sbmm_sizes sz;
+  if ((st = validate(h, P, &sz, true))) return st;
+  if (!plan || !plan->col_off || !plan->colmap || !plan->colscale) return fail(h, SBMM_E_ARG, "plan buffers missing");
+  if (P->in_dtype != SBMM_F32) return fail(h, SBMM_E_UNSUPPORTED, "the MX E4M3 sketch takes float32 inputs");
+  const int64_t nsc = round_up(sz.L_pad_max / 32, 4);
+  if (C && (!Cs || ldc < sz.L_pad_max || ldc % 16 || ldcs < nsc || ldcs % 4))
+    return fail(h, SBMM_E_ARG, "C needs ldc >= L_pad_max (multiple of 16) and scales Cs with ldcs >= %lld (multiple of 4)",
+                (long long)nsc);
+  if (Dt && (!Ds || lddt < sz.L_pad_max || lddt % 16 || ldds < nsc || ldds % 4))
+    return fail(h, SBMM_E_ARG, "Dt needs lddt >= L_pad_max (multiple of 16) and scales Ds with ldds >= %lld (multiple of 4)",
+                (long long)nsc);
+  if ((C && (uintptr_t)C % 16) || (Dt && (uintptr_t)Dt % 16) || (Cs && (uintptr_t)Cs % 4) || (Ds && (uintptr_t)Ds % 4))
+    return fail(h, SBMM_E_ARG, "C / Dt must be 16-byte aligned, Cs / Ds 4-byte aligned");
+  MxGatherLaunch g{};
+  g.M = reinterpret_cast<const float*>(P->M); g.ldm = P->ldm;
+  g.N = reinterpret_cast<const float*>(P->N); g.ldn = P->ldn; g.m = P->m; g.p = P->p;
+  g.L_dev = plan->col_off + P->c; g.L_pad_max = sz.L_pad_max;
+  g.colmap = plan->colmap; g.colscale = plan->colscale;
+  g.C = reinterpret_cast<uint8_t*>(C); g.ldc = ldc; g.Cs = reinterpret_cast<uint8_t*>(Cs); g.ldcs = ldcs;
+  g.Dt = reinterpret_cast<uint8_t*>(Dt); g.lddt = lddt; g.Ds = reinterpret_cast<uint8_t*>(Ds); g.ldds = ldds;
+  HIP_TRY(h, launch_mx_gather(g, (hipStream_t)stream));
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_sketch_gemm_mx(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_max, const int64_t* L_dev,
+                                const void* C, int64_t ldc, const void* Cs, int64_t ldcs, const void* Dt,
+                                int64_t lddt, const void* Ds, int64_t ldds, float* CD, int64_t ldcd,
+                                const float* MN, int64_t ldmn, double* err_sq, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  if (m < 0 || p < 0 || L_pad_max < 0 || !L_dev) return fail(h, SBMM_E_ARG, "bad sizes or L_dev");
+  const int64_t nsc = round_up(L_pad_max / 32, 4);
+  if (m > 0 && p > 0 && L_pad_max > 0) {
+    if (!C || !Cs || !Dt || !Ds) return fail(h, SBMM_E_ARG, "C, Cs, Dt and Ds are required");
+    if (ldc < L_pad_max || ldc % 16 || lddt < L_pad_max || lddt % 16 || ldcs < nsc || ldcs % 4 || ldds < nsc ||
+        ldds % 4)
+      return fail(h, SBMM_E_ARG, "leading dimensions: ldc, lddt >= L_pad_max (multiples of 16); ldcs, ldds >= %lld "
+                  "(multiples of 4)", (long long)nsc);
+    if ((uintptr_t)C % 16 || (uintptr_t)Dt % 16 || (uintptr_t)Cs % 4 || (uintptr_t)Ds % 4)
+      return fail(h, SBMM_E_ARG, "C / Dt must be 16-byte aligned, Cs / Ds 4-byte aligned");
+  }
+  if (CD && ldcd < p) return fail(h, SBMM_E_ARG, "ldcd < p");
+  if ((MN != nullptr) != (err_sq != nullptr)) return fail(h, SBMM_E_ARG, "MN and err_sq go together");
+  if (MN && ldmn < p) return fail(h, SBMM_E_ARG, "ldmn < p");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t tiles = mx_gemm_tiles(m, p);
+  if ((st = ensure_ws(h, 512 + sizeof(double) * (2 * std::max<int64_t>(tiles, 1) + 2)))) return st;
+  Arena ar(h->ws);
+  double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
+  double* out2 = ar.take<double>(2);
+  if (tiles == 0) {
+    if (err_sq) HIP_TRY(h, launch_fill_f64(err_sq, 1, 0.0, s));
+    return SBMM_OK;
+  }
+  MxGemmLaunch G{};
+  G.A = reinterpret_cast<const uint8_t*>(C); G.lda = ldc; G.As = reinterpret_cast<const uint8_t*>(Cs); G.ldas = ldcs;
+  G.B = reinterpret_cast<const uint8_t*>(Dt); G.ldb = lddt; G.Bs = reinterpret_cast<const uint8_t*>(Ds); G.ldbs = ldds;
+  G.m = m; G.p = p; G.K_dev = L_dev; G.Cout = CD; G.ldc = ldcd; G.Y = MN; G.ldy = ldmn;
+  G.tile_part = err_sq ? tile_part : nullptr;
+  HIP_TRY(h, launch_mx_gemm(G, s));
+  if (err_sq) {
+    HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
+    HIP_TRY(h, hipMemcpyAsync(err_sq, out2, sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return SBMM_OK;
+}
+
 sbmm_status sbmm_error(sbmm_handle h, int64_t m, int64_t p, sbmm_dtype dtype, const void* X, int64_t ldx,
                        const void* Y, int64_t ldy, double* out2, sbmm_stream stream) {
   sbmm_status st = check_handle(h);

@@ -217,6 +217,33 @@ hipError_t launch_to_bf16(const float* x, int64_t rows, int64_t cols, int64_t ld
 hipError_t launch_transpose_bf16(sbmm_dtype src_dt, const void* x, int64_t rows, int64_t cols, int64_t ldx,
                                  const int64_t* rows_dev, uint16_t* y, int64_t ldy, hipStream_t s);
 
+// MX E4M3 sketch (blocks of 32 sketch columns, E8M0 scales) and its
+// product on the block-scaled matrix instruction. C: m x L_pad bytes (ldc a
+// multiple of 16), Cs: m x L_pad/32 scales; Dt: D transposed, p x L_pad
+// bytes, Ds: p x L_pad/32 scales; scale leading dimensions at least
+// round_up(L_pad_max / 32, 4) and multiples of 4.
+struct MxGatherLaunch {
+  const float* M; int64_t ldm;
+  const float* N; int64_t ldn;
+  int64_t m, p;
+  const int64_t* L_dev; int64_t L_pad_max;
+  const int32_t* colmap; const double* colscale;
+  uint8_t* C; int64_t ldc; uint8_t* Cs; int64_t ldcs;
+  uint8_t* Dt; int64_t lddt; uint8_t* Ds; int64_t ldds;
+};
+hipError_t launch_mx_gather(const MxGatherLaunch& a, hipStream_t s);
+struct MxGemmLaunch {
+  const uint8_t* A; int64_t lda; const uint8_t* As; int64_t ldas;
+  const uint8_t* B; int64_t ldb; const uint8_t* Bs; int64_t ldbs;
+  int64_t m, p;
+  const int64_t* K_dev;
+  float* Cout; int64_t ldc;
+  const float* Y; int64_t ldy;
+  double* tile_part;
+};
+int64_t mx_gemm_tiles(int64_t m, int64_t p);
+hipError_t launch_mx_gemm(const MxGemmLaunch& a, hipStream_t s);
+
 // Fill kernels (used instead of memset so that captured graphs hold only
 // kernel nodes).
 hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s);

@@ -352,60 +352,85 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
         rb[q][e] = (krow < K && col + e < g.p) ? B[krow * g.ldb + col + e] : 0.0f;
     }
   };
-  // gathered loads (sketch read in place): a lane keeps one inner index of A
-  // (16 lanes cover 16 consecutive sketch columns of a row) and reads the
-  // drawn column of M; B rows are rows colmap[k] of N. Each value is
-  // (float)(x * scale) with the product in float64, as the gather writes it.
-  constexpr int GR = kThreads / BK;                 // A rows per pass
-  auto load_gather = [&](int64_t kt) {
+  // gathered loads (sketch read in place): the A tile is loaded in the same
+  // layout as the plain one (a lane reads 4 consecutive sketch columns of a
+  // row), from columns colmap[k..k+3] of M: one 16-byte load when they are 4
+  // consecutive columns with one scale (the common case inside a drawn
+  // block), else 4 element loads; B rows are rows colmap[k] of N. Each value
+  // is (float)(x * scale) with the product in float64, as the gather writes
+  // it. The column map and scales of step kt + 1 are fetched while step kt's
+  // matrix loads are in flight, so a step never waits on the map and then
+  // on the data.
+  int4 ja = {-1, -1, -1, -1};
+  double sa[4] = {0.0, 0.0, 0.0, 0.0};
+  int32_t jb[NB];
+  double sb[NB];
+  const int ca = tid % KC;   // A chunk of this lane (the same for every q since kThreads % KC == 0)
+  const int64_t nsteps = EDGE ? (K + BK - 1) / BK : K / BK;
+  auto load_meta = [&](int64_t kt) {
     const int64_t k0 = kt * BK;
-    {
-      const int kk = tid % BK;
-      const int64_t k = k0 + kk;
-      const int32_t j = (!EDGE || k < K) ? g.colmap[k] : -1;
-      const double sc = j >= 0 ? g.colscale[k] : 0.0;
+    const int64_t ka = k0 + 4 * ca;
+    if (!EDGE || ka < K) {
+      ja = *reinterpret_cast<const int4*>(g.colmap + ka);
+      const f64x2 s01 = *reinterpret_cast<const f64x2*>(g.colscale + ka);
+      const f64x2 s23 = *reinterpret_cast<const f64x2*>(g.colscale + ka + 2);
+      sa[0] = s01[0]; sa[1] = s01[1]; sa[2] = s23[0]; sa[3] = s23[1];
+    } else {
+      ja = int4{-1, -1, -1, -1};
+    }
 #pragma unroll
-      for (int q = 0; q < 4 * NA; ++q) {
-        const int64_t row = m0 + tid / BK + GR * q;
-        float v = 0.0f;
-        if (j >= 0 && (!EDGE || row < g.m)) v = (float)((double)A[row * g.lda + j] * sc);
-        ra[q / 4][q % 4] = v;
+    for (int q = 0; q < NB; ++q) {
+      const int64_t krow = k0 + (tid + kThreads * q) / (BN / 4);
+      jb[q] = (!EDGE || krow < K) ? g.colmap[krow] : -1;
+      sb[q] = jb[q] >= 0 ? g.colscale[krow] : 0.0;
+    }
+  };
+  auto load_gather = [&](int64_t kt) {
+    const bool run = ja.x >= 0 && ja.y == ja.x + 1 && ja.z == ja.x + 2 && ja.w == ja.x + 3 &&
+                     sa[1] == sa[0] && sa[2] == sa[0] && sa[3] == sa[0];
+    const int jj[4] = {ja.x, ja.y, ja.z, ja.w};
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int64_t row = m0 + (tid + kThreads * q) / KC;
+      const bool row_ok = !EDGE || row < g.m;
+      if (run && row_ok) {
+        f32x4 x;
+        __builtin_memcpy(&x, A + row * g.lda + ja.x, sizeof(x));   // 4-byte aligned 16-byte load
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[q][e] = (float)((double)x[e] * sa[0]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          ra[q][e] = (jj[e] >= 0 && row_ok) ? (float)((double)A[row * g.lda + jj[e]] * sa[e]) : 0.0f;
       }
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int f = tid + kThreads * q;
-      const int kr = f / (BN / 4), c4 = f % (BN / 4);
-      const int64_t krow = k0 + kr, col = n0 + 4 * c4;
-      const int32_t j = (!EDGE || krow < K) ? g.colmap[krow] : -1;
-      if (j < 0) {
+      const int64_t col = n0 + 4 * (f % (BN / 4));
+      if (jb[q] < 0) {
         rb[q] = f32x4{};
         continue;
       }
-      const double sc = g.colscale[krow];
-      const float* src = B + (int64_t)j * g.ldb + col;
+      const float* src = B + (int64_t)jb[q] * g.ldb + col;
       if (!EDGE) {
         const f32x4 x = *reinterpret_cast<const f32x4*>(src);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rb[q][e] = (float)((double)x[e] * sc);
+        for (int e = 0; e < 4; ++e) rb[q][e] = (float)((double)x[e] * sb[q]);
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) rb[q][e] = col + e < g.p ? (float)((double)src[e] * sc) : 0.0f;
+        for (int e = 0; e < 4; ++e) rb[q][e] = col + e < g.p ? (float)((double)src[e] * sb[q]) : 0.0f;
       }
     }
+    if (kt + 1 < nsteps) load_meta(kt + 1);
   };
   auto store_tile = [&](int buf) {
-    if constexpr (GATHER) {
 #pragma unroll
-      for (int q = 0; q < 4 * NA; ++q) sh.As[buf][tid % BK][tid / BK + GR * q] = ra[q / 4][q % 4];
-    } else {
+    for (int q = 0; q < NA; ++q) {
+      const int f = tid + kThreads * q;
+      const int r = f / KC, c4 = f % KC;
 #pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        const int f = tid + kThreads * q;
-        const int r = f / KC, c4 = f % KC;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) sh.As[buf][4 * c4 + e][r] = ra[q][e];
-      }
+      for (int e = 0; e < 4; ++e) sh.As[buf][4 * c4 + e][r] = ra[q][e];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -471,6 +496,7 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
     else load_fast(kt);
   };
   if (nkt > 0) {
+    if constexpr (GATHER) load_meta(0);
     load(0);
     store_tile(0);
   }

@@ -1,0 +1,336 @@
+// The sketch in 8-bit floating point with block scales (OCP MX E4M3) and
+// its product on the block-scaled matrix instruction
+// v_mfma_scale_f32_32x32x64_f8f6f4.
+//
+// Quantization (per row of C and per column of D, blocks of 32 consecutive
+// sketch columns): the sketch value x = (float)(colscale[l] * M[i, colmap[l]])
+// is formed as the float32 gather forms it; the block's shared exponent is
+// X = floor(log2(amax)) - 8 (8 = largest E4M3 exponent; 0 for an all-zero
+// block), stored as the E8M0 byte X + 127; each element is x / 2^X (exact),
+// clamped to +-448 and rounded to nearest-even E4M3. D is written transposed
+// (p x L_pad, sketch index contiguous), so both operands of the product have
+// the inner index contiguous.
+//
+// Product: 256 x 256 tiles, four waves of 128 x 128 as 4 x 4 blocks of the
+// 32x32x64 instruction; a k-step is 128 sketch columns (128 bytes per row,
+// double-buffered in LDS with the XOR chunk swizzle of the bf16 kernel);
+// lane (r = lane % 32, h = lane / 32) of a block holds 32 consecutive inner
+// indices 32h..32h+31 of row r and the E8M0 scale of that 32-block. Products
+// of E4M3 values are exact in float32 and accumulate in float32.
+#include "gemm_common.h"
+
+namespace {
+
+using namespace gemm_detail;
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBlk = 32;   // MX block
+
+// E8M0 exponent byte and the scale-down factor of one block
+__device__ __forceinline__ void mx_block_scale(float amax, uint8_t* ebyte, float* down) {
+  int X = 0;
+  if (amax > 0.0f) X = max(ilogbf(amax) - 8, -127);   // E8M0 holds 2^-127 .. 2^127
+  *ebyte = (uint8_t)(X + 127);
+  *down = ldexpf(1.0f, -X);
+}
+
+__device__ __forceinline__ uint32_t pack4_e4m3(float a, float b, float c, float d) {
+  auto cl = [](float v) { return fminf(fmaxf(v, -448.0f), 448.0f); };
+  uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32(cl(a), cl(b), 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(cl(c), cl(d), w, true);
+  return w;
+}
+
+struct MxGatherArgs {
+  const float* M; int64_t ldm;
+  const float* N; int64_t ldn;
+  int64_t m, p;
+  const int64_t* L_dev;
+  int64_t nblk_max;                 // L_pad_max / 32
+  const int32_t* colmap; const double* colscale;
+  uint8_t* C; int64_t ldc; uint8_t* Cs; int64_t ldcs;     // m x L_pad, m x L_pad/32
+  uint8_t* Dt; int64_t lddt; uint8_t* Ds; int64_t ldds;   // p x L_pad, p x L_pad/32
+  int64_t cgroups;                  // workgroups on the C part
+};
+
+// C part: workgroup (row i, group of 256 blocks), one block per thread.
+// Dt part: workgroup (256 columns j, block kb), one column per thread (the
+// reads of one sketch row are coalesced across the threads).
+__global__ __launch_bounds__(256) void mx_gather_kernel(MxGatherArgs a) {
+  const int64_t L = *a.L_dev;
+  const int64_t nblk = (L + kBlk - 1) / kBlk;
+  const int64_t bid = blockIdx.x;
+  float x[kBlk];
+  if (bid < a.cgroups) {
+    const int64_t per_row = (a.nblk_max + 255) / 256;
+    const int64_t i = bid / per_row;
+    const int64_t kb = (bid % per_row) * 256 + threadIdx.x;
+    if (kb >= nblk) {
+      // the product reads scales in words of 4 blocks: the rest of the last
+      // word is 1 (127), its data is never read
+      if (kb < (nblk + 3) / 4 * 4) a.Cs[i * a.ldcs + kb] = 127;
+      return;
+    }
+    float amax = 0.0f;
+#pragma unroll
+    for (int e = 0; e < kBlk; ++e) {
+      const int64_t l = kb * kBlk + e;
+      const int32_t j = a.colmap[l];
+      x[e] = j >= 0 ? (float)((double)a.M[i * a.ldm + j] * a.colscale[l]) : 0.0f;
+      amax = fmaxf(amax, fabsf(x[e]));
+    }
+    uint8_t eb;
+    float down;
+    mx_block_scale(amax, &eb, &down);
+    uint32_t w[kBlk / 4];
+#pragma unroll
+    for (int q = 0; q < kBlk / 4; ++q)
+      w[q] = pack4_e4m3(x[4 * q] * down, x[4 * q + 1] * down, x[4 * q + 2] * down, x[4 * q + 3] * down);
+    uint4* dst = reinterpret_cast<uint4*>(a.C + i * a.ldc + kb * kBlk);
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    a.Cs[i * a.ldcs + kb] = eb;
+  } else {
+    const int64_t b = bid - a.cgroups;
+    const int64_t jgroups = (a.p + 255) / 256;
+    const int64_t kb = b / jgroups;
+    const int64_t j = (b % jgroups) * 256 + threadIdx.x;
+    if (j >= a.p) return;
+    if (kb >= nblk) {
+      if (kb < (nblk + 3) / 4 * 4) a.Ds[j * a.ldds + kb] = 127;
+      return;
+    }
+    float amax = 0.0f;
+#pragma unroll
+    for (int e = 0; e < kBlk; ++e) {
+      const int64_t l = kb * kBlk + e;
+      const int32_t r = a.colmap[l];
+      x[e] = r >= 0 ? (float)((double)a.N[(int64_t)r * a.ldn + j] * a.colscale[l]) : 0.0f;
+      amax = fmaxf(amax, fabsf(x[e]));
+    }
+    uint8_t eb;
+    float down;
+    mx_block_scale(amax, &eb, &down);
+    uint32_t w[kBlk / 4];
+#pragma unroll
+    for (int q = 0; q < kBlk / 4; ++q)
+      w[q] = pack4_e4m3(x[4 * q] * down, x[4 * q + 1] * down, x[4 * q + 2] * down, x[4 * q + 3] * down);
+    uint4* dst = reinterpret_cast<uint4*>(a.Dt + j * a.lddt + kb * kBlk);
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    a.Ds[j * a.ldds + kb] = eb;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Product
+// ---------------------------------------------------------------------------
+struct MxArgs {
+  const uint8_t* A; int64_t lda; const uint8_t* As; int64_t ldas;   // M x K bytes, M x K/32 scales
+  const uint8_t* B; int64_t ldb; const uint8_t* Bs; int64_t ldbs;   // N x K bytes, N x K/32 scales
+  int64_t m, p;
+  const int64_t* K_dev;             // inner extent = round_up(*K_dev, 32)
+  float* C; int64_t ldc;
+  const float* Y; int64_t ldy;
+  double* tile_part;
+  int64_t tiles_m, tiles_n;
+};
+
+struct MxTile {
+  static constexpr int BM = 256, BN = 256, BK = 128, KC = BK / 16;   // 16-byte chunks per row
+  static constexpr int NL = BM * KC / kThreads;
+  uint4 As[2][BM * KC];
+  uint4 Bs[2][BN * KC];
+  double red[8];
+};
+
+__device__ __forceinline__ int mx_slot(int row, int chunk) { return row * MxTile::KC + (chunk ^ (row & 7)); }
+
+__device__ __forceinline__ void mx_tile_coords(const MxArgs& g, int64_t& tm, int64_t& tn) {
+  // the XCD-aware order of the other products
+  constexpr int64_t kXcd = 8, kGroup = 8;
+  const int64_t bid = blockIdx.x;
+  const int64_t tiles = g.tiles_m * g.tiles_n;
+  const int64_t per = tiles / kXcd;
+  const int64_t lg = bid < per * kXcd ? (bid % kXcd) * per + bid / kXcd : bid;
+  const int64_t span = kGroup * g.tiles_n;
+  const int64_t first = (lg / span) * kGroup;
+  const int64_t gm = min(g.tiles_m - first, kGroup);
+  const int64_t r = lg % span;
+  tm = first + r % gm;
+  tn = r / gm;
+}
+
+template <bool EDGE>
+__device__ __forceinline__ void mx_body(const MxArgs& g, MxTile& sh, int64_t m0, int64_t n0, int64_t K) {
+  constexpr int BK = MxTile::BK, KC = MxTile::KC, NL = MxTile::NL;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 128;
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[b][c] = f32x16{};
+
+  uint4 ra[NL], rb[NL];
+  // K is a multiple of 32; chunks past K or outside the matrix are zero
+  auto load_one = [&](const uint8_t* X, int64_t ld, int64_t r, int64_t rmax, int64_t k) -> uint4 {
+    if ((!EDGE || r < rmax) && k < K) return *reinterpret_cast<const uint4*>(X + r * ld + k);
+    return make_uint4(0, 0, 0, 0);
+  };
+  auto load = [&](int64_t kt) {
+    const int64_t k0 = kt * BK;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int f = tid + kThreads * q;
+      ra[q] = load_one(g.A, g.lda, m0 + f / KC, g.m, k0 + 16 * (f % KC));
+      rb[q] = load_one(g.B, g.ldb, n0 + f / KC, g.p, k0 + 16 * (f % KC));
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int f = tid + kThreads * q;
+      sh.As[buf][mx_slot(f / KC, f % KC)] = ra[q];
+      sh.Bs[buf][mx_slot(f / KC, f % KC)] = rb[q];
+    }
+  };
+  // the four E8M0 scales of this k-step for the rows / columns of a lane
+  // (one 32-bit word per block of the wave; 127 = 1 outside the matrix)
+  auto scales = [&](const uint8_t* S, int64_t lds, int64_t r, int64_t rmax, int64_t kt) -> uint32_t {
+    if (EDGE && r >= rmax) return 0x7f7f7f7fu;
+    return *reinterpret_cast<const uint32_t*>(S + r * lds + 4 * kt);
+  };
+  auto compute = [&](int buf, int64_t kt) {
+    uint32_t sa[4], sb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) sa[b] = scales(g.As, g.ldas, m0 + wm0 + 32 * b + lr, g.m, kt);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sb[c] = scales(g.Bs, g.ldbs, n0 + wn0 + 32 * c + lr, g.p, kt);
+#pragma unroll
+    for (int s = 0; s < BK / 64; ++s) {
+      i32x8 av[4], bv[4];
+      const int c0 = 4 * s + 2 * lh;   // this lane's two 16-byte chunks
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int row = wm0 + 32 * b + lr;
+        const uint4 u0 = sh.As[buf][mx_slot(row, c0)], u1 = sh.As[buf][mx_slot(row, c0 + 1)];
+        av[b] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w, (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int row = wn0 + 32 * c + lr;
+        const uint4 u0 = sh.Bs[buf][mx_slot(row, c0)], u1 = sh.Bs[buf][mx_slot(row, c0 + 1)];
+        bv[c] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w, (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+      }
+      const int sh_bits = 8 * (2 * s + lh);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[b][c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              av[b], bv[c], acc[b][c], 0, 0, 0, (int)((sa[b] >> sh_bits) & 0xffu), 0,
+              (int)((sb[c] >> sh_bits) & 0xffu));
+    }
+  };
+
+  const int64_t nkt = (K + BK - 1) / BK;
+  if (nkt > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nkt) load(kt + 1);
+    compute(cur, kt);
+    if (kt + 1 < nkt) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
+      if (EDGE && row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t col = n0 + wn0 + 32 * c + lr;
+        if (EDGE && col >= g.p) continue;
+        const float val = acc[b][c][v];
+        if (g.C) g.C[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (g.Y) {
+          const double d = dv - (double)g.Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  if (g.tile_part) {
+    e2 = warp_sum_f64(e2);
+    n2 = warp_sum_f64(n2);
+    if (lane == 0) { sh.red[wave] = e2; sh.red[4 + wave] = n2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int64_t tiles = g.tiles_m * g.tiles_n;
+      g.tile_part[blockIdx.x] = ((sh.red[0] + sh.red[1]) + sh.red[2]) + sh.red[3];
+      g.tile_part[tiles + blockIdx.x] = ((sh.red[4] + sh.red[5]) + sh.red[6]) + sh.red[7];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 1) void mx_gemm_kernel(MxArgs g) {
+  __shared__ MxTile sh;
+  int64_t tm, tn;
+  mx_tile_coords(g, tm, tn);
+  const int64_t m0 = tm * MxTile::BM, n0 = tn * MxTile::BN;
+  const int64_t K = (*g.K_dev + kBlk - 1) / kBlk * kBlk;
+  if (m0 + MxTile::BM <= g.m && n0 + MxTile::BN <= g.p)
+    mx_body<false>(g, sh, m0, n0, K);
+  else
+    mx_body<true>(g, sh, m0, n0, K);
+}
+
+}  // namespace
+
+hipError_t launch_mx_gather(const MxGatherLaunch& L, hipStream_t s) {
+  MxGatherArgs a{};
+  a.M = L.M; a.ldm = L.ldm; a.N = L.N; a.ldn = L.ldn; a.m = L.m; a.p = L.p; a.L_dev = L.L_dev;
+  a.nblk_max = L.L_pad_max / kBlk;
+  a.colmap = L.colmap; a.colscale = L.colscale;
+  a.C = L.C; a.ldc = L.ldc; a.Cs = L.Cs; a.ldcs = L.ldcs;
+  a.Dt = L.Dt; a.lddt = L.lddt; a.Ds = L.Ds; a.ldds = L.ldds;
+  // blocks up to the next multiple of 4 (their scales are written as 1)
+  const int64_t nblk_w = round_up(a.nblk_max, 4);
+  a.nblk_max = nblk_w;
+  const int64_t per_row = ceil_div(nblk_w, 256);
+  a.cgroups = (L.C && L.m > 0) ? L.m * per_row : 0;
+  const int64_t dgroups = (L.Dt && L.p > 0) ? nblk_w * ceil_div(L.p, 256) : 0;
+  const int64_t total = a.cgroups + dgroups;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(mx_gather_kernel, dim3((unsigned)total), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+int64_t mx_gemm_tiles(int64_t m, int64_t p) { return ceil_div(m, MxTile::BM) * ceil_div(p, MxTile::BN); }
+
+hipError_t launch_mx_gemm(const MxGemmLaunch& L, hipStream_t s) {
+  MxArgs g{};
+  g.A = L.A; g.lda = L.lda; g.As = L.As; g.ldas = L.ldas;
+  g.B = L.B; g.ldb = L.ldb; g.Bs = L.Bs; g.ldbs = L.ldbs;
+  g.m = L.m; g.p = L.p; g.K_dev = L.K_dev; g.C = L.Cout; g.ldc = L.ldc; g.Y = L.Y; g.ldy = L.ldy;
+  g.tile_part = L.tile_part;
+  g.tiles_m = ceil_div(L.m, MxTile::BM);
+  g.tiles_n = ceil_div(L.p, MxTile::BN);
+  const int64_t tiles = g.tiles_m * g.tiles_n;
+  if (tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(mx_gemm_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
+  return hipGetLastError();
+}

@@ -106,6 +106,23 @@ def test_small_batch_matches_oracle(small_batch):
         check_against_oracle(b, probs, host, t, o)
 
 
+def test_batch_equals_single_problem_path(h, small_batch):
+    # each problem of the batch (norms, plan, fused-gather product) gives the
+    # same bits as the single-problem path (gather to C, D, then the product)
+    b, probs, host = small_batch
+    b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
+    b.run()
+    torch.cuda.synchronize()
+    for t, pr in enumerate(probs):
+        r = h.run(pk.Problem(pr["M"], pr["N"], pr["off"], pr["c"], prob=pr["prob"], seed=pr["seed"],
+                             trial=pr["trial"]))
+        torch.cuda.synchronize()
+        assert torch.equal(r["plan"].idx, b.draws(t)), t
+        assert r["L"] == int(b.L[t].item()), t
+        assert torch.equal(r["CD"], b.CD[t]), t
+        assert torch.equal(r["MN"], b.MN[t]), t
+
+
 def _snapshot(b):
     return ([x.clone() for x in b.CD], [x.clone() for x in b.MN], b.err2_mn2.clone(), b.L.clone(),
             b.idx.clone())
