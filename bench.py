@@ -553,7 +553,7 @@ def main():
     t_mx = {c: avg_ms(f"mx_c{c}") for c in CS}
     mx_ms = sum(t_mx[c] for c in CS) * len(RULES)
     mx = {
-        "format": "OCP MX E4M3 (E8M0 scale per 32 sketch columns), float32 accumulation",
+        "format": "OCP MX E4M3 (E8M0 scale per 32 sketch columns), float32 accumulator across instructions",
         "sketch_gemm_TFLOPs": b16_flops / mx_ms / 1e9,
         "peak": 5000.0, "unit": "TFLOP/s",
         "frac": b16_flops / mx_ms / 1e9 / 5000.0,
