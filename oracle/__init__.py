@@ -17,9 +17,11 @@ rng       Philox4x64-10 and the counter layout used to draw sample indices.
 sampling  Integer weight quantization, per-stratum CDF, Lemire's exact
           bounded integer, CDF search and the integer draw-count allocation.
 method    The estimator itself: norms, design rules (1.1)-(1.4), (3.8), (3.9),
-          (4.2), Alg. 1 / Alg. 2 sampling, the sketch C, D, the product CD,
-          the judge ||MN - CD||_F, the closed-form expected error
-          (Thm 2 proof / Remark 2.2) and the gradient of the sketch.
+          (4.2), Alg. 1 / Alg. 2 sampling, the pilot and block sizes (4.7)
+          of the two-step Alg. 3, the sketch C, D, the product CD, the judge
+          ||MN - CD||_F, the closed-form expected error (Thm 2 proof /
+          Remark 2.2) and the gradient of the sketch.
+lowp      bfloat16, E4M3 and the MX block format (reduced-precision sketches).
 
 Pins: every function is checked in ``tests/test_oracle_*.py`` against values
 fixed by the paper or by mathematics (known-answer vectors, exhaustive

@@ -17,7 +17,8 @@ its own number of draws c_s:
 * ``stratified`` atoms are single inner indices, the K blocks are the
                  strata, block k gets c_k draws (the paper's Alg. 2 with
                  within-block probabilities (3.8) or uniform, and block sizes
-                 uniform c/K, (4.2) or (3.9)).
+                 uniform c/K, (4.2) or (3.9); or Alg. 3, whose block sizes
+                 (4.7) come from a pilot sketch).
 
 Alg. 1 (probabilities (1.1)) is either mode with K = 1 block of unit atoms.
 """
@@ -29,11 +30,12 @@ import numpy as np
 
 from .sampling import (quantize_weights, inclusive_cdf, draw_atoms,
                        allocate_draws)
-from .rng import TAG_SAMPLE
+from .rng import TAG_SAMPLE, TAG_PILOT
 
 MODES = ("block", "stratified")
 PROB_RULES = ("uniform", "norm", "exact", "user")
-ALLOC_RULES = ("uniform", "norm", "opt", "user")
+ALLOC_RULES = ("uniform", "norm", "opt", "user", "two_step")
+PILOT_RULES = ("uniform", "norm")
 
 
 # ----------------------------------------------------------------------------
@@ -192,12 +194,16 @@ def atom_weights(mode, prob, off, col_sq, row_sq, stats, blkprod_sq=None,
     raise ValueError(f"rule {prob!r} not available in {mode} mode")
 
 
-def alloc_weights(alloc, stats, blkprod_sq=None):
+def alloc_weights(alloc, stats, blkprod_sq=None, pilot_sq=None):
     """Float allocation weights g_k of the strata (stratified mode).
 
-      uniform  g_k = 1                              (c_k = c/K, method UU)
-      norm     g_k = s_k                            (4.2), method ONC
-      opt      g_k = sqrt(max(0, s_k^2 - ||M^k N_k||_F^2))   (3.9), method OPL
+      uniform   g_k = 1                              (c_k = c/K, method UU)
+      norm      g_k = s_k                            (4.2), method ONC
+      opt       g_k = sqrt(max(0, s_k^2 - ||M^k N_k||_F^2))   (3.9), method OPL
+      two_step  g_k = |s_k^2 - ||C^{0k} D_{0k}||_F^2|^(1/2)    (4.7), Alg. 3
+                (methods ONU / ONMCNR): the pilot estimate replaces
+                ||M^k N_k||_F^2 and the absolute value replaces the clamp,
+                since the estimate may exceed s_k^2
     """
     K = len(stats.s)
     if alloc == "uniform":
@@ -209,6 +215,11 @@ def alloc_weights(alloc, stats, blkprod_sq=None):
             raise ValueError("rule 'opt' needs ||M^k N_k||_F^2")
         d = stats.s * stats.s - np.asarray(blkprod_sq, dtype=np.float64)
         return np.sqrt(np.maximum(d, 0.0))
+    if alloc == "two_step":
+        if pilot_sq is None:
+            raise ValueError("rule 'two_step' needs the pilot estimates")
+        d = stats.s * stats.s - np.asarray(pilot_sq, dtype=np.float64)
+        return np.sqrt(np.abs(d))
     raise ValueError(f"allocation rule {alloc!r} unknown")
 
 
@@ -399,6 +410,60 @@ def exact_entries(M, N, rows, cols, chunk=8192):
 
 
 # ----------------------------------------------------------------------------
+# Pilot of the two-step algorithm (Alg. 3, step 1)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Pilot:
+    """Step 1 of Alg. 3: the pilot design and draws, and per block the
+    squared Frobenius norm of the pilot estimate C^{0k} D_{0k} of M^k N_k."""
+    design: Design
+    draws: Draws
+    pilot_sq: np.ndarray
+
+
+def pilot(M, N, off, c0, pilot_prob, seed, trial=0, col_row=None, forced=None):
+    """Alg. 3 step 1: in every block k, Alg. 1 with [c0/K] draws and the
+    pilot probabilities p_{0k_i} (uniform 1/n_k for ONU, (3.8) for ONMCNR),
+    giving C^{0k} (m x [c0/K]) and D_{0k}; then ||C^{0k} D_{0k}||_F^2.
+
+    Readings: [c0/K] is the integer part, so c0 >= K is required; a block
+    whose pilot weights are all zero (rule (3.8) on a block with M^k N_k's
+    outer products all zero) gets no pilot draws and estimate 0; the draws
+    read the Philox streams of tag TAG_PILOT, so they are independent of
+    step 2's. ``forced`` (tests only) fixes the local draws per block.
+    """
+    n = M.shape[1]
+    off = check_partition(off, n)
+    K = len(off) - 1
+    if pilot_prob not in PILOT_RULES:
+        raise ValueError("pilot probabilities are 'uniform' or 'norm'")
+    r = int(c0) // K
+    if r < 1:
+        raise ValueError("c0 must be at least the number of blocks")
+    col_sq, row_sq = col_row if col_row is not None else column_row_sq(M, N)
+    stats = block_stats(col_sq, row_sq, off)
+    w0 = atom_weights("stratified", pilot_prob, off, col_sq, row_sq, stats)
+    live = [bool(np.any(w0[off[k]:off[k + 1]] > 0)) for k in range(K)]
+    ck0 = [r if live[k] else 0 for k in range(K)]
+    pilot_sq = np.zeros(K)
+    if sum(ck0) == 0:
+        return Pilot(None, None, pilot_sq)
+    design0 = make_design("stratified", off, sum(ck0), w0, user_ck=ck0)
+    draws0 = sample(design0, seed, trial, tag=TAG_PILOT, forced=forced)
+    C0, D0 = sketch(M, N, draws0)
+    for k in range(K):
+        cols = np.flatnonzero(draws0.strat == k)
+        if len(cols) == 0:
+            continue
+        # unit atoms: draw t is sketch column col_off[t]
+        sel = draws0.col_off[cols]
+        Z = C0[:, sel] @ D0[sel, :]
+        pilot_sq[k] = float(np.sum(Z * Z))
+    return Pilot(design0, draws0, pilot_sq)
+
+
+# ----------------------------------------------------------------------------
 # Closed forms (Lemma 1, Thm 2 proof, Remark 2.2, Remark 2.3)
 # ----------------------------------------------------------------------------
 
@@ -493,8 +558,9 @@ class Result:
 
 
 def plan(M, N, off, c, mode="block", prob="norm", alloc="norm", user_w=None,
-         user_ck=None, blkprod_sq=None, col_row=None):
-    """Norms -> weights -> design (everything before the random draws)."""
+         user_ck=None, blkprod_sq=None, col_row=None, pilot_sq=None):
+    """Norms -> weights -> design (everything before the random draws).
+    Rule 'two_step' takes the pilot estimates (``pilot``) as pilot_sq."""
     n = M.shape[1]
     off = check_partition(off, n)
     col_sq, row_sq = col_row if col_row is not None else column_row_sq(M, N)
@@ -505,18 +571,26 @@ def plan(M, N, off, c, mode="block", prob="norm", alloc="norm", user_w=None,
     w = atom_weights(mode, prob, off, col_sq, row_sq, stats, blkprod_sq, user_w)
     g = None
     if mode == "stratified" and alloc != "user":
-        g = alloc_weights(alloc, stats, blkprod_sq)
+        g = alloc_weights(alloc, stats, blkprod_sq, pilot_sq)
     design = make_design(mode, off, c, w, g,
                          user_ck if (mode == "stratified" and alloc == "user") else None)
     return design, col_sq, row_sq, stats
 
 
 def run(M, N, off, c, seed=0, trial=0, mode="block", prob="norm",
-        alloc="norm", user_w=None, user_ck=None, blkprod_sq=None):
-    """The full forward path: Alg. 2 (or the block sampler), its product
-    and the judge."""
+        alloc="norm", user_w=None, user_ck=None, blkprod_sq=None, c0=None,
+        pilot_prob="uniform"):
+    """The full forward path: Alg. 2 (or the block sampler, or Alg. 3 when
+    alloc is 'two_step': the pilot with c0 draws first), its product and the
+    judge."""
+    pilot_sq = None
+    col_row = None
+    if mode == "stratified" and alloc == "two_step":
+        col_row = column_row_sq(M, N)
+        pilot_sq = pilot(M, N, off, c0, pilot_prob, seed, trial, col_row).pilot_sq
     design, col_sq, row_sq, stats = plan(M, N, off, c, mode, prob, alloc,
-                                         user_w, user_ck, blkprod_sq)
+                                         user_w, user_ck, blkprod_sq, col_row,
+                                         pilot_sq)
     draws = sample(design, seed, trial)
     C, D = sketch(M, N, draws)
     CD = sketch_product(C, D)
