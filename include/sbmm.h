@@ -17,8 +17,10 @@
  *                         drawn unit is one inner index (a column of M and the
  *                         matching row of N), block k receives c_k draws with
  *                         probabilities (3.8) "norm" or 1/n_k "uniform"; c_k
- *                         comes from c/K "uniform", (4.2) "norm", (3.9) "opt"
- *                         or the caller.
+ *                         comes from c/K "uniform", (4.2) "norm", (3.9) "opt",
+ *                         the caller, or "two-step" (4.7): the two-step
+ *                         Alg. 3, whose block sizes use a pilot sketch
+ *                         (sbmm_pilot) in place of ||M^k N_k||_F.
  * An "atom" is the drawn unit (a block, or one inner index); a "stratum" is a
  * group of atoms with its own draw count (the whole problem in block mode,
  * one block in stratified mode).
@@ -81,7 +83,13 @@ typedef enum {
 typedef enum { SBMM_F64 = 0, SBMM_F32 = 1, SBMM_BF16 = 2, SBMM_F8E4M3 = 3 } sbmm_dtype;
 typedef enum { SBMM_MODE_BLOCK = 0, SBMM_MODE_STRATIFIED = 1 } sbmm_mode;
 typedef enum { SBMM_P_UNIFORM = 0, SBMM_P_NORM = 1, SBMM_P_EXACT = 2, SBMM_P_USER = 3 } sbmm_prob;
-typedef enum { SBMM_ALLOC_UNIFORM = 0, SBMM_ALLOC_NORM = 1, SBMM_ALLOC_OPT = 2, SBMM_ALLOC_USER = 3 } sbmm_alloc;
+typedef enum {
+  SBMM_ALLOC_UNIFORM = 0,
+  SBMM_ALLOC_NORM = 1,
+  SBMM_ALLOC_OPT = 2,
+  SBMM_ALLOC_USER = 3,
+  SBMM_ALLOC_TWO_STEP = 4
+} sbmm_alloc;
 
 /* One sampling problem (Alg. 2 input: M, N, the block sizes n_k, c, the
  * probability rule and, in stratified mode, the block-size rule). */
@@ -100,6 +108,11 @@ typedef struct {
   const int64_t* user_ck;     /* host, K draw counts summing to c, alloc == USER */
   const double* blkprod_sq;   /* device, K values ||M^k N_k||_F^2 (from sbmm_exact), prob == EXACT or alloc == OPT */
   uint64_t seed, trial;       /* Philox key word 0 and counter word 2 */
+  /* two-step algorithm (Alg. 3), alloc == TWO_STEP only: */
+  int64_t c0;                 /* pilot draws; every block that can be sampled gets [c0 / K] (so c0 >= K) */
+  sbmm_prob pilot_prob;       /* pilot probabilities p_{0k_i}: UNIFORM (1/n_k, method ONU) or NORM ((3.8), ONMCNR) */
+  const double* pilot_sq;     /* device, K pilot estimates ||C^{0k} D_{0k}||_F^2 (from sbmm_pilot); sbmm_run
+                                 computes them when NULL */
 } sbmm_problem;
 
 /* Sizes derived from a problem (no device work). */
@@ -174,6 +187,23 @@ sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* prob,
                       const double* col_sq, const double* row_sq,
                       const double* blk, const sbmm_plan_out* out,
                       int64_t* L_host, sbmm_stream stream);
+
+/* Step 1 of the two-step algorithm (Alg. 3): in every block k, Alg. 1 with
+ * [c0 / K] draws (prob->c0) and the pilot probabilities prob->pilot_prob
+ * (UNIFORM: 1/n_k; NORM: (3.8)), i.e. a stratified plan whose draws read the
+ * Philox streams with tag 2 in counter word 3 (tag 1 is the main draws), its
+ * sketch C^{0k} (m x [c0/K]), D_{0k}, and pilot_sq[k] = ||C^{0k} D_{0k}||_F^2
+ * (float64 reduction of products accumulated in the inputs' product dtype:
+ * F64 for F64 inputs, else F32). A block whose pilot weights are all zero
+ * gets no draws and pilot_sq 0. The stratified problem's own probability
+ * and block-size rules are not used. col_sq / row_sq / blk come from
+ * sbmm_norms (row_sq / col_sq only for NORM pilots). pilot_plan (optional,
+ * may be NULL; sized for c = c0, L_pad_max = round_up(c0, 32)) receives the
+ * pilot draws; draws past sum_k ck[k] have idx -1. pilot_sq: device [K]. Pass
+ * pilot_sq as prob->pilot_sq to sbmm_plan with alloc TWO_STEP for step 2. */
+sbmm_status sbmm_pilot(sbmm_handle h, const sbmm_problem* prob, const double* col_sq, const double* row_sq,
+                       const double* blk, const sbmm_plan_out* pilot_plan, double* pilot_sq,
+                       sbmm_stream stream);
 
 /* Gather and rescale (Alg. 1 step 1(b), Alg. 2 step 3): C[:, l] = colscale[l]
  * * M[:, colmap[l]] and D[l, :] = colscale[l] * N[colmap[l], :] for

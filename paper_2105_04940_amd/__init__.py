@@ -22,7 +22,7 @@ SBMM_OK, SBMM_E_ARG, SBMM_E_BUDGET, SBMM_E_NONFINITE, SBMM_E_UNSUPPORTED, \
 SBMM_F64, SBMM_F32, SBMM_BF16, SBMM_F8E4M3 = range(4)
 MODES = {"block": 0, "stratified": 1}
 PROBS = {"uniform": 0, "norm": 1, "exact": 2, "user": 3}
-ALLOCS = {"uniform": 0, "norm": 1, "opt": 2, "user": 3}
+ALLOCS = {"uniform": 0, "norm": 1, "opt": 2, "user": 3, "two_step": 4}
 SKETCH_PAD = 32
 
 # Names of every function the C header declares (checked by the ABI test).
@@ -33,7 +33,7 @@ EXPORTS = (
     "sbmm_error", "sbmm_run", "sbmm_backward",
     "sbmm_batch_create", "sbmm_batch_destroy", "sbmm_batch_run", "sbmm_batch_capture",
     "sbmm_batch_replay", "sbmm_batch_tune", "sbmm_batch_set_tuning",
-    "sbmm_sketch_mx", "sbmm_sketch_gemm_mx",
+    "sbmm_sketch_mx", "sbmm_sketch_gemm_mx", "sbmm_pilot",
 )
 BATCH_TILES = ((128, 128), (64, 128), (128, 64), (64, 64))
 
@@ -56,6 +56,7 @@ class Problem_t(ctypes.Structure):
         ("user_w", ctypes.c_void_p), ("user_ck", ctypes.c_void_p),
         ("blkprod_sq", ctypes.c_void_p),
         ("seed", ctypes.c_uint64), ("trial", ctypes.c_uint64),
+        ("c0", ctypes.c_int64), ("pilot_prob", ctypes.c_int), ("pilot_sq", ctypes.c_void_p),
     ]
 
 
@@ -112,6 +113,7 @@ def load_library(path=LIB_PATH):
         "sbmm_norms": (st, [vp, P(Problem_t), vp, vp, vp, vp]),
         "sbmm_exact": (st, [vp, P(Problem_t), vp, i64, vp, vp, vp]),
         "sbmm_plan": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), P(i64), vp]),
+        "sbmm_pilot": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), vp, vp]),
         "sbmm_sketch": (st, [vp, P(Problem_t), P(PlanOut_t), st, vp, i64, vp, i64, vp]),
         "sbmm_sketch_gemm": (st, [vp, i64, i64, i64, vp, st, vp, i64, vp, i64, vp, i64,
                                   vp, i64, vp, vp]),
@@ -188,6 +190,9 @@ class Problem:
     user_w: object = None       # device float64 tensor
     user_ck: object = None      # host int64 sequence
     blkprod_sq: object = None   # device float64 tensor
+    c0: int = 0                 # two-step algorithm: pilot draws (alloc "two_step")
+    pilot: str = "uniform"      # pilot probabilities: "uniform" (ONU) or "norm" (ONMCNR)
+    pilot_sq: object = None     # device float64 tensor of K pilot estimates
 
     def struct(self):
         M, N = self.M, self.N
@@ -220,6 +225,9 @@ class Problem:
         s.blkprod_sq = None if self.blkprod_sq is None else self.blkprod_sq.data_ptr()
         s.seed = int(self.seed) & (2**64 - 1)
         s.trial = int(self.trial) & (2**64 - 1)
+        s.c0 = int(self.c0)
+        s.pilot_prob = PROBS[self.pilot]
+        s.pilot_sq = None if self.pilot_sq is None else self.pilot_sq.data_ptr()
         return s
 
 
@@ -236,9 +244,9 @@ def sbmm_query_sizes(problem):
 class Plan:
     """Device buffers of the planning step."""
 
-    def __init__(self, problem, sizes, device):
+    def __init__(self, problem, sizes, device, c=None):
         torch = _torch()
-        c = int(problem.c)
+        c = int(problem.c if c is None else c)
         kw = dict(device=device)
         self.idx = torch.empty(c, dtype=torch.int32, **kw)
         self.scale = torch.empty(c, dtype=torch.float64, **kw)
@@ -327,6 +335,27 @@ class Handle:
         pl.L = L.value if sync else None
         pl.sizes = sizes
         return pl
+
+    def pilot(self, problem, col_sq=None, row_sq=None, blk=None, keep_plan=False):
+        """Step 1 of the two-step algorithm: the K pilot estimates
+        ||C^{0k} D_{0k}||_F^2 (float64 tensor) and, with keep_plan, the pilot
+        draws (a Plan sized for c0 draws; entries past the drawn total have
+        idx -1)."""
+        torch = _torch()
+        s = problem.struct()
+        dev = problem.M.device
+        out = torch.empty(s.K, dtype=torch.float64, device=dev)
+        pl = None
+        if keep_plan:
+            Lp = -(-int(problem.c0) // SKETCH_PAD) * SKETCH_PAD
+            sizes = dict(atoms=s.n, strata=s.K, max_width=1, L_max=int(problem.c0), L_pad_max=Lp)
+            pl = Plan(problem, sizes, dev, c=problem.c0)
+            pl.sizes = sizes
+            pl.L = None
+        ps = pl.struct() if pl is not None else None
+        self._check(self._lib.sbmm_pilot(self.h, ctypes.byref(s), _ptr(col_sq), _ptr(row_sq), _ptr(blk),
+                                         ctypes.byref(ps) if ps is not None else None, _ptr(out), _stream()))
+        return (out, pl) if keep_plan else out
 
     def sketch(self, problem, plan, out_dtype=None, want_C=True, want_D=True):
         torch = _torch()

@@ -78,10 +78,12 @@ sbmm_status validate(sbmm_handle h, const sbmm_problem* P, sbmm_sizes* sz, bool 
     if (P->prob == SBMM_P_EXACT && !P->blkprod_sq && !blkprod_internal)
       return fail(h, SBMM_E_ARG, "rule EXACT needs blkprod_sq (from sbmm_exact)");
   } else {
-    if (P->alloc < SBMM_ALLOC_UNIFORM || P->alloc > SBMM_ALLOC_USER)
+    if (P->alloc < SBMM_ALLOC_UNIFORM || P->alloc > SBMM_ALLOC_TWO_STEP)
       return fail(h, SBMM_E_ARG, "unknown allocation rule %d", (int)P->alloc);
     if (P->alloc == SBMM_ALLOC_OPT && !P->blkprod_sq && !blkprod_internal)
       return fail(h, SBMM_E_ARG, "allocation OPT needs blkprod_sq (from sbmm_exact)");
+    if (P->alloc == SBMM_ALLOC_TWO_STEP && !P->pilot_sq && !blkprod_internal)
+      return fail(h, SBMM_E_ARG, "allocation TWO_STEP needs pilot_sq (from sbmm_pilot)");
     if (P->alloc == SBMM_ALLOC_USER) {
       if (!P->user_ck) return fail(h, SBMM_E_ARG, "allocation USER needs user_ck");
       int64_t s = 0;
@@ -100,6 +102,17 @@ sbmm_status validate(sbmm_handle h, const sbmm_problem* P, sbmm_sizes* sz, bool 
     sz->L_max = P->c * sz->max_width;
     sz->L_pad_max = round_up(sz->L_max, SBMM_SKETCH_PAD);
   }
+  return SBMM_OK;
+}
+
+// The pilot's parameters (Alg. 3 step 1): stratified mode, [c0/K] >= 1
+// draws per block, uniform or (3.8) probabilities.
+sbmm_status validate_pilot(sbmm_handle h, const sbmm_problem* P) {
+  if (P->mode != SBMM_MODE_STRATIFIED) return fail(h, SBMM_E_ARG, "the pilot needs stratified mode");
+  if (P->c0 < P->K || P->c0 > INT32_MAX)
+    return fail(h, SBMM_E_ARG, "c0 = %lld must be at least K = %d (and below 2^31)", (long long)P->c0, P->K);
+  if (P->pilot_prob != SBMM_P_UNIFORM && P->pilot_prob != SBMM_P_NORM)
+    return fail(h, SBMM_E_ARG, "pilot probabilities must be UNIFORM or NORM");
   return SBMM_OK;
 }
 
@@ -191,7 +204,7 @@ sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
 
 sbmm_status do_plan(sbmm_handle h, const sbmm_problem* P, const sbmm_sizes& sz, const int64_t* off_dev,
                     const double* col_sq, const double* row_sq, const double* blk, const sbmm_plan_out* out,
-                    Arena& ar, hipStream_t s) {
+                    Arena& ar, hipStream_t s, int64_t pilot_r = 0, int64_t** draw_off_out = nullptr) {
   PlanLaunch L{};
   L.W = ar.take<uint64_t>(sz.atoms);
   L.cdf = ar.take<uint64_t>(sz.atoms);
@@ -203,14 +216,16 @@ sbmm_status do_plan(sbmm_handle h, const sbmm_problem* P, const sbmm_sizes& sz, 
   L.rem = ar.take<uint64_t>(sz.strata);
   L.left = ar.take<int64_t>(1);
   int64_t* user_ck_dev = nullptr;
-  const bool uck = P->mode == SBMM_MODE_STRATIFIED && P->alloc == SBMM_ALLOC_USER;
+  const bool uck = P->mode == SBMM_MODE_STRATIFIED && P->alloc == SBMM_ALLOC_USER && pilot_r == 0;
   if (uck) user_ck_dev = ar.take<int64_t>(P->K);
+  if (draw_off_out) *draw_off_out = L.draw_off;
   if (!ar.base) return SBMM_OK;
   if (uck) HIP_TRY(h, hipMemcpyAsync(user_ck_dev, P->user_ck, sizeof(int64_t) * P->K, hipMemcpyHostToDevice, s));
   L.mode = P->mode; L.prob = eff_prob(P); L.alloc = P->alloc;
   L.n = P->n; L.K = P->K; L.c = P->c; L.A = sz.atoms; L.S = sz.strata;
   L.off_dev = off_dev; L.col_sq = col_sq; L.row_sq = row_sq; L.blk = blk;
   L.user_w = P->user_w; L.user_ck_dev = user_ck_dev; L.blkprod_sq = P->blkprod_sq;
+  L.pilot_sq = P->pilot_sq; L.pilot_r = pilot_r;
   L.seed = P->seed; L.trial = P->trial;
   L.idx = out->idx; L.scale = out->scale; L.col_off = out->col_off; L.ck = out->ck;
   L.p_hat = out->p_hat; L.colmap = out->colmap; L.colscale = out->colscale;
@@ -226,6 +241,66 @@ bool plan_out_ok(const sbmm_plan_out* o) {
 bool sketch_dtype_ok(sbmm_dtype in, sbmm_dtype out) {
   if (in == SBMM_F64) return out == SBMM_F64;
   return out == SBMM_F32 || out == SBMM_BF16;
+}
+
+// Alg. 3 step 1: the pilot plan ([c0/K] draws per block, tag 2), its sketch
+// C0 (m x round_up(c0, 32)) and D0 in the product dtype, and per block the
+// squared Frobenius norm of C^{0k} D_{0k}, by the block-norm form of the
+// product kernel with the strata's column ranges (draw offsets: pilot draws
+// are single columns) as the blocks. `pp` (may be NULL) receives the draws.
+sbmm_status do_pilot(sbmm_handle h, const sbmm_problem* P, const int64_t* off_dev, const double* col_sq,
+                     const double* row_sq, const double* blk, const sbmm_plan_out* pp, double* pilot_sq,
+                     Arena& ar, hipStream_t s) {
+  sbmm_problem Q = *P;
+  Q.prob = P->pilot_prob;
+  Q.c = P->c0;
+  Q.alloc = SBMM_ALLOC_UNIFORM;   // not used: the pilot counts are fixed
+  sbmm_sizes sz;
+  sz.atoms = P->n;
+  sz.strata = P->K;
+  sz.max_width = 1;
+  sz.L_max = P->c0;
+  sz.L_pad_max = round_up(P->c0, SBMM_SKETCH_PAD);
+  const int64_t Lp = sz.L_pad_max;
+  sbmm_plan_out own{};
+  if (!pp) {
+    own.idx = ar.take<int32_t>(Q.c);
+    own.scale = ar.take<double>(Q.c);
+    own.col_off = ar.take<int64_t>(Q.c + 1);
+    own.ck = ar.take<int64_t>(P->K);
+    own.colmap = ar.take<int32_t>(Lp);
+    own.colscale = ar.take<double>(Lp);
+    pp = &own;
+  }
+  const sbmm_dtype pd = product_dtype(P->in_dtype);
+  const size_t es = dtype_size(pd);
+  void* C0 = ar.take<char>(es * (size_t)std::max<int64_t>(P->m, 1) * Lp);
+  void* D0 = ar.take<char>(es * (size_t)Lp * std::max<int64_t>(P->p, 1));
+  const int64_t tiles = gemm_tiles(pd, P->m, P->p, true);
+  double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
+  double* blk_part = ar.take<double>((size_t)P->K * std::max<int64_t>(tiles, 1) * 4);
+  int64_t* draw_off = nullptr;
+  sbmm_status st = do_plan(h, &Q, sz, off_dev, col_sq, row_sq, blk, pp, ar, s, P->c0 / P->K, &draw_off);
+  if (st || !ar.base) return st;
+  if (tiles == 0) {
+    HIP_TRY(h, launch_fill_f64(pilot_sq, P->K, 0.0, s));
+    return SBMM_OK;
+  }
+  GatherLaunch g{};
+  g.in_dt = P->in_dtype; g.out_dt = pd;
+  g.M = P->M; g.ldm = P->ldm; g.N = P->N; g.ldn = P->ldn; g.m = P->m; g.p = P->p;
+  g.L_dev = pp->col_off + Q.c; g.L_pad_max = Lp;
+  g.colmap = pp->colmap; g.colscale = pp->colscale;
+  g.C = C0; g.ldc = Lp; g.D = D0; g.ldd = P->p;
+  HIP_TRY(h, launch_gather(g, s));
+  GemmLaunch G{};
+  G.dt = pd; G.A = C0; G.lda = Lp; G.B = D0; G.ldb = P->p; G.m = P->m; G.p = P->p;
+  G.K_host = 0; G.K_dev = pp->col_off + Q.c; G.Cout = nullptr; G.ldc = P->p;
+  G.Y = nullptr; G.ldy = P->p; G.tile_part = tile_part;
+  G.K_blocks = P->K; G.off_dev = draw_off; G.blk_part = blk_part; G.stage = nullptr;
+  HIP_TRY(h, launch_gemm(G, s));
+  HIP_TRY(h, launch_reduce_cols(blk_part, P->K, tiles * 4, pilot_sq, s));
+  return SBMM_OK;
 }
 
 }  // namespace
@@ -351,7 +426,9 @@ sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* P, const double* col_sq
   const int pr = eff_prob(P);
   const bool strat = P->mode == SBMM_MODE_STRATIFIED;
   const bool need_blk = (!strat && pr == SBMM_P_NORM) ||
-                        (strat && (P->alloc == SBMM_ALLOC_NORM || P->alloc == SBMM_ALLOC_OPT));
+                        (strat && (P->alloc == SBMM_ALLOC_NORM || P->alloc == SBMM_ALLOC_OPT ||
+                                   P->alloc == SBMM_ALLOC_TWO_STEP));
+  if (strat && P->alloc == SBMM_ALLOC_TWO_STEP && (st = validate_pilot(h, P))) return st;
   const bool need_colrow = strat && pr == SBMM_P_NORM;
   if ((need_blk && !blk) || (need_colrow && (!col_sq || !row_sq)))
     return fail(h, SBMM_E_ARG, "the rule needs the norm-pass outputs");
@@ -369,6 +446,27 @@ sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* P, const double* col_sq
     return read_status(h, s);
   }
   return SBMM_OK;
+}
+
+sbmm_status sbmm_pilot(sbmm_handle h, const sbmm_problem* P, const double* col_sq, const double* row_sq,
+                       const double* blk, const sbmm_plan_out* pilot_plan, double* pilot_sq, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  if ((st = validate(h, P, nullptr, true))) return st;
+  if ((st = validate_pilot(h, P))) return st;
+  if (!pilot_sq) return fail(h, SBMM_E_ARG, "pilot_sq is required");
+  if (pilot_plan && !plan_out_ok(pilot_plan)) return fail(h, SBMM_E_ARG, "pilot plan buffers missing");
+  if (P->pilot_prob == SBMM_P_NORM && (!col_sq || !row_sq))
+    return fail(h, SBMM_E_ARG, "NORM pilot probabilities need col_sq and row_sq");
+  hipStream_t s = (hipStream_t)stream;
+  Arena dry(nullptr);
+  int64_t* off = nullptr;
+  upload_offsets(h, P, dry, &off, s);
+  do_pilot(h, P, off, col_sq, row_sq, blk, pilot_plan, pilot_sq, dry, s);
+  if ((st = ensure_ws(h, dry.off))) return st;
+  Arena ar(h->ws);
+  if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+  return do_pilot(h, P, off, col_sq, row_sq, blk, pilot_plan, pilot_sq, ar, s);
 }
 
 sbmm_status sbmm_sketch(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_out* plan, sbmm_dtype out_dtype,
@@ -550,8 +648,11 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
   if (C && ldc < sz.L_pad_max) return fail(h, SBMM_E_ARG, "ldc < L_pad_max");
   if (D && ldd < P->p) return fail(h, SBMM_E_ARG, "ldd < p");
   if (MN && ldmn < P->p) return fail(h, SBMM_E_ARG, "ldmn < p");
+  const bool two = P->mode == SBMM_MODE_STRATIFIED && P->alloc == SBMM_ALLOC_TWO_STEP;
+  if (two && (st = validate_pilot(h, P))) return st;
   hipStream_t s = (hipStream_t)stream;
   const bool bp = needs_blkprod(P);
+  const bool own_pilot = two && !P->pilot_sq;
   const sbmm_dtype pd = product_dtype(P->in_dtype);
   const size_t pes = dtype_size(pd), ces = dtype_size(compute);
 
@@ -563,6 +664,7 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
     double* row_sq = ar.take<double>(P->n);
     double* blk = ar.take<double>(3 * (size_t)P->K);
     double* blkprod = bp ? ar.take<double>(P->K) : nullptr;
+    double* pilot = own_pilot ? ar.take<double>(P->K) : nullptr;
     double* ex2 = ar.take<double>(2);     // exact pass: err^2 (when fused), ||MN||^2
     double* sk2 = ar.take<double>(2);     // sketch pass: err^2, ||CD||^2
     void* Cw = C ? C : ar.take<char>(ces * (size_t)std::max<int64_t>(P->m, 1) * sz.L_pad_max);
@@ -585,6 +687,12 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
       sub2.off = ar.off;
       do_plan(h, P, sz, off, col_sq, row_sq, blk, plan, sub2, s);
       need = std::max(need, sub2.off);
+      if (own_pilot) {
+        Arena sub3(nullptr);
+        sub3.off = ar.off;
+        do_pilot(h, P, off, col_sq, row_sq, blk, nullptr, pilot, sub3, s);
+        need = std::max(need, sub3.off);
+      }
       if ((st = ensure_ws(h, need))) return st;
       continue;
     }
@@ -601,9 +709,15 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
       sub.off = base;
       if ((st = do_exact(h, P, off, MNw, ldmnw, nullptr, 0, blkprod, ex2, sub, s))) return st;
     }
-    // 3. plan
+    // 3. plan (after the pilot of the two-step algorithm, Alg. 3 step 1)
     sbmm_problem Q = *P;
     if (bp) Q.blkprod_sq = blkprod;
+    if (own_pilot) {
+      Arena sub(h->ws);
+      sub.off = base;
+      if ((st = do_pilot(h, P, off, col_sq, row_sq, blk, nullptr, pilot, sub, s))) return st;
+      Q.pilot_sq = pilot;
+    }
     {
       Arena sub(h->ws);
       sub.off = base;

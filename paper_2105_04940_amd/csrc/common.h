@@ -105,7 +105,11 @@ struct PlanLaunch {
   const int64_t* off_dev;   // K+1
   const double* col_sq; const double* row_sq; const double* blk;
   const double* user_w; const int64_t* user_ck_dev; const double* blkprod_sq;
+  const double* pilot_sq;   // K pilot estimates, alloc == TWO_STEP (4.7)
   uint64_t seed, trial;
+  // > 0: the pilot of the two-step algorithm (Alg. 3 step 1): pilot_r draws
+  // in every stratum that can be sampled, from the Philox streams of tag 2
+  int64_t pilot_r;
   // workspace
   uint64_t* W; uint64_t* cdf; uint64_t* T; int64_t* draw_off; int64_t* width;
   uint64_t* G; int64_t* quota; uint64_t* rem; int64_t* left;

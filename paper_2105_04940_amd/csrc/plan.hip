@@ -10,7 +10,11 @@
 //                    (3.8); user
 // Block sizes (stratified mode, weights g per block):
 //   uniform 1 (c/K); norm s_k (4.2); opt sqrt(max(0, s_k^2 - ||M^k N_k||_F^2))
-//   (3.9); user counts
+//   (3.9); two-step |s_k^2 - ||C^{0k} D_{0k}||_F^2|^(1/2) (4.7), from the
+//   pilot estimates; user counts
+// The pilot of the two-step algorithm (Alg. 3 step 1) is a stratified plan
+// with [c0/K] draws in every block that can be sampled, on its own Philox
+// streams (counter word 3 carries tag 2 instead of 1).
 //
 // Every step after the float64 weights is exact integer arithmetic:
 // W = ceil(w 2^(B-1-e)) with e = floor(log2 max w) and B = 63 -
@@ -51,7 +55,8 @@ __device__ __forceinline__ U64x4 philox4x64_10(U64x4 x, uint64_t k0, uint64_t k1
   return x;
 }
 
-constexpr uint64_t kTagSample = 1;
+constexpr uint64_t kTagSample = 1;   // the draws of Alg. 1 / Alg. 2
+constexpr uint64_t kTagPilot = 2;    // the pilot draws of Alg. 3 step 1
 
 // (hi * 2^64) mod T for hi < T, by shift-and-subtract long division.
 __device__ uint64_t mod_shifted(uint64_t hi, uint64_t T) {
@@ -198,6 +203,20 @@ __device__ void quota_rem(uint64_t c, uint64_t G, uint64_t tot, int64_t* q_out, 
   *r_out = num.lo - qt.lo;   // < tot, so the low word is exact
 }
 
+// Allocation weight g_s of stratum s (stratified mode).
+__device__ __forceinline__ double alloc_weight(const PlanLaunch& a, int64_t s) {
+  if (a.alloc == SBMM_ALLOC_NORM) return a.blk[2 * a.K + s];
+  if (a.alloc == SBMM_ALLOC_OPT) {
+    const double sk = a.blk[2 * a.K + s];
+    return sqrt(fmax(sk * sk - a.blkprod_sq[s], 0.0));
+  }
+  if (a.alloc == SBMM_ALLOC_TWO_STEP) {
+    const double sk = a.blk[2 * a.K + s];
+    return sqrt(fabs(sk * sk - a.pilot_sq[s]));
+  }
+  return 1.0;
+}
+
 // Stratified mode: draw counts of the K strata (single workgroup).
 __global__ __launch_bounds__(kThreads) void alloc_kernel(PlanLaunch a) {
   __shared__ double smd[kThreads];
@@ -206,7 +225,9 @@ __global__ __launch_bounds__(kThreads) void alloc_kernel(PlanLaunch a) {
   __shared__ int sm_donor;
   const int64_t S = a.S;
   const uint64_t c = (uint64_t)a.c;
-  if (a.alloc == SBMM_ALLOC_USER) {
+  if (a.pilot_r > 0) {
+    for (int64_t s = threadIdx.x; s < S; s += kThreads) a.ck[s] = a.T[s] > 0 ? a.pilot_r : 0;
+  } else if (a.alloc == SBMM_ALLOC_USER) {
     bool bad = false;
     for (int64_t s = threadIdx.x; s < S; s += kThreads) {
       const int64_t v = a.user_ck_dev[s];
@@ -219,12 +240,7 @@ __global__ __launch_bounds__(kThreads) void alloc_kernel(PlanLaunch a) {
     double mx = 0.0;
     int64_t act = 0;
     for (int64_t s = threadIdx.x; s < S; s += kThreads) {
-      double g = 1.0;
-      if (a.alloc == SBMM_ALLOC_NORM) g = a.blk[2 * a.K + s];
-      else if (a.alloc == SBMM_ALLOC_OPT) {
-        const double sk = a.blk[2 * a.K + s];
-        g = sqrt(fmax(sk * sk - a.blkprod_sq[s], 0.0));
-      }
+      double g = alloc_weight(a, s);
       if (!isfinite(g) || g < 0.0) { *a.status = SBMM_DEV_NONFINITE; g = 0.0; }
       mx = fmax(mx, g);
       a.rem[s] = 0;
@@ -237,12 +253,7 @@ __global__ __launch_bounds__(kThreads) void alloc_kernel(PlanLaunch a) {
     const int shift = (mx > 0.0) ? (63 - ceil_log2_u64((uint64_t)S)) - 1 - ilogb(mx) : 0;
     uint64_t gsum_local = 0;
     for (int64_t s = threadIdx.x; s < S; s += kThreads) {
-      double g = 1.0;
-      if (a.alloc == SBMM_ALLOC_NORM) g = a.blk[2 * a.K + s];
-      else if (a.alloc == SBMM_ALLOC_OPT) {
-        const double sk = a.blk[2 * a.K + s];
-        g = sqrt(fmax(sk * sk - a.blkprod_sq[s], 0.0));
-      }
+      double g = alloc_weight(a, s);
       if (!isfinite(g) || g < 0.0) g = 0.0;
       const uint64_t G = (a.T[s] > 0 && mx > 0.0) ? quantize(g, shift) : 0;
       a.G[s] = G;
@@ -365,7 +376,7 @@ __device__ void sample_one(const PlanLaunch& a, int64_t t) {
   bool done = false;
   for (uint64_t blk = 0; blk < 1024 && !done; ++blk) {
     U64x4 ctr;
-    ctr.v[0] = j; ctr.v[1] = (uint64_t)s; ctr.v[2] = a.trial; ctr.v[3] = (kTagSample << 32) | blk;
+    ctr.v[0] = j; ctr.v[1] = (uint64_t)s; ctr.v[2] = a.trial; ctr.v[3] = ((a.pilot_r > 0 ? kTagPilot : kTagSample) << 32) | blk;
     const U64x4 w = philox4x64_10(ctr, a.seed, 0);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {

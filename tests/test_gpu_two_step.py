@@ -1,0 +1,151 @@
+"""The two-step algorithm (Alg. 3, methods ONU and ONMCNR) on the GPU against
+the oracle: pilot draws bit for bit, the pilot estimates ||C^{0k} D_{0k}||_F^2,
+the block sizes (4.7) and the step-2 draws exactly, and CD within the dtype's
+tolerance; edge cases and argument errors; the paper's Section 4 shape."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import method as om
+
+torch = pytest.importorskip("torch")
+import paper_2105_04940_amd as pk  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = pk.Handle(0)
+    yield hd
+    hd.close()
+
+
+def to_dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV).to(dtype)
+
+
+def host64(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def check_pilot(h, M, N, off, c0, pilot, dtype, seed=5, trial=1):
+    Md, Nd = to_dev(M, dtype), to_dev(N, dtype)
+    prob = pk.Problem(Md, Nd, off, c=c0, mode="stratified", prob="norm", alloc="two_step",
+                      c0=c0, pilot=pilot, seed=seed, trial=trial)
+    col, row, blk = h.norms(prob)
+    psq, pl = h.pilot(prob, col, row, blk, keep_plan=True)
+    torch.cuda.synchronize()
+    o = om.pilot(host64(Md), host64(Nd), off, c0, pilot, seed, trial)
+    total = 0 if o.draws is None else len(o.draws.atom)
+    idx = pl.idx.cpu().numpy()
+    if o.draws is not None:
+        assert np.array_equal(idx[:total], o.draws.atom)
+        assert pl.ck.cpu().tolist() == o.design.cs
+    assert np.all(idx[total:] == -1)
+    assert pl.col_off[-1].item() == total
+    g = host64(psq)
+    assert np.all(np.abs(g - o.pilot_sq) <= TOL[dtype] * np.maximum(o.pilot_sq, 1e-300) + 1e-300)
+    return prob, psq, o
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("pilot", ["uniform", "norm"])
+def test_pilot_matches_oracle(h, dtype, pilot):
+    M, N, off = wl.random_problem(26, 3000, 28, 6, seed=21, skew=1.5)
+    check_pilot(h, M, N, off, 64, pilot, dtype)
+
+
+@pytest.mark.parametrize("shape", [(300, 2500, 260, 9, 77), (1, 400, 1, 4, 4), (70, 5000, 65, 33, 1000)])
+def test_pilot_ragged_shapes(h, shape):
+    # tiles cut through rows and columns; c0 = K (one pilot draw per block);
+    # strata wider than one product tile step
+    m, n, p, K, c0 = shape
+    M, N, off = wl.random_problem(m, n, p, K, seed=m + K, skew=1.0)
+    for dtype in (torch.float64, torch.float32):
+        check_pilot(h, M, N, off, c0, "norm", dtype, seed=m)
+
+
+def check_run(h, M, N, off, c, c0, pilot, dtype, seed=7, trial=0):
+    Md, Nd = to_dev(M, dtype), to_dev(N, dtype)
+    prob = pk.Problem(Md, Nd, off, c, mode="stratified", prob="norm", alloc="two_step",
+                      c0=c0, pilot=pilot, seed=seed, trial=trial)
+    r = h.run(prob)
+    o = om.run(host64(Md), host64(Nd), off, c, seed=seed, trial=trial, mode="stratified", prob="norm",
+               alloc="two_step", c0=c0, pilot_prob=pilot)
+    assert r["plan"].ck.cpu().tolist() == o.design.cs
+    assert np.array_equal(r["plan"].idx.cpu().numpy(), o.draws.atom)
+    assert r["L"] == o.draws.L
+    tol = TOL[dtype]
+    assert rel(host64(r["CD"]), o.CD) < tol
+    assert abs(r["rel"] - o.rel) <= tol * max(o.rel, 1.0)
+    return prob, r, o
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("pilot", ["uniform", "norm"])
+def test_two_step_run_matches_oracle(h, dtype, pilot):
+    M, N, off = wl.random_problem(26, 3000, 28, 6, seed=22, skew=1.5)
+    check_run(h, M, N, off, 600, 60, pilot, dtype)
+
+
+def test_two_step_plan_with_given_pilot_equals_run(h):
+    M, N, off = wl.random_problem(40, 2000, 30, 8, seed=23, skew=1.2)
+    prob, r, _ = check_run(h, M, N, off, 400, 80, "norm", torch.float64)
+    col, row, blk = h.norms(prob)
+    prob.pilot_sq = h.pilot(prob, col, row, blk)
+    pl = h.plan(prob, col, row, blk)
+    assert torch.equal(pl.idx, r["plan"].idx) and torch.equal(pl.ck, r["plan"].ck)
+
+
+def test_pilot_zero_block(h):
+    # a block of zero columns: no pilot draws under (3.8), estimate 0, and no
+    # step-2 draws (its weights are zero); under uniform pilot probabilities
+    # it is drawn but its estimate is still 0
+    M, N, off = wl.random_problem(20, 600, 12, 6, seed=24)
+    M[:, off[2]:off[3]] = 0.0
+    _, psq, o = check_pilot(h, M, N, off, 30, "norm", torch.float64)
+    assert o.design.cs[2] == 0 and psq[2].item() == 0.0
+    _, psq, o = check_pilot(h, M, N, off, 30, "uniform", torch.float64)
+    assert o.design.cs[2] == 5 and psq[2].item() == 0.0
+    _, r, o = check_run(h, M, N, off, 90, 30, "uniform", torch.float64)
+    assert r["plan"].ck[2].item() == 0
+
+
+def test_pilot_rejects(h):
+    M, N, off = wl.random_problem(10, 60, 8, 3, seed=25)
+    Md, Nd = to_dev(M, torch.float64), to_dev(N, torch.float64)
+    base = dict(mode="stratified", prob="norm", alloc="two_step", pilot="norm")
+    col, row, blk = h.norms(pk.Problem(Md, Nd, off, 6, **base, c0=6))
+    for kw in (dict(c0=2), dict(c0=6, pilot="exact"), dict(c0=6, mode="block")):
+        prob = pk.Problem(Md, Nd, off, 6, **{**base, **kw})
+        with pytest.raises(pk.SbmmError) as ei:
+            h.pilot(prob, col, row, blk)
+        assert ei.value.status == pk.SBMM_E_ARG
+    # step 2 without the pilot estimates
+    with pytest.raises(pk.SbmmError) as ei:
+        h.plan(pk.Problem(Md, Nd, off, 6, **base, c0=6), col, row, blk)
+    assert ei.value.status == pk.SBMM_E_ARG
+    # c0 below K in the whole-path call
+    with pytest.raises(pk.SbmmError) as ei:
+        h.run(pk.Problem(Md, Nd, off, 6, **base, c0=2))
+    assert ei.value.status == pk.SBMM_E_ARG
+
+
+@pytest.mark.parametrize("case", [1, 2])
+@pytest.mark.parametrize("pilot", ["uniform", "norm"])
+def test_two_step_section4_shape(h, case, pilot):
+    # the paper's Section 4 sizes: m = 26, p = 28, n = 5e5, K = 10 blocks of
+    # 5e4, c0 = 5000, c = 5e4; Cases I (Gaussian) and II (t_1, location 1)
+    M, N = wl.case_data(case)
+    off = wl.equal_blocks(M.shape[1], 10)
+    check_run(h, M, N, off, 50000, 5000, pilot, torch.float64, seed=3, trial=case)
