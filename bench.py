@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-linear-layer", action="store_true",
                     help="skip the bf16 linear-layer forward/backward leg")
+    ap.add_argument("--no-section4", action="store_true",
+                    help="skip the paper's Section 4 stratified-sampling leg")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 512-problem batched leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -363,6 +365,78 @@ def batched_leg(h, pk, wl, torch, steps, warmup):
     return out
 
 
+def section4_leg(h, pk, wl, torch, reps=100, warmup=3):
+    """The paper's Section 4 setting in float64: m = 26, p = 28, n = 5e5 in
+    K = 10 blocks of 5e4, c = 5e4, Cases I (Gaussian) and II (t_1, location
+    1). Per method, one step is everything the method computes before its
+    estimate is judged: norm pass, then ||M^k N_k||_F per block (OPL) or the
+    pilot with c0 = 5000 (ONU, ONMCNR), plan, gather and sketched product
+    with its error against the exact MN (computed once, outside the timing).
+    Mean relative error over `reps` replications (trials), as the paper
+    averages 100."""
+    dev = "cuda:0"
+    methods = {"UU": dict(prob="uniform", alloc="uniform"),
+               "ONC": dict(prob="norm", alloc="norm"),
+               "OPL": dict(prob="norm", alloc="opt"),
+               "ONU": dict(prob="norm", alloc="two_step", pilot="uniform"),
+               "ONMCNR": dict(prob="norm", alloc="two_step", pilot="norm")}
+    K, c, c0 = 10, 50000, 5000
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    out = {"workload": ("paper Section 4: M 26x500000, N 500000x28 float64, K=10 blocks of 50000, c=50000, "
+                        "c0=5000 (two-step pilots), Case I Gaussian rows/columns with Toeplitz covariances, "
+                        "Case II multivariate t_1 with location 1; stratified sampling (Alg. 2 / Alg. 3)"),
+           "replications": reps}
+    for case in (1, 2):
+        M, N = wl.case_data(case)
+        off = wl.equal_blocks(M.shape[1], K)
+        Md = torch.from_numpy(M).to(dev)
+        Nd = torch.from_numpy(N).to(dev)
+        del M, N
+        base = pk.Problem(Md, Nd, off, c, mode="stratified")
+        MN, _, mn_sq = h.exact(base, store=True)
+        # norm pass bandwidth on this shape
+        col, row, blk = h.norms(base)
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(10):
+            h.norms(base)
+        e1.record()
+        torch.cuda.synchronize()
+        norm_ms = e0.elapsed_time(e1) / 10
+        res = {"norm_pass_ms": norm_ms,
+               "norm_pass_GBps": (Md.numel() + Nd.numel()) * 8 / norm_ms / 1e6}
+        for name, kw in methods.items():
+            ms, errs = [], []
+            for t in range(warmup + reps):
+                prob = pk.Problem(Md, Nd, off, c, mode="stratified", c0=c0, seed=0, trial=t, **kw)
+                a, b = ev(), ev()
+                a.record()
+                col, row, blk = h.norms(prob)
+                if kw["alloc"] == "opt":
+                    _, prob.blkprod_sq, _ = h.exact(prob, store=False, blocknorm=True)
+                if kw["alloc"] == "two_step":
+                    prob.pilot_sq = h.pilot(prob, col, row, blk)
+                pl = h.plan(prob, col, row, blk, sync=False)
+                C, D = h.sketch(prob, pl)
+                _, err = h.sketch_gemm(C, D, pl, MN=MN, store=False)
+                b.record()
+                if t >= warmup:
+                    ms.append((a, b))
+                    errs.append(err)
+            torch.cuda.synchronize()
+            times = [x.elapsed_time(y) for x, y in ms]
+            rel = np.sqrt(torch.cat(errs).cpu().numpy() / mn_sq.item())
+            res[name] = {"ms_per_step_median": float(np.median(times)),
+                         "rel_err_mean": float(rel.mean()), "rel_err_std": float(rel.std())}
+        out[f"case{'I' * case}"] = res
+        del Md, Nd, MN
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.trace_summary:
@@ -601,6 +675,9 @@ def main():
         del Md, Nd, MN, res, f32, b16, mx8
         torch.cuda.empty_cache()
         out["linear_layer"] = linear_layer_leg(h, pk, wl, torch, args.steps, args.warmup)
+    if not args.no_section4:
+        print("section 4 leg", file=sys.stderr, flush=True)
+        out["section4"] = section4_leg(h, pk, wl, torch)
     if not args.no_batched:
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(h, pk, wl, torch, max(2, args.steps // 2), 1)
