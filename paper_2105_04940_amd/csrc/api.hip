@@ -153,6 +153,15 @@ sbmm_status do_norms(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
 
 sbmm_dtype product_dtype(sbmm_dtype in) { return in == SBMM_F64 ? SBMM_F64 : SBMM_F32; }
 
+// launch_gemm, or its split-K form when the caller sized a workspace for it.
+hipError_t run_product(const GemmLaunch& G, hipStream_t s) {
+  if (G.skinny_ws) {
+    const int64_t tiles = gemm_tiles(G.dt, G.m, G.p, G.blk_part != nullptr);
+    return launch_gemm_skinny(G, tiles, tiles * 4, s);
+  }
+  return launch_gemm(G, s);
+}
+
 int64_t max_block_width(const sbmm_problem* P) {
   int64_t w = 0;
   for (int32_t k = 0; k < P->K; ++k) w = std::max(w, P->block_off[k + 1] - P->block_off[k]);
@@ -185,6 +194,8 @@ sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
   double* blk_part = bn ? ar.take<double>((size_t)P->K * std::max<int64_t>(tiles, 1) * 4) : nullptr;
   float* stage = ar.take<float>(gemm_stage_bytes(P->in_dtype, P->m, P->p) / sizeof(float));
+  const size_t skb = gemm_skinny_ws_bytes(P->in_dtype, P->m, P->p, P->n, bn ? P->K : 0);
+  void* skinny = skb ? ar.take<char>(skb) : nullptr;
   if (!ar.base) return SBMM_OK;
   if (tiles == 0) {
     HIP_TRY(h, launch_fill_f64(out2, 2, 0.0, s));
@@ -196,7 +207,8 @@ sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
   G.m = P->m; G.p = P->p; G.K_host = P->n; G.K_dev = nullptr;
   G.Cout = MN; G.ldc = ldmn; G.Y = Y; G.ldy = ldy; G.tile_part = tile_part;
   G.K_blocks = P->K; G.off_dev = off_dev; G.blk_part = blk_part; G.stage = stage;
-  HIP_TRY(h, launch_gemm(G, s));
+  G.skinny_ws = skinny; G.skinny_K_max = P->n;
+  HIP_TRY(h, run_product(G, s));
   HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
   if (bn) HIP_TRY(h, launch_reduce_cols(blk_part, P->K, tiles * 4, blkprod_sq, s));
   return SBMM_OK;
@@ -279,6 +291,8 @@ sbmm_status do_pilot(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
   const int64_t tiles = gemm_tiles(pd, P->m, P->p, true);
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
   double* blk_part = ar.take<double>((size_t)P->K * std::max<int64_t>(tiles, 1) * 4);
+  const size_t skb = gemm_skinny_ws_bytes(pd, P->m, P->p, Lp, P->K);
+  void* skinny = skb ? ar.take<char>(skb) : nullptr;
   int64_t* draw_off = nullptr;
   sbmm_status st = do_plan(h, &Q, sz, off_dev, col_sq, row_sq, blk, pp, ar, s, P->c0 / P->K, &draw_off);
   if (st || !ar.base) return st;
@@ -298,7 +312,8 @@ sbmm_status do_pilot(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
   G.K_host = 0; G.K_dev = pp->col_off + Q.c; G.Cout = nullptr; G.ldc = P->p;
   G.Y = nullptr; G.ldy = P->p; G.tile_part = tile_part;
   G.K_blocks = P->K; G.off_dev = draw_off; G.blk_part = blk_part; G.stage = nullptr;
-  HIP_TRY(h, launch_gemm(G, s));
+  G.skinny_ws = skinny; G.skinny_K_max = Lp;
+  HIP_TRY(h, run_product(G, s));
   HIP_TRY(h, launch_reduce_cols(blk_part, P->K, tiles * 4, pilot_sq, s));
   return SBMM_OK;
 }
@@ -508,17 +523,20 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   const int64_t tiles = bf ? gemm_tiles_tn(m, p) : gemm_tiles(dtype, m, p, false);
   const size_t stage_elems = gemm_stage_bytes(dtype, m, p) / sizeof(float);
   const size_t dt_elems = bf ? (size_t)std::max<int64_t>(p, 1) * std::max<int64_t>(L_pad_max, 1) : 0;
+  const size_t skb = bf ? 0 : gemm_skinny_ws_bytes(dtype, m, p, L_pad_max, 0);
   Arena dry(nullptr);
   dry.take<double>(2 * std::max<int64_t>(tiles, 1));
   dry.take<double>(2);
   dry.take<float>(stage_elems);
   dry.take<uint16_t>(dt_elems);
+  dry.take<char>(skb);
   if ((st = ensure_ws(h, dry.off))) return st;
   Arena ar(h->ws);
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
   double* out2 = ar.take<double>(2);
   float* stage = ar.take<float>(stage_elems);
   uint16_t* Dt = ar.take<uint16_t>(dt_elems);
+  void* skinny = skb ? ar.take<char>(skb) : nullptr;
   if (tiles == 0) {
     if (err_sq) HIP_TRY(h, launch_fill_f64(err_sq, 1, 0.0, s));
     return SBMM_OK;
@@ -532,7 +550,8 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
     HIP_TRY(h, launch_transpose_bf16(SBMM_BF16, D, L_pad_max, p, ldd, L_dev, Dt, L_pad_max, s));
     G.B = Dt; G.ldb = L_pad_max; G.b_trans = true;
   }
-  HIP_TRY(h, launch_gemm(G, s));
+  G.skinny_ws = skinny; G.skinny_K_max = L_pad_max;
+  HIP_TRY(h, run_product(G, s));
   if (err_sq) {
     HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
     HIP_TRY(h, hipMemcpyAsync(err_sq, out2, sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -676,6 +695,8 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
     const int64_t tiles_s = gemm_tiles(compute, P->m, P->p, false);
     double* sk_part = ar.take<double>(2 * std::max<int64_t>(tiles_s, 1));
     float* sk_stage = ar.take<float>(gemm_stage_bytes(compute, P->m, P->p) / sizeof(float));
+    const size_t skb = compute == SBMM_BF16 ? 0 : gemm_skinny_ws_bytes(compute, P->m, P->p, sz.L_pad_max, 0);
+    void* sk_skinny = skb ? ar.take<char>(skb) : nullptr;
     // measure the remaining scratch of the sub-steps on a dry arena
     if (!pass) {
       do_norms(h, P, off, col_sq, row_sq, blk, ar, s);
@@ -740,7 +761,8 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
       G.K_host = 0; G.K_dev = plan->col_off + P->c; G.Cout = CD; G.ldc = ldcd;
       G.Y = bp ? MNw : nullptr; G.ldy = ldmnw; G.tile_part = bp ? sk_part : nullptr;
       G.stage = sk_stage;
-      HIP_TRY(h, launch_gemm(G, s));
+      G.skinny_ws = sk_skinny; G.skinny_K_max = sz.L_pad_max;
+      HIP_TRY(h, run_product(G, s));
       if (bp) HIP_TRY(h, launch_reduce_cols(sk_part, 2, tiles_s, sk2, s));
     }
     // 6. exact product with the error against CD

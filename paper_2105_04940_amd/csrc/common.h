@@ -154,7 +154,18 @@ struct GemmLaunch {
   bool a_trans, b_trans;
   // grouped float32 only: read the sketch in place from A = M, B = N
   const int32_t* colmap; const double* colscale;
+  // split-K path for small outputs (launch_gemm_skinny): its workspace of
+  // gemm_skinny_ws_bytes(dt, m, p, skinny_K_max, blocks) bytes
+  void* skinny_ws; int64_t skinny_K_max;
 };
+// Workspace of the split-K path for an m x p product with inner extent up to
+// K_max (nblk > 0: per-block norms of that many blocks); 0 when the product
+// should take the tiled kernels (large outputs, short inner extents).
+size_t gemm_skinny_ws_bytes(sbmm_dtype dt, int64_t m, int64_t p, int64_t K_max, int32_t nblk);
+// The same product as launch_gemm (F32 / F64), writing its epilogue sums into
+// column 0 of tile_part ([2][tiles_out]) and the block norms into column 0 of
+// blk_part ([K][blk_cols]), zeros elsewhere.
+hipError_t launch_gemm_skinny(const GemmLaunch& L, int64_t tiles_out, int64_t blk_cols, hipStream_t s);
 // bytes of the float32 staging buffer launch_gemm needs
 size_t gemm_stage_bytes(sbmm_dtype dt, int64_t m, int64_t p);
 int64_t gemm_tiles(sbmm_dtype dt, int64_t m, int64_t p, bool blocknorm);
