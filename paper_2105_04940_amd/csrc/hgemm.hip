@@ -370,6 +370,169 @@ __global__ __launch_bounds__(kThreads, 1) void hgemm_tn_kernel(GemmArgs g) {
 }
 
 
+// ============================================================================
+// The same 256 x 256 product with the operand tiles fetched straight into LDS
+// (buffer_load_dwordx4 ... lds): no staging registers and no LDS store phase,
+// so the 256 accumulator registers of a wave leave room for the fragments
+// without spilling. A wave instruction fills 64 consecutive 16-byte LDS
+// slots, lane l at slot base + l; slot P of a tile is (row P / 8, swizzled
+// chunk P % 8), so lane l fetches chunk (l & 7) ^ (l >> 3) of row
+// 64 w + 8 j + l / 8 for instruction j of wave w. Row offsets live in one
+// register per operand (the instruction's row step added per load, so the
+// hardware range check, which covers the vector offset, sees every row) and
+// the k-step in the scalar offset. Rows past the operand's end fall outside
+// the buffer's record count and chunks past the inner extent get an
+// out-of-range offset: both read as zero, so edge tiles need no separate
+// path, and a live chunk of a valid row never reads past that row's first K
+// elements. Per k-step: issue the next tile's loads, run the 64 matrix
+// instructions on the current tile, wait for the loads, barrier.
+// ============================================================================
+template <int BK_, int STAGES_>
+struct TnLdsTile {
+  static constexpr int BM = 256, BN = 256, BK = BK_, KC = BK / 8, STAGES = STAGES_;
+  uint4 As[STAGES][BM * KC];
+  uint4 Bs[STAGES][BN * KC];
+  double red[8];
+};
+
+// LDS slot of 16-byte chunk `chunk` of tile row `row`: a row holds KC chunks
+// and the chunk index is XORed with a row-dependent value chosen so that the
+// 16 consecutive rows a 16-lane group of ds_read_b128 reads (same chunk) fall
+// in 16 different 16-byte bank groups.
+template <int KC>
+__device__ __forceinline__ int tn_lds_slot(int row, int chunk) {
+  if constexpr (KC == 8) return row * 8 + (chunk ^ ((row >> 1) & 7));
+  else return row * 4 + (chunk ^ ((row >> 2) & 3));
+}
+
+// Buffer resource of a panel of `rows` rows; every field is made explicitly
+// wave-uniform (scalar registers), so the loads need no per-lane loop.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const uint16_t* base, int64_t rows, int64_t ld) {
+  const uint64_t u = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  const int bytes = __builtin_amdgcn_readfirstlane((int)(rows > 0 ? rows * ld * 2 : 0));
+  void* p = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
+}
+
+template <int BK, int STAGES>
+__global__ __launch_bounds__(kThreads, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
+  using Tile = TnLdsTile<BK, STAGES>;
+  constexpr int KC = Tile::KC;
+  constexpr int ROWS_PER_INST = 64 / KC;              // tile rows one wave instruction fills
+  constexpr int INSTS = Tile::BM / ROWS_PER_INST / 4; // instructions per wave per operand and stage
+  __shared__ Tile sh;
+  int64_t tm, tn;
+  tile_coords(g, tm, tn);
+  const int64_t m0 = tm * Tile::BM, n0 = tn * Tile::BN;
+  const int64_t K = inner_extent(g);
+  const int tid = threadIdx.x, lane = tid & 63;
+  // uniform across the wave: the LDS destination of a load is a scalar
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 31, lh = lane >> 5;
+  const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 128;
+  const uint16_t* A = reinterpret_cast<const uint16_t*>(g.A) + m0 * g.lda;
+  const uint16_t* B = reinterpret_cast<const uint16_t*>(g.B) + n0 * g.ldb;
+  const __amdgpu_buffer_rsrc_t ra = panel_rsrc(A, min((int64_t)Tile::BM, g.m - m0), g.lda);
+  const __amdgpu_buffer_rsrc_t rb = panel_rsrc(B, min((int64_t)Tile::BN, g.p - n0), g.ldb);
+  constexpr unsigned kOut = 0x80000000u;   // past any record count
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[b][c] = f32x16{};
+
+  // instruction j of wave w fills slots [(INSTS w + j) 64, +64): lane l holds
+  // slot P = (INSTS w + j) 64 + l, i.e. tile row P / KC and the chunk whose
+  // swizzled slot is P % KC
+  auto issue = [&](int64_t kt, int buf) {
+    const int64_t k0 = kt * BK;
+    const unsigned sk = (unsigned)(k0 * 2);
+#pragma unroll
+    for (int j = 0; j < INSTS; ++j) {
+      const int row = (INSTS * wave + j) * ROWS_PER_INST + lane / KC;
+      const int slot = lane % KC;
+      const int chunk = KC == 8 ? (slot ^ ((row >> 1) & 7)) : (slot ^ ((row >> 2) & 3));
+      const bool live = k0 + 8 * chunk < K;   // the inner tail reads zero
+      const unsigned oa = live ? (unsigned)(row * g.lda * 2 + chunk * 16) : kOut;
+      const unsigned ob = live ? (unsigned)(row * g.ldb * 2 + chunk * 16) : kOut;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(INSTS * wave + j) * 64], 16, oa, sk, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rb, (__attribute__((address_space(3))) void*)&sh.Bs[buf][(INSTS * wave + j) * 64], 16, ob, sk, 0, 0);
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < BK / 16; ++s) {
+      bf16x8 av[4], bv[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        av[b] = __builtin_bit_cast(bf16x8, sh.As[buf][tn_lds_slot<KC>(wm0 + 32 * b + lr, 2 * s + lh)]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        bv[c] = __builtin_bit_cast(bf16x8, sh.Bs[buf][tn_lds_slot<KC>(wn0 + 32 * c + lr, 2 * s + lh)]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[b], bv[c], acc[b][c], 0, 0, 0);
+    }
+  };
+
+  // a ring of STAGES tiles, loads issued STAGES - 1 steps ahead; before step
+  // kt computes, the loads of every step up to kt have landed (memory reads
+  // of a wave complete in order, so at most the STAGES - 2 newer steps' loads
+  // may still be outstanding) and the barrier publishes them to all waves
+  const int64_t nkt = (K + BK - 1) / BK;
+#pragma unroll
+  for (int st = 0; st < STAGES - 1; ++st)
+    if (st < nkt) issue(st, st);
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int64_t ahead = nkt - 1 - kt;   // steps issued after kt (capped below)
+    if (STAGES == 2 || ahead <= 0) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    } else if (ahead == 1) {
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * INSTS) : "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * INSTS * (STAGES - 2)) : "memory");
+    }
+    __syncthreads();
+    if (kt + STAGES - 1 < nkt) issue(kt + STAGES - 1, (int)((kt + STAGES - 1) % STAGES));
+    compute((int)(kt % STAGES));
+  }
+
+  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
+      if (row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t col = n0 + wn0 + 32 * c + lr;
+        if (col >= g.p) continue;
+        const float val = acc[b][c][v];
+        if (Cout) Cout[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (Y) {
+          const double d = dv - (double)Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
+}
+
+constexpr int TN_BK = 64, TN_STAGES = 2;
+
 constexpr int BF16_WMB = 2, BF16_WNB = 2, BF16_BK = 64, BF16_WGS = 2;   // 128 x 128
 
 }  // namespace
@@ -383,12 +546,20 @@ int64_t gemm_tiles_tn(int64_t m, int64_t p) { return ceil_div(m, TnTile::BM) * c
 hipError_t launch_hgemm(const GemmLaunch& L, hipStream_t s) {
   int64_t bm, bn;
   if (L.b_trans && !L.a_trans) {
-    // both operands inner-index contiguous: the 256 x 256 kernel
+    // both operands inner-index contiguous: the 256 x 256 kernels
     hgemm_tn_tile_shape(&bm, &bn);
     const GemmArgs g = make_gemm_args(L, bm, bn);
     const int64_t tiles = g.tiles_m * g.tiles_n;
     if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(hgemm_tn_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
+    // LDS-direct loads need whole aligned 16-byte chunks (an inner extent
+    // read on the device is a multiple of 32) and 32-bit panel offsets
+    const int64_t ld = std::max(L.lda, L.ldb);
+    const bool fits = 257 * ld * 2 < ((int64_t)1 << 31);
+    const bool chunks = L.K_dev != nullptr || L.K_host % 8 == 0;
+    if (g.vec_a && g.vec_b && fits && chunks)
+      hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES>), dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
+    else
+      hipLaunchKernelGGL(hgemm_tn_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
     return hipGetLastError();
   }
   hgemm_tile_shape(&bm, &bn);
