@@ -302,6 +302,166 @@ __global__ __launch_bounds__(kThreads, 1) void mx_gemm_kernel(MxArgs g) {
     mx_body<true>(g, sh, m0, n0, K);
 }
 
+// ============================================================================
+// The same product with the code tiles fetched straight into LDS
+// (buffer_load_dwordx4 ... lds), as the bf16 inner-index-contiguous kernel
+// does: a wave instruction fills 64 consecutive 16-byte slots (lane l at
+// slot base + l), slot P of a tile being row P / 8 and the chunk whose
+// swizzled position (chunk ^ ((row >> 1) & 7)) is P % 8, so the 16-lane
+// groups of ds_read_b128 (16 consecutive rows, one chunk) hit 16 bank
+// groups. Rows past the end lie outside the buffer's record count and
+// chunks past the inner extent get an out-of-range offset; both read zero.
+// The scale words of step k + 1 are loaded into registers before that
+// step's tile loads are issued, so the in-order wait for the tile also
+// covers them and nothing inside the compute phase waits on memory.
+// ============================================================================
+__device__ __forceinline__ int mx_lds_slot(int row, int chunk) { return row * 8 + (chunk ^ ((row >> 1) & 7)); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mx_panel_rsrc(const uint8_t* base, int64_t rows, int64_t ld) {
+  const uint64_t u = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  const int bytes = __builtin_amdgcn_readfirstlane((int)(rows > 0 ? rows * ld : 0));
+  void* p = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
+}
+
+__global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
+  __shared__ MxTile sh;
+  constexpr int BK = MxTile::BK;
+  int64_t tm, tn;
+  mx_tile_coords(g, tm, tn);
+  const int64_t m0 = tm * MxTile::BM, n0 = tn * MxTile::BN;
+  const int64_t K = (*g.K_dev + kBlk - 1) / kBlk * kBlk;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 31, lh = lane >> 5;
+  const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 128;
+  const __amdgpu_buffer_rsrc_t ra = mx_panel_rsrc(g.A + m0 * g.lda, min((int64_t)MxTile::BM, g.m - m0), g.lda);
+  const __amdgpu_buffer_rsrc_t rb = mx_panel_rsrc(g.B + n0 * g.ldb, min((int64_t)MxTile::BN, g.p - n0), g.ldb);
+  constexpr unsigned kOut = 0x80000000u;
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[b][c] = f32x16{};
+
+  auto issue = [&](int64_t kt, int buf) {
+    const int64_t k0 = kt * BK;
+    const unsigned sk = (unsigned)k0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int row = (8 * wave + j) * 8 + (lane >> 3);
+      const int chunk = (lane & 7) ^ ((row >> 1) & 7);
+      const bool live = k0 + 16 * chunk < K;
+      const unsigned oa = live ? (unsigned)(row * g.lda + chunk * 16) : kOut;
+      const unsigned ob = live ? (unsigned)(row * g.ldb + chunk * 16) : kOut;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(8 * wave + j) * 64], 16, oa, sk, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rb, (__attribute__((address_space(3))) void*)&sh.Bs[buf][(8 * wave + j) * 64], 16, ob, sk, 0, 0);
+    }
+  };
+  // the four E8M0 scales of a k-step for this lane's rows / columns (one
+  // 32-bit word per 32 x 32 block; 127 = 1 outside the matrix)
+  auto scale_word = [&](const uint8_t* S, int64_t lds, int64_t r, int64_t rmax, int64_t kt) -> uint32_t {
+    if (r >= rmax) return 0x7f7f7f7fu;
+    return *reinterpret_cast<const uint32_t*>(S + r * lds + 4 * kt);
+  };
+  uint32_t sa[4], sb[4];
+  auto load_scales = [&](int64_t kt, uint32_t* xa, uint32_t* xb) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xa[b] = scale_word(g.As, g.ldas, m0 + wm0 + 32 * b + lr, g.m, kt);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xb[c] = scale_word(g.Bs, g.ldbs, n0 + wn0 + 32 * c + lr, g.p, kt);
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < BK / 64; ++s) {
+      i32x8 av[4], bv[4];
+      const int c0 = 4 * s + lh;   // this lane's 16-byte chunks: c0 and c0 + 2
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int row = wm0 + 32 * b + lr;
+        const uint4 u0 = sh.As[buf][mx_lds_slot(row, c0)], u1 = sh.As[buf][mx_lds_slot(row, c0 + 2)];
+        av[b] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w, (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int row = wn0 + 32 * c + lr;
+        const uint4 u0 = sh.Bs[buf][mx_lds_slot(row, c0)], u1 = sh.Bs[buf][mx_lds_slot(row, c0 + 2)];
+        bv[c] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w, (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+      }
+      const int sh_bits = 8 * (2 * s + lh);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[b][c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              av[b], bv[c], acc[b][c], 0, 0, 0, (int)((sa[b] >> sh_bits) & 0xffu), 0,
+              (int)((sb[c] >> sh_bits) & 0xffu));
+    }
+  };
+
+  const int64_t nkt = (K + BK - 1) / BK;
+  if (nkt > 0) {
+    load_scales(0, sa, sb);
+    issue(0, 0);
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int cur = (int)(kt & 1);
+    uint32_t na[4], nb[4];
+    if (kt + 1 < nkt) {
+      load_scales(kt + 1, na, nb);
+      issue(kt + 1, cur ^ 1);
+    }
+    compute(cur);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (kt + 1 < nkt) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { sa[i] = na[i]; sb[i] = nb[i]; }
+    }
+  }
+
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
+      if (row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t col = n0 + wn0 + 32 * c + lr;
+        if (col >= g.p) continue;
+        const float val = acc[b][c][v];
+        if (g.C) g.C[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (g.Y) {
+          const double d = dv - (double)g.Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  if (g.tile_part) {
+    e2 = warp_sum_f64(e2);
+    n2 = warp_sum_f64(n2);
+    if (lane == 0) { sh.red[wave] = e2; sh.red[4 + wave] = n2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int64_t tiles = g.tiles_m * g.tiles_n;
+      g.tile_part[blockIdx.x] = ((sh.red[0] + sh.red[1]) + sh.red[2]) + sh.red[3];
+      g.tile_part[tiles + blockIdx.x] = ((sh.red[4] + sh.red[5]) + sh.red[6]) + sh.red[7];
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_mx_gather(const MxGatherLaunch& L, hipStream_t s) {
@@ -335,6 +495,12 @@ hipError_t launch_mx_gemm(const MxGemmLaunch& L, hipStream_t s) {
   g.tiles_n = ceil_div(L.p, MxTile::BN);
   const int64_t tiles = g.tiles_m * g.tiles_n;
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(mx_gemm_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
+  // LDS-direct loads: 32-bit offsets within a 256-row panel (the API
+  // already requires 16-byte aligned codes and leading dimensions)
+  const int64_t ld = std::max(L.lda, L.ldb);
+  if (257 * ld < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(mx_gemm_lds_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
+  else
+    hipLaunchKernelGGL(mx_gemm_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
   return hipGetLastError();
 }
