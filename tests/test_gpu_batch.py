@@ -106,21 +106,41 @@ def test_small_batch_matches_oracle(small_batch):
         check_against_oracle(b, probs, host, t, o)
 
 
+def _split_k(m, p, extent):
+    # the single-problem path takes its split-K product for outputs of at
+    # most 128 x 128 with an inner extent of at least 2048 (the batch has no
+    # such form, so there the two sum in different orders)
+    return m <= 128 and p <= 128 and extent >= 2048
+
+
+def _same_product(x, y, split_k):
+    # different summation orders of float32 products over thousands of terms
+    # differ by a few units of sqrt(K) u; both are held to the float32 bar
+    # (1e-5 relative) against the oracle elsewhere, so that bar applies here
+    if not split_k:
+        return torch.equal(x, y)
+    return ((x.double() - y.double()).norm() / y.double().norm()).item() < 1e-5
+
+
 def test_batch_equals_single_problem_path(h, small_batch):
     # each problem of the batch (norms, plan, fused-gather product) gives the
     # same bits as the single-problem path (gather to C, D, then the product)
+    # wherever both run the same tiled product
     b, probs, host = small_batch
     b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
     b.run()
     torch.cuda.synchronize()
     for t, pr in enumerate(probs):
-        r = h.run(pk.Problem(pr["M"], pr["N"], pr["off"], pr["c"], prob=pr["prob"], seed=pr["seed"],
-                             trial=pr["trial"]))
+        prob = pk.Problem(pr["M"], pr["N"], pr["off"], pr["c"], prob=pr["prob"], seed=pr["seed"],
+                          trial=pr["trial"])
+        r = h.run(prob)
         torch.cuda.synchronize()
+        m, n = pr["M"].shape
+        p = pr["N"].shape[1]
         assert torch.equal(r["plan"].idx, b.draws(t)), t
         assert r["L"] == int(b.L[t].item()), t
-        assert torch.equal(r["CD"], b.CD[t]), t
-        assert torch.equal(r["MN"], b.MN[t]), t
+        assert _same_product(r["CD"], b.CD[t], _split_k(m, p, pk.sbmm_query_sizes(prob)["L_pad_max"])), t
+        assert _same_product(r["MN"], b.MN[t], _split_k(m, p, n)), t
 
 
 def _snapshot(b):
