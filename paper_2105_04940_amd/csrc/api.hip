@@ -13,14 +13,17 @@
 namespace {
 
 // Bump allocator over the handle's workspace. A dry run (base == nullptr)
-// only measures.
+// only measures; it hands out distinct non-null placeholders (never
+// dereferenced: no launch or copy happens in a dry run) so that code which
+// decides on whether an optional buffer exists (block norms, pilot
+// estimates) sizes itself exactly as the real run does.
 struct Arena {
   char* base;
   size_t off = 0;
   explicit Arena(char* b) : base(b) {}
   template <typename T> T* take(size_t count) {
     off = (off + 255) & ~size_t(255);
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    T* p = base ? reinterpret_cast<T*>(base + off) : reinterpret_cast<T*>((uintptr_t)256 + off);
     off += sizeof(T) * (count ? count : 1);
     return p;
   }
@@ -178,11 +181,12 @@ sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
     return fail(h, SBMM_E_UNSUPPORTED, "block product norms of bf16 inputs are not built");
   const bool gram = blkprod_sq != nullptr && P->in_dtype == SBMM_F32 && max_block_width(P) <= block_gram_max_width();
   if (gram) {
+    void* gws = ar.take<char>(block_gram_ws_bytes(P->K));
     if (ar.base) {
       if (P->m > 0 && P->p > 0) {
         HIP_TRY(h, launch_block_gram(reinterpret_cast<const float*>(P->M), P->ldm,
                                      reinterpret_cast<const float*>(P->N), P->ldn, P->m, P->p, off_dev,
-                                     P->K, blkprod_sq, s));
+                                     P->K, blkprod_sq, gws, s));
       } else {
         HIP_TRY(h, launch_fill_f64(blkprod_sq, P->K, 0.0, s));
       }

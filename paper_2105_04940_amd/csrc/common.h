@@ -203,8 +203,10 @@ void hgemm_tile_shape(int64_t* bm, int64_t* bn);
 
 // ||M^k N_k||_F^2 per block through the Gram matrices (float32 inputs,
 // blocks at most block_gram_max_width() wide), one workgroup per block.
+// workspace of launch_block_gram: the two Gram matrices of every block
+size_t block_gram_ws_bytes(int32_t K);
 hipError_t launch_block_gram(const float* M, int64_t ldm, const float* N, int64_t ldn, int64_t m, int64_t p,
-                             const int64_t* off_dev, int32_t K, double* out, hipStream_t s);
+                             const int64_t* off_dev, int32_t K, double* out, void* ws, hipStream_t s);
 int64_t block_gram_max_width();
 
 // Backward of the sketch: per-atom draw lists and the scatter of dC / dD

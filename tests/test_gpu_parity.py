@@ -180,7 +180,9 @@ def _check_run(h, M, N, off, c, dtype, **kw):
     prob = pk.Problem(Md, Nd, off, c, **kw)
     r = h.run(prob)
     Mh, Nh = host64(Md), host64(Nd)
-    okw = {k: v for k, v in kw.items() if k in ("seed", "trial", "mode", "prob", "alloc")}
+    okw = {k: v for k, v in kw.items() if k in ("seed", "trial", "mode", "prob", "alloc", "c0")}
+    if "pilot" in kw:
+        okw["pilot_prob"] = kw["pilot"]
     o = oracle_run(Mh, Nh, off, c, **okw)
     tol = TOL[dtype]
     idx = r["plan"].idx.cpu().numpy()
@@ -485,3 +487,25 @@ def test_backward_bf16_linear_layer(h):
     # and an unbiased estimate of the exact gradient G W^T (reported)
     exact = G.astype(np.float64) @ Wh.T
     print("bf16 sampled dX vs exact-product gradient:", rel(host64(Xd.grad), exact))
+
+
+@pytest.mark.parametrize("kw", [dict(prob="exact", dtype=torch.float32),
+                                dict(mode="stratified", alloc="opt", dtype=torch.float64),
+                                dict(mode="stratified", alloc="opt", dtype=torch.float32),
+                                dict(mode="stratified", alloc="two_step", c0=60, pilot="norm",
+                                     dtype=torch.float64)])
+def test_run_on_fresh_handle_sizes_its_workspace(kw):
+    # the whole-path call sizes its workspace before the rules' optional
+    # buffers (block norms, pilot estimates) exist; a fresh handle has no
+    # slack from earlier calls, so an undersized workspace would show here
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    kw = dict(kw)
+    dtype = kw.pop("dtype")
+    M, N, off = wl.random_problem(200, 3000, 170, 30, seed=12, skew=1.0)
+    c = 20 if kw.get("mode", "block") == "block" else 600
+    hd = pk.Handle(0)
+    try:
+        _check_run(hd, M, N, off, c, dtype, seed=4, **kw)
+    finally:
+        hd.close()
