@@ -222,6 +222,7 @@ __device__ void block_stats_body(const StatsArgs& s, int k) {
   const int64_t lo = off[k], hi = off[k + 1];
   double am = 0.0, an = 0.0, as = 0.0;
   bool bad = false;
+#pragma unroll 8
   for (int64_t j = lo + threadIdx.x; j < hi; j += kThreads) {
     double cs = 0.0;
     for (int r = 0; r < rsplit; ++r) cs += partial[(int64_t)r * n + j];

@@ -150,6 +150,7 @@ __device__ void design_body(const PlanLaunch& a, int64_t s) {
   const int64_t As = a1 - a0;
   double mx = 0.0;
   bool bad = false;
+  #pragma unroll 8
   for (int64_t i = a0 + threadIdx.x; i < a1; i += kThreads) {
     const double w = atom_weight(a, i);
     bad |= !isfinite(w) || w < 0.0;
@@ -163,6 +164,7 @@ __device__ void design_body(const PlanLaunch& a, int64_t s) {
   const int64_t b0 = a0 + (int64_t)threadIdx.x * per;
   const int64_t b1 = min(a1, b0 + per);
   uint64_t local = 0;
+  #pragma unroll 8
   for (int64_t i = b0; i < b1; ++i) {
     const uint64_t W = (mx > 0.0) ? quantize(atom_weight(a, i), shift) : 0;
     a.W[i] = W;
@@ -170,6 +172,7 @@ __device__ void design_body(const PlanLaunch& a, int64_t s) {
   }
   uint64_t total;
   uint64_t run = block_excl_scan(local, smu, &total);
+  #pragma unroll 8
   for (int64_t i = b0; i < b1; ++i) {
     run += a.W[i];
     a.cdf[i] = run;
@@ -177,6 +180,7 @@ __device__ void design_body(const PlanLaunch& a, int64_t s) {
   if (threadIdx.x == 0) a.T[s] = total;
   if (a.p_hat) {
     __syncthreads();
+    #pragma unroll 8
     for (int64_t i = a0 + threadIdx.x; i < a1; i += kThreads)
       a.p_hat[i] = total > 0 ? (double)a.W[i] / (double)total : 0.0;
   }
@@ -414,9 +418,11 @@ __device__ void offsets_body(const PlanLaunch& a) {
   const int64_t per = (c + kThreads - 1) / kThreads;
   const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min(c, b0 + per);
   uint64_t local = 0;
+  #pragma unroll 8
   for (int64_t t = b0; t < b1; ++t) local += (uint64_t)a.width[t];
   uint64_t tot;
   uint64_t run = block_excl_scan(local, smu, &tot);
+  #pragma unroll 8
   for (int64_t t = b0; t < b1; ++t) {
     a.col_off[t] = (int64_t)run;
     run += (uint64_t)a.width[t];

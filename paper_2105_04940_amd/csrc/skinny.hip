@@ -147,8 +147,10 @@ __global__ __launch_bounds__(kThreads) void skinny_reduce_kernel(SkinnyArgs<T> a
   for (int64_t k = 0; k < nb; ++k) {
     const int64_t s0 = a.seg_first[k], s1 = a.seg_first[k + 1];
     double z = 0.0;
-    if (valid)
+    if (valid) {
+#pragma unroll 8
       for (int64_t s = s0; s < s1; ++s) z += a.part[s * mp + e];
+    }
     total += z;
     if (a.nblk > 0) {
       const double sq = wg_sum(valid ? z * z : 0.0, sm);
