@@ -51,6 +51,8 @@ def parse():
                     help="skip the bf16 linear-layer forward/backward leg")
     ap.add_argument("--no-section4", action="store_true",
                     help="skip the paper's Section 4 stratified-sampling leg")
+    ap.add_argument("--section4-sweeps", action="store_true",
+                    help="run the paper's Table 1 experiments (Cases I/II, c, K and c0 sweeps) and print their JSON")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 512-problem batched leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -437,6 +439,100 @@ def section4_leg(h, pk, wl, torch, reps=100, warmup=3):
     return out
 
 
+def section4_sweeps(h, pk, wl, torch, reps=100):
+    """The paper's Table 1 experiments at its sizes (m = 26, p = 28,
+    n = 5e5, float64, Cases I and II, `reps` replications per point):
+    1/3 vary c at K = 10, c0 = 5000; 2/4 vary K at c = 5e4, c0 = 5000; 5
+    varies c0 at c = 5e4, K = 10. Methods: UU, ONC, OPL (Alg. 2), ONU,
+    ONMCNR (Alg. 3) and SSM (block sampling with (1.4); the paper gives no
+    budget for it, so it draws round(c / n_k) blocks: a sketch as wide as
+    Alg. 2's). Per point and method: mean / std of the relative error and
+    the median step time (as in the Section 4 leg). The paper's qualitative
+    findings are evaluated on the Case II means."""
+    dev = "cuda:0"
+    methods = {"UU": dict(mode="stratified", prob="uniform", alloc="uniform"),
+               "ONC": dict(mode="stratified", prob="norm", alloc="norm"),
+               "OPL": dict(mode="stratified", prob="norm", alloc="opt"),
+               "ONU": dict(mode="stratified", prob="norm", alloc="two_step", pilot="uniform"),
+               "ONMCNR": dict(mode="stratified", prob="norm", alloc="two_step", pilot="norm"),
+               "SSM": dict(mode="block", prob="norm")}
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def point(Md, Nd, MN, mn2, K, c, c0, names):
+        off = wl.equal_blocks(Md.shape[1], K)
+        out = {}
+        for name in names:
+            kw = methods[name]
+            cc = max(1, round(c / (Md.shape[1] / K))) if name == "SSM" else c
+            ms, errs = [], []
+            for t in range(2 + reps):
+                prob = pk.Problem(Md, Nd, off, cc, c0=c0, seed=0, trial=t, **kw)
+                a, b = ev(), ev()
+                a.record()
+                col, row, blk = h.norms(prob)
+                if kw.get("alloc") == "opt":
+                    _, prob.blkprod_sq, _ = h.exact(prob, store=False, blocknorm=True)
+                if kw.get("alloc") == "two_step":
+                    prob.pilot_sq = h.pilot(prob, col, row, blk)
+                pl = h.plan(prob, col, row, blk, sync=False)
+                C, D = h.sketch(prob, pl)
+                _, err = h.sketch_gemm(C, D, pl, MN=MN, store=False)
+                b.record()
+                if t >= 2:
+                    ms.append((a, b))
+                    errs.append(err)
+            torch.cuda.synchronize()
+            rel = np.sqrt(torch.cat(errs).cpu().numpy() / mn2)
+            out[name] = {"rel_mean": float(rel.mean()), "rel_std": float(rel.std()),
+                         "ms": float(np.median([x.elapsed_time(y) for x, y in ms]))}
+        return out
+
+    a2 = ["UU", "ONC", "OPL", "SSM"]
+    a23 = ["UU", "ONC", "OPL", "ONU", "ONMCNR"]
+    res = {"replications": reps, "ssm_budget": "round(c / n_k) block draws"}
+    for case in (1, 2):
+        M, N = wl.case_data(case)
+        Md = torch.from_numpy(M).to(dev)
+        Nd = torch.from_numpy(N).to(dev)
+        del M, N
+        MN, _, mn_sq = h.exact(pk.Problem(Md, Nd, [0, Md.shape[1]], 1), store=True)
+        mn2 = mn_sq.item()
+        cs = [50000, 100000, 200000, 350000, 500000]
+        Ks = [10, 50, 100, 250, 500]
+        c0s = [500, 1000, 5000, 20000, 50000]
+        r = {"vary_c": {str(c): point(Md, Nd, MN, mn2, 10, c, 5000, sorted(set(a2 + a23))) for c in cs},
+             "vary_K": {str(K): point(Md, Nd, MN, mn2, K, 50000, 5000, sorted(set(a2 + a23))) for K in Ks},
+             "vary_c0": {str(c0): point(Md, Nd, MN, mn2, 10, 50000, c0, ["ONC", "OPL", "ONU", "ONMCNR"])
+                         for c0 in c0s}}
+        res[f"case{'I' * case}"] = r
+        del Md, Nd, MN
+        torch.cuda.empty_cache()
+
+    # the paper's qualitative findings, on the Case II means
+    r2 = res["caseII"]
+    m = lambda grp, key, name: r2[grp][key][name]["rel_mean"]
+    claims = {
+        "OPL and ONC more accurate than SSM (every c, every K)":
+            all(m(g, k, x) < m(g, k, "SSM") for g in ("vary_c", "vary_K") for k in r2[g] for x in ("OPL", "ONC")),
+        "UU more accurate than SSM somewhere (the paper says it may be)":
+            any(m(g, k, "UU") < m(g, k, "SSM") for g in ("vary_c", "vary_K") for k in r2[g]),
+        "OPL the most accurate of Alg. 2 / Alg. 3 (within 2 %) at every c and K":
+            all(m(g, k, "OPL") <= 1.02 * min(m(g, k, x) for x in a23) for g in ("vary_c", "vary_K") for k in r2[g]),
+        "ONMCNR within 10 % of OPL at every c (K = 10)":
+            all(m("vary_c", k, "ONMCNR") <= 1.10 * m("vary_c", k, "OPL") for k in r2["vary_c"]),
+        "ONMCNR the least accurate of ONC, OPL, ONU, ONMCNR at the largest K (smallest c0 / K)":
+            m("vary_K", "500", "ONMCNR") >= max(m("vary_K", "500", x) for x in ("ONC", "OPL", "ONU")),
+        "ONMCNR within 2 % of OPL at the largest c0":
+            m("vary_c0", "50000", "ONMCNR") <= 1.02 * m("vary_c0", "50000", "OPL"),
+        "ONC within 10 % of OPL at every point":
+            all(m(g, k, "ONC") <= 1.10 * m(g, k, "OPL") for g in ("vary_c", "vary_K", "vary_c0") for k in r2[g]),
+    }
+    res["paper_findings_case_II"] = claims
+    return res
+
+
 def main():
     args = parse()
     if args.trace_summary:
@@ -457,6 +553,9 @@ def main():
     import paper_2105_04940_amd as pk
     import workloads as wl
 
+    if args.section4_sweeps:
+        print(json.dumps(section4_sweeps(pk.Handle(0), pk, wl, torch)))
+        return
     dev = "cuda:0"
     M, N, off = wl.paper_scale()
     m, n = M.shape
