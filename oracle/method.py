@@ -539,6 +539,74 @@ def optimal_value(stats, blkprod_sq, c):
 
 
 # ----------------------------------------------------------------------------
+# Probability error bounds (Thm 3.3 (3.11)-(3.12), Thm 4.2 (4.3)-(4.4),
+# Thm 4.4 (4.8)-(4.9))
+# ----------------------------------------------------------------------------
+
+def sampled_beta(design, col_sq, row_sq):
+    """The largest beta <= 1 with p_hat >= beta p for the probabilities (3.8)
+    p_{k_i} = a_i b_i / s_k, over the atoms with p > 0 (stratified design)."""
+    w = np.sqrt(np.asarray(col_sq, np.float64) * np.asarray(row_sq, np.float64))
+    ph = design.p_hat()
+    beta = 1.0
+    for s in range(len(design.T)):
+        a0, a1 = design.strat_off[s], design.strat_off[s + 1]
+        ws = w[a0:a1]
+        tot = math.fsum(ws)
+        if tot <= 0:
+            continue
+        p = ws / tot
+        nz = p > 0
+        if np.any(nz):
+            beta = min(beta, float(np.min(ph[a0:a1][nz] / p[nz])))
+    return beta
+
+
+def error_bound(rule, stats, c, beta, delta, blkprod_sq, pilot_sq=None):
+    """The bound B with ||MN - CD||_F^2 <= B with probability >= 1 - delta,
+    and the bound V on the sum of the asymptotic variances, for Alg. 2 with
+    probabilities >= beta (3.8) and
+      'opt'      block sizes (3.9): Thm 3.3, (3.11) and (3.12);
+      'norm'     block sizes (4.2): Thm 4.2, (4.3) and (4.4);
+      'two_step' block sizes (4.7): Thm 4.4, (4.8) and (4.9), with the
+                 pilot estimates pilot_sq.
+    v_k s_k = ||M^k N_k||_F gives theta_1 <= 1 - v_k^2 <= theta_2 (min and
+    max over the blocks with s_k > 0); the pilot's v^_k s_k =
+    ||C^{0k} D_{0k}||_F gives theta^_1 <= |1 - v^_k^2| <= theta^_2.
+    Returns dict(phi, eta, var_bound, bound, theta1, theta2[, theta1_hat,
+    theta2_hat]); phi is infinite when theta_1 = 0 for 'opt'. In (4.8) the
+    numerator of phi~ carries theta_2 of Thm 3.3 (the exact v_k) beside the
+    pilot's theta^, as printed; its exponent (theta^_2 theta^_1)^(1/4) is read
+    as in Thm 3.3."""
+    s = np.asarray(stats.s, np.float64)
+    live = s > 0
+    v2 = np.asarray(blkprod_sq, np.float64)[live] / (s[live] ** 2)
+    t1, t2 = float(np.min(1.0 - v2)), float(np.max(1.0 - v2))
+    mn = math.fsum(stats.m_sq) * math.fsum(stats.n_sq)
+    tail = math.sqrt((8.0 / beta) * math.log(1.0 / delta))
+    out = dict(theta1=t1, theta2=t2)
+    if rule == "opt":
+        phi = (math.sqrt(t2 - t1 * beta + t2 * t1 * beta) / (t2 * t1) ** 0.25
+               if t1 > 0 else math.inf)
+        eta = phi + (math.sqrt(t2 / t1) * tail if t1 > 0 else math.inf)
+    elif rule == "norm":
+        phi = math.sqrt(1.0 - beta * (1.0 - t2))
+        eta = phi + tail
+    elif rule == "two_step":
+        vh2 = np.asarray(pilot_sq, np.float64)[live] / (s[live] ** 2)
+        h1, h2 = float(np.min(np.abs(1.0 - vh2))), float(np.max(np.abs(1.0 - vh2)))
+        out.update(theta1_hat=h1, theta2_hat=h2)
+        phi = (math.sqrt(h2 - h1 * beta + t2 * h1 * beta) / (h2 * h1) ** 0.25
+               if h1 > 0 else math.inf)
+        eta = phi + (math.sqrt(h2 / h1) * tail if h1 > 0 else math.inf)
+    else:
+        raise ValueError(f"no bound for rule {rule!r}")
+    out.update(phi=phi, eta=eta, var_bound=phi * phi / (beta * c) * mn,
+               bound=eta * eta / (beta * c) * mn)
+    return out
+
+
+# ----------------------------------------------------------------------------
 # Whole pipeline
 # ----------------------------------------------------------------------------
 

@@ -149,3 +149,19 @@ def test_two_step_section4_shape(h, case, pilot):
     M, N = wl.case_data(case)
     off = wl.equal_blocks(M.shape[1], 10)
     check_run(h, M, N, off, 50000, 5000, pilot, torch.float64, seed=3, trial=case)
+
+
+@pytest.mark.parametrize("c", [1, 10])
+def test_ssm_section4_shape(h, c):
+    # block sampling with (1.4) at the paper's Section 4 sizes (the SSM
+    # comparison of Experiments 1-2): one or ten draws of 5e4-column blocks
+    M, N = wl.case_data(2)
+    off = wl.equal_blocks(M.shape[1], 10)
+    Md, Nd = to_dev(M, torch.float64), to_dev(N, torch.float64)
+    prob = pk.Problem(Md, Nd, off, c, mode="block", prob="norm", seed=1, trial=c)
+    r = h.run(prob)
+    o = om.run(host64(Md), host64(Nd), off, c, seed=1, trial=c, mode="block", prob="norm")
+    assert np.array_equal(r["plan"].idx.cpu().numpy(), o.draws.atom)
+    assert r["L"] == o.draws.L
+    assert rel(host64(r["CD"]), o.CD) < 1e-12
+    assert abs(r["rel"] - o.rel) <= 1e-12 * max(o.rel, 1.0)
