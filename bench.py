@@ -53,6 +53,8 @@ def parse():
                     help="skip the paper's Section 4 stratified-sampling leg")
     ap.add_argument("--section4-sweeps", action="store_true",
                     help="run the paper's Table 1 experiments (Cases I/II, c, K and c0 sweeps) and print their JSON")
+    ap.add_argument("--bound-checks", action="store_true",
+                    help="the probability error bounds of Thms 3.3, 4.2, 4.4 at the Section 4 sizes")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 512-problem batched leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -533,6 +535,82 @@ def section4_sweeps(h, pk, wl, torch, reps=100):
     return res
 
 
+def bound_checks(h, pk, wl, torch, reps=100, deltas=(0.5, 0.1, 0.01)):
+    """The probability error bounds at the paper's Section 4 sizes (m = 26,
+    p = 28, n = 5e5 float64 in K = 10 blocks of 5e4, c = 5e4, c0 = 5000,
+    Cases I and II), for the methods they cover: OPL (Thm 3.3, (3.12)), ONC
+    (Thm 4.2, (4.4)), ONU and ONMCNR (Thm 4.4, (4.9); the bound changes with
+    every pilot). Per method over `reps` trials: theta_1, theta_2 (and the
+    range of the pilot's theta^_1, theta^_2), the sampled beta, phi, the
+    variance bound against E ||MN - CD||_F^2 of the design and the mean
+    squared error; per delta the bound, the fraction of trials whose squared
+    error exceeds it (the theorems claim at most delta) and the empirical
+    (1 - delta) quantile of the squared error over the bound."""
+    dev = "cuda:0"
+    methods = {"OPL": dict(prob="norm", alloc="opt"),
+               "ONC": dict(prob="norm", alloc="norm"),
+               "ONU": dict(prob="norm", alloc="two_step", pilot="uniform"),
+               "ONMCNR": dict(prob="norm", alloc="two_step", pilot="norm")}
+    K, c, c0 = 10, 50000, 5000
+    out = {"workload": "paper Section 4 sizes, float64, K=10 blocks of 50000, c=50000, c0=5000",
+           "replications": reps, "deltas": list(deltas)}
+    checks = {}
+    for case in (1, 2):
+        M, N = wl.case_data(case)
+        off = wl.equal_blocks(M.shape[1], K)
+        Md = torch.from_numpy(M).to(dev)
+        Nd = torch.from_numpy(N).to(dev)
+        del M, N
+        base = pk.Problem(Md, Nd, off, c, mode="stratified")
+        MN, bp, _ = h.exact(base, store=True, blocknorm=True)
+        col, row, blk = h.norms(base)
+        res = {}
+        for name, kw in methods.items():
+            err2, g = [], []
+            for t in range(reps):
+                prob = pk.Problem(Md, Nd, off, c, mode="stratified", c0=c0, seed=0, trial=t, **kw)
+                if kw["alloc"] == "opt":
+                    prob.blkprod_sq = bp
+                if kw["alloc"] == "two_step":
+                    prob.pilot_sq = h.pilot(prob, col, row, blk)
+                pl = h.plan(prob, col, row, blk, sync=False)
+                C, D = h.sketch(prob, pl)
+                _, e = h.sketch_gemm(C, D, pl, MN=MN, store=False)
+                err2.append(e)
+                g.append(h.bound(prob, col, row, blk, bp, pl, deltas=deltas))
+            e2 = torch.cat(err2).cpu().numpy()
+            exp = np.array([x["expected"] for x in g])
+            r = {"beta": min(x["beta"] for x in g), "theta1": g[0]["theta1"], "theta2": g[0]["theta2"],
+                 "phi_range": [min(x["phi"] for x in g), max(x["phi"] for x in g)],
+                 "var_bound_median": float(np.median([x["var_bound"] for x in g])),
+                 "expected_sq_err_mean": float(exp.mean()),
+                 "sq_err_mean": float(e2.mean()),
+                 "sq_err_mean_over_expected": float(e2.mean() / exp.mean()),
+                 "std_errors_from_expected": float((e2.mean() - exp.mean()) / (e2.std(ddof=1) / np.sqrt(reps))),
+                 "expected_over_var_bound": float(np.max(exp / np.array([x["var_bound"] for x in g])))}
+            if kw["alloc"] == "two_step":
+                r["theta1_hat_range"] = [min(x["theta1_hat"] for x in g), max(x["theta1_hat"] for x in g)]
+                r["theta2_hat_range"] = [min(x["theta2_hat"] for x in g), max(x["theta2_hat"] for x in g)]
+            per = {}
+            for j, d in enumerate(deltas):
+                b = np.array([x["bound"][j] for x in g])
+                per[str(d)] = {"bound_median": float(np.median(b)),
+                               "exceed_frac": float(np.mean(e2 > b)),
+                               "quantile_over_bound": float(np.quantile(e2, 1 - d) / np.median(b))}
+                checks[f"case{'I' * case} {name} delta={d}: exceedance <= delta"] = bool(np.mean(e2 > b) <= d)
+            r["per_delta"] = per
+            checks[f"case{'I' * case} {name}: E||MN-CD||^2 <= variance bound"] = bool(r["expected_over_var_bound"] <= 1)
+            checks[f"case{'I' * case} {name}: mean squared error within 5 s.e. of its expectation"] = \
+                bool(abs(r["std_errors_from_expected"]) <= 5)
+            res[name] = r
+        out[f"case{'I' * case}"] = res
+        del Md, Nd, MN
+        torch.cuda.empty_cache()
+    out["checks"] = checks
+    out["all_hold"] = all(checks.values())
+    return out
+
+
 def main():
     args = parse()
     if args.trace_summary:
@@ -555,6 +633,9 @@ def main():
 
     if args.section4_sweeps:
         print(json.dumps(section4_sweeps(pk.Handle(0), pk, wl, torch)))
+        return
+    if args.bound_checks:
+        print(json.dumps(bound_checks(pk.Handle(0), pk, wl, torch)))
         return
     dev = "cuda:0"
     M, N, off = wl.paper_scale()

@@ -291,6 +291,48 @@ sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* prob, const sbmm_pl
                           sbmm_stream stream);
 
 
+/* Probability error bounds of the stratified sampler (Alg. 2 and Alg. 3),
+ * evaluated from the data and the design that was sampled, by the problem's
+ * block-size rule:
+ *   alloc OPT      (3.9): Thm 3.3, the variance bound (3.11) and the
+ *                  probability bound (3.12);
+ *   alloc NORM     (4.2): Thm 4.2, (4.3) and (4.4);
+ *   alloc TWO_STEP (4.7): Thm 4.4, (4.8) and (4.9), with the pilot
+ *                  estimates prob->pilot_sq (required) that built the plan.
+ * With v_k s_k = ||M^k N_k||_F and s_k = sum_{i in k} ||M^(i)||_2 ||N_(i)||_2,
+ * theta_1 / theta_2 are the min / max of 1 - v_k^2 over the blocks with
+ * s_k > 0 (Thm 3.3), theta^_1 / theta^_2 those of |1 - v^_k^2| with
+ * v^_k s_k = ||C^{0k} D_{0k}||_F (Thm 4.3). beta > 0 is used as given (the
+ * caller asserts p_hat >= beta (3.8)); beta = 0 takes the largest value the
+ * sampled probabilities satisfy, min over atoms with a_i b_i > 0 of
+ * p_hat_i / (a_i b_i / s_k) (at most 1). The exponent of Thm 4.4's
+ * denominator is read as 1/4, as in Thm 3.3; its numerator carries theta_2
+ * of the exact v_k, as printed.
+ * Also returned: E ||MN - CD||_F^2 of the design actually sampled, the sum
+ * over the blocks with c_k > 0 of (sum_i a_i^2 b_i^2 / p_hat_i -
+ * ||M^k N_k||_F^2) / c_k (the per-entry variances of Thm 3.1 summed).
+ * Inputs (device): col_sq, row_sq, blk from sbmm_norms; blkprod_sq [K] from
+ * sbmm_exact (required for every rule: theta_1, theta_2 and the expected
+ * error need it); plan->p_hat and plan->ck of the plan built for this
+ * problem (other plan fields are not read). delta: host, n_delta (0..8)
+ * values in (0, 1). out: HOST, SBMM_BOUND_FIXED + 2 n_delta doubles laid out
+ * as the SBMM_BOUND_* indices, then eta_j and the bound eta_j^2 / (beta c)
+ * ||M||_F^2 ||N||_F^2 for every delta_j; phi and the bounds are +inf when
+ * the rule divides by theta_1 = 0 (or theta^_1 = 0), and every field but beta
+ * and ||M||^2 ||N||^2 is 0 when no block has s_k > 0. The call
+ * synchronizes `stream`. Errors: SBMM_E_ARG for block mode, another
+ * block-size rule, a missing input, n_delta outside 0..8, delta outside
+ * (0, 1) or beta outside [0, 1]. */
+enum {
+  SBMM_BOUND_THETA1 = 0, SBMM_BOUND_THETA2 = 1, SBMM_BOUND_THETA1_HAT = 2, SBMM_BOUND_THETA2_HAT = 3,
+  SBMM_BOUND_BETA = 4, SBMM_BOUND_MN = 5, SBMM_BOUND_PHI = 6, SBMM_BOUND_VAR = 7,
+  SBMM_BOUND_EXPECTED = 8, SBMM_BOUND_FIXED = 9, SBMM_BOUND_MAX_DELTA = 8
+};
+sbmm_status sbmm_bound(sbmm_handle h, const sbmm_problem* prob, const double* col_sq, const double* row_sq,
+                       const double* blk, const double* blkprod_sq, const sbmm_plan_out* plan, double beta,
+                       int32_t n_delta, const double* delta, double* out, sbmm_stream stream);
+
+
 /* ------------------------------------------------------------------------ */
 /* Many independent problems in one pass                                     */
 /* ------------------------------------------------------------------------ */

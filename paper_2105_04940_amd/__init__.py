@@ -33,8 +33,13 @@ EXPORTS = (
     "sbmm_error", "sbmm_run", "sbmm_backward",
     "sbmm_batch_create", "sbmm_batch_destroy", "sbmm_batch_run", "sbmm_batch_capture",
     "sbmm_batch_replay", "sbmm_batch_tune", "sbmm_batch_set_tuning",
-    "sbmm_sketch_mx", "sbmm_sketch_gemm_mx", "sbmm_pilot",
+    "sbmm_sketch_mx", "sbmm_sketch_gemm_mx", "sbmm_pilot", "sbmm_bound",
 )
+# Layout of sbmm_bound's output (SBMM_BOUND_* in the header), then eta_j and
+# the bound of every delta_j.
+BOUND_FIELDS = ("theta1", "theta2", "theta1_hat", "theta2_hat", "beta", "mn", "phi",
+                "var_bound", "expected")
+BOUND_MAX_DELTA = 8
 BATCH_TILES = ((128, 128), (64, 128), (128, 64), (64, 64))
 
 
@@ -114,6 +119,8 @@ def load_library(path=LIB_PATH):
         "sbmm_exact": (st, [vp, P(Problem_t), vp, i64, vp, vp, vp]),
         "sbmm_plan": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), P(i64), vp]),
         "sbmm_pilot": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), vp, vp]),
+        "sbmm_bound": (st, [vp, P(Problem_t), vp, vp, vp, vp, P(PlanOut_t), ctypes.c_double, i32,
+                            P(ctypes.c_double), P(ctypes.c_double), vp]),
         "sbmm_sketch": (st, [vp, P(Problem_t), P(PlanOut_t), st, vp, i64, vp, i64, vp]),
         "sbmm_sketch_gemm": (st, [vp, i64, i64, i64, vp, st, vp, i64, vp, i64, vp, i64,
                                   vp, i64, vp, vp]),
@@ -356,6 +363,27 @@ class Handle:
         self._check(self._lib.sbmm_pilot(self.h, ctypes.byref(s), _ptr(col_sq), _ptr(row_sq), _ptr(blk),
                                          ctypes.byref(ps) if ps is not None else None, _ptr(out), _stream()))
         return (out, pl) if keep_plan else out
+
+    def bound(self, problem, col_sq, row_sq, blk, blkprod_sq, plan, beta=0.0, deltas=()):
+        """Probability error bounds of the problem's block-size rule (OPT:
+        Thm 3.3, NORM: Thm 4.2, TWO_STEP: Thm 4.4 with problem.pilot_sq) and
+        the expected squared error of the sampled design (synchronizing).
+        Returns a dict with the BOUND_FIELDS and lists ``eta`` and ``bound``,
+        one entry per delta."""
+        s = problem.struct()
+        deltas = [float(d) for d in deltas]
+        nd = len(deltas)
+        out = (ctypes.c_double * (len(BOUND_FIELDS) + 2 * nd))()
+        dl = (ctypes.c_double * max(nd, 1))(*deltas)
+        ps = plan.struct()
+        self._check(self._lib.sbmm_bound(self.h, ctypes.byref(s), _ptr(col_sq), _ptr(row_sq), _ptr(blk),
+                                         _ptr(blkprod_sq), ctypes.byref(ps), float(beta), nd, dl, out,
+                                         _stream()))
+        r = {f: out[i] for i, f in enumerate(BOUND_FIELDS)}
+        base = len(BOUND_FIELDS)
+        r["eta"] = [out[base + 2 * j] for j in range(nd)]
+        r["bound"] = [out[base + 2 * j + 1] for j in range(nd)]
+        return r
 
     def sketch(self, problem, plan, out_dtype=None, want_C=True, want_D=True):
         torch = _torch()

@@ -792,6 +792,55 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
   return SBMM_OK;
 }
 
+sbmm_status sbmm_bound(sbmm_handle h, const sbmm_problem* P, const double* col_sq, const double* row_sq,
+                       const double* blk, const double* blkprod_sq, const sbmm_plan_out* plan, double beta,
+                       int32_t n_delta, const double* delta, double* out, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  if ((st = validate(h, P, nullptr, true))) return st;
+  if (P->mode != SBMM_MODE_STRATIFIED) return fail(h, SBMM_E_ARG, "the bounds are those of the stratified sampler");
+  if (P->alloc != SBMM_ALLOC_OPT && P->alloc != SBMM_ALLOC_NORM && P->alloc != SBMM_ALLOC_TWO_STEP)
+    return fail(h, SBMM_E_ARG, "no bound for block-size rule %d (OPT, NORM or TWO_STEP)", (int)P->alloc);
+  if (P->alloc == SBMM_ALLOC_TWO_STEP && !P->pilot_sq) return fail(h, SBMM_E_ARG, "TWO_STEP needs prob->pilot_sq");
+  if (!col_sq || !row_sq || !blk || !blkprod_sq || !plan || !plan->p_hat || !plan->ck || !out)
+    return fail(h, SBMM_E_ARG, "the bounds need col_sq, row_sq, blk, blkprod_sq, plan p_hat and ck, and out");
+  if (n_delta < 0 || n_delta > SBMM_BOUND_MAX_DELTA || (n_delta > 0 && !delta))
+    return fail(h, SBMM_E_ARG, "n_delta = %d (0..%d)", n_delta, (int)SBMM_BOUND_MAX_DELTA);
+  if (!(beta >= 0.0 && beta <= 1.0)) return fail(h, SBMM_E_ARG, "beta must be in [0, 1]");
+  BoundLaunch a{};
+  for (int32_t j = 0; j < n_delta; ++j) {
+    if (!(delta[j] > 0.0 && delta[j] < 1.0)) return fail(h, SBMM_E_ARG, "delta[%d] must be in (0, 1)", j);
+    a.delta[j] = delta[j];
+  }
+  std::vector<int64_t> chunk_off(P->K + 1, 0);
+  for (int32_t k = 0; k < P->K; ++k)
+    chunk_off[k + 1] = chunk_off[k] + bound_chunks(P->block_off[k + 1] - P->block_off[k]);
+  const int64_t nout = SBMM_BOUND_FIXED + 2 * (int64_t)n_delta;
+  hipStream_t s = (hipStream_t)stream;
+  for (int pass = 0; pass < 2; ++pass) {
+    Arena ar(pass ? h->ws : nullptr);
+    int64_t* off = nullptr;
+    if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+    int64_t* coff = ar.take<int64_t>(P->K + 1);
+    double* part = ar.take<double>(2 * (size_t)chunk_off[P->K]);
+    double* dout = ar.take<double>(nout);
+    if (!pass) {
+      if ((st = ensure_ws(h, ar.off))) return st;
+      continue;
+    }
+    HIP_TRY(h, hipMemcpyAsync(coff, chunk_off.data(), sizeof(int64_t) * (P->K + 1), hipMemcpyHostToDevice, s));
+    a.K = P->K; a.off = off; a.chunk_off = coff; a.chunks = chunk_off[P->K];
+    a.col_sq = col_sq; a.row_sq = row_sq; a.blk = blk; a.blkprod_sq = blkprod_sq;
+    a.pilot_sq = P->alloc == SBMM_ALLOC_TWO_STEP ? P->pilot_sq : nullptr;
+    a.p_hat = plan->p_hat; a.ck = plan->ck; a.part = part;
+    a.rule = P->alloc; a.c = P->c; a.beta = beta; a.n_delta = n_delta; a.out = dout;
+    HIP_TRY(h, launch_bound(a, s));
+    HIP_TRY(h, hipMemcpyAsync(out, dout, sizeof(double) * nout, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+  }
+  return SBMM_OK;
+}
+
 sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_out* plan, int64_t L,
                           sbmm_dtype compute, const void* C, int64_t ldc, const void* D, int64_t ldd,
                           const void* G, int64_t ldg, void* dM, int64_t lddm, void* dN, int64_t lddn,

@@ -261,6 +261,28 @@ struct MxGemmLaunch {
 int64_t mx_gemm_tiles(int64_t m, int64_t p);
 hipError_t launch_mx_gemm(const MxGemmLaunch& a, hipStream_t s);
 
+// Probability error bounds (Thm 3.3, 4.2, 4.4) and the expected squared
+// error of a stratified design; every block is split into chunks of
+// bound_chunks(n_k) workgroups.
+struct BoundLaunch {
+  int32_t K;
+  const int64_t* off;         // [K+1] block offsets
+  const int64_t* chunk_off;   // [K+1] first chunk of every block
+  int64_t chunks;             // chunk_off[K]
+  const double* col_sq; const double* row_sq; const double* blk;
+  const double* blkprod_sq; const double* pilot_sq;   // pilot_sq: TWO_STEP only, else null
+  const double* p_hat; const int64_t* ck;
+  double* part;               // [2 * chunks]
+  int32_t rule;               // SBMM_ALLOC_OPT / NORM / TWO_STEP
+  int64_t c;
+  double beta;                // > 0: given; 0: the sampled one
+  int32_t n_delta;
+  double delta[SBMM_BOUND_MAX_DELTA];
+  double* out;                // device [SBMM_BOUND_FIXED + 2 n_delta]
+};
+int64_t bound_chunks(int64_t width);
+hipError_t launch_bound(const BoundLaunch& a, hipStream_t s);
+
 // Fill kernels (used instead of memset so that captured graphs hold only
 // kernel nodes).
 hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t s);
