@@ -374,13 +374,19 @@ typedef struct sbmm_batch_s* sbmm_batch;
 
 /* Tile configuration of the two grouped products (exact MN, sketched CD)
  * and whether their work lists start with the longest inner extents. cfg
- * indexes the tile shapes 128x128, 64x128, 128x64, 64x64. The timings are
- * filled by sbmm_batch_tune: ms[g][2 cfg + lpt] for product g (0 exact, 1
- * sketch), -1 where not measured. */
+ * indexes the tile shapes 128x128, 64x128, 128x64, 64x64 (0..3). For the
+ * sketched product, 0..3 read the drawn columns of M and rows of N in place
+ * (the gather fused into the product's loads) and 4..7 are the same tile
+ * shapes over sketches C, D first gathered into a workspace the batch owns
+ * (at most 8 GiB, or one problem's sketches if larger, filled by groups of
+ * problems, one gather and one product launch per group); 4..7 exist when
+ * that workspace could be allocated at sbmm_batch_create. Both forms give the
+ * same bits. The timings are filled by sbmm_batch_tune: ms[g][2 cfg + lpt]
+ * for product g (0 exact, 1 sketch), -1 where not measured. */
 typedef struct {
   int32_t cfg[2];
   int32_t lpt[2];
-  float ms[2][8];
+  float ms[2][16];
 } sbmm_batch_tuning;
 
 /* Validate T problems, allocate the batch's device memory (owned by the

@@ -97,7 +97,7 @@ class BatchOutputs_t(ctypes.Structure):
 
 class BatchTuning_t(ctypes.Structure):
     _fields_ = [("cfg", ctypes.c_int32 * 2), ("lpt", ctypes.c_int32 * 2),
-                ("ms", (ctypes.c_float * 8) * 2)]
+                ("ms", (ctypes.c_float * 16) * 2)]
 
 
 def load_library(path=LIB_PATH):
@@ -577,15 +577,17 @@ class Batch:
         for g in range(2):
             t.cfg[g] = d["cfg"][g]
             t.lpt[g] = d["lpt"][g]
-            for i in range(8):
-                t.ms[g][i] = d.get("ms", [[-1.0] * 8] * 2)[g][i]
+            for i in range(16):
+                t.ms[g][i] = d.get("ms", [[-1.0] * 16] * 2)[g][i]
         self.handle._check(self._lib.sbmm_batch_set_tuning(self.handle.h, self.b, ctypes.byref(t)))
 
     @staticmethod
     def _tuning_dict(t):
+        n = len(BATCH_TILES)
         return {"cfg": [t.cfg[0], t.cfg[1]], "lpt": [t.lpt[0], t.lpt[1]],
-                "tiles": [list(BATCH_TILES[t.cfg[0]]), list(BATCH_TILES[t.cfg[1]])],
-                "ms": [[t.ms[g][i] for i in range(8)] for g in range(2)]}
+                "tiles": [list(BATCH_TILES[t.cfg[0] % n]), list(BATCH_TILES[t.cfg[1] % n])],
+                "sketch_materialized": t.cfg[1] >= n,
+                "ms": [[t.ms[g][i] for i in range(16)] for g in range(2)]}
 
     def draws(self, t):
         """The drawn blocks of problem t (device tensor view)."""

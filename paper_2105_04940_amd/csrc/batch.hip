@@ -7,6 +7,16 @@
 // work lists of the grouped products) are built on the host when the
 // batch is created or retuned and live in one device allocation owned by the
 // batch; a run only launches kernels.
+//
+// The sketched product has two forms, both chosen among by the tuner: the
+// drawn columns of M and rows of N read in place by the product (the gather
+// fused into its loads), or the sketches C, D materialized first by a grouped
+// gather into a workspace of the batch and then multiplied by the plain
+// grouped product. The workspace holds the sketches of a group of problems
+// at a time (problems taken longest first until kSketchCap bytes are used),
+// so the materialized form runs one gather and one product launch per group.
+// Both forms feed the matrix cores the same float32 values in the same
+// order, so they give the same bits.
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -18,6 +28,7 @@
 namespace {
 
 constexpr int kProducts = 2;   // 0: exact MN, 1: sketched CD
+constexpr size_t kSketchCap = size_t(8) << 30;   // bytes of materialized sketches at a time
 
 // Bump layout over one allocation; a pass with base == nullptr measures.
 struct Layout {
@@ -63,6 +74,15 @@ struct sbmm_batch_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // materialized sketches (sketch configurations grouped_cfg_count() and up)
+  char* sk_mem = nullptr;                 // null: only the fused form is available
+  std::vector<int32_t> gm_prob;           // problems in group-major order
+  std::vector<int32_t> grp_begin;         // G + 1 offsets into gm_prob
+  std::vector<int64_t> grp_wg;            // gather workgroups of each group
+  std::vector<int64_t> grp_items;         // G + 1 offsets into the current work list
+  std::vector<GemmLaunch> mat_launch;     // per problem: the product over its materialized sketch
+  void* gather_args = nullptr;            // T gather records, group-major
+  int64_t* gather_wg = nullptr;           // per group its count + 1 workgroup offsets (T + G entries)
 };
 
 namespace {
@@ -120,22 +140,48 @@ size_t max_stage_floats(const std::vector<sbmm_batch_item>& items) {
   return best;
 }
 
+// Configurations of product g: the tile shapes, and for the sketched
+// product the same shapes again over materialized sketches.
+int product_cfgs(const sbmm_batch b, int g) {
+  return grouped_cfg_count() * ((g == 1 && b->sk_mem) ? 2 : 1);
+}
+
+bool materialized(const sbmm_batch b, int g, int cfg) { return g == 1 && cfg >= grouped_cfg_count(); }
+
 // Rebuild and upload the tables of product g for configuration (cfg, lpt).
+// Materialized sketches: the work list runs group by group (each group's
+// problems in their own order), with the group boundaries kept in grp_items.
 sbmm_status apply_product(sbmm_batch b, int g, int cfg, int lpt) {
   sbmm_handle h = b->h;
   const int32_t T = b->T;
+  const bool mat = materialized(b, g, cfg);
+  const int tcfg = mat ? cfg - grouped_cfg_count() : cfg;
+  const std::vector<GemmLaunch>& src = mat ? b->mat_launch : b->launches[g];
   const size_t ab = grouped_gemm_args_bytes();
   std::vector<char> args((size_t)T * ab);
   std::vector<int64_t> base(T + 1, 0);
   for (int32_t t = 0; t < T; ++t) {
-    build_grouped_gemm_args(b->launches[g][t], cfg, args.data() + (size_t)t * ab);
-    base[t + 1] = base[t] + tiles_for(b->items[t], cfg);
+    build_grouped_gemm_args(src[t], tcfg, args.data() + (size_t)t * ab);
+    base[t + 1] = base[t] + tiles_for(b->items[t], tcfg);
   }
-  std::vector<int32_t> order(T);
-  std::iota(order.begin(), order.end(), 0);
-  if (lpt)
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t x, int32_t y) { return b->work_key[g][x] > b->work_key[g][y]; });
+  auto longer = [&](int32_t x, int32_t y) { return b->work_key[g][x] > b->work_key[g][y]; };
+  std::vector<int32_t> order;
+  if (mat) {
+    b->grp_items.assign(1, 0);
+    for (size_t gi = 0; gi + 1 < b->grp_begin.size(); ++gi) {
+      std::vector<int32_t> part(b->gm_prob.begin() + b->grp_begin[gi], b->gm_prob.begin() + b->grp_begin[gi + 1]);
+      if (lpt) std::stable_sort(part.begin(), part.end(), longer);
+      else std::sort(part.begin(), part.end());
+      int64_t n = 0;
+      for (int32_t t : part) n += base[t + 1] - base[t];
+      b->grp_items.push_back(b->grp_items.back() + n);
+      order.insert(order.end(), part.begin(), part.end());
+    }
+  } else {
+    order.resize(T);
+    std::iota(order.begin(), order.end(), 0);
+    if (lpt) std::stable_sort(order.begin(), order.end(), longer);
+  }
   const int64_t n_items = base[T];
   std::vector<int32_t> iprob((size_t)n_items), itile((size_t)n_items);
   int64_t k = 0;
@@ -173,7 +219,101 @@ hipError_t enqueue_product(sbmm_batch b, int g, hipStream_t s) {
   L.stage = b->stage;
   L.cfg = b->tuning.cfg[g];
   L.gather = g == 1;
-  return launch_grouped_gemm(L, s);
+  if (!materialized(b, g, L.cfg)) return launch_grouped_gemm(L, s);
+  // group by group: gather the sketches, then multiply them
+  L.cfg -= grouped_cfg_count();
+  L.gather = false;
+  const size_t ab = batch_gather_args_bytes();
+  for (size_t gi = 0; gi + 1 < b->grp_begin.size(); ++gi) {
+    const int32_t first = b->grp_begin[gi], count = b->grp_begin[gi + 1] - first;
+    hipError_t e = launch_batch_gather(static_cast<const char*>(b->gather_args) + (size_t)first * ab,
+                                       b->gather_wg + first + gi, count, b->grp_wg[gi], s);
+    if (e != hipSuccess) return e;
+    GroupedLaunch G = L;
+    G.item_prob = b->item_prob[g] + b->grp_items[gi];
+    G.item_tile = b->item_tile[g] + b->grp_items[gi];
+    G.items = b->grp_items[gi + 1] - b->grp_items[gi];
+    if ((e = launch_grouped_gemm(G, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Place the sketches of every problem (longest expected width first) into
+// groups that fit the sketch workspace, allocate it, and build the gather
+// records and the products over the materialized sketches. Leaves sk_mem
+// null (only the fused form) when the workspace cannot be allocated.
+void setup_materialized(sbmm_batch b, const std::vector<int64_t>& lpm,
+                        const std::vector<const int64_t*>& col_end, const std::vector<const int32_t*>& colmap,
+                        const std::vector<const double*>& colscale) {
+  const int32_t T = b->T;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  std::vector<size_t> cb(T), db(T);
+  size_t total = 0, most = 0;
+  for (int32_t t = 0; t < T; ++t) {
+    const sbmm_batch_item& it = b->items[t];
+    cb[t] = al(sizeof(float) * (size_t)it.m * lpm[t]);
+    db[t] = al(sizeof(float) * (size_t)lpm[t] * round_up(it.p, 4));
+    total += cb[t] + db[t];
+    most = std::max(most, cb[t] + db[t]);
+  }
+  const size_t cap = std::min(total, std::max(kSketchCap, most));
+  std::vector<int32_t> order(T);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return b->work_key[1][x] > b->work_key[1][y]; });
+  std::vector<size_t> at(T);
+  b->grp_begin.assign(1, 0);
+  size_t cur = 0;
+  for (int32_t i = 0; i < T; ++i) {
+    const int32_t t = order[i];
+    if (cur > 0 && cur + cb[t] + db[t] > cap) {
+      b->grp_begin.push_back(i);
+      cur = 0;
+    }
+    at[t] = cur;
+    cur += cb[t] + db[t];
+  }
+  b->grp_begin.push_back(T);
+  if (hipMalloc(&b->sk_mem, cap) != hipSuccess) {
+    b->sk_mem = nullptr;
+    (void)hipGetLastError();   // the fused form needs no workspace
+    return;
+  }
+  b->gm_prob = order;
+  const size_t G = b->grp_begin.size() - 1;
+  const size_t ab = batch_gather_args_bytes();
+  std::vector<char> gargs((size_t)T * ab);
+  std::vector<int64_t> wg;
+  b->grp_wg.assign(G, 0);
+  b->mat_launch.resize(T);
+  for (size_t gi = 0; gi < G; ++gi) {
+    wg.push_back(0);
+    for (int32_t i = b->grp_begin[gi]; i < b->grp_begin[gi + 1]; ++i) {
+      const int32_t t = order[i];
+      const sbmm_batch_item& it = b->items[t];
+      float* C = reinterpret_cast<float*>(b->sk_mem + at[t]);
+      float* D = reinterpret_cast<float*>(b->sk_mem + at[t] + cb[t]);
+      const int64_t ldd = round_up(it.p, 4);
+      GatherLaunch gl{};
+      gl.in_dt = SBMM_F32; gl.out_dt = SBMM_F32;
+      gl.M = it.M; gl.ldm = it.ldm; gl.N = it.N; gl.ldn = it.ldn; gl.m = it.m; gl.p = it.p;
+      gl.L_dev = col_end[t]; gl.L_pad_max = lpm[t]; gl.colmap = colmap[t]; gl.colscale = colscale[t];
+      gl.C = C; gl.ldc = lpm[t]; gl.D = D; gl.ldd = ldd;
+      wg.push_back(wg.back() + build_batch_gather_args(gl, gargs.data() + (size_t)i * ab));
+      GemmLaunch mk = b->launches[1][t];
+      mk.A = C; mk.lda = lpm[t]; mk.B = D; mk.ldb = ldd;
+      mk.colmap = nullptr; mk.colscale = nullptr;
+      b->mat_launch[t] = mk;
+    }
+    b->grp_wg[gi] = wg.back();
+  }
+  hipError_t e = hipMemcpy(b->gather_args, gargs.data(), gargs.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->gather_wg, wg.data(), sizeof(int64_t) * wg.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(b->sk_mem);
+    b->sk_mem = nullptr;
+    (void)hipGetLastError();
+  }
 }
 
 sbmm_status enqueue_pass(sbmm_batch b, hipStream_t s) {
@@ -262,6 +402,8 @@ sbmm_status sbmm_batch_create(sbmm_handle h, int32_t T, const sbmm_batch_item* i
     }
     b->stage = lay.take<float>(max_stage_floats(b->items));
     b->col_end = lay.take<const int64_t*>(T);
+    b->gather_args = lay.take<char>((size_t)T * batch_gather_args_bytes());
+    b->gather_wg = lay.take<int64_t>(2 * (size_t)T);
     for (int32_t t = 0; t < T; ++t) {
       const sbmm_batch_item& it = items[t];
       PerProblem& q = pp[t];
@@ -290,6 +432,8 @@ sbmm_status sbmm_batch_create(sbmm_handle h, int32_t T, const sbmm_batch_item* i
   std::vector<int64_t> wg(T + 1, 0), bo(T + 1, 0);
   std::vector<PlanLaunch> plans(T);
   std::vector<const int64_t*> col_end(T);
+  std::vector<const int32_t*> colmaps(T);
+  std::vector<const double*> colscales(T);
   int64_t idx_at = 0;
   for (int g = 0; g < kProducts; ++g) {
     b->launches[g].resize(T);
@@ -331,6 +475,8 @@ sbmm_status sbmm_batch_create(sbmm_handle h, int32_t T, const sbmm_batch_item* i
     sk.colmap = q.colmap; sk.colscale = q.colscale;
     b->launches[1][t] = sk;
     b->work_key[1][t] = (double)it.c * (double)it.n / (double)it.K;   // expected sketch width
+    colmaps[t] = q.colmap;
+    colscales[t] = q.colscale;
   }
   b->total_wg = wg[T];
   b->total_blk = bo[T];
@@ -348,8 +494,9 @@ sbmm_status sbmm_batch_create(sbmm_handle h, int32_t T, const sbmm_batch_item* i
     sbmm_batch_destroy(b);
     return fail(h, SBMM_E_HIP, "uploading batch tables: %s", hipGetErrorString(e));
   }
+  setup_materialized(b, lpm, col_end, colmaps, colscales);
   for (int g = 0; g < kProducts; ++g) {
-    for (int i = 0; i < 8; ++i) b->tuning.ms[g][i] = -1.0f;
+    for (int i = 0; i < 16; ++i) b->tuning.ms[g][i] = -1.0f;
     if ((st = apply_product(b, g, 0, 1)) != SBMM_OK) {
       sbmm_batch_destroy(b);
       return st;
@@ -366,6 +513,7 @@ sbmm_status sbmm_batch_destroy(sbmm_batch b) {
   drop_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->mem) (void)hipFree(b->mem);
+  if (b->sk_mem) (void)hipFree(b->sk_mem);
   delete b;
   return SBMM_OK;
 }
@@ -427,7 +575,7 @@ sbmm_status sbmm_batch_tune(sbmm_handle h, sbmm_batch b, int32_t reps, sbmm_batc
   for (int g = 0; g < kProducts && st == SBMM_OK; ++g) {
     float best = -1.0f;
     int best_cfg = 0, best_lpt = 1;
-    for (int cfg = 0; cfg < grouped_cfg_count() && st == SBMM_OK; ++cfg)
+    for (int cfg = 0; cfg < product_cfgs(b, g) && st == SBMM_OK; ++cfg)
       for (int lpt = 0; lpt < 2 && st == SBMM_OK; ++lpt) {
         if (hipStreamSynchronize(s) != hipSuccess) { st = fail(h, SBMM_E_HIP, "sync"); break; }
         if ((st = apply_product(b, g, cfg, lpt)) != SBMM_OK) break;
@@ -457,14 +605,14 @@ sbmm_status sbmm_batch_set_tuning(sbmm_handle h, sbmm_batch b, const sbmm_batch_
   if (st != SBMM_OK) return st;
   if (!t) return fail(h, SBMM_E_ARG, "tuning is NULL");
   for (int g = 0; g < kProducts; ++g)
-    if (t->cfg[g] < 0 || t->cfg[g] >= grouped_cfg_count() || (t->lpt[g] != 0 && t->lpt[g] != 1))
+    if (t->cfg[g] < 0 || t->cfg[g] >= product_cfgs(b, g) || (t->lpt[g] != 0 && t->lpt[g] != 1))
       return fail(h, SBMM_E_ARG, "tuning: configuration out of range");
   HIP_TRY(h, hipDeviceSynchronize());
   drop_graph(b);
   for (int g = 0; g < kProducts; ++g)
     if ((st = apply_product(b, g, t->cfg[g], t->lpt[g])) != SBMM_OK) return st;
   for (int g = 0; g < kProducts; ++g)
-    for (int i = 0; i < 8; ++i) b->tuning.ms[g][i] = t->ms[g][i];
+    for (int i = 0; i < 16; ++i) b->tuning.ms[g][i] = t->ms[g][i];
   return SBMM_OK;
 }
 

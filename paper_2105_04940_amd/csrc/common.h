@@ -134,6 +134,13 @@ struct GatherLaunch {
   void* D; int64_t ldd;
 };
 hipError_t launch_gather(const GatherLaunch& a, hipStream_t s);
+// float32 gathers of many problems in one launch: args holds one
+// build_batch_gather_args record per problem (which returns that problem's
+// workgroup count), wg_off the count + 1 running workgroup offsets.
+size_t batch_gather_args_bytes();
+int64_t build_batch_gather_args(const GatherLaunch& g, void* out);
+hipError_t launch_batch_gather(const void* args, const int64_t* wg_off, int32_t count, int64_t total_wg,
+                               hipStream_t s);
 
 struct GemmLaunch {
   sbmm_dtype dt;            // F64 or F32 operands

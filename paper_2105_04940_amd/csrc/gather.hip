@@ -7,6 +7,8 @@
 //
 // The sketch width L is read on the device; the grid covers the upper bound
 // L_pad_max and workgroups past round_up(L, 32) exit at once.
+#include <cstring>
+
 #include "common.h"
 
 namespace {
@@ -41,11 +43,12 @@ struct GatherArgs {
   void* D; int64_t ldd;
 };
 
+// Workgroup `bid` of one problem's gather: the first cblocks workgroups
+// write C (256 sketch columns x 16 rows each), the rest D (one row per wave).
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(kThreads) void gather_kernel(GatherArgs a) {
+__device__ __forceinline__ void gather_body(const GatherArgs& a, int64_t bid) {
   const int64_t L = *a.L_dev;
   const int64_t Lp = (L + SBMM_SKETCH_PAD - 1) / SBMM_SKETCH_PAD * SBMM_SKETCH_PAD;
-  const int64_t bid = blockIdx.x;
   if (bid < a.cblocks) {
     if (!a.C) return;
     const int64_t lt = bid % a.ctiles;
@@ -73,6 +76,31 @@ __global__ __launch_bounds__(kThreads) void gather_kernel(GatherArgs a) {
   }
 }
 
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kThreads) void gather_kernel(GatherArgs a) {
+  gather_body<Tin, Tout>(a, blockIdx.x);
+}
+
+// the problem t with wg_off[t] <= x < wg_off[t + 1]
+__device__ __forceinline__ int32_t find_item(const int64_t* __restrict__ off, int32_t count, int64_t x) {
+  int32_t lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The float32 gathers of many problems in one launch: workgroup b runs
+// workgroup b - wg_off[t] of problem t.
+__global__ __launch_bounds__(kThreads) void batch_gather_kernel(const GatherArgs* __restrict__ args,
+                                                                const int64_t* __restrict__ wg_off,
+                                                                int32_t count) {
+  const int64_t bid = blockIdx.x;
+  const int32_t t = find_item(wg_off, count, bid);
+  gather_body<float, float>(args[t], bid - wg_off[t]);
+}
+
 template <typename Tin>
 hipError_t dispatch_out(const GatherArgs& a, sbmm_dtype out, dim3 grid, hipStream_t s) {
   switch (out) {
@@ -84,9 +112,7 @@ hipError_t dispatch_out(const GatherArgs& a, sbmm_dtype out, dim3 grid, hipStrea
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_gather(const GatherLaunch& g, hipStream_t s) {
+GatherArgs make_gather_args(const GatherLaunch& g, int64_t* total) {
   GatherArgs a{};
   a.M = g.M; a.ldm = g.ldm; a.N = g.N; a.ldn = g.ldn;
   a.m = g.m; a.p = g.p; a.L_dev = g.L_dev;
@@ -95,7 +121,15 @@ hipError_t launch_gather(const GatherLaunch& g, hipStream_t s) {
   a.ctiles = ceil_div(g.L_pad_max, kThreads);
   a.cblocks = (g.C && g.m > 0) ? a.ctiles * ceil_div(g.m, kRowsC) : 0;
   const int64_t dblocks = (g.D && g.p > 0) ? ceil_div(g.L_pad_max, kRowsD) : 0;
-  const int64_t total = a.cblocks + dblocks;
+  *total = a.cblocks + dblocks;
+  return a;
+}
+
+}  // namespace
+
+hipError_t launch_gather(const GatherLaunch& g, hipStream_t s) {
+  int64_t total = 0;
+  const GatherArgs a = make_gather_args(g, &total);
   if (total == 0) return hipSuccess;
   dim3 grid((unsigned)total);
   switch (g.in_dt) {
@@ -104,4 +138,21 @@ hipError_t launch_gather(const GatherLaunch& g, hipStream_t s) {
     case SBMM_BF16: return dispatch_out<uint16_t>(a, g.out_dt, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+size_t batch_gather_args_bytes() { return sizeof(GatherArgs); }
+
+int64_t build_batch_gather_args(const GatherLaunch& g, void* out) {
+  int64_t total = 0;
+  const GatherArgs a = make_gather_args(g, &total);
+  std::memcpy(out, &a, sizeof(a));
+  return total;
+}
+
+hipError_t launch_batch_gather(const void* args, const int64_t* wg_off, int32_t count, int64_t total_wg,
+                               hipStream_t s) {
+  if (count <= 0 || total_wg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_gather_kernel, dim3((unsigned)total_wg), dim3(kThreads), 0, s,
+                     reinterpret_cast<const GatherArgs*>(args), wg_off, count);
+  return hipGetLastError();
 }

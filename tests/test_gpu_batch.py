@@ -175,8 +175,9 @@ def test_results_do_not_depend_on_tiles_or_order(small_batch):
     b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
     b.run()
     ref = _snapshot(b)
+    # sketch configurations 4..7: the same tiles over materialized sketches
     for cfg_ex in range(4):
-        for cfg_sk in range(4):
+        for cfg_sk in range(8):
             for lpt in (0, 1):
                 _clear(b)
                 b.set_tuning({"cfg": [cfg_ex, cfg_sk], "lpt": [lpt, 1 - lpt]})
@@ -189,9 +190,12 @@ def test_tuner_picks_a_measured_configuration(small_batch):
     b, probs, host = small_batch
     t = b.tune(reps=2)
     for g in range(2):
+        # 4 tile shapes x 2 orders, and for the sketch both forms of each
         ms = t["ms"][g]
-        assert all(v > 0 for v in ms)
-        assert ms[2 * t["cfg"][g] + t["lpt"][g]] == min(ms)
+        n = 8 if g == 0 else 16
+        assert all(v > 0 for v in ms[:n]) and all(v == -1.0 for v in ms[n:])
+        assert ms[2 * t["cfg"][g] + t["lpt"][g]] == min(ms[:n])
+    assert t["sketch_materialized"] == (t["cfg"][1] >= 4)
     _clear(b)
     b.run()
     torch.cuda.synchronize()
@@ -199,9 +203,11 @@ def test_tuner_picks_a_measured_configuration(small_batch):
     check_against_oracle(b, probs, host, 3, o)
 
 
-def test_graph_replays_match_eager(small_batch):
+@pytest.mark.parametrize("sk", [2, 6])
+def test_graph_replays_match_eager(small_batch, sk):
+    # sk 6: the materialized sketch (a gather and a product launch per group)
     b, *_ = small_batch
-    b.set_tuning({"cfg": [1, 2], "lpt": [1, 0]})
+    b.set_tuning({"cfg": [1, sk], "lpt": [1, 0]})
     b.run()
     torch.cuda.synchronize()
     ref = _snapshot(b)
@@ -219,6 +225,14 @@ def test_graph_replays_match_eager(small_batch):
         torch.cuda.synchronize()
         assert _same(ref, _snapshot(b)), rep
         assert torch.isfinite(y).all()
+
+
+def test_tuning_out_of_range(small_batch):
+    b, *_ = small_batch
+    for cfg in ([4, 0], [0, 8], [-1, 0]):
+        with pytest.raises(pk.SbmmError):
+            b.set_tuning({"cfg": cfg, "lpt": [1, 1]})
+    b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
 
 
 def test_graph_sees_new_inputs(small_batch):
@@ -318,4 +332,16 @@ def test_full_batched_workload_sampled(h):
         mn = MNs[t].cpu().numpy()[rows, cols]
         assert rel(cd, om.sketch_entries(Mh, Nh, draws, rows, cols)) < 1e-5, t
         assert rel(mn, om.exact_entries(Mh, Nh, rows, cols)) < 1e-5, t
+    # both forms of the sketched product (gather fused; sketches materialized
+    # group by group, about 80 GB of them in 8 GiB groups) give the bits of
+    # the tuned run for every problem
+    ref = [x.clone() for x in CDs]
+    for sk in (2, 6):
+        for x in b.CD:
+            x.fill_(float("nan"))
+        b.set_tuning({"cfg": [0, sk], "lpt": [1, 1]})
+        b.run()
+        torch.cuda.synchronize()
+        for t in range(len(items)):
+            assert torch.equal(b.CD[t], ref[t]), (sk, t)
     b.close()
