@@ -350,8 +350,8 @@ def batched_leg(h, pk, wl, torch, steps, warmup):
         "workload": ("512 independent block-sampling problems: m, p uniform in [256, 2048], n uniform in "
                      "[4096, 32768], uneven blocks of 8..128, c uniform in [16, 256], rule (1.4), float32 "
                      "inputs from the counter-based stream written on the device; one pass = grouped norm "
-                     "pass + per-problem plans + grouped exact MN + grouped sketched CD (gather fused) + "
-                     "per-problem errors"),
+                     "pass + per-problem plans + grouped exact MN + grouped sketched CD (gather fused, or "
+                     "sketches materialized group by group, as tuned) + per-problem errors"),
         "pass_ms_eager": eager_ms,
         "pass_ms_graph": graph_ms,
         "TFLOPs_graph": (exact_flops + sketch_flops) / graph_ms / 1e9,
