@@ -727,6 +727,17 @@ def main():
     # bf16 sketches of the same draws (beside the float32 step, not in it)
     base = pk.Problem(Md, Nd, off, CS[-1])
     col, row, blk = h.norms(base)
+    # the norm pass on its own: 20 back-to-back calls between two events (the
+    # events around each call inside the step leave the GPU idle for about
+    # 10 us each, which the per-call figure includes)
+    torch.cuda.synchronize()
+    n0, n1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n0.record()
+    for _ in range(20):
+        h.norms(base)
+    n1.record()
+    torch.cuda.synchronize()
+    t_norm_b2b = n0.elapsed_time(n1) / 20
     MN, bp, _ = h.exact(base, store=True, blocknorm=True)
     f32 = sketch_leg(False, col, row, blk, MN, bp, torch.float32, "f32")
     for _ in range(args.warmup):
@@ -754,11 +765,13 @@ def main():
     sketch_flops = {c: float(np.mean([2.0 * m * p * Ls[f"{r}/c{c}"] for r in RULES])) for c in CS}
     step_flops = exact_flops + sum(2.0 * m * p * L for L in Ls.values())
 
-    t_norm = avg_ms("norm_pass")
+    t_norm_step = avg_ms("norm_pass")
+    t_norm = t_norm_b2b
     t_exact = avg_ms("exact_gemm")
     t_sk = {c: avg_ms(f"sketch_gemm_c{c}") for c in CS}
     kernels = {
-        "norm_pass": {"ms": t_norm, "GB/s": norm_bytes / t_norm / 1e6},
+        "norm_pass": {"ms": t_norm, "GB/s": norm_bytes / t_norm / 1e6, "timing": "20 back-to-back passes",
+                      "in_step_ms": t_norm_step, "in_step_GB/s": norm_bytes / t_norm_step / 1e6},
         "exact_gemm": {"ms": t_exact, "TFLOP/s": exact_flops / t_exact / 1e9},
         "plan": {"ms": avg_ms("plan")},
         "gather": {"ms": avg_ms("gather"),

@@ -132,11 +132,46 @@ bool needs_blkprod(const sbmm_problem* P) {
 
 // --- internal steps (work on an arena that already has room) --------------
 
+// The device copy of the problem's block offsets. The handle keeps the last
+// partition it uploaded and enqueues a copy only when the partition differs
+// (the copy is ordered on `s` after the work already enqueued there). A dry
+// run gets a placeholder and no copy.
 sbmm_status upload_offsets(sbmm_handle h, const sbmm_problem* P, Arena& ar, int64_t** out, hipStream_t s) {
-  int64_t* d = ar.take<int64_t>(P->K + 1);
-  if (ar.base) HIP_TRY(h, hipMemcpyAsync(d, P->block_off, sizeof(int64_t) * (P->K + 1), hipMemcpyHostToDevice, s));
-  *out = d;
+  const size_t cnt = (size_t)P->K + 1;
+  if (!ar.base) {
+    *out = reinterpret_cast<int64_t*>((uintptr_t)256);
+    return SBMM_OK;
+  }
+  if (h->off_dev && h->off_host.size() == cnt &&
+      std::memcmp(h->off_host.data(), P->block_off, sizeof(int64_t) * cnt) == 0) {
+    *out = h->off_dev;
+    return SBMM_OK;
+  }
+  if (cnt > h->off_cap) {
+    HIP_TRY(h, hipDeviceSynchronize());   // earlier work may still read the old copy
+    if (h->off_dev) HIP_TRY(h, hipFree(h->off_dev));
+    h->off_dev = nullptr;
+    h->off_cap = 0;
+    h->off_host.clear();
+    const size_t cap = std::max(cnt, (size_t)1024);
+    hipError_t e = hipMalloc(&h->off_dev, sizeof(int64_t) * cap);
+    if (e != hipSuccess) {
+      h->off_dev = nullptr;
+      return fail(h, SBMM_E_NOMEM, "block offsets: %s", hipGetErrorString(e));
+    }
+    h->off_cap = cap;
+  }
+  h->off_host.clear();   // stale until the copy is enqueued
+  HIP_TRY(h, hipMemcpyAsync(h->off_dev, P->block_off, sizeof(int64_t) * cnt, hipMemcpyHostToDevice, s));
+  h->off_host.assign(P->block_off, P->block_off + cnt);
+  *out = h->off_dev;
   return SBMM_OK;
+}
+
+int64_t max_block_width(const sbmm_problem* P) {
+  int64_t w = 0;
+  for (int32_t k = 0; k < P->K; ++k) w = std::max(w, P->block_off[k + 1] - P->block_off[k]);
+  return w;
 }
 
 sbmm_status do_norms(sbmm_handle h, const sbmm_problem* P, const int64_t* off_dev, double* col_sq,
@@ -144,12 +179,14 @@ sbmm_status do_norms(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
   int R = 1;
   const size_t pe = norms_partial_elems(P->in_dtype, P->m, P->n, &R);
   double* partial = ar.take<double>(pe);
+  const int32_t chunks = norms_stats_chunks(P->n, P->K, max_block_width(P));
+  double* stats_part = chunks > 1 ? ar.take<double>(3 * (size_t)P->K * chunks) : nullptr;
   if (!ar.base) return SBMM_OK;
   NormLaunch L{};
   L.dt = P->in_dtype; L.M = P->M; L.ldm = P->ldm; L.N = P->N; L.ldn = P->ldn;
   L.m = P->m; L.n = P->n; L.p = P->p; L.K = P->K; L.off_dev = off_dev;
   L.partial = partial; L.rsplit = R; L.col_sq = col_sq; L.row_sq = row_sq; L.blk = blk;
-  L.status = h->status;
+  L.status = h->status; L.stats_chunks = chunks; L.stats_part = stats_part;
   HIP_TRY(h, launch_norms(L, s));
   return SBMM_OK;
 }
@@ -163,12 +200,6 @@ hipError_t run_product(const GemmLaunch& G, hipStream_t s) {
     return launch_gemm_skinny(G, tiles, tiles * 4, s);
   }
   return launch_gemm(G, s);
-}
-
-int64_t max_block_width(const sbmm_problem* P) {
-  int64_t w = 0;
-  for (int32_t k = 0; k < P->K; ++k) w = std::max(w, P->block_off[k + 1] - P->block_off[k]);
-  return w;
 }
 
 // Exact product with optional MN store, block norms and error vs Y.
@@ -369,6 +400,7 @@ sbmm_status sbmm_destroy(sbmm_handle h) {
   // teardown is best effort: the handle is gone whatever these return
   (void)hipSetDevice(h->device);
   if (h->ws) (void)hipFree(h->ws);
+  if (h->off_dev) (void)hipFree(h->off_dev);
   if (h->status) (void)hipFree(h->status);
   h->status = nullptr;
   delete h;

@@ -3,6 +3,7 @@
 #pragma once
 #include <cstdarg>
 #include <cstdio>
+#include <vector>
 
 #include "common.h"
 
@@ -12,6 +13,11 @@ struct sbmm_handle_s {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int32_t* status = nullptr;   // device status word
+  // device copy of the last block partition used, and its host shadow: a
+  // call with the same partition enqueues no copy
+  int64_t* off_dev = nullptr;
+  size_t off_cap = 0;
+  std::vector<int64_t> off_host;
 };
 
 namespace {

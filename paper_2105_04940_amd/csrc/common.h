@@ -81,8 +81,15 @@ struct NormLaunch {
   int rsplit;               // R
   double* col_sq; double* row_sq; double* blk;
   int32_t* status;
+  // blocks wider than one statistics chunk: chunks per block (1: one
+  // workgroup per block writes blk directly) and the [3][K][chunks] partials
+  int32_t stats_chunks = 1;
+  double* stats_part = nullptr;
 };
 size_t norms_partial_elems(sbmm_dtype dt, int64_t m, int64_t n, int* rsplit_out);
+// statistics chunks per block for a partition whose widest block is max_width
+// (1 when a workgroup per block suffices)
+int32_t norms_stats_chunks(int64_t n, int32_t K, int64_t max_width);
 hipError_t launch_norms(const NormLaunch& a, hipStream_t s);
 // Batched norm pass: per problem, build_batch_norm_args writes the argument
 // blocks (batch_norm_args_bytes / batch_stats_args_bytes bytes) of a

@@ -204,11 +204,17 @@ struct StatsArgs {
   const int64_t* off; int32_t K;
   double* col_sq; const double* row_sq; double* blk;
   int32_t* status;
+  int32_t chunks;            // workgroups per block (1: whole block, writes blk)
+  double* stats_part;        // chunks > 1: [3][K][chunks]
 };
 
-// One workgroup per block: finish the column sums over the row splits and
-// form the three block statistics.
-__device__ void block_stats_body(const StatsArgs& s, int k) {
+// Columns of a statistics chunk (blocks wider than one workgroup's share).
+constexpr int64_t kStatsChunk = (int64_t)kThreads * 8;
+
+// Workgroup (block k, chunk c): finish the column sums over the row splits
+// for its columns and form the three block statistics over them (the whole
+// block when chunks == 1, then written to blk; else to the chunk partials).
+__device__ void block_stats_body(const StatsArgs& s, int k, int c) {
   const double* __restrict__ partial = s.partial;
   const int rsplit = s.rsplit;
   const int64_t n = s.n;
@@ -219,7 +225,11 @@ __device__ void block_stats_body(const StatsArgs& s, int k) {
   double* __restrict__ blk = s.blk;
   int32_t* status = s.status;
   __shared__ double sm[3][kThreads];
-  const int64_t lo = off[k], hi = off[k + 1];
+  int64_t lo = off[k], hi = off[k + 1];
+  if (s.chunks > 1) {
+    lo += c * kStatsChunk;
+    hi = min(hi, lo + kStatsChunk);
+  }
   double am = 0.0, an = 0.0, as = 0.0;
   bool bad = false;
 #pragma unroll 8
@@ -238,22 +248,44 @@ __device__ void block_stats_body(const StatsArgs& s, int k) {
   sm[1][threadIdx.x] = an;
   sm[2][threadIdx.x] = as;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      sm[0][threadIdx.x] += sm[0][threadIdx.x + s];
-      sm[1][threadIdx.x] += sm[1][threadIdx.x + s];
-      sm[2][threadIdx.x] += sm[2][threadIdx.x + s];
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + h];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + h];
+      sm[2][threadIdx.x] += sm[2][threadIdx.x + h];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    blk[k] = sm[0][0];
-    blk[K + k] = sm[1][0];
-    blk[2 * K + k] = sm[2][0];
+    if (s.chunks == 1) {
+      blk[k] = sm[0][0];
+      blk[K + k] = sm[1][0];
+      blk[2 * K + k] = sm[2][0];
+    } else {
+      const int64_t q = (int64_t)k * s.chunks + c, stride = (int64_t)K * s.chunks;
+      s.stats_part[q] = sm[0][0];
+      s.stats_part[stride + q] = sm[1][0];
+      s.stats_part[2 * stride + q] = sm[2][0];
+    }
   }
 }
 
-__global__ __launch_bounds__(kThreads) void block_stats_kernel(StatsArgs s) { block_stats_body(s, blockIdx.x); }
+// chunks > 1: per block, the chunk partials summed in chunk order (chunks
+// past the block's end hold zeros)
+__global__ __launch_bounds__(kThreads) void block_stats_combine_kernel(StatsArgs s) {
+  const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= s.K) return;
+  const int64_t stride = (int64_t)s.K * s.chunks;
+  for (int f = 0; f < 3; ++f) {
+    double v = 0.0;
+    for (int c = 0; c < s.chunks; ++c) v += s.stats_part[f * stride + k * s.chunks + c];
+    s.blk[f * s.K + k] = v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void block_stats_kernel(StatsArgs s) {
+  block_stats_body(s, blockIdx.x / s.chunks, blockIdx.x % s.chunks);
+}
 
 // Last t with off[t] <= x (off ascending, off[0] = 0 <= x).
 __device__ __forceinline__ int32_t find_problem(const int64_t* __restrict__ off, int32_t T, int64_t x) {
@@ -286,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void batch_stats_kernel(const StatsArgs* 
                                                                const int64_t* __restrict__ blk_off, int32_t count) {
   const int64_t bid = blockIdx.x;
   const int32_t t = find_problem(blk_off, count, bid);
-  block_stats_body(args[t], (int)(bid - blk_off[t]));
+  block_stats_body(args[t], (int)(bid - blk_off[t]), 0);
 }
 
 int elems_per_vec(sbmm_dtype dt) { return 16 / (int)dtype_size(dt); }
@@ -310,7 +342,7 @@ int64_t make_norm_args(const NormLaunch& L, NormArgs* out) {
   while (G < 64 && G < nvec) G <<= 1;
   a.n_group = G;
   const int64_t rows_per_step = 4 * (64 / G);
-  const int64_t steps = L.p > 0 ? std::max<int64_t>(1, ceil_div(L.n, rows_per_step * 4096)) : 0;
+  const int64_t steps = L.p > 0 ? std::max<int64_t>(1, ceil_div(L.n, rows_per_step * 8192)) : 0;
   a.rows_per_wg_n = rows_per_step * std::max<int64_t>(steps, 1);
   const int64_t nblocks_n = L.p > 0 ? ceil_div(L.n, a.rows_per_wg_n) : 0;
   *out = a;
@@ -318,16 +350,20 @@ int64_t make_norm_args(const NormLaunch& L, NormArgs* out) {
 }
 
 StatsArgs make_stats_args(const NormLaunch& L) {
-  return StatsArgs{L.partial, L.m > 0 ? L.rsplit : 1, L.n, L.off_dev, L.K, L.col_sq, L.row_sq, L.blk, L.status};
+  return StatsArgs{L.partial, L.m > 0 ? L.rsplit : 1, L.n, L.off_dev, L.K, L.col_sq, L.row_sq, L.blk, L.status,
+                   L.stats_part ? std::max<int32_t>(L.stats_chunks, 1) : 1, L.stats_part};
 }
 
 }  // namespace
 
-// Row splits of M: enough workgroups to fill the chip several times over,
-// but at least 32 rows per split.
+// Row splits of M: about 1024 workgroups on M (four per CU, each streaming
+// a long run of rows: on a 4096 x 65536 float32 M this reads at 6.2 TB/s,
+// against 5.9 TB/s with 4096 shorter ones), but at least 32 rows per split.
+// The N part adds about 8192 workgroups of its own (8 rows of 16 KB each at
+// that shape).
 size_t norms_partial_elems(sbmm_dtype dt, int64_t m, int64_t n, int* rsplit_out) {
   const int64_t tiles = ceil_div(n, 64 * elems_per_vec(dt));
-  int64_t want = ceil_div(4096, tiles > 0 ? tiles : 1);
+  int64_t want = ceil_div(1024, tiles > 0 ? tiles : 1);
   int64_t maxr = m / 32 > 1 ? m / 32 : 1;
   int64_t R = want < 1 ? 1 : (want > maxr ? maxr : want);
   if (R > 64) R = 64;
@@ -350,8 +386,20 @@ hipError_t launch_norms(const NormLaunch& L, hipStream_t s) {
       default: return hipErrorInvalidValue;
     }
   }
-  hipLaunchKernelGGL(block_stats_kernel, dim3(L.K), dim3(kThreads), 0, s, make_stats_args(L));
+  const StatsArgs st = make_stats_args(L);
+  hipLaunchKernelGGL(block_stats_kernel, dim3((unsigned)((int64_t)L.K * st.chunks)), dim3(kThreads), 0, s, st);
+  if (st.chunks > 1)
+    hipLaunchKernelGGL(block_stats_combine_kernel, dim3((unsigned)ceil_div(L.K, kThreads)), dim3(kThreads), 0, s, st);
   return hipGetLastError();
+}
+
+// Blocks wider than two chunks are split when that keeps the grid dense
+// (at most twice the workgroups a perfect split would need).
+int32_t norms_stats_chunks(int64_t n, int32_t K, int64_t max_width) {
+  const int64_t c = ceil_div(max_width, kStatsChunk);
+  if (c <= 2) return 1;
+  const int64_t dense = ceil_div(n, kStatsChunk) + K;
+  return (int64_t)K * c <= 2 * dense ? (int32_t)c : 1;
 }
 
 // ----------------------------------------------------------------------------

@@ -94,6 +94,43 @@ def test_norms_strided_rows(h):
     assert rel(host64(col), ocol) < 1e-13 and rel(host64(row), orow) < 1e-13
 
 
+@pytest.mark.parametrize("K", [1, 4, 10, 40])
+def test_norms_wide_blocks(h, K):
+    # blocks of 5e5 / K columns: the block statistics run in chunks of
+    # columns per block and are combined in chunk order (K = 40: 12 500
+    # columns, 7 chunks; K = 1: 245 chunks)
+    g = np.random.Generator(np.random.PCG64(K))
+    n = 500000
+    M = g.standard_normal((6, n)) * np.exp(g.normal(0, 1.0, n))
+    N = g.standard_normal((n, 5))
+    off = wl.equal_blocks(n, K)
+    prob = pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), off, c=3)
+    col, row, blk = h.norms(prob)
+    torch.cuda.synchronize()
+    ocol, orow = om.column_row_sq(M, N)
+    st = om.block_stats(ocol, orow, off)
+    b = host64(blk)
+    assert rel(host64(col), ocol) < 1e-13
+    assert rel(b[:K], st.m_sq) < 1e-13 and rel(b[K:2 * K], st.n_sq) < 1e-13 and rel(b[2 * K:], st.s) < 1e-13
+
+
+def test_partition_changes_between_calls(h):
+    # one handle, the same inputs under partitions that alternate (same K,
+    # then another K, then the first again): each call uses its own offsets
+    M, N, _ = wl.random_problem(20, 3000, 15, 5, seed=77)
+    Md, Nd = to_dev(M, torch.float64), to_dev(N, torch.float64)
+    ocol, orow = om.column_row_sq(M, N)
+    offs = [[0, 700, 1500, 3000], [0, 100, 2900, 3000], [0, 1000, 2000, 2500, 2999, 3000],
+            [0, 700, 1500, 3000]]
+    for off in offs + offs[::-1]:
+        col, row, blk = h.norms(pk.Problem(Md, Nd, off, c=4))
+        torch.cuda.synchronize()
+        st = om.block_stats(ocol, orow, off)
+        K = len(off) - 1
+        assert rel(host64(blk)[2 * K:], st.s) < 1e-13, off
+        assert rel(host64(blk)[:K], st.m_sq) < 1e-13, off
+
+
 def test_norms_bitwise_reproducible(h):
     M, N, off = wl.random_problem(200, 4000, 150, 40, seed=9)
     prob = pk.Problem(to_dev(M, torch.float32), to_dev(N, torch.float32), off, c=4)
