@@ -265,6 +265,13 @@ sbmm_status do_plan(sbmm_handle h, const sbmm_problem* P, const sbmm_sizes& sz, 
   int64_t* user_ck_dev = nullptr;
   const bool uck = P->mode == SBMM_MODE_STRATIFIED && P->alloc == SBMM_ALLOC_USER && pilot_r == 0;
   if (uck) user_ck_dev = ar.take<int64_t>(P->K);
+  const int64_t max_atoms = P->mode == SBMM_MODE_BLOCK ? P->K : max_block_width(P);
+  L.dchunks = plan_design_chunks(max_atoms, sz.atoms, sz.strata);
+  if (L.dchunks > 1) {
+    L.dpart_max = ar.take<double>((size_t)sz.strata * L.dchunks);
+    L.dpart_sum = ar.take<uint64_t>((size_t)sz.strata * L.dchunks);
+  }
+  if (plan_wide_offsets(P->c)) L.wpart = ar.take<uint64_t>(ceil_div(P->c, 256));
   if (draw_off_out) *draw_off_out = L.draw_off;
   if (!ar.base) return SBMM_OK;
   if (uck) HIP_TRY(h, hipMemcpyAsync(user_ck_dev, P->user_ck, sizeof(int64_t) * P->K, hipMemcpyHostToDevice, s));

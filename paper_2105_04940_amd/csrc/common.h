@@ -124,7 +124,20 @@ struct PlanLaunch {
   int32_t* idx; double* scale; int64_t* col_off; int64_t* ck; double* p_hat;
   int32_t* colmap; double* colscale; int64_t L_pad_max;
   int32_t* status;
+  // strata wider than two design chunks: chunks per stratum (1: one
+  // workgroup per stratum) and the per-chunk maxima and integer sums
+  int32_t dchunks = 1;
+  double* dpart_max = nullptr;
+  uint64_t* dpart_sum = nullptr;
+  // non-null: the draw offsets run on many workgroups, from the width sum
+  // of every 256 draws that the sampler leaves here
+  uint64_t* wpart = nullptr;
 };
+// design chunks per stratum for strata of at most max_atoms atoms (A atoms,
+// S strata in all); 1 when a workgroup per stratum suffices
+int32_t plan_design_chunks(int64_t max_atoms, int64_t A, int64_t S);
+// whether the draw offsets of c draws take the many-workgroup form
+bool plan_wide_offsets(int64_t c);
 hipError_t launch_plan(const PlanLaunch& a, hipStream_t s);
 // block-mode plans of many problems, one workgroup each (plans in device memory)
 hipError_t launch_batch_plan(const PlanLaunch* plans_dev, int32_t count, hipStream_t s);

@@ -188,6 +188,118 @@ __device__ void design_body(const PlanLaunch& a, int64_t s) {
 
 __global__ __launch_bounds__(kThreads) void design_kernel(PlanLaunch a) { design_body(a, blockIdx.x); }
 
+// ----------------------------------------------------------------------------
+// The same design for wide strata, in chunks of kDesignChunk atoms (one
+// workgroup each, dchunks per stratum): the chunk maxima; then the stratum
+// maximum, the quantization and the chunk sums; then the CDF from the sums of
+// the chunks before (exact integers, so W, CDF, T and p_hat are the bits of
+// the one-workgroup form).
+// ----------------------------------------------------------------------------
+constexpr int kDesignPer = 8;
+constexpr int64_t kDesignChunk = (int64_t)kThreads * kDesignPer;
+
+__device__ __forceinline__ void chunk_range(const PlanLaunch& a, int64_t* s, int64_t* a0, int64_t* a1) {
+  const int64_t b = blockIdx.x;
+  *s = b / a.dchunks;
+  const int64_t c = b % a.dchunks;
+  *a0 = strat_begin(a, *s) + c * kDesignChunk;
+  *a1 = min(strat_begin(a, *s + 1), *a0 + kDesignChunk);
+}
+
+__global__ __launch_bounds__(kThreads) void design_max_kernel(PlanLaunch a) {
+  __shared__ double smd[kThreads];
+  int64_t s, a0, a1;
+  chunk_range(a, &s, &a0, &a1);
+  double mx = 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int u = 0; u < kDesignPer; ++u) {
+    const int64_t i = a0 + threadIdx.x + (int64_t)u * kThreads;
+    if (i < a1) {
+      const double w = atom_weight(a, i);
+      bad |= !isfinite(w) || w < 0.0;
+      mx = fmax(mx, w);
+    }
+  }
+  if (bad) *a.status = SBMM_DEV_NONFINITE;
+  mx = block_max(mx, smd);
+  if (threadIdx.x == 0) a.dpart_max[blockIdx.x] = mx;
+}
+
+__global__ __launch_bounds__(kThreads) void design_quant_kernel(PlanLaunch a) {
+  __shared__ double smd[kThreads];
+  __shared__ uint64_t smu[kThreads];
+  int64_t s, a0, a1;
+  chunk_range(a, &s, &a0, &a1);
+  double mx = 0.0;
+  for (int64_t c = threadIdx.x; c < a.dchunks; c += kThreads) mx = fmax(mx, a.dpart_max[s * a.dchunks + c]);
+  mx = block_max(mx, smd);
+  const int64_t As = strat_begin(a, s + 1) - strat_begin(a, s);
+  const int shift = (mx > 0.0) ? (63 - ceil_log2_u64((uint64_t)As)) - 1 - ilogb(mx) : 0;
+  uint64_t local = 0;
+#pragma unroll
+  for (int u = 0; u < kDesignPer; ++u) {
+    const int64_t i = a0 + threadIdx.x + (int64_t)u * kThreads;
+    if (i < a1) {
+      const uint64_t W = (mx > 0.0) ? quantize(atom_weight(a, i), shift) : 0;
+      a.W[i] = W;
+      local += W;
+    }
+  }
+  uint64_t total;
+  block_excl_scan(local, smu, &total);
+  if (threadIdx.x == 0) a.dpart_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void design_scan_kernel(PlanLaunch a) {
+  __shared__ uint64_t tile[kDesignChunk];
+  __shared__ uint64_t smu[kThreads];
+  __shared__ uint64_t sm_base[2];
+  int64_t s, a0, a1;
+  chunk_range(a, &s, &a0, &a1);
+  const int64_t c = blockIdx.x % a.dchunks;
+  if (threadIdx.x == 0) {
+    uint64_t before = 0, total = 0;
+    for (int64_t q = 0; q < a.dchunks; ++q) {
+      const uint64_t v = a.dpart_sum[s * a.dchunks + q];
+      if (q < c) before += v;
+      total += v;
+    }
+    sm_base[0] = before;
+    sm_base[1] = total;
+  }
+  uint64_t w[kDesignPer];
+#pragma unroll
+  for (int u = 0; u < kDesignPer; ++u) {
+    const int64_t i = a0 + threadIdx.x + (int64_t)u * kThreads;
+    w[u] = i < a1 ? a.W[i] : 0;
+    tile[threadIdx.x + u * kThreads] = w[u];
+  }
+  __syncthreads();
+  // each thread scans its run of kDesignPer consecutive atoms of the chunk
+  uint64_t local = 0;
+#pragma unroll
+  for (int u = 0; u < kDesignPer; ++u) local += tile[threadIdx.x * kDesignPer + u];
+  uint64_t tot;
+  uint64_t run = block_excl_scan(local, smu, &tot) + sm_base[0];
+#pragma unroll
+  for (int u = 0; u < kDesignPer; ++u) {
+    run += tile[threadIdx.x * kDesignPer + u];
+    tile[threadIdx.x * kDesignPer + u] = run;
+  }
+  __syncthreads();
+  const uint64_t T = sm_base[1];
+#pragma unroll
+  for (int u = 0; u < kDesignPer; ++u) {
+    const int64_t i = a0 + threadIdx.x + (int64_t)u * kThreads;
+    if (i < a1) {
+      a.cdf[i] = tile[threadIdx.x + u * kThreads];
+      if (a.p_hat) a.p_hat[i] = T > 0 ? (double)w[u] / (double)T : 0.0;
+    }
+  }
+  if (c == 0 && threadIdx.x == 0) a.T[s] = T;
+}
+
 // 128-bit helpers for the apportionment.
 struct U128 { uint64_t hi, lo; };
 __device__ __forceinline__ U128 mul64(uint64_t x, uint64_t y) { return {__umul64hi(x, y), x * y}; }
@@ -405,10 +517,34 @@ __device__ void sample_one(const PlanLaunch& a, int64_t t) {
   a.width[t] = a.mode == SBMM_MODE_BLOCK ? a.off_dev[atom + 1] - a.off_dev[atom] : 1;
 }
 
-// One thread per draw.
+// One thread per draw; with wpart, the workgroup also leaves the sum of its
+// draws' widths for the many-workgroup offsets pass.
 __global__ __launch_bounds__(kThreads) void sample_kernel(PlanLaunch a) {
+  __shared__ uint64_t smu[kThreads];
   const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (t < a.c) sample_one(a, t);
+  if (a.wpart) {
+    uint64_t tot;
+    block_excl_scan(t < a.c ? (uint64_t)a.width[t] : 0, smu, &tot);
+    if (threadIdx.x == 0) a.wpart[blockIdx.x] = tot;
+  }
+}
+
+// Draw offsets on many workgroups: workgroup b scans the widths of its 256
+// draws on top of the width sums of the workgroups before it.
+__global__ __launch_bounds__(kThreads) void offsets_wide_kernel(PlanLaunch a) {
+  __shared__ uint64_t smu[kThreads];
+  const int64_t b = blockIdx.x;
+  uint64_t before = 0;
+  for (int64_t q = threadIdx.x; q < b; q += kThreads) before += a.wpart[q];
+  uint64_t base;
+  block_excl_scan(before, smu, &base);
+  const int64_t t = b * kThreads + threadIdx.x;
+  const uint64_t w = t < a.c ? (uint64_t)a.width[t] : 0;
+  uint64_t tot;
+  const uint64_t ex = block_excl_scan(w, smu, &tot);
+  if (t < a.c) a.col_off[t] = (int64_t)(base + ex);
+  if (b == gridDim.x - 1 && threadIdx.x == 0) a.col_off[a.c] = (int64_t)(base + tot);
 }
 
 // Exclusive scan of the draw widths into col_off (single workgroup).
@@ -495,15 +631,37 @@ hipError_t launch_batch_plan(const PlanLaunch* plans_dev, int32_t count, hipStre
   return hipGetLastError();
 }
 
+// Strata wider than two chunks are cut into chunks when that keeps the grid
+// dense (at most twice the workgroups a perfect split would need).
+int32_t plan_design_chunks(int64_t max_atoms, int64_t A, int64_t S) {
+  const int64_t c = ceil_div(max_atoms, kDesignChunk);
+  if (c <= 2) return 1;
+  return S * c <= 2 * (ceil_div(A, kDesignChunk) + S) ? (int32_t)c : 1;
+}
+
+// Many-workgroup offsets for more than one workgroup of draws, up to 2^20
+// draws (each workgroup sums the width sums before it).
+bool plan_wide_offsets(int64_t c) { return c > kThreads && c <= (int64_t(1) << 20); }
+
 hipError_t launch_plan(const PlanLaunch& a, hipStream_t s) {
-  hipLaunchKernelGGL(design_kernel, dim3((unsigned)a.S), dim3(kThreads), 0, s, a);
+  if (a.dchunks > 1) {
+    const dim3 grid((unsigned)(a.S * a.dchunks));
+    hipLaunchKernelGGL(design_max_kernel, grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(design_quant_kernel, grid, dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(design_scan_kernel, grid, dim3(kThreads), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(design_kernel, dim3((unsigned)a.S), dim3(kThreads), 0, s, a);
+  }
   if (a.mode == SBMM_MODE_BLOCK)
     hipLaunchKernelGGL(alloc_block_kernel, dim3(1), dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL(alloc_kernel, dim3(1), dim3(kThreads), 0, s, a);
   const unsigned nb = (unsigned)ceil_div(a.c, kThreads);
   hipLaunchKernelGGL(sample_kernel, dim3(nb), dim3(kThreads), 0, s, a);
-  hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kThreads), 0, s, a);
+  if (a.wpart)
+    hipLaunchKernelGGL(offsets_wide_kernel, dim3(nb), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(kThreads), 0, s, a);
   hipLaunchKernelGGL(colmap_kernel, dim3(nb), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

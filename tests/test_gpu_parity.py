@@ -153,7 +153,8 @@ def _user_weights(n_atoms, seed, zeros=0.2):
     return w
 
 
-@pytest.mark.parametrize("K,c,seed", [(64, 16, 0), (1024, 256, 1), (7, 300, 2), (1, 5, 3)])
+@pytest.mark.parametrize("K,c,seed", [(64, 16, 0), (1024, 256, 1), (7, 300, 2), (1, 5, 3),
+                                      (20000, 5000, 4)])   # design in chunks, offsets on many workgroups
 def test_plan_block_user_weights_bit_exact(h, K, c, seed):
     n = K * 3
     off = wl.equal_blocks(n, K)
@@ -206,6 +207,35 @@ def test_plan_stratified_user_weights_bit_exact(h, alloc):
     assert np.array_equal(pl.idx.cpu().numpy(), draws.atom)
     assert np.array_equal(pl.scale.cpu().numpy(), draws.scale)
     assert np.array_equal(pl.col_off.cpu().numpy(), draws.col_off)
+
+
+@pytest.mark.parametrize("alloc", ["uniform", "user"])
+def test_plan_wide_strata_bit_exact(h, alloc):
+    # strata of up to 20 000 atoms: the design runs in chunks of 2048 atoms per
+    # stratum and the draw offsets on many workgroups; W, CDF, T, p_hat and the
+    # draws are those of the oracle bit for bit
+    off = [0, 20000, 31999, 32000, 50000]
+    n = 50000
+    w = _user_weights(n, 12, zeros=0.3)
+    w[31999] = 2.5
+    c = 3000
+    ck = [1000, 700, 300, 1000] if alloc == "user" else None
+    M = np.zeros((1, n))
+    N = np.zeros((n, 1))
+    prob = pk.Problem(to_dev(M, torch.float64), to_dev(N, torch.float64), off, c,
+                      mode="stratified", prob="user", alloc=alloc,
+                      user_w=to_dev(w, torch.float64), user_ck=ck, seed=6, trial=2)
+    col, row, blk = h.norms(prob)
+    pl = h.plan(prob, col, row, blk)
+    g = np.ones(4) if alloc == "uniform" else None
+    design = om.make_design("stratified", off, c, w, g=g, user_ck=ck)
+    draws = om.sample(design, 6, 2)
+    assert pl.ck.cpu().tolist() == design.cs
+    assert np.array_equal(pl.p_hat.cpu().numpy(), design.p_hat())
+    assert np.array_equal(pl.idx.cpu().numpy(), draws.atom)
+    assert np.array_equal(pl.scale.cpu().numpy(), draws.scale)
+    assert np.array_equal(pl.col_off.cpu().numpy(), draws.col_off)
+    assert pl.L == draws.L == c
 
 
 # --------------------------------------------------------------------------
