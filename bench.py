@@ -227,16 +227,67 @@ def cpu_baseline(M, N, off, target_s):
             flops += 2.0 * r * r * draws.L
             Ls.append(draws.L)
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": flops / dt / 1e12,
         "unit": "TFLOP/s",
         "cores": int(threads),
+        "cpu_model": model,
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": (f"one whole step of the oracle in float64 (norms, exact MN, per-block "
                    f"norms, 9 x (design, draws, sketch, CD, error), L = {Ls}) on M[:{r}, :] "
                    f"(x{n}) and N[:, :{r}]; {dt:.1f} s"),
         "seconds": dt,
     }
+
+
+def stream_copy_GBps(torch, nbytes=1 << 30, reps=10):
+    """A plain device-to-device copy of nbytes (torch's copy kernel): bytes
+    read plus written per second, the box's own streaming reference."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / ms / 1e6
+
+
+def fused_vs_materialized(h, pk, torch, Md, Nd, off, c, reps=3):
+    """The paper-scale problem as a batch of one (rule (1.4), c draws): the
+    sketched product with the gather fused into its loads against gathering C,
+    D first, per tile shape, as the batch tuner times them (HIP events)."""
+    b = pk.Batch(h, [dict(M=Md, N=Nd, off=off, c=c, prob="norm", seed=0, trial=0)])
+    t = b.tune(reps=reps)
+    b.run()
+    torch.cuda.synchronize()
+    L = int(b.L[0].item())
+    flops = 2.0 * Md.shape[0] * Nd.shape[1] * L
+    ms = t["ms"][1]
+    n = len(pk.BATCH_TILES)
+    best_f = min(v for v in ms[:2 * n] if v > 0)
+    best_m = min(v for v in ms[2 * n:4 * n] if v > 0) if any(v > 0 for v in ms[2 * n:4 * n]) else None
+    out = {"c": c, "L": L,
+           "fused_ms": best_f, "fused_TFLOPs": flops / best_f / 1e9,
+           "materialized_ms": best_m,
+           "materialized_TFLOPs": flops / best_m / 1e9 if best_m else None,
+           "note": "materialized includes its gather; tiles of the batched grouped product"}
+    b.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def linear_layer_leg(h, pk, wl, torch, steps, warmup):
@@ -799,9 +850,13 @@ def main():
     roofline = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic,
                 "flops_per_launch": per_launch}
+    copy_gbs = stream_copy_GBps(torch)
     norm_roof = {"kernel": "norm_pass", "bound": "hbm", "achieved": kernels["norm_pass"]["GB/s"],
                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": kernels["norm_pass"]["GB/s"] / HBM_PEAK_GBS, "bytes_per_launch": norm_bytes}
+                 "frac": kernels["norm_pass"]["GB/s"] / HBM_PEAK_GBS, "bytes_per_launch": norm_bytes,
+                 "measured_copy_GBps": copy_gbs,
+                 "frac_of_measured_copy": kernels["norm_pass"]["GB/s"] / copy_gbs}
+    fvm = fused_vs_materialized(h, pk, torch, Md, Nd, off, CS[-1])
 
     t_b16 = {c: avg_ms(f"bf16_c{c}") for c in CS}
     b16_flops = sum(sketch_flops[c] for c in CS) * len(RULES)
@@ -861,6 +916,7 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "roofline_norm_pass": norm_roof,
+        "sketch_fused_vs_materialized": fvm,
         "bf16": bf16,
         "mx_e4m3": mx,
     }
