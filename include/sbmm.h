@@ -54,7 +54,10 @@
  * map to SBMM_E_HIP with the HIP text in sbmm_last_error().
  *
  * Streams and threads: calls are asynchronous on the given stream unless
- * documented as synchronizing. Use one handle per host thread.
+ * documented as synchronizing. Use one handle per host thread. Calls on one
+ * handle share its workspace and its device copy of the last partition: work
+ * enqueued through one handle on different streams must not overlap (order
+ * the streams, or use one handle per stream).
  */
 #ifndef SBMM_H
 #define SBMM_H
@@ -153,6 +156,17 @@ sbmm_status sbmm_reserve(sbmm_handle h, size_t bytes);
 sbmm_status sbmm_sync(sbmm_handle h, sbmm_stream stream);
 /* Fill `out` from the problem's shape (host only; validates the problem). */
 sbmm_status sbmm_query_sizes(const sbmm_problem* prob, sbmm_sizes* out);
+/* Host only: *bytes = the device workspace that sbmm_run needs for this
+ * problem with sketched-product dtype `compute` and every optional buffer
+ * (C, D, MN) left to the library, which also covers sbmm_norms, sbmm_plan,
+ * sbmm_exact and sbmm_exact_error (with per-block norms), sbmm_pilot and
+ * sbmm_bound of the same problem; *L_max (optional) = c * widest atom. After
+ * sbmm_reserve(h, *bytes) none of these calls grows the workspace, so none
+ * allocates device memory (the handle also keeps a device copy of the last
+ * partition, with room for 1023 blocks from sbmm_create on; a partition of
+ * more blocks enlarges it once, by 8 bytes a block). SBMM_E_ARG for an
+ * invalid problem or a compute dtype the input dtype does not allow. */
+sbmm_status sbmm_workspace_size(const sbmm_problem* prob, sbmm_dtype compute, size_t* bytes, int64_t* L_max);
 
 /* ------------------------------------------------------------------------ */
 /* Steps of the path                                                         */
@@ -254,6 +268,15 @@ sbmm_status sbmm_sketch_gemm_mx(sbmm_handle h, int64_t m, int64_t p, int64_t L_p
                                 const void* C, int64_t ldc, const void* Cs, int64_t ldcs, const void* Dt,
                                 int64_t lddt, const void* Ds, int64_t ldds, float* CD, int64_t ldcd,
                                 const float* MN, int64_t ldmn, double* err_sq, sbmm_stream stream);
+
+/* The exact product with the judge in its epilogue (the error of a given
+ * estimate): err2_and_mn2[0] = ||MN - CD||_F^2, err2_and_mn2[1] =
+ * ||MN||_F^2 (device, float64, fixed order). CD is m x p (ldcd >= p) in the
+ * product dtype cd_dtype (F64 for F64 inputs, else F32). MN (optional) and
+ * blkprod_sq (optional, device [K]: ||M^k N_k||_F^2) as in sbmm_exact. */
+sbmm_status sbmm_exact_error(sbmm_handle h, const sbmm_problem* prob, const void* CD, int64_t ldcd,
+                             sbmm_dtype cd_dtype, void* MN, int64_t ldmn, double* blkprod_sq,
+                             double* err2_and_mn2, sbmm_stream stream);
 
 /* ||X - Y||_F^2 and ||Y||_F^2 of two m x p matrices (F64 or F32) into
  * out2[0..1] (device, float64, fixed order). */

@@ -34,6 +34,7 @@ EXPORTS = (
     "sbmm_batch_create", "sbmm_batch_destroy", "sbmm_batch_run", "sbmm_batch_capture",
     "sbmm_batch_replay", "sbmm_batch_tune", "sbmm_batch_set_tuning",
     "sbmm_sketch_mx", "sbmm_sketch_gemm_mx", "sbmm_pilot", "sbmm_bound",
+    "sbmm_workspace_size", "sbmm_exact_error",
 )
 # Layout of sbmm_bound's output (SBMM_BOUND_* in the header), then eta_j and
 # the bound of every delta_j.
@@ -121,6 +122,8 @@ def load_library(path=LIB_PATH):
         "sbmm_pilot": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), vp, vp]),
         "sbmm_bound": (st, [vp, P(Problem_t), vp, vp, vp, vp, P(PlanOut_t), ctypes.c_double, i32,
                             P(ctypes.c_double), P(ctypes.c_double), vp]),
+        "sbmm_workspace_size": (st, [P(Problem_t), st, P(ctypes.c_size_t), P(i64)]),
+        "sbmm_exact_error": (st, [vp, P(Problem_t), vp, i64, st, vp, i64, vp, vp, vp]),
         "sbmm_sketch": (st, [vp, P(Problem_t), P(PlanOut_t), st, vp, i64, vp, i64, vp]),
         "sbmm_sketch_gemm": (st, [vp, i64, i64, i64, vp, st, vp, i64, vp, i64, vp, i64,
                                   vp, i64, vp, vp]),
@@ -238,6 +241,19 @@ class Problem:
         return s
 
 
+def sbmm_workspace_size(problem, compute=None):
+    """Device workspace bytes the problem's calls need (see the header) and
+    L_max; host only."""
+    s = problem.struct()
+    cd = dtype_code(compute or problem.M.dtype)
+    b = ctypes.c_size_t()
+    L = ctypes.c_int64()
+    st = lib().sbmm_workspace_size(ctypes.byref(s), cd, ctypes.byref(b), ctypes.byref(L))
+    if st != SBMM_OK:
+        raise SbmmError(st, "sbmm_workspace_size: invalid problem or compute dtype")
+    return b.value, L.value
+
+
 def sbmm_query_sizes(problem):
     s = problem.struct()
     out = Sizes_t()
@@ -329,6 +345,24 @@ class Handle:
         self._check(self._lib.sbmm_exact(self.h, ctypes.byref(s), _ptr(MN), s.p if store else 0,
                                          _ptr(bp), _ptr(mn_sq), _stream()))
         return MN, bp, mn_sq
+
+    def reserve(self, nbytes):
+        self._check(self._lib.sbmm_reserve(self.h, int(nbytes)))
+
+    def exact_error(self, problem, CD, store=False, blocknorm=False):
+        """The exact product with ||MN - CD||_F^2 and ||MN||_F^2 from its
+        epilogue (device float64 tensor of 2); MN and the per-block norms
+        optional."""
+        torch = _torch()
+        s = problem.struct()
+        dev = problem.M.device
+        pd = torch.float64 if problem.M.dtype == torch.float64 else torch.float32
+        MN = torch.empty((s.m, s.p), dtype=pd, device=dev) if store else None
+        bp = torch.empty(s.K, dtype=torch.float64, device=dev) if blocknorm else None
+        out = torch.empty(2, dtype=torch.float64, device=dev)
+        self._check(self._lib.sbmm_exact_error(self.h, ctypes.byref(s), _ptr(CD), CD.stride(0), dtype_code(CD.dtype),
+                                               _ptr(MN), s.p if store else 0, _ptr(bp), _ptr(out), _stream()))
+        return out, MN, bp
 
     def plan(self, problem, col_sq=None, row_sq=None, blk=None, sync=True):
         s = problem.struct()

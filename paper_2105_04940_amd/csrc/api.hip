@@ -398,6 +398,13 @@ sbmm_status sbmm_create(sbmm_handle* out, int device) {
     delete h;
     return SBMM_E_HIP;
   }
+  // room for the partition of up to 1023 blocks
+  if (hipMalloc(&h->off_dev, sizeof(int64_t) * 1024) != hipSuccess) {
+    (void)hipFree(h->status);
+    delete h;
+    return SBMM_E_NOMEM;
+  }
+  h->off_cap = 1024;
   *out = h;
   return SBMM_OK;
 }
@@ -695,11 +702,17 @@ sbmm_status sbmm_error(sbmm_handle h, int64_t m, int64_t p, sbmm_dtype dtype, co
   return SBMM_OK;
 }
 
-sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, void* C, int64_t ldc, void* D,
+}  // extern "C"
+
+namespace {
+
+// The whole forward path. With `measure` non-null nothing is launched or
+// allocated (h may then be null): *measure receives the workspace bytes the
+// call needs, from the same arena layout as the real pass.
+sbmm_status run_impl(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, void* C, int64_t ldc, void* D,
                      int64_t ldd, void* CD, int64_t ldcd, void* MN, int64_t ldmn, const sbmm_plan_out* plan,
-                     double* err_host, double* rel_host, int64_t* L_host, sbmm_stream stream) {
-  sbmm_status st = check_handle(h);
-  if (st) return st;
+                     double* err_host, double* rel_host, int64_t* L_host, sbmm_stream stream, size_t* measure) {
+  sbmm_status st = SBMM_OK;
   sbmm_sizes sz;
   if ((st = validate(h, P, &sz, true))) return st;
   if (!plan_out_ok(plan)) return fail(h, SBMM_E_ARG, "plan output buffers missing");
@@ -756,6 +769,10 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
         sub3.off = ar.off;
         do_pilot(h, P, off, col_sq, row_sq, blk, nullptr, pilot, sub3, s);
         need = std::max(need, sub3.off);
+      }
+      if (measure) {
+        *measure = need;
+        return SBMM_OK;
       }
       if ((st = ensure_ws(h, need))) return st;
       continue;
@@ -831,6 +848,10 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
   return SBMM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 sbmm_status sbmm_bound(sbmm_handle h, const sbmm_problem* P, const double* col_sq, const double* row_sq,
                        const double* blk, const double* blkprod_sq, const sbmm_plan_out* plan, double beta,
                        int32_t n_delta, const double* delta, double* out, sbmm_stream stream) {
@@ -877,6 +898,91 @@ sbmm_status sbmm_bound(sbmm_handle h, const sbmm_problem* P, const double* col_s
     HIP_TRY(h, hipMemcpyAsync(out, dout, sizeof(double) * nout, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
   }
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, void* C, int64_t ldc, void* D,
+                     int64_t ldd, void* CD, int64_t ldcd, void* MN, int64_t ldmn, const sbmm_plan_out* plan,
+                     double* err_host, double* rel_host, int64_t* L_host, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  return run_impl(h, P, compute, C, ldc, D, ldd, CD, ldcd, MN, ldmn, plan, err_host, rel_host, L_host, stream,
+                  nullptr);
+}
+
+sbmm_status sbmm_exact_error(sbmm_handle h, const sbmm_problem* P, const void* CD, int64_t ldcd,
+                             sbmm_dtype cd_dtype, void* MN, int64_t ldmn, double* blkprod_sq,
+                             double* err2_and_mn2, sbmm_stream stream) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  sbmm_sizes sz;
+  if ((st = validate(h, P, &sz, true))) return st;
+  if (!err2_and_mn2) return fail(h, SBMM_E_ARG, "err2_and_mn2 is required");
+  if (cd_dtype != product_dtype(P->in_dtype))
+    return fail(h, SBMM_E_ARG, "CD must be in the product dtype (F64 for F64 inputs, else F32)");
+  if ((P->m > 0 && P->p > 0 && !CD) || ldcd < P->p) return fail(h, SBMM_E_ARG, "CD is required with ldcd >= p");
+  if (MN && ldmn < P->p) return fail(h, SBMM_E_ARG, "ldmn < p");
+  hipStream_t s = (hipStream_t)stream;
+  Arena dry(nullptr);
+  int64_t* off = nullptr;
+  upload_offsets(h, P, dry, &off, s);
+  if ((st = do_exact(h, P, off, MN, ldmn, CD, ldcd, blkprod_sq, err2_and_mn2, dry, s))) return st;
+  if ((st = ensure_ws(h, dry.off))) return st;
+  Arena ar(h->ws);
+  if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+  return do_exact(h, P, off, MN, ldmn, CD, ldcd, blkprod_sq, err2_and_mn2, ar, s);
+}
+
+sbmm_status sbmm_workspace_size(const sbmm_problem* P, sbmm_dtype compute, size_t* bytes, int64_t* L_max) {
+  if (!bytes) return SBMM_E_ARG;
+  sbmm_sizes sz;
+  sbmm_status st = validate(nullptr, P, &sz, true);
+  if (st) return st;
+  if (!sketch_dtype_ok(P->in_dtype, compute) ||
+      (compute != SBMM_F64 && compute != SBMM_F32 && compute != SBMM_BF16))
+    return SBMM_E_ARG;
+  // placeholders: never dereferenced by a measuring pass
+  char* const ph = reinterpret_cast<char*>((uintptr_t)256);
+  sbmm_plan_out pl{};
+  pl.idx = reinterpret_cast<int32_t*>(ph); pl.scale = reinterpret_cast<double*>(ph);
+  pl.col_off = reinterpret_cast<int64_t*>(ph); pl.ck = reinterpret_cast<int64_t*>(ph);
+  pl.colmap = reinterpret_cast<int32_t*>(ph); pl.colscale = reinterpret_cast<double*>(ph);
+  size_t need = 0, x = 0;
+  // sbmm_run with C, D and MN left to the library
+  if ((st = run_impl(nullptr, P, compute, nullptr, 0, nullptr, 0, ph, P->p, nullptr, 0, &pl, nullptr, nullptr,
+                     nullptr, nullptr, &x)))
+    return st;
+  need = std::max(need, x);
+  int64_t* off = nullptr;
+  // sbmm_exact / sbmm_exact_error with per-block norms
+  if (P->in_dtype != SBMM_BF16) {
+    Arena dry(nullptr);
+    upload_offsets(nullptr, P, dry, &off, nullptr);
+    double* out2 = dry.take<double>(2);
+    if ((st = do_exact(nullptr, P, off, nullptr, 0, nullptr, 0, reinterpret_cast<double*>(ph), out2, dry, nullptr)))
+      return st;
+    need = std::max(need, dry.off);
+  }
+  // sbmm_pilot without a pilot plan of the caller's
+  if (P->mode == SBMM_MODE_STRATIFIED && P->alloc == SBMM_ALLOC_TWO_STEP) {
+    if ((st = validate_pilot(nullptr, P))) return st;
+    Arena dry(nullptr);
+    upload_offsets(nullptr, P, dry, &off, nullptr);
+    do_pilot(nullptr, P, off, nullptr, nullptr, nullptr, nullptr, reinterpret_cast<double*>(ph), dry, nullptr);
+    need = std::max(need, dry.off);
+  }
+  // sbmm_bound with eight deltas
+  if (P->mode == SBMM_MODE_STRATIFIED) {
+    int64_t chunks = 0;
+    for (int32_t k = 0; k < P->K; ++k) chunks += bound_chunks(P->block_off[k + 1] - P->block_off[k]);
+    Arena dry(nullptr);
+    dry.take<int64_t>(P->K + 1);
+    dry.take<double>(2 * (size_t)chunks);
+    dry.take<double>(SBMM_BOUND_FIXED + 2 * SBMM_BOUND_MAX_DELTA);
+    need = std::max(need, dry.off);
+  }
+  *bytes = need;
+  if (L_max) *L_max = sz.L_max;
   return SBMM_OK;
 }
 

@@ -131,6 +131,67 @@ def test_partition_changes_between_calls(h):
         assert rel(host64(blk)[:K], st.m_sq) < 1e-13, off
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_exact_error(h, dtype):
+    # the exact product with the judge of a given CD in its epilogue, MN and
+    # the per-block norms beside it, against the oracle and the run's error
+    M, N, off = wl.random_problem(130, 3000, 70, 30, seed=41, skew=0.8)
+    prob = pk.Problem(to_dev(M, dtype), to_dev(N, dtype), off, 100, prob="norm", seed=1)
+    r = h.run(prob)
+    out, MN, bp = h.exact_error(prob, r["CD"], store=True, blocknorm=True)
+    torch.cuda.synchronize()
+    Mh, Nh = host64(prob.M), host64(prob.N)
+    MNo = om.exact_product(Mh, Nh)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    e2 = float(np.sum((host64(r["CD"]) - MNo) ** 2))
+    assert abs(out[0].item() - e2) <= tol * e2
+    assert abs(out[1].item() - float(np.sum(MNo ** 2))) <= tol * float(np.sum(MNo ** 2))
+    # the run's own judge: the same sums in float64; with float32 products the
+    # block-norm form of the product accumulates MN in another order
+    assert abs(math.sqrt(out[0].item()) - r["err"]) <= tol * r["err"]
+    assert rel(host64(MN), MNo) < tol
+    assert rel(host64(bp), om.block_product_sq(Mh, Nh, off)) < tol
+    with pytest.raises(pk.SbmmError):   # CD in another dtype than the product's
+        h.exact_error(prob, r["CD"].to(torch.float32 if dtype == torch.float64 else torch.float64))
+
+
+def test_reserved_workspace_needs_no_allocation():
+    # after sbmm_reserve(sbmm_workspace_size(...)) the problem's calls on a
+    # fresh handle allocate no device memory (torch's outputs are served from
+    # its cache, warmed by the same calls on another handle)
+    M, N, off = wl.random_problem(96, 20000, 80, 10, seed=43, skew=1.0)
+    Md, Nd = to_dev(M, torch.float64), to_dev(N, torch.float64)
+
+    def calls(hd):
+        prob = pk.Problem(Md, Nd, off, 3000, mode="stratified", prob="norm", alloc="two_step", c0=500,
+                          pilot="norm", seed=3)
+        col, row, blk = hd.norms(prob)
+        _, bp, _ = hd.exact(prob, store=False, blocknorm=True)
+        prob.pilot_sq = hd.pilot(prob, col, row, blk)
+        pl = hd.plan(prob, col, row, blk)
+        g = hd.bound(prob, col, row, blk, bp, pl, deltas=(0.1,))
+        r = hd.run(prob)
+        out, _, _ = hd.exact_error(prob, r["CD"], blocknorm=True)
+        torch.cuda.synchronize()
+        return r["err"], g["bound"][0], out[0].item()
+
+    h0 = pk.Handle(0)
+    ref = calls(h0)
+    calls(h0)
+    h0.close()
+    prob = pk.Problem(Md, Nd, off, 3000, mode="stratified", prob="norm", alloc="two_step", c0=500, pilot="norm")
+    nbytes, _ = pk.sbmm_workspace_size(prob)
+    h1 = pk.Handle(0)
+    h1.reserve(nbytes)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    got = calls(h1)
+    free1 = torch.cuda.mem_get_info()[0]
+    h1.close()
+    assert got == ref
+    assert free1 == free0
+
+
 def test_norms_bitwise_reproducible(h):
     M, N, off = wl.random_problem(200, 4000, 150, 40, seed=9)
     prob = pk.Problem(to_dev(M, torch.float32), to_dev(N, torch.float32), off, c=4)
