@@ -570,6 +570,226 @@ __global__ __launch_bounds__(kThreads, WG_PER_CU) void sgemm_kernel(GemmArgs g) 
 }
 
 // ============================================================================
+// Float32 products on 256 x 256 tiles with LDS-direct loads: one workgroup of
+// eight waves per CU (two per SIMD), each wave a 128 x 64 part of the tile as
+// 4 x 2 blocks of v_mfma_f32_32x32x2_f32 (128 accumulators). A (m x K) rows
+// are streamed into LDS as 16-byte chunks of 4 consecutive k, XOR-swizzled per
+// row; B (K x p, row-major) rows are streamed as they are (rows padded by 8
+// floats so the two half-waves of a column read hit different banks). A step
+// covers 32 k: a lane reads one chunk of its A row (4 k) and the matching 4
+// rows of its B columns, and feeds 4 MFMAs whose k are the chunk's 4 entries
+// in the lane's half-wave (half h takes k = 8u + 4h + q in MFMA q of
+// super-step u): every k of the step meets its partner exactly once. Two
+// stages in LDS, the next step's loads in flight while the current one
+// computes.
+//
+// The output is accounted for in the 128 x 128 tiling of the other float32
+// kernels: the two waves of a 128 x 128 quarter share its staging slot (the
+// fold every 4096 k, one half each) and its error partials (combined in LDS,
+// written once), so callers size and reduce both as before.
+// ============================================================================
+
+struct SgemmLdsTile {
+  static constexpr int BM = 256, BN = 256, BK = 32, KC = 8, STAGES = 2;
+  static constexpr int SBN = BN + 8;           // padded B row (floats)
+  static constexpr int FOLD_STEPS = 4096 / BK;
+  uint4 As[STAGES][BM * KC];
+  float Bs[STAGES][BK][SBN];
+  double red[2][8];
+};
+
+// waves per workgroup of the kernel below: two per SIMD, 128 x 64 each (one
+// per SIMD with 128 x 128 each spills its registers)
+constexpr int kLdsWaves = 8;
+
+__device__ __forceinline__ int lds_a_slot(int row, int chunk) { return row * 8 + (chunk ^ ((row >> 1) & 7)); }
+
+// Buffer resource over `bytes` bytes from `base` (fields made wave-uniform).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t f32_rsrc(const float* base, int64_t bytes) {
+  const uint64_t u = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  const int nb = __builtin_amdgcn_readfirstlane((int)(bytes > 0 ? bytes : 0));
+  void* p = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, nb, 0x00020000);
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
+  using T = SgemmLdsTile;
+  constexpr int KC = T::KC, BK = T::BK;
+  constexpr int CB = 16 / NW;                    // 32-column blocks per wave (2 or 4)
+  constexpr int AINSTS = T::BM * KC / 64 / NW;   // A: instructions per wave per stage (4)
+  constexpr int BINSTS = BK / NW;                // B: rows per wave per stage (4)
+  __shared__ T sh;
+  int64_t tm, tn;
+  tile_coords(g, tm, tn);
+  const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
+  const int64_t K = inner_extent(g);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 31, lh = lane >> 5;
+  const int qm = wave & 1, qn = wave >> 1;       // 128-row half, column part of 32 CB
+  const int wm0 = qm * 128, wn0 = qn * 32 * CB;
+  const float* A = reinterpret_cast<const float*>(g.A) + m0 * g.lda;
+  const float* B = reinterpret_cast<const float*>(g.B);
+  const int64_t arows = min((int64_t)T::BM, g.m - m0);
+  const __amdgpu_buffer_rsrc_t ra = f32_rsrc(A, arows * g.lda * 4);
+  constexpr unsigned kOut = 0x80000000u;   // past any record count
+
+  f32x16 acc[4][CB];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[b][c] = f32x16{};
+
+  auto issue = [&](int64_t kt, int buf) {
+    const int64_t k0 = kt * BK;
+    const unsigned sk = (unsigned)(k0 * 4);
+#pragma unroll
+    for (int j = 0; j < AINSTS; ++j) {
+      const int row = (AINSTS * wave + j) * (64 / KC) + lane / KC;
+      const int chunk = (lane % KC) ^ ((row >> 1) & 7);
+      const bool live = k0 + 4 * chunk < K;
+      const unsigned oa = live ? (unsigned)(row * g.lda * 4 + chunk * 16) : kOut;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(AINSTS * wave + j) * 64], 16, oa, sk, 0, 0);
+    }
+    // B: rows k0 .. k0 + 31 of columns n0 .. n0 + 255; a row past K, or a
+    // chunk past p in the last row, lies past the record count and reads 0
+    const int64_t brows = min((int64_t)BK, K - k0);
+    const int64_t bbytes = brows > 0 ? ((brows - 1) * g.ldb + (g.p - n0)) * 4 : 0;
+    const __amdgpu_buffer_rsrc_t rb = f32_rsrc(B + k0 * g.ldb + n0, bbytes);
+#pragma unroll
+    for (int j = 0; j < BINSTS; ++j) {
+      const int r = BINSTS * wave + j;
+      const unsigned ob = (unsigned)(r * g.ldb * 4 + lane * 16);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (__attribute__((address_space(3))) void*)&sh.Bs[buf][r][0], 16,
+                                               ob, 0, 0, 0);
+    }
+  };
+  // the fragments of super-step u + 1 are read from LDS while the MFMAs of
+  // super-step u run (two register sets)
+  auto compute = [&](int buf) {
+    f32x4 av[2][4];
+    float bv[2][CB][4];
+    auto frag = [&](int u, int r) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        av[r][b] = __builtin_bit_cast(f32x4, sh.As[buf][lds_a_slot(wm0 + 32 * b + lr, 2 * u + lh)]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) bv[r][c][q] = sh.Bs[buf][8 * u + 4 * lh + q][wn0 + 32 * c + lr];
+    };
+    frag(0, 0);
+#pragma unroll
+    for (int u = 0; u < BK / 8; ++u) {
+      if (u + 1 < BK / 8) frag(u + 1, (u + 1) & 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int c = 0; c < CB; ++c)
+            acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u & 1][b][q], bv[u & 1][c][q], acc[b][c], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+  // the 128 x 128 tile of the 128 x 128 tiling this wave's part lies in
+  // (staging slot and error partials), if it lies inside the output
+  const int64_t tn128 = (g.p + 127) / 128, tiles128 = ((g.m + 127) / 128) * tn128;
+  constexpr int PER = 4 / CB;                    // waves sharing a 128 x 128 tile (2 or 1)
+  const int64_t srow = 2 * tm + qm, scol = 2 * tn + qn / PER;
+  const bool inside = srow * 128 < g.m && scol * 128 < g.p;
+  const int64_t slot = inside ? srow * tn128 + scol : 0;
+  // this wave's half of the slot, [accumulator][lane], through a buffer
+  // resource so that each accumulator's offset is a scalar (no per-lane
+  // address registers); a wave outside the output gets no records
+  const __amdgpu_buffer_rsrc_t rs = f32_rsrc(g.stage + slot * (128 * 128) + (qn % PER) * (128 * 32 * CB),
+                                             inside ? 128 * 32 * CB * 4 : 0);
+  const int vo = lane * 4;
+  int folds = 0;
+  auto fold = [&]() {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int so = ((b * CB + c) * 16 + v) * 256;
+          float x = acc[b][c][v];
+          if (folds) x += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, vo, so, 0);
+        }
+        acc[b][c] = f32x16{};
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    ++folds;
+  };
+
+  const int64_t nkt = (K + BK - 1) / BK;
+  if (nkt > 0) issue(0, 0);
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (kt + 1 < nkt) issue(kt + 1, (int)((kt + 1) & 1));
+    compute((int)(kt & 1));
+    if ((kt + 1) % T::FOLD_STEPS == 0 && kt + 1 < nkt) fold();
+  }
+
+  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
+      if (row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int64_t col = n0 + wn0 + 32 * c + lr;
+        if (col >= g.p) continue;
+        float val = acc[b][c][v];
+        if (folds) val += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, ((b * CB + c) * 16 + v) * 256, 0));
+        if (Cout) Cout[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (Y) {
+          const double d = dv - (double)Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  if (g.tile_part) {
+    // the two waves of a 128 x 128 tile (qn = 2s, 2s + 1): the first adds
+    // the second's sums after its own, in that order
+    e2 = warp_sum_f64(e2);
+    n2 = warp_sum_f64(n2);
+    if constexpr (PER == 1) {
+      if (inside && lane == 0) {
+        g.tile_part[slot] = e2;
+        g.tile_part[tiles128 + slot] = n2;
+      }
+    } else {
+      if (lane == 0) {
+        sh.red[0][wave] = e2;
+        sh.red[1][wave] = n2;
+      }
+      __syncthreads();
+      if (inside && lane == 0 && (qn & 1) == 0) {
+        g.tile_part[slot] = sh.red[0][wave] + sh.red[0][wave + 2];
+        g.tile_part[tiles128 + slot] = sh.red[1][wave] + sh.red[1][wave + 2];
+      }
+    }
+  }
+}
+
+// ============================================================================
 // Many independent float32 products in one launch. The host lists the work
 // items (problem, tile) in the order they should start (longest inner extent
 // first) and workgroup i takes item i; the hardware dispatches workgroups in
@@ -894,6 +1114,20 @@ void tile_shape(sbmm_dtype dt, bool blocknorm, int64_t* bm, int64_t* bn) {
 
 }  // namespace
 
+namespace {
+// The LDS-direct float32 kernel needs 16-byte rows and chunks (A and B
+// aligned with leading dimensions of whole chunks, p and a host inner extent
+// multiples of 4 floats; a device extent is padded to 32) and 32-bit panel
+// offsets.
+bool sgemm_lds_ok(const GemmLaunch& L, const GemmArgs& g) {
+  if (!g.vec_a || !g.vec_b || L.p % 4 != 0 || L.stage == nullptr) return false;
+  if (L.K_dev == nullptr && L.K_host % 4 != 0) return false;
+  const int64_t kmax = L.K_dev ? L.lda : L.K_host;
+  const int64_t lim = (int64_t)1 << 31;
+  return 257 * L.lda * 4 + kmax * 4 < lim && 33 * L.ldb * 4 < lim;
+}
+}  // namespace
+
 int64_t gemm_tiles(sbmm_dtype dt, int64_t m, int64_t p, bool blocknorm) {
   int64_t bm, bn;
   tile_shape(dt, blocknorm, &bm, &bn);
@@ -916,8 +1150,16 @@ hipError_t launch_gemm(const GemmLaunch& L, hipStream_t s) {
     if (blocknorm) hipLaunchKernelGGL((gemm_f64_kernel<F64_WMB, F64_WNB, true>), grid, block, 0, s, g);
     else hipLaunchKernelGGL((gemm_f64_kernel<F64_WMB, F64_WNB, false>), grid, block, 0, s, g);
   } else if (L.dt == SBMM_F32) {
-    if (blocknorm) hipLaunchKernelGGL((gemm_f32_kernel<F32B_WMB, F32B_WNB, true>), grid, block, 0, s, g);
-    else hipLaunchKernelGGL((sgemm_kernel<F32_WMB, F32_WNB, F32_BK, F32_WGS>), grid, block, 0, s, g);
+    if (blocknorm) {
+      hipLaunchKernelGGL((gemm_f32_kernel<F32B_WMB, F32B_WNB, true>), grid, block, 0, s, g);
+    } else if (sgemm_lds_ok(L, g)) {
+      // 256 x 256 tiles over the same 128 x 128 accounting
+      const GemmArgs g2 = make_gemm_args(L, SgemmLdsTile::BM, SgemmLdsTile::BN);
+      hipLaunchKernelGGL(sgemm_lds_kernel<kLdsWaves>, dim3((unsigned)(g2.tiles_m * g2.tiles_n)), dim3(kLdsWaves * 64), 0,
+                         s, g2);
+    } else {
+      hipLaunchKernelGGL((sgemm_kernel<F32_WMB, F32_WNB, F32_BK, F32_WGS>), grid, block, 0, s, g);
+    }
   } else {
     return hipErrorInvalidValue;
   }

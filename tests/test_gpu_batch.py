@@ -113,19 +113,26 @@ def _split_k(m, p, extent):
     return m <= 128 and p <= 128 and extent >= 2048
 
 
-def _same_product(x, y, split_k):
+def _wide_tiles(p, extent):
+    # the single-problem path takes its 256 x 256 LDS-direct product when the
+    # rows of B and the inner extent are whole 16-byte chunks (the batch keeps
+    # 128 x 128 tiles, so there the two sum in different orders)
+    return p % 4 == 0 and extent % 4 == 0
+
+
+def _same_product(x, y, other_order):
     # different summation orders of float32 products over thousands of terms
     # differ by a few units of sqrt(K) u; both are held to the float32 bar
     # (1e-5 relative) against the oracle elsewhere, so that bar applies here
-    if not split_k:
+    if not other_order:
         return torch.equal(x, y)
     return ((x.double() - y.double()).norm() / y.double().norm()).item() < 1e-5
 
 
 def test_batch_equals_single_problem_path(h, small_batch):
     # each problem of the batch (norms, plan, fused-gather product) gives the
-    # same bits as the single-problem path (gather to C, D, then the product)
-    # wherever both run the same tiled product
+    # same draws as the single-problem path (gather to C, D, then the
+    # product), and the same bits wherever both run the same tiled product
     b, probs, host = small_batch
     b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
     b.run()
@@ -139,8 +146,9 @@ def test_batch_equals_single_problem_path(h, small_batch):
         p = pr["N"].shape[1]
         assert torch.equal(r["plan"].idx, b.draws(t)), t
         assert r["L"] == int(b.L[t].item()), t
-        assert _same_product(r["CD"], b.CD[t], _split_k(m, p, pk.sbmm_query_sizes(prob)["L_pad_max"])), t
-        assert _same_product(r["MN"], b.MN[t], _split_k(m, p, n)), t
+        lp = pk.sbmm_query_sizes(prob)["L_pad_max"]
+        assert _same_product(r["CD"], b.CD[t], _split_k(m, p, lp) or _wide_tiles(p, 32)), t
+        assert _same_product(r["MN"], b.MN[t], _split_k(m, p, n) or _wide_tiles(p, n)), t
 
 
 def _snapshot(b):
