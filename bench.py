@@ -125,7 +125,7 @@ def pmc_summary(fetch_csv, write_csv, command):
         groups = {"sketch_gemm": [], "exact_gemm": []}
         prev = ""
         for _, name, grid, v in rs:
-            if "sgemm_kernel" in name:
+            if _is_f32_product(name):
                 groups["exact_gemm" if "block_gram" in prev else "sketch_gemm"].append(v * factor)
             if "copyBuffer" not in name:
                 prev = name
@@ -146,6 +146,12 @@ def pmc_summary(fetch_csv, write_csv, command):
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def _is_f32_product(name):
+    """The single-problem float32 product kernels (128 x 128 and 256 x 256
+    tiles), not the grouped ones of the batched path."""
+    return "sgemm_kernel" in name or "sgemm_lds_kernel" in name
 
 
 def _short(name):
@@ -173,7 +179,7 @@ def trace_summary(trace_csv, command):
         name = _short(r["Kernel_Name"])
         us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
         key = name
-        if "sgemm_kernel" in name:
+        if _is_f32_product(name):
             key = name + (" — exact MN" if "block_gram" in prev else " — sketched CD")
         stats.setdefault(key, []).append(us)
         if "copyBuffer" not in name:
@@ -671,7 +677,7 @@ def main():
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1],
                     "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o run -- "
                     "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-linear-layer --no-batched "
-                    "--calibration-copy")
+                    "--no-section4 --calibration-copy")
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the path "
