@@ -392,7 +392,7 @@ struct TnLdsTile {
   static constexpr int BM = 256, BN = 256, BK = BK_, KC = BK / 8, STAGES = STAGES_;
   uint4 As[STAGES][BM * KC];
   uint4 Bs[STAGES][BN * KC];
-  double red[8];
+  double red[16];
 };
 
 // LDS slot of 16-byte chunk `chunk` of tile row `row`: a row holds KC chunks
@@ -416,12 +416,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const uint16_t* bas
   return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
 }
 
-template <int BK, int STAGES>
-__global__ __launch_bounds__(kThreads, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
+// NW waves per workgroup: 4 (one per SIMD, 128 x 128 each) or 8 (two per
+// SIMD, 128 x 64 each)
+template <int BK, int STAGES, int NW>
+__global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   using Tile = TnLdsTile<BK, STAGES>;
   constexpr int KC = Tile::KC;
-  constexpr int ROWS_PER_INST = 64 / KC;              // tile rows one wave instruction fills
-  constexpr int INSTS = Tile::BM / ROWS_PER_INST / 4; // instructions per wave per operand and stage
+  constexpr int CB = 16 / NW;                          // 32-column blocks per wave
+  constexpr int ROWS_PER_INST = 64 / KC;               // tile rows one wave instruction fills
+  constexpr int INSTS = Tile::BM / ROWS_PER_INST / NW; // instructions per wave per operand and stage
   __shared__ Tile sh;
   int64_t tm, tn;
   tile_coords(g, tm, tn);
@@ -431,18 +434,18 @@ __global__ __launch_bounds__(kThreads, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   // uniform across the wave: the LDS destination of a load is a scalar
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 31, lh = lane >> 5;
-  const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 128;
+  const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 32 * CB;
   const uint16_t* A = reinterpret_cast<const uint16_t*>(g.A) + m0 * g.lda;
   const uint16_t* B = reinterpret_cast<const uint16_t*>(g.B) + n0 * g.ldb;
   const __amdgpu_buffer_rsrc_t ra = panel_rsrc(A, min((int64_t)Tile::BM, g.m - m0), g.lda);
   const __amdgpu_buffer_rsrc_t rb = panel_rsrc(B, min((int64_t)Tile::BN, g.p - n0), g.ldb);
   constexpr unsigned kOut = 0x80000000u;   // past any record count
 
-  f32x16 acc[4][4];
+  f32x16 acc[4][CB];
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[b][c] = f32x16{};
+    for (int c = 0; c < CB; ++c) acc[b][c] = f32x16{};
 
   // instruction j of wave w fills slots [(INSTS w + j) 64, +64): lane l holds
   // slot P = (INSTS w + j) 64 + l, i.e. tile row P / KC and the chunk whose
@@ -467,17 +470,17 @@ __global__ __launch_bounds__(kThreads, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   auto compute = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < BK / 16; ++s) {
-      bf16x8 av[4], bv[4];
+      bf16x8 av[4], bv[CB];
 #pragma unroll
       for (int b = 0; b < 4; ++b)
         av[b] = __builtin_bit_cast(bf16x8, sh.As[buf][tn_lds_slot<KC>(wm0 + 32 * b + lr, 2 * s + lh)]);
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < CB; ++c)
         bv[c] = __builtin_bit_cast(bf16x8, sh.Bs[buf][tn_lds_slot<KC>(wn0 + 32 * c + lr, 2 * s + lh)]);
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < CB; ++c)
           acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[b], bv[c], acc[b][c], 0, 0, 0);
     }
   };
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(kThreads, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
       if (row >= g.m) continue;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < CB; ++c) {
         const int64_t col = n0 + wn0 + 32 * c + lr;
         if (col >= g.p) continue;
         const float val = acc[b][c][v];
@@ -528,10 +531,28 @@ __global__ __launch_bounds__(kThreads, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       }
       if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
-  if (g.tile_part) write_tile_partials(g, e2, n2, sh.red);
+  if (g.tile_part) {
+    // NW waves' sums added in wave order
+    e2 = warp_sum_f64(e2);
+    n2 = warp_sum_f64(n2);
+    if (lane == 0) {
+      sh.red[wave] = e2;
+      sh.red[NW + wave] = n2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        a += sh.red[w];
+        b += sh.red[NW + w];
+      }
+      g.tile_part[blockIdx.x] = a;
+      g.tile_part[g.tiles_m * g.tiles_n + blockIdx.x] = b;
+    }
+  }
 }
 
-constexpr int TN_BK = 64, TN_STAGES = 2;
+constexpr int TN_BK = 64, TN_STAGES = 2, TN_WAVES = 8;
 
 constexpr int BF16_WMB = 2, BF16_WNB = 2, BF16_BK = 64, BF16_WGS = 2;   // 128 x 128
 
@@ -557,7 +578,8 @@ hipError_t launch_hgemm(const GemmLaunch& L, hipStream_t s) {
     const bool fits = 257 * ld * 2 < ((int64_t)1 << 31);
     const bool chunks = L.K_dev != nullptr || L.K_host % 8 == 0;
     if (g.vec_a && g.vec_b && fits && chunks)
-      hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES>), dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
+      hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES, TN_WAVES>), dim3((unsigned)tiles), dim3(TN_WAVES * 64),
+                         0, s, g);
     else
       hipLaunchKernelGGL(hgemm_tn_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
     return hipGetLastError();
