@@ -146,7 +146,7 @@ struct MxTile {
   static constexpr int NL = BM * KC / kThreads;
   uint4 As[2][BM * KC];
   uint4 Bs[2][BN * KC];
-  double red[8];
+  double red[16];
 };
 
 __device__ __forceinline__ int mx_slot(int row, int chunk) { return row * MxTile::KC + (chunk ^ (row & 7)); }
@@ -326,9 +326,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t mx_panel_rsrc(const uint8_t* b
   return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
 }
 
-__global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
+// eight waves (two per SIMD), each 128 x 64 of the tile
+constexpr int kMxWaves = 8;
+
+__global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g) {
   __shared__ MxTile sh;
-  constexpr int BK = MxTile::BK;
+  constexpr int BK = MxTile::BK, NW = kMxWaves, CB = 16 / NW;
+  constexpr int INSTS = MxTile::BM / 8 / NW;   // load instructions per wave per operand and step
   int64_t tm, tn;
   mx_tile_coords(g, tm, tn);
   const int64_t m0 = tm * MxTile::BM, n0 = tn * MxTile::BN;
@@ -336,50 +340,57 @@ __global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 31, lh = lane >> 5;
-  const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 128;
+  const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 32 * CB;
   const __amdgpu_buffer_rsrc_t ra = mx_panel_rsrc(g.A + m0 * g.lda, min((int64_t)MxTile::BM, g.m - m0), g.lda);
   const __amdgpu_buffer_rsrc_t rb = mx_panel_rsrc(g.B + n0 * g.ldb, min((int64_t)MxTile::BN, g.p - n0), g.ldb);
   constexpr unsigned kOut = 0x80000000u;
 
-  f32x16 acc[4][4];
+  f32x16 acc[4][CB];
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[b][c] = f32x16{};
+    for (int c = 0; c < CB; ++c) acc[b][c] = f32x16{};
 
   auto issue = [&](int64_t kt, int buf) {
     const int64_t k0 = kt * BK;
     const unsigned sk = (unsigned)k0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int row = (8 * wave + j) * 8 + (lane >> 3);
+    for (int j = 0; j < INSTS; ++j) {
+      const int row = (INSTS * wave + j) * 8 + (lane >> 3);
       const int chunk = (lane & 7) ^ ((row >> 1) & 7);
       const bool live = k0 + 16 * chunk < K;
       const unsigned oa = live ? (unsigned)(row * g.lda + chunk * 16) : kOut;
       const unsigned ob = live ? (unsigned)(row * g.ldb + chunk * 16) : kOut;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(8 * wave + j) * 64], 16, oa, sk, 0, 0);
+          ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(INSTS * wave + j) * 64], 16, oa, sk, 0, 0);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rb, (__attribute__((address_space(3))) void*)&sh.Bs[buf][(8 * wave + j) * 64], 16, ob, sk, 0, 0);
+          rb, (__attribute__((address_space(3))) void*)&sh.Bs[buf][(INSTS * wave + j) * 64], 16, ob, sk, 0, 0);
     }
   };
   // the four E8M0 scales of a k-step for this lane's rows / columns (one
   // 32-bit word per 32 x 32 block; 127 = 1 outside the matrix)
-  auto scale_word = [&](const uint8_t* S, int64_t lds, int64_t r, int64_t rmax, int64_t kt) -> uint32_t {
-    if (r >= rmax) return 0x7f7f7f7fu;
-    return *reinterpret_cast<const uint32_t*>(S + r * lds + 4 * kt);
-  };
-  uint32_t sa[4], sb[4];
+  // through buffer resources over the scale arrays, so that a lane keeps one
+  // 32-bit offset per row and the step is a scalar offset; rows past the
+  // matrix read 0 (scale 2^-127 on zero codes)
+  const __amdgpu_buffer_rsrc_t rsa = mx_panel_rsrc(g.As, g.m, g.ldas);
+  const __amdgpu_buffer_rsrc_t rsb = mx_panel_rsrc(g.Bs, g.p, g.ldbs);
+  int voa[4], vob[CB];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) voa[b] = (int)((m0 + wm0 + 32 * b + lr) * g.ldas);
+#pragma unroll
+  for (int c = 0; c < CB; ++c) vob[c] = (int)((n0 + wn0 + 32 * c + lr) * g.ldbs);
+  uint32_t sa[4], sb[CB];
   auto load_scales = [&](int64_t kt, uint32_t* xa, uint32_t* xb) {
+    const int so = (int)(4 * kt);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) xa[b] = scale_word(g.As, g.ldas, m0 + wm0 + 32 * b + lr, g.m, kt);
+    for (int b = 0; b < 4; ++b) xa[b] = __builtin_amdgcn_raw_buffer_load_b32(rsa, voa[b], so, 0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) xb[c] = scale_word(g.Bs, g.ldbs, n0 + wn0 + 32 * c + lr, g.p, kt);
+    for (int c = 0; c < CB; ++c) xb[c] = __builtin_amdgcn_raw_buffer_load_b32(rsb, vob[c], so, 0);
   };
   auto compute = [&](int buf) {
-#pragma unroll
+#pragma unroll 1
     for (int s = 0; s < BK / 64; ++s) {
-      i32x8 av[4], bv[4];
+      i32x8 av[4], bv[CB];
       const int c0 = 4 * s + lh;   // this lane's 16-byte chunks: c0 and c0 + 2
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
@@ -388,7 +399,7 @@ __global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
         av[b] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w, (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
       }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < CB; ++c) {
         const int row = wn0 + 32 * c + lr;
         const uint4 u0 = sh.Bs[buf][mx_lds_slot(row, c0)], u1 = sh.Bs[buf][mx_lds_slot(row, c0 + 2)];
         bv[c] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w, (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
@@ -397,7 +408,7 @@ __global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < CB; ++c)
           acc[b][c] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
               av[b], bv[c], acc[b][c], 0, 0, 0, (int)((sa[b] >> sh_bits) & 0xffu), 0,
               (int)((sb[c] >> sh_bits) & 0xffu));
@@ -413,7 +424,7 @@ __global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
   __syncthreads();
   for (int64_t kt = 0; kt < nkt; ++kt) {
     const int cur = (int)(kt & 1);
-    uint32_t na[4], nb[4];
+    uint32_t na[4], nb[CB];
     if (kt + 1 < nkt) {
       load_scales(kt + 1, na, nb);
       issue(kt + 1, cur ^ 1);
@@ -423,7 +434,9 @@ __global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
     __syncthreads();
     if (kt + 1 < nkt) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) { sa[i] = na[i]; sb[i] = nb[i]; }
+      for (int i = 0; i < 4; ++i) sa[i] = na[i];
+#pragma unroll
+      for (int i = 0; i < CB; ++i) sb[i] = nb[i];
     }
   }
 
@@ -435,7 +448,7 @@ __global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
       const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
       if (row >= g.m) continue;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < CB; ++c) {
         const int64_t col = n0 + wn0 + 32 * c + lr;
         if (col >= g.p) continue;
         const float val = acc[b][c][v];
@@ -452,12 +465,17 @@ __global__ __launch_bounds__(kThreads, 1) void mx_gemm_lds_kernel(MxArgs g) {
   if (g.tile_part) {
     e2 = warp_sum_f64(e2);
     n2 = warp_sum_f64(n2);
-    if (lane == 0) { sh.red[wave] = e2; sh.red[4 + wave] = n2; }
+    if (lane == 0) { sh.red[wave] = e2; sh.red[NW + wave] = n2; }
     __syncthreads();
     if (threadIdx.x == 0) {
       const int64_t tiles = g.tiles_m * g.tiles_n;
-      g.tile_part[blockIdx.x] = ((sh.red[0] + sh.red[1]) + sh.red[2]) + sh.red[3];
-      g.tile_part[tiles + blockIdx.x] = ((sh.red[4] + sh.red[5]) + sh.red[6]) + sh.red[7];
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        a += sh.red[w];
+        b += sh.red[NW + w];
+      }
+      g.tile_part[blockIdx.x] = a;
+      g.tile_part[tiles + blockIdx.x] = b;
     }
   }
 }
@@ -499,7 +517,7 @@ hipError_t launch_mx_gemm(const MxGemmLaunch& L, hipStream_t s) {
   // already requires 16-byte aligned codes and leading dimensions)
   const int64_t ld = std::max(L.lda, L.ldb);
   if (257 * ld < ((int64_t)1 << 31))
-    hipLaunchKernelGGL(mx_gemm_lds_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
+    hipLaunchKernelGGL(mx_gemm_lds_kernel, dim3((unsigned)tiles), dim3(kMxWaves * 64), 0, s, g);
   else
     hipLaunchKernelGGL(mx_gemm_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
   return hipGetLastError();
