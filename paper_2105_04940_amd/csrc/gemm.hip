@@ -633,8 +633,12 @@ __global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
   const int wm0 = qm * 128, wn0 = qn * 32 * CB;
   const float* A = reinterpret_cast<const float*>(g.A) + m0 * g.lda;
   const float* B = reinterpret_cast<const float*>(g.B);
+  // A records end at the last row's K-th entry: the range check is per
+  // dword (and counts the scalar offset), so a chunk straddling K in the
+  // last row reads zeros past K; in the other rows it reads the row's next
+  // entries, which the last step clears in LDS (below)
   const int64_t arows = min((int64_t)T::BM, g.m - m0);
-  const __amdgpu_buffer_rsrc_t ra = f32_rsrc(A, arows * g.lda * 4);
+  const __amdgpu_buffer_rsrc_t ra = f32_rsrc(A, arows > 0 ? ((arows - 1) * g.lda + K) * 4 : 0);
   constexpr unsigned kOut = 0x80000000u;   // past any record count
 
   f32x16 acc[4][CB];
@@ -655,8 +659,10 @@ __global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(AINSTS * wave + j) * 64], 16, oa, sk, 0, 0);
     }
-    // B: rows k0 .. k0 + 31 of columns n0 .. n0 + 255; a row past K, or a
-    // chunk past p in the last row, lies past the record count and reads 0
+    // B: rows k0 .. k0 + 31 of columns n0 .. n0 + 255; a row past K, or an
+    // entry past p in the stage's last row, lies past the record count and
+    // reads 0 (the check is per dword); entries past p in the other rows
+    // only feed output columns that are not stored
     const int64_t brows = min((int64_t)BK, K - k0);
     const int64_t bbytes = brows > 0 ? ((brows - 1) * g.ldb + (g.p - n0)) * 4 : 0;
     const __amdgpu_buffer_rsrc_t rb = f32_rsrc(B + k0 * g.ldb + n0, bbytes);
@@ -735,7 +741,18 @@ __global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
   for (int64_t kt = 0; kt < nkt; ++kt) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (kt + 1 < nkt) issue(kt + 1, (int)((kt + 1) & 1));
+    if (kt + 1 < nkt) {
+      issue(kt + 1, (int)((kt + 1) & 1));
+    } else if (K & 3) {
+      // the inner extent ends inside a chunk: clear the A entries past K
+      // of that chunk in every row (B rows past K already read zero)
+      const int kz = (int)(K - kt * BK), cs = kz >> 2, e0 = kz & 3;
+      if (tid < T::BM) {
+        float* q = reinterpret_cast<float*>(&sh.As[kt & 1][lds_a_slot(tid, cs)]);
+        for (int e = e0; e < 4; ++e) q[e] = 0.0f;
+      }
+      __syncthreads();
+    }
     compute((int)(kt & 1));
     if ((kt + 1) % T::FOLD_STEPS == 0 && kt + 1 < nkt) fold();
   }
@@ -1115,13 +1132,11 @@ void tile_shape(sbmm_dtype dt, bool blocknorm, int64_t* bm, int64_t* bn) {
 }  // namespace
 
 namespace {
-// The LDS-direct float32 kernel needs 16-byte rows and chunks (A and B
-// aligned with leading dimensions of whole chunks, p and a host inner extent
-// multiples of 4 floats; a device extent is padded to 32) and 32-bit panel
-// offsets.
+// The LDS-direct float32 kernel needs 16-byte aligned rows (A and B aligned
+// with leading dimensions of whole 16-byte chunks; any p and inner extent)
+// and 32-bit panel offsets.
 bool sgemm_lds_ok(const GemmLaunch& L, const GemmArgs& g) {
-  if (!g.vec_a || !g.vec_b || L.p % 4 != 0 || L.stage == nullptr) return false;
-  if (L.K_dev == nullptr && L.K_host % 4 != 0) return false;
+  if (!g.vec_a || !g.vec_b || L.stage == nullptr) return false;
   const int64_t kmax = L.K_dev ? L.lda : L.K_host;
   const int64_t lim = (int64_t)1 << 31;
   return 257 * L.lda * 4 + kmax * 4 < lim && 33 * L.ldb * 4 < lim;

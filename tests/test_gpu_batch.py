@@ -113,11 +113,12 @@ def _split_k(m, p, extent):
     return m <= 128 and p <= 128 and extent >= 2048
 
 
-def _wide_tiles(p, extent):
+def _wide_tiles(lda, ldb):
     # the single-problem path takes its 256 x 256 LDS-direct product when the
-    # rows of B and the inner extent are whole 16-byte chunks (the batch keeps
-    # 128 x 128 tiles, so there the two sum in different orders)
-    return p % 4 == 0 and extent % 4 == 0
+    # rows of both operands start on 16-byte boundaries (leading dimensions of
+    # whole 4-float chunks); the batch keeps 128 x 128 tiles, so there the two
+    # sum in different orders
+    return lda % 4 == 0 and ldb % 4 == 0
 
 
 def _same_product(x, y, other_order):
@@ -147,8 +148,9 @@ def test_batch_equals_single_problem_path(h, small_batch):
         assert torch.equal(r["plan"].idx, b.draws(t)), t
         assert r["L"] == int(b.L[t].item()), t
         lp = pk.sbmm_query_sizes(prob)["L_pad_max"]
-        assert _same_product(r["CD"], b.CD[t], _split_k(m, p, lp) or _wide_tiles(p, 32)), t
-        assert _same_product(r["MN"], b.MN[t], _split_k(m, p, n) or _wide_tiles(p, n)), t
+        # the sketch C has rows of L_pad_max (a multiple of 32) entries, D rows of p
+        assert _same_product(r["CD"], b.CD[t], _split_k(m, p, lp) or _wide_tiles(32, p)), t
+        assert _same_product(r["MN"], b.MN[t], _split_k(m, p, n) or _wide_tiles(SMALL[t]["ldm"], SMALL[t]["ldn"])), t
 
 
 def _snapshot(b):

@@ -192,6 +192,33 @@ def test_reserved_workspace_needs_no_allocation():
     assert free1 == free0
 
 
+@pytest.mark.parametrize("m,n,p", [(300, 2001, 259), (257, 4099, 513), (64, 130, 33)])
+def test_f32_products_with_ragged_extents(h, m, n, p):
+    # float32 rows padded to 16 bytes but n, p not multiples of 4: the
+    # 256 x 256 product's per-dword zero fill of the last rows and its
+    # clearing of the entries past the inner extent, on the exact product
+    # and on the sketched one (D rows of p entries), against the oracle
+    g = np.random.Generator(np.random.PCG64(m + n + p))
+    Mb = torch.from_numpy(g.standard_normal((m, (n + 3) // 4 * 4)).astype(np.float32)).to(DEV)
+    Nb = torch.from_numpy(g.standard_normal((n, (p + 3) // 4 * 4)).astype(np.float32)).to(DEV)
+    # garbage in the padding must not reach the results
+    Mb[:, n:] = float("nan")
+    Nb[:, p:] = float("nan")
+    M, N = Mb[:, :n], Nb[:, :p]
+    off = wl.equal_blocks(n, 1) if n % 3 else wl.equal_blocks(n, 3)
+    prob = pk.Problem(M, N, off, 40, prob="norm", seed=5)
+    MN, _, mn_sq = h.exact(prob, store=True)
+    torch.cuda.synchronize()
+    Mh, Nh = host64(M), host64(N)
+    MNo = om.exact_product(Mh, Nh)
+    assert rel(host64(MN), MNo) < 1e-5
+    assert abs(mn_sq.item() - float(np.sum(MNo ** 2))) <= 1e-5 * float(np.sum(MNo ** 2))
+    r = h.run(prob)
+    o = om.run(Mh, Nh, off, 40, seed=5, prob="norm")
+    assert np.array_equal(r["plan"].idx.cpu().numpy(), o.draws.atom)
+    assert rel(host64(r["CD"]), o.CD) < 1e-5
+
+
 def test_norms_bitwise_reproducible(h):
     M, N, off = wl.random_problem(200, 4000, 150, 40, seed=9)
     prob = pk.Problem(to_dev(M, torch.float32), to_dev(N, torch.float32), off, c=4)
