@@ -396,20 +396,25 @@ typedef struct {
 typedef struct sbmm_batch_s* sbmm_batch;
 
 /* Tile configuration of the two grouped products (exact MN, sketched CD)
- * and whether their work lists start with the longest inner extents. cfg
- * indexes the tile shapes 128x128, 64x128, 128x64, 64x64 (0..3). For the
- * sketched product, 0..3 read the drawn columns of M and rows of N in place
- * (the gather fused into the product's loads) and 4..7 are the same tile
- * shapes over sketches C, D first gathered into a workspace the batch owns
- * (at most 8 GiB, or one problem's sketches if larger, filled by groups of
- * problems, one gather and one product launch per group); 4..7 exist when
- * that workspace could be allocated at sbmm_batch_create. Both forms give the
- * same bits. The timings are filled by sbmm_batch_tune: ms[g][2 cfg + lpt]
- * for product g (0 exact, 1 sketch), -1 where not measured. */
+ * and whether their work lists start with the longest inner extents. A tile
+ * configuration is one of 128x128, 64x128, 128x64, 64x64 (0..3, a
+ * register-staged kernel) and 256x256 (4, LDS-direct loads, eight waves per
+ * workgroup). The sketched product has two forms: cfg 0..3 read the drawn
+ * columns of M and rows of N in place (the gather fused into the product's
+ * loads), cfg 5..9 are tile configurations 0..4 over sketches C, D first
+ * gathered into a workspace the batch owns (at most 8 GiB, or one problem's
+ * sketches if larger, filled by groups of problems, one gather and one
+ * product launch per group); 5..9 exist when that workspace could be
+ * allocated at sbmm_batch_create, and exact cfg 4 when every problem's M and
+ * N rows start on 16-byte boundaries. Configurations 0..3 and their
+ * materialized forms give the same bits; the 256x256 tiles sum in another
+ * order and agree with them to float32 rounding. The timings are filled by
+ * sbmm_batch_tune: ms[g][2 cfg + lpt] for product g (0 exact, 1 sketch), -1
+ * where not measured. */
 typedef struct {
   int32_t cfg[2];
   int32_t lpt[2];
-  float ms[2][16];
+  float ms[2][20];
 } sbmm_batch_tuning;
 
 /* Validate T problems, allocate the batch's device memory (owned by the
@@ -433,11 +438,13 @@ sbmm_status sbmm_batch_run(sbmm_handle h, sbmm_batch batch, sbmm_stream stream);
 sbmm_status sbmm_batch_capture(sbmm_handle h, sbmm_batch batch);
 sbmm_status sbmm_batch_replay(sbmm_handle h, sbmm_batch batch, sbmm_stream stream);
 
-/* Autotuner: run the pass once, then time each tile configuration and work
- * order of the two grouped products on this batch (`reps` launches each,
- * HIP events on `stream`), keep the fastest and report all timings in
- * *out (optional). Synchronizing. Results do not depend on the
- * configuration (same accumulation order per output element). */
+/* Autotuner: run the pass once, then time each available configuration and
+ * work order of the two grouped products on this batch (`reps` launches
+ * each, HIP events on `stream`), keep the fastest and report all timings in
+ * *out (optional). Synchronizing. Results do not depend on the choice among
+ * configurations 0..3 and their materialized forms (same accumulation order
+ * per output element); the 256x256 tiles agree to float32 rounding (store a
+ * tuning with sbmm_batch_set_tuning to fix the bits across runs). */
 sbmm_status sbmm_batch_tune(sbmm_handle h, sbmm_batch batch, int32_t reps, sbmm_batch_tuning* out,
                             sbmm_stream stream);
 /* Apply a stored configuration (e.g. from an earlier tuning of the same

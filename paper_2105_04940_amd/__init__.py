@@ -41,7 +41,7 @@ EXPORTS = (
 BOUND_FIELDS = ("theta1", "theta2", "theta1_hat", "theta2_hat", "beta", "mn", "phi",
                 "var_bound", "expected")
 BOUND_MAX_DELTA = 8
-BATCH_TILES = ((128, 128), (64, 128), (128, 64), (64, 64))
+BATCH_TILES = ((128, 128), (64, 128), (128, 64), (64, 64), (256, 256))
 
 
 class SbmmError(RuntimeError):
@@ -98,7 +98,7 @@ class BatchOutputs_t(ctypes.Structure):
 
 class BatchTuning_t(ctypes.Structure):
     _fields_ = [("cfg", ctypes.c_int32 * 2), ("lpt", ctypes.c_int32 * 2),
-                ("ms", (ctypes.c_float * 16) * 2)]
+                ("ms", (ctypes.c_float * 20) * 2)]
 
 
 def load_library(path=LIB_PATH):
@@ -611,8 +611,8 @@ class Batch:
         for g in range(2):
             t.cfg[g] = d["cfg"][g]
             t.lpt[g] = d["lpt"][g]
-            for i in range(16):
-                t.ms[g][i] = d.get("ms", [[-1.0] * 16] * 2)[g][i]
+            for i in range(20):
+                t.ms[g][i] = d.get("ms", [[-1.0] * 20] * 2)[g][i]
         self.handle._check(self._lib.sbmm_batch_set_tuning(self.handle.h, self.b, ctypes.byref(t)))
 
     @staticmethod
@@ -621,7 +621,7 @@ class Batch:
         return {"cfg": [t.cfg[0], t.cfg[1]], "lpt": [t.lpt[0], t.lpt[1]],
                 "tiles": [list(BATCH_TILES[t.cfg[0] % n]), list(BATCH_TILES[t.cfg[1] % n])],
                 "sketch_materialized": t.cfg[1] >= n,
-                "ms": [[t.ms[g][i] for i in range(16)] for g in range(2)]}
+                "ms": [[t.ms[g][i] for i in range(20)] for g in range(2)]}
 
     def draws(self, t):
         """The drawn blocks of problem t (device tensor view)."""

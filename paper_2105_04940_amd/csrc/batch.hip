@@ -83,6 +83,7 @@ struct sbmm_batch_s {
   std::vector<GemmLaunch> mat_launch;     // per problem: the product over its materialized sketch
   void* gather_args = nullptr;            // T gather records, group-major
   int64_t* gather_wg = nullptr;           // per group its count + 1 workgroup offsets (T + G entries)
+  bool exact_lds = false;                 // every exact product can take the 256 x 256 tiles
 };
 
 namespace {
@@ -147,6 +148,18 @@ int product_cfgs(const sbmm_batch b, int g) {
 }
 
 bool materialized(const sbmm_batch b, int g, int cfg) { return g == 1 && cfg >= grouped_cfg_count(); }
+
+// Whether configuration cfg of product g can run: the 256 x 256 tiles
+// (tile configuration 4) take no fused gather, and for the exact product need
+// every problem's rows 16-byte aligned.
+bool cfg_ok(const sbmm_batch b, int g, int cfg) {
+  if (cfg < 0 || cfg >= product_cfgs(b, g)) return false;
+  const bool mat = materialized(b, g, cfg);
+  const int tile = mat ? cfg - grouped_cfg_count() : cfg;
+  if (tile != 4) return true;
+  if (g == 0) return b->exact_lds;
+  return mat;
+}
 
 // Rebuild and upload the tables of product g for configuration (cfg, lpt).
 // Materialized sketches: the work list runs group by group (each group's
@@ -495,8 +508,10 @@ sbmm_status sbmm_batch_create(sbmm_handle h, int32_t T, const sbmm_batch_item* i
     return fail(h, SBMM_E_HIP, "uploading batch tables: %s", hipGetErrorString(e));
   }
   setup_materialized(b, lpm, col_end, colmaps, colscales);
+  b->exact_lds = true;
+  for (int32_t t = 0; t < T; ++t) b->exact_lds = b->exact_lds && grouped_lds_ok(b->launches[0][t]);
   for (int g = 0; g < kProducts; ++g) {
-    for (int i = 0; i < 16; ++i) b->tuning.ms[g][i] = -1.0f;
+    for (int i = 0; i < 20; ++i) b->tuning.ms[g][i] = -1.0f;
     if ((st = apply_product(b, g, 0, 1)) != SBMM_OK) {
       sbmm_batch_destroy(b);
       return st;
@@ -576,7 +591,7 @@ sbmm_status sbmm_batch_tune(sbmm_handle h, sbmm_batch b, int32_t reps, sbmm_batc
     float best = -1.0f;
     int best_cfg = 0, best_lpt = 1;
     for (int cfg = 0; cfg < product_cfgs(b, g) && st == SBMM_OK; ++cfg)
-      for (int lpt = 0; lpt < 2 && st == SBMM_OK; ++lpt) {
+      for (int lpt = 0; lpt < 2 && st == SBMM_OK && cfg_ok(b, g, cfg); ++lpt) {
         if (hipStreamSynchronize(s) != hipSuccess) { st = fail(h, SBMM_E_HIP, "sync"); break; }
         if ((st = apply_product(b, g, cfg, lpt)) != SBMM_OK) break;
         hipError_t e = enqueue_product(b, g, s);   // warm-up
@@ -605,14 +620,14 @@ sbmm_status sbmm_batch_set_tuning(sbmm_handle h, sbmm_batch b, const sbmm_batch_
   if (st != SBMM_OK) return st;
   if (!t) return fail(h, SBMM_E_ARG, "tuning is NULL");
   for (int g = 0; g < kProducts; ++g)
-    if (t->cfg[g] < 0 || t->cfg[g] >= product_cfgs(b, g) || (t->lpt[g] != 0 && t->lpt[g] != 1))
+    if (!cfg_ok(b, g, t->cfg[g]) || (t->lpt[g] != 0 && t->lpt[g] != 1))
       return fail(h, SBMM_E_ARG, "tuning: configuration out of range");
   HIP_TRY(h, hipDeviceSynchronize());
   drop_graph(b);
   for (int g = 0; g < kProducts; ++g)
     if ((st = apply_product(b, g, t->cfg[g], t->lpt[g])) != SBMM_OK) return st;
   for (int g = 0; g < kProducts; ++g)
-    for (int i = 0; i < 16; ++i) b->tuning.ms[g][i] = t->ms[g][i];
+    for (int i = 0; i < 20; ++i) b->tuning.ms[g][i] = t->ms[g][i];
   return SBMM_OK;
 }
 

@@ -213,6 +213,9 @@ struct GroupedLaunch {
   bool gather;
 };
 int grouped_cfg_count();
+// whether a product can take grouped configuration 4 (256 x 256 tiles with
+// LDS-direct loads: 16-byte aligned rows, 32-bit panel offsets)
+bool grouped_lds_ok(const GemmLaunch& L);
 void grouped_cfg_shape(int cfg, int64_t* bm, int64_t* bn, int* wg_per_cu);
 size_t grouped_gemm_args_bytes();
 void build_grouped_gemm_args(const GemmLaunch& L, int cfg, void* out);

@@ -614,16 +614,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t f32_rsrc(const float* base, in
   return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, nb, 0x00020000);
 }
 
-template <int NW>
-__global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
+// Tile (tm, tn) of a product. GROUPED: one work item of a grouped launch,
+// whose staging slot is the item (a 256 x 256 slot, one eighth per wave) and
+// whose error partials go to slot `part` of [2][nparts] (the eight waves'
+// sums added in wave order). Otherwise the 128 x 128 accounting above.
+template <int NW, bool GROUPED>
+__device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& sh, int64_t tm, int64_t tn,
+                                               int64_t item, int64_t part, int64_t nparts) {
   using T = SgemmLdsTile;
   constexpr int KC = T::KC, BK = T::BK;
   constexpr int CB = 16 / NW;                    // 32-column blocks per wave (2 or 4)
   constexpr int AINSTS = T::BM * KC / 64 / NW;   // A: instructions per wave per stage (4)
   constexpr int BINSTS = BK / NW;                // B: rows per wave per stage (4)
-  __shared__ T sh;
-  int64_t tm, tn;
-  tile_coords(g, tm, tn);
   const int64_t m0 = tm * T::BM, n0 = tn * T::BN;
   const int64_t K = inner_extent(g);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -709,13 +711,14 @@ __global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
   const int64_t tn128 = (g.p + 127) / 128, tiles128 = ((g.m + 127) / 128) * tn128;
   constexpr int PER = 4 / CB;                    // waves sharing a 128 x 128 tile (2 or 1)
   const int64_t srow = 2 * tm + qm, scol = 2 * tn + qn / PER;
-  const bool inside = srow * 128 < g.m && scol * 128 < g.p;
-  const int64_t slot = inside ? srow * tn128 + scol : 0;
-  // this wave's half of the slot, [accumulator][lane], through a buffer
+  const bool inside = GROUPED || (srow * 128 < g.m && scol * 128 < g.p);
+  const int64_t slot = GROUPED ? 0 : (inside ? srow * tn128 + scol : 0);
+  // this wave's part of the slot, [accumulator][lane], through a buffer
   // resource so that each accumulator's offset is a scalar (no per-lane
   // address registers); a wave outside the output gets no records
-  const __amdgpu_buffer_rsrc_t rs = f32_rsrc(g.stage + slot * (128 * 128) + (qn % PER) * (128 * 32 * CB),
-                                             inside ? 128 * 32 * CB * 4 : 0);
+  float* const sbase = GROUPED ? g.stage + item * (256 * 256) + wave * (128 * 32 * CB)
+                               : g.stage + slot * (128 * 128) + (qn % PER) * (128 * 32 * CB);
+  const __amdgpu_buffer_rsrc_t rs = f32_rsrc(sbase, inside ? 128 * 32 * CB * 4 : 0);
   const int vo = lane * 4;
   int folds = 0;
   auto fold = [&]() {
@@ -782,7 +785,24 @@ __global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
       }
       if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
-  if (g.tile_part) {
+  if (g.tile_part && GROUPED) {
+    e2 = warp_sum_f64(e2);
+    n2 = warp_sum_f64(n2);
+    if (lane == 0) {
+      sh.red[0][wave] = e2;
+      sh.red[1][wave] = n2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        a += sh.red[0][w];
+        b += sh.red[1][w];
+      }
+      g.tile_part[part] = a;
+      g.tile_part[nparts + part] = b;
+    }
+  } else if (g.tile_part) {
     // the two waves of a 128 x 128 tile (qn = 2s, 2s + 1): the first adds
     // the second's sums after its own, in that order
     e2 = warp_sum_f64(e2);
@@ -804,6 +824,14 @@ __global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
       }
     }
   }
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64, 1) void sgemm_lds_kernel(GemmArgs g) {
+  __shared__ SgemmLdsTile sh;
+  int64_t tm, tn;
+  tile_coords(g, tm, tn);
+  sgemm_lds_body<NW, false>(g, sh, tm, tn, 0, 0, 0);
 }
 
 // ============================================================================
@@ -842,6 +870,18 @@ __global__ __launch_bounds__(kThreads, WG_PER_CU) void sgemm_grouped_kernel(Grou
     sgemm_body<WMB, WNB, BK, false, GATHER>(g, sh, m0, n0, K, it, part, ga.nparts);
   else
     sgemm_body<WMB, WNB, BK, true, GATHER>(g, sh, m0, n0, K, it, part, ga.nparts);
+}
+
+// The 256 x 256 LDS-direct tiles as a grouped launch (sketch materialized or
+// exact product; no fused gather).
+template <int NW>
+__global__ __launch_bounds__(NW * 64, 1) void sgemm_grouped_lds_kernel(GroupedArgs ga) {
+  __shared__ SgemmLdsTile sh;
+  const int64_t it = blockIdx.x;
+  const int32_t pi = ga.item_prob[it];
+  const int64_t local = ga.item_tile[it];
+  const GemmArgs& g = ga.probs[pi];
+  sgemm_lds_body<NW, true>(g, sh, local / g.tiles_n, local % g.tiles_n, it, ga.part_base[pi] + local, ga.nparts);
 }
 
 // Per problem t: out[2t] = sum of the error partials of its sketched tiles,
@@ -1186,7 +1226,9 @@ hipError_t launch_gemm(const GemmLaunch& L, hipStream_t s) {
 // ----------------------------------------------------------------------------
 namespace {
 struct GroupedCfg { int bm, bn, wg_per_cu; };
-constexpr GroupedCfg kGroupedCfgs[] = {{128, 128, 2}, {64, 128, 2}, {128, 64, 2}, {64, 64, 4}};
+// 0..3: the register-staged kernel; 4: 256 x 256 tiles with LDS-direct loads
+// (no fused gather, 16-byte aligned rows)
+constexpr GroupedCfg kGroupedCfgs[] = {{128, 128, 2}, {64, 128, 2}, {128, 64, 2}, {64, 64, 4}, {256, 256, 1}};
 constexpr int kGroupedCfgCount = sizeof(kGroupedCfgs) / sizeof(kGroupedCfgs[0]);
 
 template <bool GATHER>
@@ -1196,7 +1238,11 @@ void launch_grouped_cfg(int cfg, dim3 grid, const GroupedArgs& ga, hipStream_t s
     case 0: hipLaunchKernelGGL((sgemm_grouped_kernel<2, 2, F32_BK, 2, GATHER>), grid, block, 0, s, ga); break;
     case 1: hipLaunchKernelGGL((sgemm_grouped_kernel<1, 2, F32_BK, 2, GATHER>), grid, block, 0, s, ga); break;
     case 2: hipLaunchKernelGGL((sgemm_grouped_kernel<2, 1, F32_BK, 2, GATHER>), grid, block, 0, s, ga); break;
-    default: hipLaunchKernelGGL((sgemm_grouped_kernel<1, 1, F32_BK, 4, GATHER>), grid, block, 0, s, ga); break;
+    case 3: hipLaunchKernelGGL((sgemm_grouped_kernel<1, 1, F32_BK, 4, GATHER>), grid, block, 0, s, ga); break;
+    default:
+      if constexpr (!GATHER)
+        hipLaunchKernelGGL(sgemm_grouped_lds_kernel<kLdsWaves>, grid, dim3(kLdsWaves * 64), 0, s, ga);
+      break;
   }
 }
 }  // namespace
@@ -1218,9 +1264,17 @@ void build_grouped_gemm_args(const GemmLaunch& L, int cfg, void* out) {
   std::memcpy(out, &g, sizeof(g));
 }
 
+bool grouped_lds_ok(const GemmLaunch& L) {
+  const GemmArgs g = make_gemm_args(L, SgemmLdsTile::BM, SgemmLdsTile::BN);
+  GemmLaunch S = L;
+  S.stage = reinterpret_cast<float*>(256);   // presence only
+  return sgemm_lds_ok(S, g);
+}
+
 hipError_t launch_grouped_gemm(const GroupedLaunch& L, hipStream_t s) {
   if (L.items <= 0) return hipSuccess;
   if (L.stage == nullptr) return hipErrorInvalidValue;
+  if (L.gather && L.cfg >= 4) return hipErrorInvalidValue;   // no fused gather on the 256 x 256 tiles
   GroupedArgs ga{reinterpret_cast<const GemmArgs*>(L.probs), L.item_prob, L.item_tile, L.part_base,
                  L.items, L.nparts};
   const dim3 grid((unsigned)L.items);
