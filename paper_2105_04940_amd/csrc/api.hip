@@ -210,7 +210,8 @@ sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
                      const void* Y, int64_t ldy, double* blkprod_sq, double* out2, Arena& ar, hipStream_t s) {
   if (P->in_dtype == SBMM_BF16 && blkprod_sq)
     return fail(h, SBMM_E_UNSUPPORTED, "block product norms of bf16 inputs are not built");
-  const bool gram = blkprod_sq != nullptr && P->in_dtype == SBMM_F32 && max_block_width(P) <= block_gram_max_width();
+  const bool gram = blkprod_sq != nullptr && P->in_dtype == SBMM_F32 && max_block_width(P) <= block_gram_max_width() &&
+                    block_gram_strides_ok(P->ldm, P->ldn);
   if (gram) {
     void* gws = ar.take<char>(block_gram_ws_bytes(P->K));
     if (ar.base) {

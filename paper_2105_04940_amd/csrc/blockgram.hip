@@ -8,29 +8,31 @@
 // much narrower than m and p (the block-sampling workloads) this is far
 // cheaper, so the exact product can run without per-block bookkeeping.
 //
-// One workgroup per (block, operand) (n_k <= 128) forms one Gram matrix on
-// matrix cores (v_mfma_f32_32x32x2_f32) in a 128 x 128 tile split in 64 x 64
-// quadrants over the four waves; since both are symmetric only the quadrants
-// (0,0), (0,1), (1,1) are formed and (0,1) counts twice. The contraction runs
-// over the rows of M^k (stored as loaded: step k = row h, index i = column)
-// and over the columns of N_k (stored transposed), so both operands of every
-// step come from the same LDS tile layout [k][i], and the two Gram matrices
-// of a block land in the same lane layout. They are written to a workspace
-// in that layout and a second kernel forms the inner product in float64 in a
-// fixed order. Splitting the two operands over workgroups halves the
-// accumulators a workgroup holds, which lets two workgroups share a compute
-// unit and doubles the workgroups streaming the inputs.
+// One workgroup per (block, operand) (n_k <= 128) forms the upper triangle
+// of one Gram matrix on matrix cores (v_mfma_f32_16x16x4_f32) in 16 x 16
+// tiles: with T = ceil(n_k / 16) index tiles, only the T (T + 1) / 2 tiles
+// (ti <= tj) the block needs are formed, the off-diagonal ones counting twice
+// in the inner product. Tile rows are dealt out in pairs (r, T - 1 - r), one
+// pair per wave (T + 1 tiles each), and the wave that takes pair 0 turns
+// with the block index, so the four SIMDs of a compute unit carry the same
+// work on average. The contraction runs over the rows of M^k (stored as
+// loaded: step k = row h, index i = column) and over the columns of N_k
+// (stored transposed), so both operands of every step come from the same LDS
+// tile layout [k][i], and the two Gram matrices of a block land in the same
+// lane layout. They are written to a workspace in that layout and a second
+// kernel forms the inner product in float64 in a fixed order. Splitting the
+// two operands over workgroups halves the accumulators a workgroup holds and
+// doubles the workgroups streaming the inputs.
 #include "common.h"
 
 namespace {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kT = 128;         // Gram tile (max block width)
-constexpr int kBK = 32;         // contraction step
-constexpr int kS = kT + 4;      // LDS row stride
+constexpr int kT = 128;          // Gram tile (max block width)
+constexpr int kTiles = kT / 16;  // index tiles of 16
+constexpr int kBK = 32;          // contraction step
 
 struct GramArgs {
   const float* M; int64_t ldm;
@@ -41,65 +43,130 @@ struct GramArgs {
 };
 
 struct GramWs {
-  float* g;        // [K][2][4 waves][2][2][16][64 lanes]
+  float* g;        // [K][2][kTiles][kTiles][4 values][64 lanes], tiles ti <= tj written
 };
 
-constexpr int kGramVals = 2 * 2 * 16;                   // accumulator values per lane
-constexpr int64_t kGramPerOperand = 4 * kGramVals * 64;  // floats per (block, operand)
+constexpr int64_t kTileVals = 4 * 64;
+constexpr int64_t kGramPerOperand = (int64_t)kTiles * kTiles * kTileVals;
 
-__device__ __forceinline__ bool gram_wave_active(int wave, int nk) {
-  // quadrant (1,0) mirrors (0,1); quadrants outside the block are all zero
-  const int wave_m0 = (wave & 1) * 64, wave_n0 = (wave >> 1) * 64;
-  return wave != 1 && wave_m0 < nk && wave_n0 < nk;
+// LDS column of index i in contraction row kk: i XOR ((kk & 1) << 4 | kk >> 1).
+// The transposed store of N_k (32 lanes writing rows 0..31 of one column) and
+// the matrix-core reads (16 lanes on each of rows kk, kk + 1 of a step) both
+// fall on distinct banks.
+__device__ __forceinline__ int lds_col(int kk, int i) { return i ^ (((kk & 1) << 4) | (kk >> 1)); }
+
+// Buffer resource over `bytes` bytes from `base` (fields made wave-uniform).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t gram_rsrc(const float* base, int64_t bytes) {
+  const uint64_t u = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  const int nb = __builtin_amdgcn_readfirstlane((int)(bytes > 0 ? bytes : 0));
+  void* p = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, nb, 0x00020000);
 }
 
-__global__ __launch_bounds__(kThreads, 2) void block_gram_half_kernel(GramArgs a, GramWs w) {
-  __shared__ float Xs[2][kBK][kS];
+// Accumulator slots of a wave: tile (A, A + j) in slot j < T - A, tile
+// (B, B + j') in slot T - A + j'; at most T + 1 <= kTiles + 1 of them.
+constexpr int kSlots = kTiles + 1;
+
+// One contraction step of the tile rows A and B = T - 1 - A (B >= A; B == A
+// holds one row) over the 32 rows of a stage. Lane l reads row
+// kk = 4 s + (l >> 4) at column (16 t + (l & 15)) XOR the row's swizzle,
+// i.e. 16 (t XOR hb) + ((l & 15) XOR (2 s + (l >> 5))) with hb = (l >> 4) & 1:
+// pe (even t) and po (odd t) hold the lane's row and the +-16 hb shift, so
+// the tile offset 16 t and the row offset of s are immediates.
+template <int T, int A>
+__device__ __forceinline__ void gram_step(const float* pe, const float* po, int x0, f32x4 (&acc)[kSlots]) {
+  constexpr int B = T - 1 - A;
+#pragma unroll
+  for (int s = 0; s < kBK / 4; ++s) {
+    const int xo = x0 ^ (2 * s);
+    const float* re = pe + xo + s * 4 * kT;
+    const float* ro = po + xo + s * 4 * kT;
+    float fr[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) fr[t] = (t & 1 ? ro : re)[16 * t];
+#pragma unroll
+    for (int t = A; t < T; ++t)
+      acc[t - A] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[A], fr[t], acc[t - A], 0, 0, 0);
+    if constexpr (B > A) {
+#pragma unroll
+      for (int t = B; t < T; ++t)
+        acc[T - A + t - B] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[B], fr[t], acc[T - A + t - B], 0, 0, 0);
+    }
+  }
+}
+
+// (T, A) pairs with A <= T - 1 - A
+#define SBMM_GRAM_CASES(X) \
+  X(1, 0) X(2, 0) X(3, 0) X(3, 1) X(4, 0) X(4, 1) X(5, 0) X(5, 1) X(5, 2) X(6, 0) X(6, 1) X(6, 2) \
+  X(7, 0) X(7, 1) X(7, 2) X(7, 3) X(8, 0) X(8, 1) X(8, 2) X(8, 3)
+
+__global__ __launch_bounds__(kThreads, 4) void block_gram_half_kernel(GramArgs a, GramWs w) {
+  __shared__ float Xs[2][kBK][kT];
   const int k = blockIdx.x;
   const int phase = blockIdx.y;   // 0: rows of M^k; 1: columns of N_k
   const int64_t lo = a.off[k];
   const int nk = (int)(a.off[k + 1] - lo);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 31, lh = lane >> 5;
-  const int wave_m0 = (wave & 1) * 64, wave_n0 = (wave >> 1) * 64;
-  const bool active = gram_wave_active(wave, nk);
+  const int T = (nk + 15) >> 4;
+  const int ra = (wave + k) & 3, rb = T - 1 - ra;
+  const bool active = ra <= rb;
+  const int code = active ? T * 4 + ra : -1;
 
-  f32x16 acc[2][2];
+  f32x4 acc[kSlots];
 #pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[b][c] = f32x16{};
+  for (int j = 0; j < kSlots; ++j) acc[j] = f32x4{};
+  const int hb = (lane >> 4) & 1;
+  const int x0 = (lane & 15) ^ (lane >> 5);
+  const int lrow = (lane >> 4) * kT;
 
+  // Buffer loads: per step a resource whose base is the step's first element
+  // and whose range ends after the last valid one, a 32-bit lane offset and a
+  // scalar offset per pass. Lanes past the block or the extent take offset
+  // 2^31, beyond every range (the strides are bounded on the host so that
+  // 2^31 plus the largest scalar offset stays below 2^32); the range check
+  // returns zero for them.
   float r[kBK * kT / kThreads];
   const int64_t ext = phase == 0 ? a.m : a.p;
   const int64_t nsteps = (ext + kBK - 1) / kBK;
+  constexpr uint32_t kOut = 0x80000000u;
   auto load = [&](int64_t st) {
     const int64_t s0 = st * kBK;
+    const int64_t live = min((int64_t)kBK, ext - s0);   // valid contraction rows of the step
     if (phase == 0) {
       // 2 rows per pass, 128 consecutive columns per row
+      const int64_t bytes = ((live - 1) * a.ldm + nk) * 4;
+      const __amdgpu_buffer_rsrc_t rs = gram_rsrc(a.M + s0 * a.ldm + lo, bytes);
+      const int i = tid & 127;
+      const uint32_t vo = i < nk ? (uint32_t)(((tid >> 7) * a.ldm + i) * 4) : kOut;
 #pragma unroll
-      for (int q = 0; q < kBK * kT / kThreads; ++q) {
-        const int row = q * 2 + (tid >> 7), i = tid & 127;
-        const int64_t h = s0 + row;
-        r[q] = (h < a.m && i < nk) ? a.M[h * a.ldm + lo + i] : 0.0f;
-      }
+      for (int q = 0; q < kBK * kT / kThreads; ++q)
+        r[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, (int)(q * 2 * a.ldm * 4), 0));
     } else {
       // 8 rows of N_k per pass, 32 consecutive columns per row
+      const int64_t bytes = nk > 0 ? ((nk - 1) * a.ldn + live) * 4 : 0;
+      const __amdgpu_buffer_rsrc_t rs = gram_rsrc(a.N + lo * a.ldn + s0, bytes);
+      const int f = tid & 31;
+      const uint32_t vo = f < live ? (uint32_t)(((tid >> 5) * a.ldn + f) * 4) : kOut;
 #pragma unroll
-      for (int q = 0; q < kBK * kT / kThreads; ++q) {
-        const int i = q * 8 + (tid >> 5), f = tid & 31;
-        const int64_t col = s0 + f;
-        r[q] = (col < a.p && i < nk) ? a.N[(lo + i) * a.ldn + col] : 0.0f;
-      }
+      for (int q = 0; q < kBK * kT / kThreads; ++q)
+        r[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, (int)(q * 8 * a.ldn * 4), 0));
     }
   };
   auto store = [&](int buf) {
     if (phase == 0) {
 #pragma unroll
-      for (int q = 0; q < kBK * kT / kThreads; ++q) Xs[buf][q * 2 + (tid >> 7)][tid & 127] = r[q];
+      for (int q = 0; q < kBK * kT / kThreads; ++q) {
+        const int row = q * 2 + (tid >> 7);
+        Xs[buf][row][lds_col(row, tid & 127)] = r[q];
+      }
     } else {
 #pragma unroll
-      for (int q = 0; q < kBK * kT / kThreads; ++q) Xs[buf][tid & 31][q * 8 + (tid >> 5)] = r[q];
+      for (int q = 0; q < kBK * kT / kThreads; ++q) {
+        const int kk = tid & 31;
+        Xs[buf][kk][lds_col(kk, q * 8 + (tid >> 5))] = r[q];
+      }
     }
   };
   if (nsteps > 0) {
@@ -110,47 +177,57 @@ __global__ __launch_bounds__(kThreads, 2) void block_gram_half_kernel(GramArgs a
   for (int64_t st = 0; st < nsteps; ++st) {
     const int cur = (int)(st & 1);
     if (st + 1 < nsteps) load(st + 1);
-    if (active) {
-#pragma unroll
-      for (int s = 0; s < kBK / 2; ++s) {
-        const int kk = 2 * s + lh;
-        const f32x2 av = *reinterpret_cast<const f32x2*>(&Xs[cur][kk][wave_m0 + 2 * lr]);
-        const f32x2 bv = *reinterpret_cast<const f32x2*>(&Xs[cur][kk][wave_n0 + 2 * lr]);
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int c = 0; c < 2; ++c)
-            acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[b], bv[c], acc[b][c], 0, 0, 0);
-      }
+    switch (code) {
+#define SBMM_GRAM_STEP(TT, AA) \
+      case TT * 4 + AA:                                                                   \
+        gram_step<TT, AA>(&Xs[cur][0][0] + lrow + 16 * hb, &Xs[cur][0][0] + lrow - 16 * hb, x0, acc); \
+        break;
+      SBMM_GRAM_CASES(SBMM_GRAM_STEP)
+#undef SBMM_GRAM_STEP
+      default: break;
     }
     if (st + 1 < nsteps) store(cur ^ 1);
     __syncthreads();
   }
   if (!active) return;
-  float* out = w.g + ((int64_t)k * 2 + phase) * kGramPerOperand + (int64_t)wave * kGramVals * 64;
+  float* out = w.g + ((int64_t)k * 2 + phase) * kGramPerOperand + lane;
+  const int na = T - ra, nb = rb > ra ? T - rb : 0;
 #pragma unroll
-  for (int b = 0; b < 2; ++b)
+  for (int j = 0; j < kSlots; ++j) {
+    int tile = -1;
+    if (j < na) tile = ra * kTiles + ra + j;
+    else if (j < na + nb) tile = rb * kTiles + rb + (j - na);
+    if (tile >= 0) {
+      float* o = out + tile * kTileVals;
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) out[((b * 2 + c) * 16 + v) * 64 + lane] = acc[b][c][v];
+      for (int v = 0; v < 4; ++v) o[v * 64] = acc[j][v];
+    }
+  }
 }
 
-// < G_M, G_N > per block: each lane multiplies the values it holds in both
-// matrices (same layout) in float64, in the order (b, c, v); the quadrant
-// (0,1) counts twice; fixed-order reduction over lanes and waves.
+// < G_M, G_N > per block: the tiles ti <= tj in row order are dealt to the
+// waves in turn; each lane multiplies the values it holds in both matrices
+// (same layout) in float64, an off-diagonal tile counting twice; fixed-order
+// reduction over lanes and waves.
 __global__ __launch_bounds__(kThreads) void block_gram_dot_kernel(GramArgs a, GramWs w) {
   __shared__ double red[4];
   const int k = blockIdx.x;
   const int nk = (int)(a.off[k + 1] - a.off[k]);
+  const int T = (nk + 15) >> 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const float* gm = w.g + (int64_t)k * 2 * kGramPerOperand + lane;
+  const float* gn = gm + kGramPerOperand;
   double dot = 0.0;
-  if (gram_wave_active(wave, nk)) {
-    const float* gm = w.g + (int64_t)k * 2 * kGramPerOperand + (int64_t)wave * kGramVals * 64;
-    const float* gn = gm + kGramPerOperand;
+  int e = 0;
+  for (int ti = 0; ti < T; ++ti) {
+    for (int tj = ti; tj < T; ++tj, ++e) {
+      if ((e & 3) != wave) continue;
+      const int64_t base = (ti * kTiles + tj) * kTileVals;
+      double ts = 0.0;
 #pragma unroll
-    for (int e = 0; e < kGramVals; ++e) dot = fma((double)gm[e * 64 + lane], (double)gn[e * 64 + lane], dot);
-    if (wave == 2) dot *= 2.0;
+      for (int v = 0; v < 4; ++v) ts = fma((double)gm[base + v * 64], (double)gn[base + v * 64], ts);
+      dot += ti < tj ? 2.0 * ts : ts;
+    }
   }
   dot = warp_sum_f64(dot);
   if (lane == 0) red[wave] = dot;
@@ -173,3 +250,8 @@ hipError_t launch_block_gram(const float* M, int64_t ldm, const float* N, int64_
 }
 
 int64_t block_gram_max_width() { return kT; }
+
+// The 32-bit buffer offsets of the Gram kernel: 2^31 plus the largest scalar
+// offset of a step (30 rows of M, 120 rows of N) stays below 2^32 and every
+// range below 2^31.
+bool block_gram_strides_ok(int64_t ldm, int64_t ldn) { return ldm < (int64_t(1) << 24) && ldn < (int64_t(1) << 22); }

@@ -238,6 +238,8 @@ size_t block_gram_ws_bytes(int32_t K);
 hipError_t launch_block_gram(const float* M, int64_t ldm, const float* N, int64_t ldn, int64_t m, int64_t p,
                              const int64_t* off_dev, int32_t K, double* out, void* ws, hipStream_t s);
 int64_t block_gram_max_width();
+// the row strides (elements) the Gram kernel's 32-bit buffer offsets cover
+bool block_gram_strides_ok(int64_t ldm, int64_t ldn);
 
 // Backward of the sketch: per-atom draw lists and the scatter of dC / dD
 // into dM / dN.

@@ -411,6 +411,23 @@ def test_block_product_norms(h):
         assert abs(mn_sq.item() - float(np.sum(MNo**2))) < TOL[dtype] * float(np.sum(MNo**2))
 
 
+def test_block_gram_tile_counts(h):
+    # per block, against the oracle: widths giving every count of 16-wide
+    # index tiles (1..8), on and off the tile edges, row and column extents
+    # that leave ragged contraction steps
+    widths = [1, 15, 16, 17, 31, 32, 33, 48, 63, 64, 65, 80, 97, 100, 112, 113, 127, 128, 2, 7, 50]
+    off = [0]
+    for wdt in widths:
+        off.append(off[-1] + wdt)
+    M, N, _ = wl.random_problem(150, off[-1], 70, 1, seed=41, skew=0.8)
+    prob = pk.Problem(to_dev(M, torch.float32), to_dev(N, torch.float32), off, c=3)
+    _, bp, _ = h.exact(prob, store=False, blocknorm=True)
+    torch.cuda.synchronize()
+    ref = om.block_product_sq(host64(prob.M), host64(prob.N), off)
+    got = host64(bp)
+    assert np.all(np.abs(got - ref) <= TOL[torch.float32] * ref), np.max(np.abs(got - ref) / ref)
+
+
 def test_block_product_norms_wide_blocks(h):
     # blocks wider than the Gram tile take the block-by-block product path
     M, N, _ = wl.random_problem(140, 700, 90, 1, seed=33, skew=0.5)
