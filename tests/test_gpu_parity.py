@@ -428,6 +428,23 @@ def test_block_gram_tile_counts(h):
     assert np.all(np.abs(got - ref) <= TOL[torch.float32] * ref), np.max(np.abs(got - ref) / ref)
 
 
+def test_block_gram_large_strides(h):
+    # row strides past the Gram kernel's 32-bit offsets (M: 2^24 floats, N:
+    # 2^22) take the block-by-block product path, with the same result
+    M, N, off = wl.random_problem(3, 300, 5, 6, seed=42, skew=0.5)
+    bigM = torch.zeros((3, (1 << 24) + 8), dtype=torch.float32, device=DEV)
+    bigM[:, :300] = to_dev(M, torch.float32)
+    bigN = torch.zeros((300, (1 << 22) + 8), dtype=torch.float32, device=DEV)
+    bigN[:, :5] = to_dev(N, torch.float32)
+    Mv, Nv = bigM[:, :300], bigN[:, :5]
+    ref = om.block_product_sq(host64(Mv), host64(Nv), off)
+    for Md, Nd in ((Mv, to_dev(N, torch.float32)), (to_dev(M, torch.float32), Nv)):
+        _, bp, _ = h.exact(pk.Problem(Md, Nd, off, c=3), store=False, blocknorm=True)
+        torch.cuda.synchronize()
+        assert np.all(np.abs(host64(bp) - ref) <= TOL[torch.float32] * ref)
+    del bigM, bigN
+
+
 def test_block_product_norms_wide_blocks(h):
     # blocks wider than the Gram tile take the block-by-block product path
     M, N, _ = wl.random_problem(140, 700, 90, 1, seed=33, skew=0.5)
