@@ -32,7 +32,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int kT = 128;          // Gram tile (max block width)
 constexpr int kTiles = kT / 16;  // index tiles of 16
-constexpr int kBK = 32;          // contraction step
 
 struct GramArgs {
   const float* M; int64_t ldm;
@@ -49,11 +48,21 @@ struct GramWs {
 constexpr int64_t kTileVals = 4 * 64;
 constexpr int64_t kGramPerOperand = (int64_t)kTiles * kTiles * kTileVals;
 
-// LDS column of index i in contraction row kk: i XOR ((kk & 1) << 4 | kk >> 1).
-// The transposed store of N_k (32 lanes writing rows 0..31 of one column) and
-// the matrix-core reads (16 lanes on each of rows kk, kk + 1 of a step) both
-// fall on distinct banks.
-__device__ __forceinline__ int lds_col(int kk, int i) { return i ^ (((kk & 1) << 4) | (kk >> 1)); }
+// A stage holds kStage floats: R = kStage / W contraction rows of W block
+// columns, W = 32, 64 or 128 the smallest multiple of 32 (a power of two)
+// that covers the block, so a narrow block streams more rows per step with
+// the same registers and LDS.
+constexpr int kStage = 4096;
+__host__ __device__ constexpr int stage_width(int T) { return T <= 2 ? 32 : (T <= 4 ? 64 : 128); }
+
+// Position of element (contraction row kk, block column i) in a stage of
+// width W: i XOR ((kk & 1) << 4 | (kk >> 1) & 15). The transposed store of
+// N_k (32 lanes writing 32 consecutive rows of one column) and the
+// matrix-core reads (16 lanes on each of rows kk, kk + 1) both fall on
+// distinct banks, W being a multiple of 32.
+__device__ __forceinline__ int lds_pos(int W, int kk, int i) {
+  return kk * W + (i ^ (((kk & 1) << 4) | ((kk >> 1) & 15)));
+}
 
 // Buffer resource over `bytes` bytes from `base` (fields made wave-uniform).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t gram_rsrc(const float* base, int64_t bytes) {
@@ -69,30 +78,40 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t gram_rsrc(const float* base, i
 // (B, B + j') in slot T - A + j'; at most T + 1 <= kTiles + 1 of them.
 constexpr int kSlots = kTiles + 1;
 
-// One contraction step of the tile rows A and B = T - 1 - A (B >= A; B == A
-// holds one row) over the 32 rows of a stage. Lane l reads row
-// kk = 4 s + (l >> 4) at column (16 t + (l & 15)) XOR the row's swizzle,
-// i.e. 16 (t XOR hb) + ((l & 15) XOR (2 s + (l >> 5))) with hb = (l >> 4) & 1:
-// pe (even t) and po (odd t) hold the lane's row and the +-16 hb shift, so
-// the tile offset 16 t and the row offset of s are immediates.
+// One stage of the tile rows A and B = T - 1 - A (B >= A; B == A holds one
+// row). Sub-step s of group g covers rows 32 g + 4 s .. + 3; lane l reads row
+// kk = 32 g + 4 s + (l >> 4) at column (16 t + (l & 15)) XOR the row's
+// swizzle, i.e. 16 (t XOR hb) + ((l & 15) XOR (2 s + (l >> 5))) with
+// hb = (l >> 4) & 1: pe (even t) and po (odd t) hold the lane's row and the
+// +-16 hb shift, so the tile offset 16 t and the row offset of s are
+// immediates.
 template <int T, int A>
-__device__ __forceinline__ void gram_step(const float* pe, const float* po, int x0, f32x4 (&acc)[kSlots]) {
+__device__ __forceinline__ void gram_step(const float* xs, int lane, f32x4 (&acc)[kSlots]) {
   constexpr int B = T - 1 - A;
+  constexpr int W = stage_width(T), R = kStage / W;
+  const int hb = (lane >> 4) & 1;
+  const int x0 = (lane & 15) ^ (lane >> 5);
+  // the swizzle repeats every 8 sub-steps (32 rows): groups of 8 unrolled
+#pragma unroll 1
+  for (int g = 0; g < R / 32; ++g) {
+    const float* pe = xs + (32 * g + (lane >> 4)) * W + 16 * hb;
+    const float* po = xs + (32 * g + (lane >> 4)) * W - 16 * hb;
 #pragma unroll
-  for (int s = 0; s < kBK / 4; ++s) {
-    const int xo = x0 ^ (2 * s);
-    const float* re = pe + xo + s * 4 * kT;
-    const float* ro = po + xo + s * 4 * kT;
-    float fr[T];
+    for (int s = 0; s < 8; ++s) {
+      const int xo = x0 ^ (2 * s);
+      const float* re = pe + xo + s * 4 * W;
+      const float* ro = po + xo + s * 4 * W;
+      float fr[T];
 #pragma unroll
-    for (int t = 0; t < T; ++t) fr[t] = (t & 1 ? ro : re)[16 * t];
+      for (int t = 0; t < T; ++t) fr[t] = (t & 1 ? ro : re)[16 * t];
 #pragma unroll
-    for (int t = A; t < T; ++t)
-      acc[t - A] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[A], fr[t], acc[t - A], 0, 0, 0);
-    if constexpr (B > A) {
+      for (int t = A; t < T; ++t)
+        acc[t - A] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[A], fr[t], acc[t - A], 0, 0, 0);
+      if constexpr (B > A) {
 #pragma unroll
-      for (int t = B; t < T; ++t)
-        acc[T - A + t - B] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[B], fr[t], acc[T - A + t - B], 0, 0, 0);
+        for (int t = B; t < T; ++t)
+          acc[T - A + t - B] = __builtin_amdgcn_mfma_f32_16x16x4f32(fr[B], fr[t], acc[T - A + t - B], 0, 0, 0);
+      }
     }
   }
 }
@@ -102,71 +121,58 @@ __device__ __forceinline__ void gram_step(const float* pe, const float* po, int 
   X(1, 0) X(2, 0) X(3, 0) X(3, 1) X(4, 0) X(4, 1) X(5, 0) X(5, 1) X(5, 2) X(6, 0) X(6, 1) X(6, 2) \
   X(7, 0) X(7, 1) X(7, 2) X(7, 3) X(8, 0) X(8, 1) X(8, 2) X(8, 3)
 
-__global__ __launch_bounds__(kThreads, 4) void block_gram_half_kernel(GramArgs a, GramWs w) {
-  __shared__ float Xs[2][kBK][kT];
-  const int k = blockIdx.x;
-  const int phase = blockIdx.y;   // 0: rows of M^k; 1: columns of N_k
-  const int64_t lo = a.off[k];
-  const int nk = (int)(a.off[k + 1] - lo);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int T = (nk + 15) >> 4;
-  const int ra = (wave + k) & 3, rb = T - 1 - ra;
-  const bool active = ra <= rb;
-  const int code = active ? T * 4 + ra : -1;
-
-  f32x4 acc[kSlots];
-#pragma unroll
-  for (int j = 0; j < kSlots; ++j) acc[j] = f32x4{};
-  const int hb = (lane >> 4) & 1;
-  const int x0 = (lane & 15) ^ (lane >> 5);
-  const int lrow = (lane >> 4) * kT;
-
+// The stage loop of one workgroup for stage width W (uniform over the
+// block): loads of the next stage into registers, the matrix-core work of
+// the current one, stores into the other LDS buffer, one barrier per stage.
+template <int W>
+__device__ __forceinline__ void gram_loop(const GramArgs& a, float (*Xs)[kStage], int phase, int64_t lo, int nk,
+                                          int code, f32x4 (&acc)[kSlots]) {
+  constexpr int R = kStage / W;                   // contraction rows per stage
+  constexpr int kPasses = kStage / kThreads;
+  constexpr int PR0 = kThreads / W, PR1 = kThreads / R;   // rows per pass (phase 0: of M, 1: of N_k)
+  const int tid = threadIdx.x, lane = tid & 63;
   // Buffer loads: per step a resource whose base is the step's first element
   // and whose range ends after the last valid one, a 32-bit lane offset and a
   // scalar offset per pass. Lanes past the block or the extent take offset
   // 2^31, beyond every range (the strides are bounded on the host so that
   // 2^31 plus the largest scalar offset stays below 2^32); the range check
-  // returns zero for them.
-  float r[kBK * kT / kThreads];
+  // returns zero for them. Phase 0: lane -> (row tid / W, column tid % W);
+  // phase 1: lane -> (row of N_k tid / R, column tid % R); both read runs of
+  // consecutive elements.
+  float r[kPasses];
   const int64_t ext = phase == 0 ? a.m : a.p;
-  const int64_t nsteps = (ext + kBK - 1) / kBK;
+  const int64_t nsteps = (ext + R - 1) / R;
   constexpr uint32_t kOut = 0x80000000u;
+  const int p_lo = phase == 0 ? tid / W : tid / R;
+  const int p_in = phase == 0 ? tid % W : tid % R;
   auto load = [&](int64_t st) {
-    const int64_t s0 = st * kBK;
-    const int64_t live = min((int64_t)kBK, ext - s0);   // valid contraction rows of the step
+    const int64_t s0 = st * R;
+    const int64_t live = min((int64_t)R, ext - s0);   // valid contraction rows of the step
     if (phase == 0) {
-      // 2 rows per pass, 128 consecutive columns per row
       const int64_t bytes = ((live - 1) * a.ldm + nk) * 4;
       const __amdgpu_buffer_rsrc_t rs = gram_rsrc(a.M + s0 * a.ldm + lo, bytes);
-      const int i = tid & 127;
-      const uint32_t vo = i < nk ? (uint32_t)(((tid >> 7) * a.ldm + i) * 4) : kOut;
+      const uint32_t vo = p_in < nk ? (uint32_t)((p_lo * a.ldm + p_in) * 4) : kOut;
+      const int pass = (int)(PR0 * a.ldm * 4);
 #pragma unroll
-      for (int q = 0; q < kBK * kT / kThreads; ++q)
-        r[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, (int)(q * 2 * a.ldm * 4), 0));
+      for (int q = 0; q < kPasses; ++q)
+        r[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, q * pass, 0));
     } else {
-      // 8 rows of N_k per pass, 32 consecutive columns per row
       const int64_t bytes = nk > 0 ? ((nk - 1) * a.ldn + live) * 4 : 0;
       const __amdgpu_buffer_rsrc_t rs = gram_rsrc(a.N + lo * a.ldn + s0, bytes);
-      const int f = tid & 31;
-      const uint32_t vo = f < live ? (uint32_t)(((tid >> 5) * a.ldn + f) * 4) : kOut;
+      const uint32_t vo = p_in < live ? (uint32_t)((p_lo * a.ldn + p_in) * 4) : kOut;
+      const int pass = (int)(PR1 * a.ldn * 4);
 #pragma unroll
-      for (int q = 0; q < kBK * kT / kThreads; ++q)
-        r[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, (int)(q * 8 * a.ldn * 4), 0));
+      for (int q = 0; q < kPasses; ++q)
+        r[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, q * pass, 0));
     }
   };
   auto store = [&](int buf) {
     if (phase == 0) {
 #pragma unroll
-      for (int q = 0; q < kBK * kT / kThreads; ++q) {
-        const int row = q * 2 + (tid >> 7);
-        Xs[buf][row][lds_col(row, tid & 127)] = r[q];
-      }
+      for (int q = 0; q < kPasses; ++q) Xs[buf][lds_pos(W, p_lo + q * PR0, p_in)] = r[q];
     } else {
 #pragma unroll
-      for (int q = 0; q < kBK * kT / kThreads; ++q) {
-        const int kk = tid & 31;
-        Xs[buf][kk][lds_col(kk, q * 8 + (tid >> 5))] = r[q];
-      }
+      for (int q = 0; q < kPasses; ++q) Xs[buf][lds_pos(W, p_in, p_lo + q * PR1)] = r[q];
     }
   };
   if (nsteps > 0) {
@@ -178,9 +184,9 @@ __global__ __launch_bounds__(kThreads, 4) void block_gram_half_kernel(GramArgs a
     const int cur = (int)(st & 1);
     if (st + 1 < nsteps) load(st + 1);
     switch (code) {
-#define SBMM_GRAM_STEP(TT, AA) \
-      case TT * 4 + AA:                                                                   \
-        gram_step<TT, AA>(&Xs[cur][0][0] + lrow + 16 * hb, &Xs[cur][0][0] + lrow - 16 * hb, x0, acc); \
+#define SBMM_GRAM_STEP(TT, AA)                                                    \
+      case TT * 4 + AA:                                                           \
+        if constexpr (stage_width(TT) == W) gram_step<TT, AA>(&Xs[cur][0], lane, acc); \
         break;
       SBMM_GRAM_CASES(SBMM_GRAM_STEP)
 #undef SBMM_GRAM_STEP
@@ -189,6 +195,27 @@ __global__ __launch_bounds__(kThreads, 4) void block_gram_half_kernel(GramArgs a
     if (st + 1 < nsteps) store(cur ^ 1);
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kThreads, 4) void block_gram_half_kernel(GramArgs a, GramWs w) {
+  __shared__ float Xs[2][kStage];
+  const int k = blockIdx.x;
+  const int phase = blockIdx.y;   // 0: rows of M^k; 1: columns of N_k
+  const int64_t lo = a.off[k];
+  const int nk = (int)(a.off[k + 1] - lo);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int T = (nk + 15) >> 4;
+  const int ra = (wave + k) & 3, rb = T - 1 - ra;
+  const bool active = ra <= rb;
+  const int code = active ? T * 4 + ra : -1;
+
+  f32x4 acc[kSlots];
+#pragma unroll
+  for (int j = 0; j < kSlots; ++j) acc[j] = f32x4{};
+  const int W = stage_width(T);
+  if (W == 32) gram_loop<32>(a, Xs, phase, lo, nk, code, acc);
+  else if (W == 64) gram_loop<64>(a, Xs, phase, lo, nk, code, acc);
+  else gram_loop<128>(a, Xs, phase, lo, nk, code, acc);
   if (!active) return;
   float* out = w.g + ((int64_t)k * 2 + phase) * kGramPerOperand + lane;
   const int na = T - ra, nb = rb > ra ? T - rb : 0;
@@ -251,7 +278,7 @@ hipError_t launch_block_gram(const float* M, int64_t ldm, const float* N, int64_
 
 int64_t block_gram_max_width() { return kT; }
 
-// The 32-bit buffer offsets of the Gram kernel: 2^31 plus the largest scalar
-// offset of a step (30 rows of M, 120 rows of N) stays below 2^32 and every
-// range below 2^31.
-bool block_gram_strides_ok(int64_t ldm, int64_t ldn) { return ldm < (int64_t(1) << 24) && ldn < (int64_t(1) << 22); }
+// The 32-bit buffer offsets of the Gram kernel: a stage spans at most 128
+// rows of M or N, so every range stays below 2^31 and 2^31 plus the largest
+// scalar offset (120 rows) below 2^32.
+bool block_gram_strides_ok(int64_t ldm, int64_t ldn) { return ldm < (int64_t(1) << 22) && ldn < (int64_t(1) << 22); }

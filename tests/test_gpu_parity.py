@@ -428,20 +428,22 @@ def test_block_gram_tile_counts(h):
     assert np.all(np.abs(got - ref) <= TOL[torch.float32] * ref), np.max(np.abs(got - ref) / ref)
 
 
-def test_block_gram_large_strides(h):
-    # row strides past the Gram kernel's 32-bit offsets (M: 2^24 floats, N:
-    # 2^22) take the block-by-block product path, with the same result
+@pytest.mark.parametrize("ld_m,ld_n", [((1 << 22) - 8, (1 << 22) - 8), ((1 << 22) + 8, 8), (8, (1 << 22) + 8)])
+def test_block_gram_large_strides(h, ld_m, ld_n):
+    # row strides just below 2^22 floats take the Gram kernel at its largest
+    # 32-bit buffer offsets; at 2^22 or more they take the block-by-block
+    # product path; the same result either way
     M, N, off = wl.random_problem(3, 300, 5, 6, seed=42, skew=0.5)
-    bigM = torch.zeros((3, (1 << 24) + 8), dtype=torch.float32, device=DEV)
+    off = [0, 16, 50, 128, 131, 200, 300]
+    bigM = torch.zeros((3, max(ld_m, 300)), dtype=torch.float32, device=DEV)
     bigM[:, :300] = to_dev(M, torch.float32)
-    bigN = torch.zeros((300, (1 << 22) + 8), dtype=torch.float32, device=DEV)
+    bigN = torch.zeros((300, max(ld_n, 5)), dtype=torch.float32, device=DEV)
     bigN[:, :5] = to_dev(N, torch.float32)
     Mv, Nv = bigM[:, :300], bigN[:, :5]
     ref = om.block_product_sq(host64(Mv), host64(Nv), off)
-    for Md, Nd in ((Mv, to_dev(N, torch.float32)), (to_dev(M, torch.float32), Nv)):
-        _, bp, _ = h.exact(pk.Problem(Md, Nd, off, c=3), store=False, blocknorm=True)
-        torch.cuda.synchronize()
-        assert np.all(np.abs(host64(bp) - ref) <= TOL[torch.float32] * ref)
+    _, bp, _ = h.exact(pk.Problem(Mv, Nv, off, c=3), store=False, blocknorm=True)
+    torch.cuda.synchronize()
+    assert np.all(np.abs(host64(bp) - ref) <= TOL[torch.float32] * ref)
     del bigM, bigN
 
 
