@@ -405,7 +405,7 @@ typedef struct sbmm_batch_s* sbmm_batch;
  * workgroup). The sketched product has two forms: cfg 0..3 read the drawn
  * columns of M and rows of N in place (the gather fused into the product's
  * loads), cfg 5..9 are tile configurations 0..4 over sketches C, D first
- * gathered into a workspace the batch owns (at most 8 GiB, or one problem's
+ * gathered into a workspace the batch owns (at most 32 GiB, or one problem's
  * sketches if larger, filled by groups of problems, one gather and one
  * product launch per group); 5..9 exist when that workspace could be
  * allocated at sbmm_batch_create, and exact cfg 4 when every problem's M and

@@ -28,7 +28,7 @@
 namespace {
 
 constexpr int kProducts = 2;   // 0: exact MN, 1: sketched CD
-constexpr size_t kSketchCap = size_t(8) << 30;   // bytes of materialized sketches at a time
+constexpr size_t kSketchCap = size_t(32) << 30;  // bytes of materialized sketches at a time
 
 // Bump layout over one allocation; a pass with base == nullptr measures.
 struct Layout {

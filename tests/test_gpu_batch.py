@@ -406,7 +406,7 @@ def test_full_batched_workload_sampled(h):
         assert rel(cd, om.sketch_entries(Mh, Nh, draws, rows, cols)) < 1e-5, t
         assert rel(mn, om.exact_entries(Mh, Nh, rows, cols)) < 1e-5, t
     # both forms of the sketched product (gather fused; sketches materialized
-    # group by group, about 80 GB of them in 8 GiB groups) give the same bits
+    # group by group, about 80 GB of them in 32 GiB groups) give the same bits
     # on the register-staged tiles, and agree to float32 rounding on the
     # 256 x 256 tiles, for every problem
     b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
