@@ -13,16 +13,16 @@
 // tiles: with T = ceil(n_k / 16) index tiles, only the T (T + 1) / 2 tiles
 // (ti <= tj) the block needs are formed, the off-diagonal ones counting twice
 // in the inner product. Tile rows are dealt out in pairs (r, T - 1 - r), one
-// pair per wave (T + 1 tiles each), and the wave that takes pair 0 turns
-// with the block index, so the four SIMDs of a compute unit carry the same
-// work on average. The contraction runs over the rows of M^k (stored as
-// loaded: step k = row h, index i = column) and over the columns of N_k
-// (stored transposed), so both operands of every step come from the same LDS
-// tile layout [k][i], and the two Gram matrices of a block land in the same
-// lane layout. They are written to a workspace in that layout and a second
-// kernel forms the inner product in float64 in a fixed order. Splitting the
-// two operands over workgroups halves the accumulators a workgroup holds and
-// doubles the workgroups streaming the inputs.
+// pair per wave (T + 1 tiles; a middle row alone when T is odd), and the
+// wave that takes pair 0 turns with the block index, so the four SIMDs of a
+// compute unit carry the same work on average. The contraction runs over the
+// rows of M^k (stored as loaded: step k = row h, index i = column) and over
+// the columns of N_k (stored transposed), so both operands of every step come
+// from the same LDS layout [k][i], and the two Gram matrices of a block land
+// in the same lane layout. They are written to a workspace in that layout and
+// a second kernel forms the inner product in float64 in a fixed order.
+// Splitting the two operands over workgroups halves the accumulators a
+// workgroup holds and doubles the workgroups streaming the inputs.
 #include "common.h"
 
 namespace {
