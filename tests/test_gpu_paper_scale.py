@@ -68,6 +68,10 @@ def test_paper_scale_run(h, paper_inputs, paper_blkprod, c, prob):
         _, bpd, _ = h.exact(pk.Problem(Md, Nd, off, c), store=False, blocknorm=True)
         torch.cuda.synchronize()
         assert rel(bpd.cpu().numpy(), paper_blkprod) < 1e-5
+        # and block by block (1024 blocks of 16..112 columns, every tile count 1..7)
+        got = bpd.cpu().numpy()
+        assert np.all(np.abs(got - paper_blkprod) <= 1e-5 * paper_blkprod), \
+            float(np.max(np.abs(got - paper_blkprod) / paper_blkprod))
         bp = paper_blkprod
     r = h.run(pk.Problem(Md, Nd, off, c, prob=prob, seed=0, trial=0))
     design, *_ = om.plan(M, N, off, c, prob=prob, col_row=(col, row), blkprod_sq=bp)
