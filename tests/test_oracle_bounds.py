@@ -117,3 +117,80 @@ def test_sampled_beta_brute_force():
     w38 = om.atom_weights("stratified", "norm", off, col, row, st)
     d38 = om.make_design("stratified", off, 12, w38, g=np.ones(3))
     assert 1 - 1e-12 <= om.sampled_beta(d38, col, row) <= 1.0
+
+
+def _hand_problem(second):
+    """Two blocks of two atoms, 3 rows, 1 column, ||M||_F^2 = ||N||_F^2 = 4.
+
+    Block 0: columns e1, u = (1/2, sqrt(3)/2, 0) of M against rows 1, 1 of N:
+    s_0 = 2, ||M^0 N_0||_F^2 = ||e1 + u||^2 = 3, so 1 - v_0^2 = 1/4.
+    second = "zero": columns e1, e1 against rows 1, -1: the block product is
+    0 and s_1 = 2, so 1 - v_1^2 = 1.
+    second = "orth": columns e1, e2 against rows 1, 1: ||e1 + e2||^2 = 2,
+    s_1 = 2, so 1 - v_1^2 = 1/2.
+    """
+    u = np.array([0.5, math.sqrt(3.0) / 2.0, 0.0])
+    e1 = np.array([1.0, 0.0, 0.0])
+    e2 = np.array([0.0, 1.0, 0.0])
+    if second == "zero":
+        M = np.stack([e1, u, e1, e1], axis=1)
+        N = np.array([[1.0], [1.0], [1.0], [-1.0]])
+    else:
+        M = np.stack([e1, u, e1, e2], axis=1)
+        N = np.array([[1.0], [1.0], [1.0], [1.0]])
+    return _stats(M, N, [0, 2, 4])
+
+
+def test_bounds_hand_values_unequal_theta():
+    # theta_1 = 1/4, theta_2 = 1, c = 8, ||M||^2 ||N||^2 = 16, and
+    # delta = exp(-1/8) so that sqrt((8/beta) log(1/delta)) = sqrt(1/beta).
+    col, row, off, st, bp = _hand_problem("zero")
+    assert st.s == pytest.approx([2.0, 2.0], rel=1e-15)
+    assert bp == pytest.approx([3.0, 0.0], abs=1e-15)
+    delta = math.exp(-1.0 / 8.0)
+    c = 8
+    r2 = math.sqrt(2.0)
+    # Thm 3.3: phi = sqrt(1 - beta/4 + beta/4) / (1/4)^(1/4) = sqrt(2) for any
+    # beta; eta = phi + (theta_2/theta_1)^(1/2) sqrt(1/beta) = sqrt(2) + 2 sqrt(1/beta)
+    for beta, eta, bound in ((1.0, r2 + 2.0, 12.0 + 8.0 * r2),
+                             (0.5, 3.0 * r2, 72.0)):
+        b = om.error_bound("opt", st, c, beta, delta, bp)
+        assert b["theta1"] == pytest.approx(0.25, rel=1e-14)
+        assert b["theta2"] == 1.0
+        assert b["phi"] == pytest.approx(r2, rel=1e-13)
+        assert b["eta"] == pytest.approx(eta, rel=1e-13)
+        assert b["var_bound"] == pytest.approx(2.0 / (beta * c) * 16.0, rel=1e-13)
+        assert b["bound"] == pytest.approx(bound, rel=1e-13)
+    # Thm 4.2: phi^ = sqrt(1 - beta (1 - theta_2)) = 1; eta = 1 + sqrt(1/beta)
+    for beta, bound in ((1.0, 8.0), (0.5, 12.0 + 8.0 * r2)):
+        b = om.error_bound("norm", st, c, beta, delta, bp)
+        assert b["phi"] == pytest.approx(1.0, rel=1e-14)
+        assert b["bound"] == pytest.approx(bound, rel=1e-13)
+    # Thm 4.4 with pilot estimates 3 and 20: |1 - v^_k^2| = 1/4 and
+    # |1 - 20/4| = 4, so theta^_1 = 1/4, theta^_2 = 4 while the exact theta_2
+    # stays 1: phi~ = sqrt(4 - beta/4 + 1 * beta/4) / (4 * 1/4)^(1/4) = 2 and
+    # eta = 2 + (theta^_2/theta^_1)^(1/2) = 2 + 4 = 6 at beta = 1
+    b = om.error_bound("two_step", st, c, 1.0, delta, bp, pilot_sq=[3.0, 20.0])
+    assert b["theta1_hat"] == pytest.approx(0.25, rel=1e-14)
+    assert b["theta2_hat"] == pytest.approx(4.0, rel=1e-14)
+    assert b["phi"] == pytest.approx(2.0, rel=1e-13)
+    assert b["eta"] == pytest.approx(6.0, rel=1e-13)
+    assert b["var_bound"] == pytest.approx(8.0, rel=1e-13)
+    assert b["bound"] == pytest.approx(72.0, rel=1e-13)
+
+
+def test_bounds_hand_values_beta_terms():
+    # theta_1 = 1/4, theta_2 = 1/2, beta = 1/2, c = 8:
+    # Thm 3.3 phi^2 = (1/2 - 1/8 + 1/16) / (1/8)^(1/2) = 7 sqrt(2) / 8,
+    #         variance bound phi^2 / (beta c) * 16 = 7 sqrt(2) / 2;
+    # Thm 4.2 phi^2 = 1 - (1/2)(1/2) = 3/4, variance bound 3.
+    col, row, off, st, bp = _hand_problem("orth")
+    assert bp == pytest.approx([3.0, 2.0], rel=1e-15)
+    a = om.error_bound("opt", st, 8, 0.5, 0.1, bp)
+    assert a["theta1"] == pytest.approx(0.25, rel=1e-14)
+    assert a["theta2"] == pytest.approx(0.5, rel=1e-14)
+    assert a["phi"] ** 2 == pytest.approx(7.0 * math.sqrt(2.0) / 8.0, rel=1e-13)
+    assert a["var_bound"] == pytest.approx(7.0 * math.sqrt(2.0) / 2.0, rel=1e-13)
+    b = om.error_bound("norm", st, 8, 0.5, 0.1, bp)
+    assert b["phi"] ** 2 == pytest.approx(0.75, rel=1e-14)
+    assert b["var_bound"] == pytest.approx(3.0, rel=1e-13)

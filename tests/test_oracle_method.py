@@ -337,6 +337,74 @@ def test_integer_design_matches_real_formula_when_exact():
     assert math.isclose(om.expected_sq_error(M, N, design), real, rel_tol=1e-12)
 
 
+def _block_rule_terms(M, N, off):
+    """Per block, with library routines only: ||M^k N_k||_F (the block
+    product multiplied out), F_k = ||M^k||_F ||N_k||_F, and ||MN||_F^2."""
+    K = len(off) - 1
+    x = np.array([np.linalg.norm(M[:, off[k]:off[k + 1]] @ N[off[k]:off[k + 1], :])
+                  for k in range(K)])
+    f = np.array([np.linalg.norm(M[:, off[k]:off[k + 1]]) * np.linalg.norm(N[off[k]:off[k + 1], :])
+                  for k in range(K)])
+    return x, f, float(np.linalg.norm(M @ N) ** 2)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_block_rule_closed_forms(seed):
+    # Substituting each block rule's p_k into the block-mode mean squared
+    # error (1/c)(sum_k ||M^k N_k||_F^2 / p_k - ||MN||_F^2) gives
+    #   uniform p_k = 1/K:         (1/c)(K sum_k x_k^2 - ||MN||^2)
+    #   (1.4) p_k = F_k / sum F:   (1/c)(sum F * sum_k x_k^2 / F_k - ||MN||^2)
+    #   (1.2) p_k = x_k / sum x:   (1/c)((sum_k x_k)^2 - ||MN||^2)
+    # with x_k = ||M^k N_k||_F. The integer design samples p_hat = W / T,
+    # which is within 2^-50 of p here, so the oracle's error of the design
+    # matches these real-valued forms to 1e-12.
+    M, N, off = wl.random_problem(7, 120, 6, 9, seed=40 + seed, skew=1.2)
+    c = 5
+    x, f, mn2 = _block_rule_terms(M, N, off)
+    K = len(off) - 1
+    want = {
+        "uniform": (K * float(np.sum(x * x)) - mn2) / c,
+        "norm": (float(np.sum(f)) * float(np.sum(x * x / f)) - mn2) / c,
+        "exact": (float(np.sum(x)) ** 2 - mn2) / c,
+    }
+    for prob, ref in want.items():
+        design, *_ = om.plan(M, N, off, c, mode="block", prob=prob)
+        assert math.isclose(om.expected_sq_error(M, N, design), ref, rel_tol=1e-12), prob
+    # (1.2) is the minimum of the block-mode error over all block
+    # probabilities (Cauchy-Schwarz), strictly below the other two rules here
+    assert want["exact"] < want["norm"] and want["exact"] < want["uniform"]
+
+
+def test_block_rule_12_is_the_minimizer():
+    # Any other positive block probabilities give a larger block-mode error
+    # than (1.2); checked over random perturbations through user weights.
+    M, N, off = wl.random_problem(6, 80, 5, 7, seed=51, skew=1.0)
+    c = 4
+    x, _, mn2 = _block_rule_terms(M, N, off)
+    best, *_ = om.plan(M, N, off, c, mode="block", prob="exact")
+    e_best = om.expected_sq_error(M, N, best)
+    assert math.isclose(e_best, (float(np.sum(x)) ** 2 - mn2) / c, rel_tol=1e-12)
+    g = wl.rng(52)
+    for _ in range(50):
+        w = x * g.uniform(0.3, 3.0, size=x.shape)
+        d, *_ = om.plan(M, N, off, c, mode="block", prob="user", user_w=w)
+        assert om.expected_sq_error(M, N, d) > e_best
+
+
+def test_block_rule_12_hand_values():
+    # Orthogonal outer products: block k's product is diagonal, so
+    # ||M^k N_k||_F is the root of the sum of squares of its a_i b_i.
+    # Blocks [3, 4] -> 5, [6, 8] -> 10, [12] -> 12: p_k = 5/27, 10/27, 12/27.
+    M, N, off = _orthogonal_outer_products([3, 4, 6, 8, 12], [1] * 5, [0, 2, 4, 5])
+    design, *_ = om.plan(M, N, off, 2, mode="block", prob="exact")
+    assert np.allclose(design.p_hat(), [5 / 27, 10 / 27, 12 / 27], rtol=1e-15)
+    # (1.4) on the same blocks: F_k = ||M^k||_F ||N_k||_F = 5 sqrt(2), 10 sqrt(2), 12
+    design, *_ = om.plan(M, N, off, 2, mode="block", prob="norm")
+    tot = 15 * math.sqrt(2) + 12
+    assert np.allclose(design.p_hat(), [5 * math.sqrt(2) / tot, 10 * math.sqrt(2) / tot, 12 / tot],
+                       rtol=1e-15)
+
+
 def _orthogonal_outer_products(alpha, beta, blocks):
     """M, N whose outer products M^(i) N_(i) = alpha_i beta_i E_{i,i} are
     mutually orthogonal: a_i b_i = alpha_i beta_i and ||M^k N_k||_F^2 is the
