@@ -84,6 +84,7 @@ struct sbmm_batch_s {
   void* gather_args = nullptr;            // T gather records, group-major
   int64_t* gather_wg = nullptr;           // per group its count + 1 workgroup offsets (T + G entries)
   bool exact_lds = false;                 // every exact product can take the 256 x 256 tiles
+  bool sketch_lds = false;                // every product over a materialized sketch can take them
 };
 
 namespace {
@@ -158,7 +159,7 @@ bool cfg_ok(const sbmm_batch b, int g, int cfg) {
   const int tile = mat ? cfg - grouped_cfg_count() : cfg;
   if (tile != 4) return true;
   if (g == 0) return b->exact_lds;
-  return mat;
+  return mat && b->sketch_lds;
 }
 
 // Rebuild and upload the tables of product g for configuration (cfg, lpt).
@@ -320,6 +321,10 @@ void setup_materialized(sbmm_batch b, const std::vector<int64_t>& lpm,
     }
     b->grp_wg[gi] = wg.back();
   }
+  // the 256 x 256 tiles address a panel with 32-bit offsets: a sketch width
+  // (C's leading dimension) past about 2^21 floats rules them out
+  b->sketch_lds = true;
+  for (int32_t t = 0; t < T; ++t) b->sketch_lds = b->sketch_lds && grouped_lds_ok(b->mat_launch[t]);
   hipError_t e = hipMemcpy(b->gather_args, gargs.data(), gargs.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->gather_wg, wg.data(), sizeof(int64_t) * wg.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {

@@ -308,6 +308,31 @@ def test_wide_tiles_in_batches(h):
         b.close()
 
 
+def test_wide_sketch_rules_out_wide_tiles(h):
+    # one block of 16384 columns drawn 128 times: the materialized sketch C has
+    # a leading dimension of 2^21 floats, past the 32-bit panel offsets of the
+    # 256 x 256 tiles, so the materialized configuration 9 is refused and not
+    # timed, and the other configurations still give the oracle's result
+    n, m, p = 16384, 2, 4
+    g = wl.rng(300)
+    M = g.standard_normal((m, n)).astype(np.float32)
+    N = g.standard_normal((n, p)).astype(np.float32)
+    probs = [dict(M=padded(M, n), N=padded(N, p), off=[0, n], c=128, prob="norm", seed=0, trial=0)]
+    b = pk.Batch(h, probs)
+    try:
+        with pytest.raises(pk.SbmmError):
+            b.set_tuning({"cfg": [0, 9], "lpt": [1, 1]})
+        t = b.tune(reps=1)
+        assert t["ms"][1][18] == -1.0 and t["ms"][1][19] == -1.0
+        assert t["cfg"][1] != 9
+        b.run()
+        torch.cuda.synchronize()
+        o = oracle_problem(M, N, [0, n], 128, "norm", 0)
+        check_against_oracle(b, probs, [(M, N, [0, n])], 0, o)
+    finally:
+        b.close()
+
+
 def test_graph_sees_new_inputs(small_batch):
     # the graph holds pointers, not values: new contents of M give new results
     b, probs, host = small_batch
