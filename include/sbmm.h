@@ -205,6 +205,27 @@ sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* prob,
                       const double* blk, const sbmm_plan_out* out,
                       int64_t* L_host, sbmm_stream stream);
 
+/* sbmm_plan for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels, arguments, outputs and status reporting as sbmm_plan, but every
+ * scratch buffer of the design and the draws, and the device copy of the
+ * partition, lives in a fixed array of SBMM_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends; the call
+ * neither grows nor touches the handle's workspace and calls no allocating
+ * routine. The array is shared by every call on that GPU, from any handle or
+ * thread, and keeps the last call's contents: calls that overlap on one GPU
+ * (different streams, or threads) race and must be ordered by the caller.
+ * A problem whose plan needs more scratch than the array holds is rejected
+ * with SBMM_E_ARG before anything is enqueued (about 16 bytes per atom plus
+ * 48 bytes per stratum and 8 per draw: block mode with up to ~10^6 blocks, or
+ * stratified mode with n up to ~10^6). The block offsets are copied from the
+ * host with hipMemcpyAsync. */
+enum { SBMM_NOALLOC_SCRATCH_BYTES = 16 << 20 };
+sbmm_status sbmm_plan_noalloc(sbmm_handle h, const sbmm_problem* prob,
+                              const double* col_sq, const double* row_sq,
+                              const double* blk, const sbmm_plan_out* out,
+                              int64_t* L_host, sbmm_stream stream);
+
 /* Step 1 of the two-step algorithm (Alg. 3): in every block k, Alg. 1 with
  * [c0 / K] draws (prob->c0) and the pilot probabilities prob->pilot_prob
  * (UNIFORM: 1/n_k; NORM: (3.8)), i.e. a stratified plan whose draws read the

@@ -34,8 +34,9 @@ EXPORTS = (
     "sbmm_batch_create", "sbmm_batch_destroy", "sbmm_batch_run", "sbmm_batch_capture",
     "sbmm_batch_replay", "sbmm_batch_tune", "sbmm_batch_set_tuning",
     "sbmm_sketch_mx", "sbmm_sketch_gemm_mx", "sbmm_pilot", "sbmm_bound",
-    "sbmm_workspace_size", "sbmm_exact_error",
+    "sbmm_workspace_size", "sbmm_exact_error", "sbmm_plan_noalloc",
 )
+NOALLOC_SCRATCH_BYTES = 16 << 20   # SBMM_NOALLOC_SCRATCH_BYTES
 # Layout of sbmm_bound's output (SBMM_BOUND_* in the header), then eta_j and
 # the bound of every delta_j.
 BOUND_FIELDS = ("theta1", "theta2", "theta1_hat", "theta2_hat", "beta", "mn", "phi",
@@ -119,6 +120,7 @@ def load_library(path=LIB_PATH):
         "sbmm_norms": (st, [vp, P(Problem_t), vp, vp, vp, vp]),
         "sbmm_exact": (st, [vp, P(Problem_t), vp, i64, vp, vp, vp]),
         "sbmm_plan": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), P(i64), vp]),
+        "sbmm_plan_noalloc": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), P(i64), vp]),
         "sbmm_pilot": (st, [vp, P(Problem_t), vp, vp, vp, P(PlanOut_t), vp, vp]),
         "sbmm_bound": (st, [vp, P(Problem_t), vp, vp, vp, vp, P(PlanOut_t), ctypes.c_double, i32,
                             P(ctypes.c_double), P(ctypes.c_double), vp]),
@@ -364,15 +366,22 @@ class Handle:
                                                _ptr(MN), s.p if store else 0, _ptr(bp), _ptr(out), _stream()))
         return out, MN, bp
 
-    def plan(self, problem, col_sq=None, row_sq=None, blk=None, sync=True):
+    def plan(self, problem, col_sq=None, row_sq=None, blk=None, sync=True, out=None):
+        return self._plan(self._lib.sbmm_plan, problem, col_sq, row_sq, blk, sync, out)
+
+    def plan_noalloc(self, problem, col_sq=None, row_sq=None, blk=None, sync=True, out=None):
+        """sbmm_plan_noalloc: the plan with its scratch in the library's fixed
+        per-GPU array (the caller's output Plan may be passed as `out`)."""
+        return self._plan(self._lib.sbmm_plan_noalloc, problem, col_sq, row_sq, blk, sync, out)
+
+    def _plan(self, fn, problem, col_sq, row_sq, blk, sync, out):
         s = problem.struct()
         sizes = sbmm_query_sizes(problem)
-        pl = Plan(problem, sizes, problem.M.device)
+        pl = out if out is not None else Plan(problem, sizes, problem.M.device)
         ps = pl.struct()
         L = ctypes.c_int64(-1)
-        self._check(self._lib.sbmm_plan(self.h, ctypes.byref(s), _ptr(col_sq), _ptr(row_sq),
-                                        _ptr(blk), ctypes.byref(ps),
-                                        ctypes.byref(L) if sync else None, _stream()))
+        self._check(fn(self.h, ctypes.byref(s), _ptr(col_sq), _ptr(row_sq), _ptr(blk), ctypes.byref(ps),
+                       ctypes.byref(L) if sync else None, _stream()))
         pl.L = L.value if sync else None
         pl.sizes = sizes
         return pl

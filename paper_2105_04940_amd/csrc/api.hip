@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -367,6 +368,33 @@ sbmm_status do_pilot(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
 // Public entry points
 // ============================================================================
 
+// Fixed scratch of sbmm_plan_noalloc, one copy per GPU, held until the
+// process ends. Host code never uses this name as an address: each device's
+// copy is found once with hipGetSymbolAddress (with that device current) and
+// that pointer is what the kernels receive.
+static __device__ __align__(256) char scratch[SBMM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<char*> g_scratch_dev;   // indexed by device; nullptr until bound
+
+sbmm_status bind_scratch(sbmm_handle h) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev.size() <= (size_t)h->device) g_scratch_dev.resize((size_t)h->device + 1, nullptr);
+  if (!g_scratch_dev[h->device]) {
+    char* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(h, SBMM_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[h->device] = ptr;
+  }
+  h->scratch = g_scratch_dev[h->device];
+  return SBMM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sbmm_status_string(sbmm_status s) {
@@ -406,6 +434,12 @@ sbmm_status sbmm_create(sbmm_handle* out, int device) {
     return SBMM_E_NOMEM;
   }
   h->off_cap = 1024;
+  if (bind_scratch(h) != SBMM_OK) {
+    (void)hipFree(h->off_dev);
+    (void)hipFree(h->status);
+    delete h;
+    return SBMM_E_HIP;
+  }
   *out = h;
   return SBMM_OK;
 }
@@ -482,12 +516,12 @@ sbmm_status sbmm_exact(sbmm_handle h, const sbmm_problem* P, void* MN, int64_t l
   return SBMM_OK;
 }
 
-sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* P, const double* col_sq, const double* row_sq,
-                      const double* blk, const sbmm_plan_out* out, int64_t* L_host, sbmm_stream stream) {
+// Argument checks shared by sbmm_plan and sbmm_plan_noalloc.
+static sbmm_status plan_args(sbmm_handle h, const sbmm_problem* P, const double* col_sq, const double* row_sq,
+                      const double* blk, const sbmm_plan_out* out, sbmm_sizes* sz) {
   sbmm_status st = check_handle(h);
   if (st) return st;
-  sbmm_sizes sz;
-  if ((st = validate(h, P, &sz))) return st;
+  if ((st = validate(h, P, sz))) return st;
   if (!plan_out_ok(out)) return fail(h, SBMM_E_ARG, "plan output buffers missing");
   const int pr = eff_prob(P);
   const bool strat = P->mode == SBMM_MODE_STRATIFIED;
@@ -498,6 +532,14 @@ sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* P, const double* col_sq
   const bool need_colrow = strat && pr == SBMM_P_NORM;
   if ((need_blk && !blk) || (need_colrow && (!col_sq || !row_sq)))
     return fail(h, SBMM_E_ARG, "the rule needs the norm-pass outputs");
+  return SBMM_OK;
+}
+
+sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* P, const double* col_sq, const double* row_sq,
+                      const double* blk, const sbmm_plan_out* out, int64_t* L_host, sbmm_stream stream) {
+  sbmm_sizes sz;
+  sbmm_status st = plan_args(h, P, col_sq, row_sq, blk, out, &sz);
+  if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   Arena dry(nullptr);
   int64_t* off = nullptr;
@@ -506,6 +548,33 @@ sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* P, const double* col_sq
   if ((st = ensure_ws(h, dry.off))) return st;
   Arena ar(h->ws);
   if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+  if ((st = do_plan(h, P, sz, off, col_sq, row_sq, blk, out, ar, s))) return st;
+  if (L_host) {
+    HIP_TRY(h, hipMemcpyAsync(L_host, out->col_off + P->c, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    return read_status(h, s);
+  }
+  return SBMM_OK;
+}
+
+// The same plan with every scratch buffer, the device copy of the partition
+// included, in the GPU's fixed scratch array: no workspace growth, no
+// allocation. The dry pass measures the layout the real pass takes.
+sbmm_status sbmm_plan_noalloc(sbmm_handle h, const sbmm_problem* P, const double* col_sq, const double* row_sq,
+                              const double* blk, const sbmm_plan_out* out, int64_t* L_host, sbmm_stream stream) {
+  sbmm_sizes sz;
+  sbmm_status st = plan_args(h, P, col_sq, row_sq, blk, out, &sz);
+  if (st) return st;
+  if (!h->scratch) return fail(h, SBMM_E_STATE, "the fixed scratch array of device %d is not bound", h->device);
+  hipStream_t s = (hipStream_t)stream;
+  Arena dry(nullptr);
+  int64_t* off = dry.take<int64_t>((size_t)P->K + 1);
+  do_plan(h, P, sz, off, col_sq, row_sq, blk, out, dry, s);
+  if (dry.off > (size_t)SBMM_NOALLOC_SCRATCH_BYTES)
+    return fail(h, SBMM_E_ARG, "the plan needs %zu bytes of scratch, above the fixed %zu of sbmm_plan_noalloc",
+                dry.off, (size_t)SBMM_NOALLOC_SCRATCH_BYTES);
+  Arena ar(h->scratch);
+  off = ar.take<int64_t>((size_t)P->K + 1);
+  HIP_TRY(h, hipMemcpyAsync(off, P->block_off, sizeof(int64_t) * ((size_t)P->K + 1), hipMemcpyHostToDevice, s));
   if ((st = do_plan(h, P, sz, off, col_sq, row_sq, blk, out, ar, s))) return st;
   if (L_host) {
     HIP_TRY(h, hipMemcpyAsync(L_host, out->col_off + P->c, sizeof(int64_t), hipMemcpyDeviceToHost, s));

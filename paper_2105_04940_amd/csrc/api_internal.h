@@ -12,6 +12,7 @@ struct sbmm_handle_s {
   char err[512] = {0};
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  char* scratch = nullptr;     // this device's copy of the fixed scratch of sbmm_plan_noalloc
   int32_t* status = nullptr;   // device status word
   // device copy of the last block partition used, and its host shadow: a
   // call with the same partition enqueues no copy
