@@ -299,8 +299,10 @@ def fused_vs_materialized(h, pk, torch, Md, Nd, off, c, reps=3):
 def linear_layer_leg(h, pk, wl, torch, steps, warmup):
     """The differentiable linear layer Y ~ X W (bf16, 512 blocks of 32,
     c = 128): forward (norms, plan, gather, sketched product) and backward
-    (dC = G D^T, dD = C^T G and the scatter into dX, dW), beside the dense
-    backward G W^T, X^T G with torch's bf16 matmul for context."""
+    (draws merged per block; dX[:, drawn] = w G W_U^T and dW[drawn, :] =
+    w X_U^T G over the L_U distinct drawn columns, written by the products'
+    epilogues, the undrawn columns / rows zeroed), beside the dense backward
+    G W^T, X^T G with torch's bf16 matmul for context."""
     dev = "cuda:0"
     X, W, G = wl.linear_layer()
     off = wl.equal_blocks(X.shape[1], 512)
@@ -329,12 +331,13 @@ def linear_layer_leg(h, pk, wl, torch, steps, warmup):
         e0.record()
         pl, C, D, Y = fwd()
         e1.record()
-        dX, dW = h.backward(prob, pl, C, D, Gd)
+        dX, dW = h.backward(prob, pl, None, None, Gd, compute=torch.bfloat16)
         e2.record()
         if it >= warmup:
             fw.append((e0, e1))
             bw.append((e1, e2))
     L = int(pl.col_off[-1].item())
+    L_u = 32 * int(torch.unique(pl.idx).numel())   # distinct drawn columns
     # dense backward in bf16 for context (transposed operands made contiguous)
     G16 = Gd.to(torch.bfloat16)
     Wt = Wd.t().contiguous()
@@ -351,11 +354,13 @@ def linear_layer_leg(h, pk, wl, torch, steps, warmup):
     torch.cuda.synchronize()
     ms = lambda ev_list: float(np.mean([s.elapsed_time(e) for s, e in ev_list]))
     t_f, t_b, t_d = ms(fw), ms(bw), ms(dense)
-    bwd_flops = 2 * (2.0 * b * d_out * L)
+    bwd_flops = 2 * (2.0 * b * d_out * L_u)
     return {
         "workload": (f"linear layer X {b}x{d_in}, W {d_in}x{d_out} bf16, 512 blocks of 32, "
                      f"c={c}, G {b}x{d_out} float32"),
         "L": L,
+        "L_distinct": L_u,
+        "backward_flops": bwd_flops,
         "forward_ms": t_f,
         "backward_ms": t_b,
         "backward_TFLOPs": bwd_flops / t_b / 1e9,

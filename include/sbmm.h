@@ -323,15 +323,24 @@ sbmm_status sbmm_run(sbmm_handle h, const sbmm_problem* prob, sbmm_dtype compute
                      double* rel_host, int64_t* L_host, sbmm_stream stream);
 
 /* Gradient of <G, CD> with respect to M and N, the draws and p held fixed
- * (CD is bilinear in M and N, eq. 3.3): dC = G D^T and dD = C^T G on matrix
- * cores (bf16) or in a float64-accumulating kernel (F32 / F64), then
- * dM[:, i] = sum of scale_l dC[:, l] over the sketch columns l fed by column
- * i, dN[i, :] likewise from dD, in draw order; columns of M / rows of N that
- * no draw touched get 0. plan, C (m x L, ldc), D (L x p, ldd) come from the
- * forward (sbmm_plan / sbmm_sketch in dtype `compute`); L is the sketch width
- * (host; at most L_pad_max). G is m x p (ldg) in F64 for F64 compute, else
- * F32 (converted to bf16 inside for bf16 compute). dM (m x n, lddm) and dN
- * (n x p, lddn) are written in full in the problem's input dtype. */
+ * (CD is bilinear in M and N, eq. 3.3); columns of M / rows of N that no draw
+ * touched get 0.
+ *   F64 / F32 compute: dC = G D^T and dD = C^T G in a float64-accumulating
+ *   kernel, then dM[:, i] = sum of scale_l dC[:, l] over the sketch columns l
+ *   fed by column i, dN[i, :] likewise from dD, in draw order; C (m x L,
+ *   ldc) and D (L x p, ldd) come from the forward (sbmm_sketch in dtype
+ *   `compute`).
+ *   BF16 compute: the draws of each atom a are merged, w_a = sum of scale^2
+ *   over its draws (in draw order, float64), and for every inner index i of a
+ *   dM[:, i] = w_a G N[i, :]^T and dN[i, :] = w_a M[:, i]^T G, on the bf16
+ *   matrix instructions (float32 accumulation) over bf16(G) and the bf16
+ *   values of M and N (M and N of the problem are read; C and D are not and
+ *   may be NULL), each product written by its epilogue. The result is the
+ *   gradient of the estimator sum_t scale_t^2 M^{a_t} N_{a_t} itself.
+ * plan comes from sbmm_plan; L is the sketch width (host; at most
+ * L_pad_max; an L below the plan's width sets the status word). G is m x p
+ * (ldg) in F64 for F64 compute, else F32. dM (m x n, lddm) and dN (n x p,
+ * lddn) are written in full in the problem's input dtype. */
 sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* prob, const sbmm_plan_out* plan, int64_t L,
                           sbmm_dtype compute, const void* C, int64_t ldc, const void* D, int64_t ldd,
                           const void* G, int64_t ldg, void* dM, int64_t lddm, void* dN, int64_t lddn,

@@ -492,24 +492,27 @@ class Handle:
                                          _stream()))
         return out
 
-    def backward(self, problem, plan, C, D, G, L=None):
+    def backward(self, problem, plan, C, D, G, L=None, compute=None):
         """dM, dN of <G, CD> with the draws of `plan` held fixed (C, D from
-        the forward in the compute dtype; G float64 for float64 compute, else
-        float32). Returns tensors in the dtype of M and N."""
+        the forward in the compute dtype; bf16 compute reads M and N instead
+        and takes C = D = None with compute=torch.bfloat16; G float64 for
+        float64 compute, else float32). Returns tensors in the dtype of M
+        and N."""
         torch = _torch()
         s = problem.struct()
         ps = plan.struct()
         if L is None:
             L = plan.L if plan.L is not None else plan.sizes["L_pad_max"]
-        want = torch.float64 if C.dtype == torch.float64 else torch.float32
+        cdt = compute if compute is not None else C.dtype
+        want = torch.float64 if cdt == torch.float64 else torch.float32
         if G.dtype != want or G.stride(1) != 1:
             raise ValueError(f"G must be a row-major {want} tensor")
         dM = torch.empty((s.m, s.n), dtype=problem.M.dtype, device=problem.M.device)
         dN = torch.empty((s.n, s.p), dtype=problem.N.dtype, device=problem.N.device)
         self._check(self._lib.sbmm_backward(
-            self.h, ctypes.byref(s), ctypes.byref(ps), int(L), dtype_code(C.dtype),
-            _ptr(C), C.stride(0), _ptr(D), D.stride(0), _ptr(G), G.stride(0),
-            _ptr(dM), s.n, _ptr(dN), s.p, _stream()))
+            self.h, ctypes.byref(s), ctypes.byref(ps), int(L), dtype_code(cdt),
+            _ptr(C), C.stride(0) if C is not None else 0, _ptr(D), D.stride(0) if D is not None else 0,
+            _ptr(G), G.stride(0), _ptr(dM), s.n, _ptr(dN), s.p, _stream()))
         return dM, dN
 
     def sync(self):
@@ -683,14 +686,18 @@ def _sampled_matmul_class():
             plan = h.plan(problem, col, row, blk, sync=True)
             C, D = h.sketch(problem, plan, out_dtype=compute or X.dtype)
             CD, _ = h.sketch_gemm(C, D, plan)
-            ctx.save_for_backward(C, D)
+            ctx.compute = C.dtype
+            if C.dtype == torch.bfloat16:
+                ctx.save_for_backward()       # the bf16 gradient reads X and W, not the sketch
+            else:
+                ctx.save_for_backward(C, D)
             ctx.problem, ctx.plan, ctx.h = problem, plan, h
             return CD
 
         @staticmethod
         def backward(ctx, G):
-            C, D = ctx.saved_tensors
-            dM, dN = ctx.h.backward(ctx.problem, ctx.plan, C, D, G.contiguous())
+            C, D = ctx.saved_tensors if ctx.compute != torch.bfloat16 else (None, None)
+            dM, dN = ctx.h.backward(ctx.problem, ctx.plan, C, D, G.contiguous(), compute=ctx.compute)
             return dM, dN, None, None, None, None, None, None, None
 
     return SampledMatmul

@@ -1070,13 +1070,67 @@ sbmm_status sbmm_backward(sbmm_handle h, const sbmm_problem* P, const sbmm_plan_
   const int64_t m = P->m, n = P->n, p = P->p;
   if ((m > 0 && !dM) || (p > 0 && !dN)) return fail(h, SBMM_E_ARG, "dM and dN are required");
   if ((dM && lddm < n) || (dN && lddn < p)) return fail(h, SBMM_E_ARG, "lddm < n or lddn < p");
+  // bf16: the draws merged per atom, both products over the compact width
+  // with their epilogues writing dM / dN (operands padded to whole 16-byte
+  // chunks; the 256 x 256 kernel's panels need 32-bit offsets). This form
+  // reads M and N, not C and D.
+  const int64_t ldp8 = round_up(std::max<int64_t>(p, 1), 8), ldm8 = round_up(std::max<int64_t>(m, 1), 8);
+  const bool merged = compute == SBMM_BF16 && 257 * std::max(ldp8, ldm8) * 2 < ((int64_t)1 << 31);
   if (L > 0 && m > 0 && p > 0) {
-    if (!C || !D || !G) return fail(h, SBMM_E_ARG, "C, D and G are required");
-    if (ldc < L || ldd < p || ldg < p) return fail(h, SBMM_E_ARG, "ldc < L, ldd < p or ldg < p");
+    if (!G || (!merged && (!C || !D))) return fail(h, SBMM_E_ARG, "C, D and G are required");
+    if (ldg < p || (!merged && (ldc < L || ldd < p))) return fail(h, SBMM_E_ARG, "ldc < L, ldd < p or ldg < p");
   }
   hipStream_t s = (hipStream_t)stream;
   const sbmm_dtype gd = compute == SBMM_F64 ? SBMM_F64 : SBMM_F32;   // dtype of G, dC, dD
   const size_t ges = dtype_size(gd);
+  if (merged && L > 0 && m > 0 && p > 0) {
+    const int64_t Lu = std::min<int64_t>(L, n);   // compact width bound
+    for (int pass = 0; pass < 2; ++pass) {
+      Arena ar(pass ? h->ws : nullptr);
+      int64_t* off = nullptr;
+      if ((st = upload_offsets(h, P, ar, &off, s))) return st;
+      int32_t* cnt = ar.take<int32_t>(sz.atoms);
+      int32_t* rank = ar.take<int32_t>(P->c);
+      int64_t* aoff = ar.take<int64_t>(sz.atoms + 1);
+      int32_t* list = ar.take<int32_t>(P->c);
+      BackwardDedup d{};
+      d.uoff = ar.take<int64_t>(sz.atoms);
+      d.wsum = ar.take<double>(sz.atoms);
+      d.ucol = ar.take<int32_t>(Lu);
+      d.uw = ar.take<double>(Lu);
+      d.drawn = ar.take<uint8_t>(n);
+      d.lu = ar.take<int64_t>(1);
+      uint16_t* NU = ar.take<uint16_t>((size_t)Lu * ldp8);
+      uint16_t* MUt = ar.take<uint16_t>((size_t)Lu * ldm8);
+      uint16_t* G16 = ar.take<uint16_t>((size_t)m * ldp8);
+      uint16_t* G16t = ar.take<uint16_t>((size_t)p * ldm8);
+      if (!pass) {
+        if ((st = ensure_ws(h, ar.off))) return st;
+        continue;
+      }
+      HIP_TRY(h, launch_draw_lists(plan->idx, P->c, sz.atoms, cnt, rank, aoff, list, s));
+      d.mode = P->mode; d.off_dev = off; d.K = P->K; d.A = sz.atoms; d.n = n;
+      d.cnt = cnt; d.aoff = aoff; d.list = list; d.scale = plan->scale; d.cap = Lu; d.status = h->status;
+      HIP_TRY(h, launch_dedup(d, s));
+      HIP_TRY(h, launch_g_prep(reinterpret_cast<const float*>(G), ldg, m, p, G16, ldp8, G16t, ldm8, s));
+      HIP_TRY(h, launch_gather_compact(P->in_dtype, P->N, P->ldn, p, P->M, P->ldm, m, d.ucol, d.lu, Lu, NU, ldp8,
+                                       MUt, ldm8, s));
+      HIP_TRY(h, launch_zero_undrawn(P->in_dtype, dM, lddm, m, dN, lddn, p, n, d.drawn, s));
+      GemmLaunch g1{};   // dM[:, ucol] = uw * (G N_U^T)   (m x Lu, inner p)
+      g1.dt = SBMM_BF16; g1.A = G16; g1.lda = ldp8; g1.B = NU; g1.ldb = ldp8; g1.b_trans = true;
+      g1.m = m; g1.p = Lu; g1.p_dev = d.lu; g1.K_host = ldp8;
+      g1.sc_mode = SC_COLS; g1.sc_out = dM; g1.sc_ld = lddm; g1.sc_f32 = P->in_dtype == SBMM_F32;
+      g1.sc_map = d.ucol; g1.sc_w = d.uw;
+      HIP_TRY(h, launch_gemm(g1, s));
+      GemmLaunch g2{};   // dN[ucol, :] = uw * (M_U^T G)   (Lu x p, inner m)
+      g2.dt = SBMM_BF16; g2.A = MUt; g2.lda = ldm8; g2.B = G16t; g2.ldb = ldm8; g2.b_trans = true;
+      g2.m = Lu; g2.m_dev = d.lu; g2.p = p; g2.K_host = ldm8;
+      g2.sc_mode = SC_ROWS; g2.sc_out = dN; g2.sc_ld = lddn; g2.sc_f32 = P->in_dtype == SBMM_F32;
+      g2.sc_map = d.ucol; g2.sc_w = d.uw;
+      HIP_TRY(h, launch_gemm(g2, s));
+    }
+    return SBMM_OK;
+  }
   for (int pass = 0; pass < 2; ++pass) {
     Arena ar(pass ? h->ws : nullptr);
     int64_t* off = nullptr;

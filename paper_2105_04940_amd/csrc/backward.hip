@@ -206,6 +206,222 @@ __global__ __launch_bounds__(256) void transpose_bf16_kernel(const Tin* __restri
   }
 }
 
+// ---------------------------------------------------------------------------
+// bf16 backward with the draws merged per atom. Every draw t of atom a feeds
+// the same columns of M and rows of N, so the gradient of the estimator
+// sum_t scale_t^2 M^{a_t} N_{a_t} is w_a G N_a^T for the columns of atom a
+// and w_a M^{aT} G for its rows, w_a = sum of scale_t^2 over a's draws: the
+// drawn atoms are compacted once (each drawn inner index is one column of the
+// compact operands), the two products run over the compact width L_U <= L,
+// and their epilogues write w_a times the product straight into dM / dN.
+// ---------------------------------------------------------------------------
+
+// One workgroup: per atom the compact offset (-1 if undrawn) and w_a summed
+// over its draws in draw order; the compact width, at most cap, goes to *lu.
+__global__ __launch_bounds__(1024) void dedup_atoms_kernel(int mode, const int64_t* __restrict__ off, int64_t A,
+                                                           const int32_t* __restrict__ cnt,
+                                                           const int64_t* __restrict__ aoff,
+                                                           const int32_t* __restrict__ list,
+                                                           const double* __restrict__ scale,
+                                                           int64_t* __restrict__ uoff, double* __restrict__ wsum,
+                                                           int64_t cap, int64_t* __restrict__ lu,
+                                                           int32_t* __restrict__ status) {
+  __shared__ int64_t sm[1024];
+  const int nt = blockDim.x;
+  const int64_t per = (A + nt - 1) / nt;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min(A, b0 + per);
+  auto width = [&](int64_t a) { return mode == SBMM_MODE_BLOCK ? off[a + 1] - off[a] : (int64_t)1; };
+  int64_t local = 0;
+  for (int64_t a = b0; a < b1; ++a)
+    if (cnt[a] > 0) local += width(a);
+  sm[threadIdx.x] = local;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {
+    const int64_t add = (int)threadIdx.x >= o ? sm[threadIdx.x - o] : 0;
+    __syncthreads();
+    sm[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t run = sm[threadIdx.x] - local;
+  for (int64_t a = b0; a < b1; ++a) {
+    if (cnt[a] > 0) {
+      double w = 0.0;
+      for (int64_t q = aoff[a]; q < aoff[a + 1]; ++q) {
+        const double sc = scale[list[q]];
+        w += sc * sc;
+      }
+      uoff[a] = run;
+      wsum[a] = w;
+      run += width(a);
+    } else {
+      uoff[a] = -1;
+      wsum[a] = 0.0;
+    }
+  }
+  if (threadIdx.x == nt - 1) {
+    // the compact width cannot pass the sketch width the caller sized for;
+    // a smaller L than the plan's is an argument error
+    *lu = min(sm[nt - 1], cap);
+    if (sm[nt - 1] > cap) *status = SBMM_DEV_USER_CK;
+  }
+}
+
+// One thread per inner index: its compact column (map and weight) if its
+// atom was drawn, and the drawn flag every index gets.
+__global__ __launch_bounds__(kThreads) void dedup_cols_kernel(int mode, const int64_t* __restrict__ off, int32_t K,
+                                                              int64_t n, const int64_t* __restrict__ uoff,
+                                                              const double* __restrict__ wsum,
+                                                              int32_t* __restrict__ ucol, double* __restrict__ uw,
+                                                              uint8_t* __restrict__ drawn, int64_t cap) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  int64_t atom = i, lo = i;
+  if (mode == SBMM_MODE_BLOCK) {
+    int64_t a = 0, b = K;            // last block with off[k] <= i
+    while (b - a > 1) {
+      const int64_t mid = (a + b) >> 1;
+      if (off[mid] <= i) a = mid; else b = mid;
+    }
+    atom = a;
+    lo = off[a];
+  }
+  const int64_t u = uoff[atom];
+  drawn[i] = u >= 0;
+  if (u >= 0 && u + (i - lo) < cap) {
+    ucol[u + (i - lo)] = (int32_t)i;
+    uw[u + (i - lo)] = wsum[atom];
+  }
+}
+
+template <typename T> __device__ __forceinline__ uint16_t to_bf16(T x);
+template <> __device__ __forceinline__ uint16_t to_bf16<uint16_t>(uint16_t x) { return x; }
+template <> __device__ __forceinline__ uint16_t to_bf16<float>(float x) { return float_to_bf16_bits(x); }
+
+// NU[j, :] = bf16(N[ucol[j], :]) for the live compact rows j < *lu, zero in
+// the columns p .. ld - 1: one wave per row, 8 elements per lane and step.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gather_rows_bf16_kernel(const T* __restrict__ N, int64_t ldn, int64_t p,
+                                                                    const int32_t* __restrict__ ucol,
+                                                                    const int64_t* __restrict__ lu, int64_t L_max,
+                                                                    uint16_t* __restrict__ out, int64_t ld) {
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= min(*lu, L_max)) return;
+  const T* src = N + (int64_t)ucol[j] * ldn;
+  uint16_t* dst = out + j * ld;
+  for (int64_t f = 8 * (int64_t)lane; f < ld; f += 512) {
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint16_t lo = f + 2 * e < p ? to_bf16<T>(src[f + 2 * e]) : 0;
+      const uint16_t hi = f + 2 * e + 1 < p ? to_bf16<T>(src[f + 2 * e + 1]) : 0;
+      w[e] = lo | (uint32_t)hi << 16;
+    }
+    *reinterpret_cast<uint4*>(dst + f) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// MUt[j, h] = bf16(M[h, ucol[j]]) for j < *lu, zero for m <= h < ld:
+// 64 x 64 tiles through LDS, reads along j (the drawn columns of a row, runs
+// of whole atoms), writes along h.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gather_cols_t_bf16_kernel(const T* __restrict__ M, int64_t ldm, int64_t m,
+                                                                      const int32_t* __restrict__ ucol,
+                                                                      const int64_t* __restrict__ lu, int64_t L_max,
+                                                                      int64_t h_tiles, uint16_t* __restrict__ out,
+                                                                      int64_t ld) {
+  __shared__ uint16_t t[64][66];
+  const int64_t j0 = (int64_t)(blockIdx.x / h_tiles) * 64, h0 = (int64_t)(blockIdx.x % h_tiles) * 64;
+  const int64_t L = min(*lu, L_max);
+  if (j0 >= L) return;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t jr = j0 + tx;
+  const int64_t col = jr < L ? (int64_t)ucol[jr] : -1;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t h = h0 + i;
+    t[i][tx] = (col >= 0 && h < m) ? to_bf16<T>(M[h * ldm + col]) : (uint16_t)0;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t j = j0 + i, h = h0 + tx;
+    if (j < L && h < ld) out[j * ld + h] = t[tx][i];
+  }
+}
+
+// G16 (m x ldp, bf16 of G, zero in columns p .. ldp - 1) and G16t (p x ldm,
+// bf16 of G^T, zero in columns m .. ldm - 1) from one read of G (m x p
+// float32), 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(kThreads) void g_prep_kernel(const float* __restrict__ G, int64_t ldg, int64_t m,
+                                                          int64_t p, int64_t c_tiles, uint16_t* __restrict__ G16,
+                                                          int64_t ldp, uint16_t* __restrict__ G16t, int64_t ldm) {
+  __shared__ uint16_t t[64][66];
+  const int64_t r0 = (int64_t)(blockIdx.x / c_tiles) * 64, c0 = (int64_t)(blockIdx.x % c_tiles) * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    const uint16_t v = (r < m && c < p) ? float_to_bf16_bits(G[r * ldg + c]) : (uint16_t)0;
+    t[i][tx] = v;
+    if (r < m && c < ldp) G16[r * ldp + c] = v;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < p && r < ldm) G16t[c * ldm + r] = t[tx][i];
+  }
+}
+
+// Zero the columns of dM (m x n, ld) whose inner index was not drawn: one
+// thread per 8-column chunk and rows h0 .. h0 + R - 1; whole undrawn chunks
+// as 16-byte stores when rows are 16-byte aligned (vec).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void zero_undrawn_cols_kernel(T* __restrict__ dM, int64_t ld, int64_t m,
+                                                                     int64_t n, const uint8_t* __restrict__ drawn,
+                                                                     int64_t chunk_blocks, int rows_per, int vec) {
+  const int64_t e = (int64_t)(blockIdx.x % chunk_blocks) * kThreads + threadIdx.x;
+  const int64_t h0 = (int64_t)(blockIdx.x / chunk_blocks) * rows_per;
+  const int64_t c0 = 8 * e;
+  if (c0 >= n) return;
+  uint32_t mask = 0;   // bit q: column c0 + q must be zeroed
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (c0 + q < n && !drawn[c0 + q]) mask |= 1u << q;
+  if (!mask) return;
+  const int64_t h1 = min(m, h0 + rows_per);
+  const bool whole = vec && mask == 0xffu;
+  for (int64_t h = h0; h < h1; ++h) {
+    T* row = dM + h * ld + c0;
+    if (whole) {
+      uint4* v = reinterpret_cast<uint4*>(row);
+#pragma unroll
+      for (int q = 0; q < (int)(8 * sizeof(T) / 16); ++q) v[q] = make_uint4(0, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (mask >> q & 1u) row[q] = T(0);
+    }
+  }
+}
+
+// Zero the rows of dN (n x p, ld) whose inner index was not drawn: one wave
+// per row, 16-byte stores when rows are 16-byte aligned (vec).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void zero_undrawn_rows_kernel(T* __restrict__ dN, int64_t ld, int64_t n,
+                                                                     int64_t p, const uint8_t* __restrict__ drawn,
+                                                                     int vec) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n || drawn[i]) return;
+  T* row = dN + i * ld;
+  constexpr int E = 16 / sizeof(T);   // elements per 16-byte store
+  int64_t f = 0;
+  if (vec) {
+    for (f = (int64_t)E * lane; f + E <= p; f += (int64_t)E * 64)
+      *reinterpret_cast<uint4*>(row + f) = make_uint4(0, 0, 0, 0);
+    f = p / E * E;
+  }
+  for (int64_t q = f + lane; q < p; q += 64) row[q] = T(0);
+}
+
 }  // namespace
 
 hipError_t launch_transpose_bf16(sbmm_dtype src_dt, const void* x, int64_t rows, int64_t cols, int64_t ldx,
@@ -286,5 +502,73 @@ hipError_t launch_gemm_strided(sbmm_dtype dt, const void* A, int64_t ars, int64_
                        (const float*)B, bks, bjs, (float*)C, ldc, M, Nc, K, tm);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_dedup(const BackwardDedup& d, hipStream_t s) {
+  hipLaunchKernelGGL(dedup_atoms_kernel, dim3(1), dim3(1024), 0, s, d.mode, d.off_dev, d.A, d.cnt, d.aoff, d.list,
+                     d.scale, d.uoff, d.wsum, d.cap, d.lu, d.status);
+  hipLaunchKernelGGL(dedup_cols_kernel, dim3((unsigned)ceil_div(d.n, kThreads)), dim3(kThreads), 0, s, d.mode,
+                     d.off_dev, d.K, d.n, d.uoff, d.wsum, d.ucol, d.uw, d.drawn, d.cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_compact(sbmm_dtype in_dt, const void* N, int64_t ldn, int64_t p, const void* M, int64_t ldm,
+                                 int64_t m, const int32_t* ucol, const int64_t* lu, int64_t L_max, uint16_t* NU,
+                                 int64_t ldnu, uint16_t* MUt, int64_t ldmu, hipStream_t s) {
+  if (L_max <= 0) return hipSuccess;
+  const dim3 gr((unsigned)ceil_div(L_max, 4));
+  const int64_t ht = ceil_div(ldmu, 64);
+  const dim3 gc((unsigned)(ceil_div(L_max, 64) * ht));
+  if (in_dt == SBMM_BF16) {
+    hipLaunchKernelGGL(gather_rows_bf16_kernel<uint16_t>, gr, dim3(kThreads), 0, s, (const uint16_t*)N, ldn, p, ucol,
+                       lu, L_max, NU, ldnu);
+    hipLaunchKernelGGL(gather_cols_t_bf16_kernel<uint16_t>, gc, dim3(kThreads), 0, s, (const uint16_t*)M, ldm, m,
+                       ucol, lu, L_max, ht, MUt, ldmu);
+  } else if (in_dt == SBMM_F32) {
+    hipLaunchKernelGGL(gather_rows_bf16_kernel<float>, gr, dim3(kThreads), 0, s, (const float*)N, ldn, p, ucol, lu,
+                       L_max, NU, ldnu);
+    hipLaunchKernelGGL(gather_cols_t_bf16_kernel<float>, gc, dim3(kThreads), 0, s, (const float*)M, ldm, m, ucol,
+                       lu, L_max, ht, MUt, ldmu);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_g_prep(const float* G, int64_t ldg, int64_t m, int64_t p, uint16_t* G16, int64_t ldp,
+                         uint16_t* G16t, int64_t ldm, hipStream_t s) {
+  if (m <= 0 || p <= 0) return hipSuccess;
+  // tiles cover the padded extents, so every padding element is written
+  const int64_t ct = ceil_div(std::max(p, ldp), 64), rt = ceil_div(std::max(m, ldm), 64);
+  hipLaunchKernelGGL(g_prep_kernel, dim3((unsigned)(rt * ct)), dim3(kThreads), 0, s, G, ldg, m, p, ct, G16, ldp, G16t,
+                     ldm);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_undrawn(sbmm_dtype out_dt, void* dM, int64_t lddm, int64_t m, void* dN, int64_t lddn,
+                               int64_t p, int64_t n, const uint8_t* drawn, hipStream_t s) {
+  const int64_t es = out_dt == SBMM_BF16 ? 2 : 4;
+  if (m > 0 && dM) {
+    const int vec = (uintptr_t)dM % 16 == 0 && (lddm * es) % 16 == 0;
+    const int64_t cb = ceil_div(ceil_div(n, 8), kThreads);
+    const int rows_per = 16;
+    const dim3 g((unsigned)(cb * ceil_div(m, rows_per)));
+    if (out_dt == SBMM_BF16)
+      hipLaunchKernelGGL(zero_undrawn_cols_kernel<uint16_t>, g, dim3(kThreads), 0, s, (uint16_t*)dM, lddm, m, n,
+                         drawn, cb, rows_per, vec);
+    else
+      hipLaunchKernelGGL(zero_undrawn_cols_kernel<float>, g, dim3(kThreads), 0, s, (float*)dM, lddm, m, n, drawn, cb,
+                         rows_per, vec);
+  }
+  if (p > 0 && dN) {
+    const int vec = (uintptr_t)dN % 16 == 0 && (lddn * es) % 16 == 0;
+    const dim3 g((unsigned)ceil_div(n, 4));
+    if (out_dt == SBMM_BF16)
+      hipLaunchKernelGGL(zero_undrawn_rows_kernel<uint16_t>, g, dim3(kThreads), 0, s, (uint16_t*)dN, lddn, n, p, drawn,
+                         vec);
+    else
+      hipLaunchKernelGGL(zero_undrawn_rows_kernel<float>, g, dim3(kThreads), 0, s, (float*)dN, lddn, n, p, drawn, vec);
+  }
   return hipGetLastError();
 }

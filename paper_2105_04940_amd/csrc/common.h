@@ -184,7 +184,15 @@ struct GemmLaunch {
   // split-K path for small outputs (launch_gemm_skinny): its workspace of
   // gemm_skinny_ws_bytes(dt, m, p, skinny_K_max, blocks) bytes
   void* skinny_ws; int64_t skinny_K_max;
+  // bf16 256 x 256 product only: output extents read on the device (at most
+  // m / p, which size the grid; tiles past them exit), and the scatter
+  // epilogue: instead of Cout, output element (r, j) goes, times sc_w[j], to
+  // sc_out[r][sc_map[j]] (SC_COLS), or times sc_w[r] to sc_out[sc_map[r]][j]
+  // (SC_ROWS), as bf16 or (sc_f32) float32, leading dimension sc_ld
+  const int64_t* m_dev; const int64_t* p_dev;
+  int sc_mode; void* sc_out; int64_t sc_ld; int sc_f32; const int32_t* sc_map; const double* sc_w;
 };
+enum { SC_NONE = 0, SC_COLS = 1, SC_ROWS = 2 };
 // Workspace of the split-K path for an m x p product with inner extent up to
 // K_max (nblk > 0: per-block norms of that many blocks); 0 when the product
 // should take the tiled kernels (large outputs, short inner extents).
@@ -256,6 +264,29 @@ struct BackwardScatter {
   int64_t L; int32_t* status;
 };
 hipError_t launch_scatter(const BackwardScatter& b, hipStream_t s);
+// bf16 backward over the drawn atoms merged: per atom the compact offset
+// uoff (-1 undrawn) and w = sum of scale^2 over its draws; per compact column
+// its inner index ucol and weight uw; per inner index the drawn flag; the
+// compact width in *lu.
+struct BackwardDedup {
+  int mode; const int64_t* off_dev; int32_t K; int64_t A, n;
+  const int32_t* cnt; const int64_t* aoff; const int32_t* list; const double* scale;
+  int64_t* uoff; double* wsum; int32_t* ucol; double* uw; uint8_t* drawn; int64_t* lu;
+  int64_t cap;        // room in ucol / uw (the compact width is clamped to it)
+  int32_t* status;    // device status word (a compact width above cap)
+};
+hipError_t launch_dedup(const BackwardDedup& d, hipStream_t s);
+// NU (L_max x ldnu) = bf16 rows ucol of N, MUt (L_max x ldmu) = bf16 of the
+// columns ucol of M transposed; rows past *lu untouched, padding zero.
+hipError_t launch_gather_compact(sbmm_dtype in_dt, const void* N, int64_t ldn, int64_t p, const void* M, int64_t ldm,
+                                 int64_t m, const int32_t* ucol, const int64_t* lu, int64_t L_max, uint16_t* NU,
+                                 int64_t ldnu, uint16_t* MUt, int64_t ldmu, hipStream_t s);
+// G16 = bf16(G) (m x ldp), G16t = bf16(G^T) (p x ldm), padding zero.
+hipError_t launch_g_prep(const float* G, int64_t ldg, int64_t m, int64_t p, uint16_t* G16, int64_t ldp,
+                         uint16_t* G16t, int64_t ldm, hipStream_t s);
+// Zero the columns of dM and rows of dN whose inner index was not drawn.
+hipError_t launch_zero_undrawn(sbmm_dtype out_dt, void* dM, int64_t lddm, int64_t m, void* dN, int64_t lddn,
+                               int64_t p, int64_t n, const uint8_t* drawn, hipStream_t s);
 hipError_t launch_gemm_strided(sbmm_dtype dt, const void* A, int64_t ars, int64_t aks, const void* B,
                                int64_t bks, int64_t bjs, void* C, int64_t ldc, int64_t M, int64_t Nc,
                                int64_t K, hipStream_t s);

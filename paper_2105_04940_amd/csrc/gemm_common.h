@@ -29,6 +29,9 @@ struct GemmArgs {
   // colscale[k] * M[:, colmap[k]] and B row k is colscale[k] * N[colmap[k], :]
   // (colmap < 0: zero), with A = M and B = N
   const int32_t* colmap; const double* colscale;
+  // device output extents and scatter epilogue (GemmLaunch)
+  const int64_t* m_dev; const int64_t* p_dev;
+  int sc_mode; void* sc_out; int64_t sc_ld; int sc_f32; const int32_t* sc_map; const double* sc_w;
 };
 
 __device__ inline __attribute__((always_inline)) int64_t inner_extent(const GemmArgs& g) {
@@ -93,6 +96,9 @@ inline GemmArgs make_gemm_args(const GemmLaunch& L, int64_t bm, int64_t bn) {
   g.ldstage = 0;
   g.colmap = L.colmap;
   g.colscale = L.colscale;
+  g.m_dev = L.m_dev; g.p_dev = L.p_dev;
+  g.sc_mode = L.sc_mode; g.sc_out = L.sc_out; g.sc_ld = L.sc_ld; g.sc_f32 = L.sc_f32;
+  g.sc_map = L.sc_map; g.sc_w = L.sc_w;
   const int64_t es = (int64_t)dtype_size(L.dt);
   const int64_t vb = 16;
   g.vec_a = ((uintptr_t)L.A % vb == 0) && ((L.lda * es) % vb == 0);

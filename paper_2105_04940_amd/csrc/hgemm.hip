@@ -417,8 +417,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const uint16_t* bas
 }
 
 // NW waves per workgroup: 4 (one per SIMD, 128 x 128 each) or 8 (two per
-// SIMD, 128 x 64 each)
-template <int BK, int STAGES, int NW>
+// SIMD, 128 x 64 each). EPI: SC_NONE stores the float32 product (and the
+// error partials); SC_COLS / SC_ROWS scatter the weighted product into the
+// columns / rows of another matrix (the backward's dM, dN).
+template <int BK, int STAGES, int NW, int EPI>
 __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   using Tile = TnLdsTile<BK, STAGES>;
   constexpr int KC = Tile::KC;
@@ -429,6 +431,11 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   int64_t tm, tn;
   tile_coords(g, tm, tn);
   const int64_t m0 = tm * Tile::BM, n0 = tn * Tile::BN;
+  // output extents: the grid covers m x p, the live part may be smaller
+  // (read on the device); a tile past it leaves before any barrier
+  if (g.m_dev) g.m = min(g.m, *g.m_dev);
+  if (g.p_dev) g.p = min(g.p, *g.p_dev);
+  if (m0 >= g.m || n0 >= g.p) return;
   const int64_t K = inner_extent(g);
   const int tid = threadIdx.x, lane = tid & 63;
   // uniform across the wave: the LDS destination of a load is a scalar
@@ -507,6 +514,46 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
     compute((int)(kt % STAGES));
   }
 
+  if constexpr (EPI != SC_NONE) {
+    // weighted scatter: consecutive lanes hold consecutive columns, so a
+    // store instruction writes 32-element runs wherever the map is contiguous
+    uint16_t* __restrict__ o16 = reinterpret_cast<uint16_t*>(g.sc_out);
+    float* __restrict__ o32 = reinterpret_cast<float*>(g.sc_out);
+    int64_t cdst[CB];
+    double cw[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int64_t col = n0 + wn0 + 32 * c + lr;
+      const bool ok = col < g.p;
+      cdst[c] = EPI == SC_COLS ? (ok ? (int64_t)g.sc_map[col] : -1) : col;
+      cw[c] = (EPI == SC_COLS && ok) ? g.sc_w[col] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
+        if (row >= g.m) continue;
+        int64_t rdst = row;
+        double rw = 1.0;
+        if constexpr (EPI == SC_ROWS) {
+          rdst = g.sc_map[row];
+          rw = g.sc_w[row];
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const int64_t col = n0 + wn0 + 32 * c + lr;
+          if (col >= g.p) continue;
+          const double w = EPI == SC_COLS ? cw[c] : rw;
+          const float val = (float)(w * (double)acc[b][c][v]);
+          const int64_t e = rdst * g.sc_ld + cdst[c];
+          if (g.sc_f32) o32[e] = val;
+          else o16[e] = float_to_bf16_bits(val);
+        }
+        if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    return;
+  }
   float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
   const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
   double e2 = 0.0, n2 = 0.0;
@@ -577,9 +624,24 @@ hipError_t launch_hgemm(const GemmLaunch& L, hipStream_t s) {
     const int64_t ld = std::max(L.lda, L.ldb);
     const bool fits = 257 * ld * 2 < ((int64_t)1 << 31);
     const bool chunks = L.K_dev != nullptr || L.K_host % 8 == 0;
-    if (g.vec_a && g.vec_b && fits && chunks)
-      hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES, TN_WAVES>), dim3((unsigned)tiles), dim3(TN_WAVES * 64),
-                         0, s, g);
+    const bool lds = g.vec_a && g.vec_b && fits && chunks;
+    if (L.sc_mode != SC_NONE || L.m_dev || L.p_dev) {
+      // the scatter epilogue and device extents exist on the LDS-direct kernel only
+      if (!lds) return hipErrorInvalidValue;
+      if (L.sc_mode == SC_COLS)
+        hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES, TN_WAVES, SC_COLS>), dim3((unsigned)tiles),
+                           dim3(TN_WAVES * 64), 0, s, g);
+      else if (L.sc_mode == SC_ROWS)
+        hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES, TN_WAVES, SC_ROWS>), dim3((unsigned)tiles),
+                           dim3(TN_WAVES * 64), 0, s, g);
+      else
+        hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES, TN_WAVES, SC_NONE>), dim3((unsigned)tiles),
+                           dim3(TN_WAVES * 64), 0, s, g);
+      return hipGetLastError();
+    }
+    if (lds)
+      hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES, TN_WAVES, SC_NONE>), dim3((unsigned)tiles),
+                         dim3(TN_WAVES * 64), 0, s, g);
     else
       hipLaunchKernelGGL(hgemm_tn_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, g);
     return hipGetLastError();

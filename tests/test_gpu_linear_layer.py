@@ -3,9 +3,9 @@
 upstream gradient G 8192 x 8192 ~ N(0,1), through SampledMatmul.
 
 The oracle draws from its own norms; the gradients are checked on a seeded
-sample of columns of dX and rows of dW against float64 products of the same
-bf16-rounded operands (the scaled sketch and G), and every untouched column /
-row must be exactly zero."""
+sample of columns of dX and rows of dW against float64 products of the bf16
+operands (X, W and G rounded to bf16) with each block's draws merged (the sum
+of scale^2), and every untouched column / row must be exactly zero."""
 import numpy as np
 import pytest
 
@@ -55,23 +55,17 @@ def test_linear_layer_full_size():
     Gq = bf16_round(G)
     g = wl.rng(5)
     cols = g.choice(np.nonzero(hit)[0], size=12, replace=False)
-    # the draws feeding each sampled inner index, with their sketch positions
+    # the gradient of the estimator: each sampled inner index gets the sum of
+    # scale^2 over the draws of its block times G W[i, :]^T (dX) and
+    # X[:, i]^T G (dW), over the bf16 values the kernels multiply
     ref_x, ref_w, got_x, got_w = [], [], [], []
     for i in cols:
-        sx = np.zeros(G.shape[0])
-        sw = np.zeros(G.shape[1])
-        for t in range(len(draws.atom)):
-            lo, wd, c0 = int(draws.lo[t]), int(draws.width[t]), int(draws.col_off[t])
-            if lo <= i < lo + wd:
-                s = draws.scale[t]
-                d_row = bf16_round(s * Wh[i, :])        # row of D fed by i
-                c_col = bf16_round(s * Xh[:, i])        # column of C fed by i
-                sx += s * (Gq @ d_row)
-                sw += s * (c_col @ Gq)
-        ref_x.append(sx)
-        ref_w.append(sw)
+        f = sum(draws.scale[t] ** 2 for t in range(len(draws.atom))
+                if draws.lo[t] <= i < draws.lo[t] + draws.width[t])
+        ref_x.append(f * (Gq @ Wh[i, :]))
+        ref_w.append(f * (Xh[:, i] @ Gq))
         got_x.append(dX[:, i])
         got_w.append(dW[i, :])
-    # bf16 outputs: a few bf16 units of the float64 reference
-    assert rel(np.array(got_x), np.array(ref_x)) < 1e-2
-    assert rel(np.array(got_w), np.array(ref_w)) < 1e-2
+    # bf16 outputs: within the bf16 rounding of the float64 reference
+    assert rel(np.array(got_x), np.array(ref_x)) < 4e-3
+    assert rel(np.array(got_w), np.array(ref_w)) < 4e-3

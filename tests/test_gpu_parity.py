@@ -660,24 +660,50 @@ def test_backward_bf16_linear_layer(h):
     Y.backward(Gd)
     Xh, Wh = host64(Xd), host64(Wd)
     o = om.run(Xh, Wh, off, 32, seed=5, prob="norm")
-    ctx_idx = np.array(o.draws.atom)
-    # reference from the same bf16 operands the kernels multiply: the scaled
-    # sketch rounded to bf16 and G rounded to bf16
-    Cq, Dq = _bf16_round(o.C), _bf16_round(o.D)
-    Gq = _bf16_round(G.astype(np.float64))
-    dC = Gq @ Dq.T
-    dD = Cq.T @ Gq
-    dX = np.zeros_like(Xh)
-    dW = np.zeros_like(Wh)
-    for t in range(len(o.draws.atom)):
-        lo, wd, c0 = int(o.draws.lo[t]), int(o.draws.width[t]), int(o.draws.col_off[t])
-        dX[:, lo:lo + wd] += o.draws.scale[t] * dC[:, c0:c0 + wd]
-        dW[lo:lo + wd] += o.draws.scale[t] * dD[c0:c0 + wd]
-    # bf16 outputs: within a few bf16 units of the float64 reference
-    assert rel(host64(Xd.grad), dX) < 1e-2 and rel(host64(Wd.grad), dW) < 1e-2
+    assert np.array_equal(Y.grad_fn.plan.idx.cpu().numpy(), o.draws.atom)
+    # the gradient of the estimator over the bf16 operands the kernels
+    # multiply (X, W as stored, G rounded to bf16), draws merged per block
+    dX, dW = om.backward(Xh, Wh, o.draws, _bf16_round(G))
+    # bf16 outputs: within the bf16 rounding of the float64 reference
+    assert rel(host64(Xd.grad), dX) < 4e-3 and rel(host64(Wd.grad), dW) < 4e-3
     # and an unbiased estimate of the exact gradient G W^T (reported)
     exact = G.astype(np.float64) @ Wh.T
     print("bf16 sampled dX vs exact-product gradient:", rel(host64(Xd.grad), exact))
+
+
+# ragged extents (m, p not multiples of 8, uneven blocks), many duplicate
+# draws (c above K), stratified mode, float32 and bf16 inputs
+BF16_BACKWARD = [
+    dict(m=203, n=517, p=139, K=9, c=40, mode="block", dtype=torch.bfloat16),
+    dict(m=203, n=517, p=139, K=9, c=40, mode="block", dtype=torch.float32),
+    dict(m=300, n=700, p=260, K=7, c=300, mode="stratified", dtype=torch.bfloat16),
+    dict(m=64, n=2000, p=520, K=40, c=300, mode="block", dtype=torch.float32),
+]
+
+
+@pytest.mark.parametrize("d", BF16_BACKWARD)
+def test_backward_bf16_merged_matches_oracle(h, d):
+    M, N, off = wl.random_problem(d["m"], d["n"], d["p"], d["K"], seed=48, skew=1.0)
+    dt = d["dtype"]
+    Md, Nd = to_dev(M, dt), to_dev(N, dt)
+    Mq, Nq = host64(Md), host64(Nd)          # the values the GPU holds
+    kw = dict(mode=d["mode"], prob="norm", alloc="norm", seed=9)
+    prob = pk.Problem(Md, Nd, off, d["c"], **kw)
+    col, row, blk = h.norms(prob)
+    pl = h.plan(prob, col, row, blk)
+    G = wl.rng(49).standard_normal((d["m"], d["p"]))
+    dM, dN = h.backward(prob, pl, None, None, to_dev(G, torch.float32), compute=torch.bfloat16)
+    o = om.run(Mq, Nq, off, d["c"], **kw)
+    assert np.array_equal(pl.idx.cpu().numpy(), o.draws.atom)
+    # products of the bf16 values of M, N and G: float32 outputs carry only
+    # float32 accumulation, bf16 outputs their own rounding
+    odM, odN = om.backward(_bf16_round(Mq), _bf16_round(Nq), o.draws, _bf16_round(G))
+    tol = 1e-5 if dt == torch.float32 else 4e-3
+    assert rel(host64(dM), odM) < tol and rel(host64(dN), odN) < tol
+    hit = np.zeros(d["n"], bool)
+    for lo, w in zip(o.draws.lo, o.draws.width):
+        hit[lo:lo + w] = True
+    assert np.all(host64(dM)[:, ~hit] == 0) and np.all(host64(dN)[~hit] == 0)
 
 
 @pytest.mark.parametrize("kw", [dict(prob="exact", dtype=torch.float32),
