@@ -14,22 +14,36 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRowsC = 16;   // rows of C per workgroup
-constexpr int kRowsD = 4;    // rows of D per workgroup (one per wave)
+constexpr int kColsC = 4;                  // consecutive sketch columns per thread
+constexpr int kTileC = kThreads * kColsC;  // sketch columns per workgroup of C
+constexpr int kRowsC = 16;                 // rows of C per workgroup
+constexpr int kRowsD = 4;                  // rows of D per workgroup (one per wave)
+constexpr int kBatch = 4;                  // loads a thread issues before their stores
 
-template <typename T> __device__ __forceinline__ double load_d(const void* p, int64_t i) {
-  return Elem<T>::to_double(reinterpret_cast<const T*>(p)[i]);
-}
+// Four consecutive elements through one (or, for float64, two) vector
+// memory instruction. Global vector accesses need only element alignment on
+// this target, so these are used wherever the four elements are consecutive
+// in memory.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4), aligned(4))); };
+template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4), aligned(8))); };
+template <> struct Vec4<uint16_t> { typedef uint16_t type __attribute__((ext_vector_type(4), aligned(2))); };
 
-template <typename T> __device__ __forceinline__ void store_d(void* p, int64_t i, double v);
-template <> __device__ __forceinline__ void store_d<double>(void* p, int64_t i, double v) {
-  reinterpret_cast<double*>(p)[i] = v;
+template <typename T> __device__ __forceinline__ double to_d(T x) { return Elem<T>::to_double(x); }
+
+template <typename T> __device__ __forceinline__ T from_d(double v);
+template <> __device__ __forceinline__ double from_d<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_d<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ uint16_t from_d<uint16_t>(double v) { return float_to_bf16_bits((float)v); }
+
+template <typename T> __device__ __forceinline__ void load4(const T* p, double* v) {
+  const typename Vec4<T>::type x = *reinterpret_cast<const typename Vec4<T>::type*>(p);
+  v[0] = to_d<T>(x[0]); v[1] = to_d<T>(x[1]); v[2] = to_d<T>(x[2]); v[3] = to_d<T>(x[3]);
 }
-template <> __device__ __forceinline__ void store_d<float>(void* p, int64_t i, double v) {
-  reinterpret_cast<float*>(p)[i] = (float)v;
-}
-template <> __device__ __forceinline__ void store_d<uint16_t>(void* p, int64_t i, double v) {
-  reinterpret_cast<uint16_t*>(p)[i] = float_to_bf16_bits((float)v);
+template <typename T> __device__ __forceinline__ void store4(T* p, const double* v) {
+  typename Vec4<T>::type x;
+  x[0] = from_d<T>(v[0]); x[1] = from_d<T>(v[1]); x[2] = from_d<T>(v[2]); x[3] = from_d<T>(v[3]);
+  *reinterpret_cast<typename Vec4<T>::type*>(p) = x;
 }
 
 struct GatherArgs {
@@ -44,7 +58,10 @@ struct GatherArgs {
 };
 
 // Workgroup `bid` of one problem's gather: the first cblocks workgroups
-// write C (256 sketch columns x 16 rows each), the rest D (one row per wave).
+// write C (1024 sketch columns x 16 rows each, four consecutive columns per
+// thread: one vector load when they are four consecutive columns of M, as
+// inside a drawn block, one vector store), the rest D (one row per wave, four
+// consecutive elements per lane and step).
 template <typename Tin, typename Tout>
 __device__ __forceinline__ void gather_body(const GatherArgs& a, int64_t bid) {
   const int64_t L = *a.L_dev;
@@ -53,14 +70,47 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int64_t bid) {
     if (!a.C) return;
     const int64_t lt = bid % a.ctiles;
     const int64_t hb = bid / a.ctiles;
-    const int64_t l = lt * kThreads + threadIdx.x;
-    if (l >= Lp) return;
-    const int32_t j = a.colmap[l];
-    const double sc = a.colscale[l];
+    const int64_t l0 = lt * kTileC + (int64_t)threadIdx.x * kColsC;
+    if (l0 >= Lp) return;          // Lp is a multiple of 32: the four columns are all in or all out
+    int32_t j[4];
+    double sc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      j[q] = a.colmap[l0 + q];
+      sc[q] = a.colscale[l0 + q];
+    }
+    const bool run = j[0] >= 0 && j[1] == j[0] + 1 && j[2] == j[0] + 2 && j[3] == j[0] + 3;
+    const bool vst = (a.ldc % 4 == 0) && ((uintptr_t)a.C % (4 * sizeof(Tout)) == 0);
+    const Tin* M = reinterpret_cast<const Tin*>(a.M);
+    Tout* C = reinterpret_cast<Tout*>(a.C);
     const int64_t h1 = min(a.m, (hb + 1) * kRowsC);
-    for (int64_t h = hb * kRowsC; h < h1; ++h) {
-      const double v = j >= 0 ? load_d<Tin>(a.M, h * a.ldm + j) * sc : 0.0;
-      store_d<Tout>(a.C, h * a.ldc + l, v);
+    // rows in groups of kBatch: every load of a group is issued before its
+    // stores (C may not alias M, which the compiler cannot know)
+    for (int64_t hg = hb * kRowsC; hg < h1; hg += kBatch) {
+      double v[kBatch][4];
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r) {
+        const int64_t h = min(hg + r, h1 - 1);   // a short last group re-reads its last row
+        if (run) {
+          load4<Tin>(M + h * a.ldm + j[0], v[r]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[r][q] = j[q] >= 0 ? to_d<Tin>(M[h * a.ldm + j[q]]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r) {
+        const int64_t h = hg + r;
+        if (h >= h1) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[r][q] = j[q] >= 0 ? v[r][q] * sc[q] : 0.0;
+        if (vst) {
+          store4<Tout>(C + h * a.ldc + l0, v[r]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) C[h * a.ldc + l0 + q] = from_d<Tout>(v[r][q]);
+        }
+      }
     }
   } else {
     if (!a.D) return;
@@ -69,10 +119,29 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int64_t bid) {
     const int lane = threadIdx.x & 63;
     const int32_t j = a.colmap[l];
     const double sc = a.colscale[l];
-    for (int64_t f = lane; f < a.p; f += 64) {
-      const double v = j >= 0 ? load_d<Tin>(a.N, (int64_t)j * a.ldn + f) * sc : 0.0;
-      store_d<Tout>(a.D, l * a.ldd + f, v);
+    const Tin* src = reinterpret_cast<const Tin*>(a.N) + (int64_t)(j >= 0 ? j : 0) * a.ldn;
+    Tout* dst = reinterpret_cast<Tout*>(a.D) + l * a.ldd;
+    const bool vst = (a.ldd % 4 == 0) && ((uintptr_t)a.D % (4 * sizeof(Tout)) == 0);
+    const int64_t p4 = vst ? a.p / 4 * 4 : 0;   // elements written four at a time
+    for (int64_t f0 = 4 * (int64_t)lane; f0 < p4; f0 += 256 * kBatch) {
+      double v[kBatch][4];
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r) {
+        const int64_t f = f0 + 256 * r;
+        if (j >= 0 && f < p4) load4<Tin>(src + f, v[r]);
+        else v[r][0] = v[r][1] = v[r][2] = v[r][3] = 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < kBatch; ++r) {
+        const int64_t f = f0 + 256 * r;
+        if (f >= p4) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[r][q] *= sc;
+        store4<Tout>(dst + f, v[r]);
+      }
     }
+    for (int64_t f = p4 + lane; f < a.p; f += 64)
+      dst[f] = from_d<Tout>(j >= 0 ? to_d<Tin>(src[f]) * sc : 0.0);
   }
 }
 
@@ -118,7 +187,7 @@ GatherArgs make_gather_args(const GatherLaunch& g, int64_t* total) {
   a.m = g.m; a.p = g.p; a.L_dev = g.L_dev;
   a.colmap = g.colmap; a.colscale = g.colscale;
   a.C = g.C; a.ldc = g.ldc; a.D = g.D; a.ldd = g.ldd;
-  a.ctiles = ceil_div(g.L_pad_max, kThreads);
+  a.ctiles = ceil_div(g.L_pad_max, kTileC);
   a.cblocks = (g.C && g.m > 0) ? a.ctiles * ceil_div(g.m, kRowsC) : 0;
   const int64_t dblocks = (g.D && g.p > 0) ? ceil_div(g.L_pad_max, kRowsD) : 0;
   *total = a.cblocks + dblocks;
