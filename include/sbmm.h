@@ -186,10 +186,12 @@ sbmm_status sbmm_norms(sbmm_handle h, const sbmm_problem* prob, double* col_sq,
  * order). MN (optional, may be NULL) gets the product in the compute dtype
  * (F64 for F64 inputs, else F32). blkprod_sq (optional, device [K]) gets
  * ||M^k N_k||_F^2 per block, the quantity (1.2) and (3.9) need: for F32
- * inputs with blocks at most 128 wide (and row strides below 2^22 floats)
- * as the inner product of the blocks' float32 Gram matrices,
- * summed in float64; otherwise from the block sums of the product itself.
- * mn_sq: device [1], required. */
+ * and BF16 inputs with blocks at most 128 wide (and row strides below 2^22
+ * elements) as the inner product of the blocks' float32 Gram matrices (bf16
+ * values promoted exactly), summed in float64; otherwise from the block sums
+ * of the product itself (F64: the float64 product; F32: the float32 product;
+ * BF16: the float32 product over exact float32 copies of M and N that the
+ * workspace holds, m n + n p floats). mn_sq: device [1], required. */
 sbmm_status sbmm_exact(sbmm_handle h, const sbmm_problem* prob, void* MN,
                        int64_t ldmn, double* blkprod_sq, double* mn_sq,
                        sbmm_stream stream);

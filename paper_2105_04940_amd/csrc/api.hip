@@ -204,27 +204,40 @@ hipError_t run_product(const GemmLaunch& G, hipStream_t s) {
 }
 
 // Exact product with optional MN store, block norms and error vs Y.
-// Block norms of float32 problems with blocks up to 128 wide come from the
-// Gram-matrix kernel (cheap, separate launch); otherwise the product kernel
-// accumulates them block by block.
+// Block norms of float32 and bf16 problems with blocks up to 128 wide come
+// from the Gram-matrix kernel (cheap, separate launch); otherwise the float32
+// product kernel accumulates them block by block (bf16 inputs promoted
+// exactly to float32 copies in the workspace first).
 sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_dev, void* MN, int64_t ldmn,
                      const void* Y, int64_t ldy, double* blkprod_sq, double* out2, Arena& ar, hipStream_t s) {
-  if (P->in_dtype == SBMM_BF16 && blkprod_sq)
-    return fail(h, SBMM_E_UNSUPPORTED, "block product norms of bf16 inputs are not built");
-  const bool gram = blkprod_sq != nullptr && P->in_dtype == SBMM_F32 && max_block_width(P) <= block_gram_max_width() &&
-                    block_gram_strides_ok(P->ldm, P->ldn);
+  const int64_t wmax = max_block_width(P);
+  const bool gram = blkprod_sq != nullptr && (P->in_dtype == SBMM_F32 || P->in_dtype == SBMM_BF16) &&
+                    wmax <= block_gram_max_width() && block_gram_strides_ok(P->ldm, P->ldn);
   if (gram) {
-    void* gws = ar.take<char>(block_gram_ws_bytes(P->K));
+    void* gws = ar.take<char>(block_gram_ws_bytes(P->K, wmax));
     if (ar.base) {
       if (P->m > 0 && P->p > 0) {
-        HIP_TRY(h, launch_block_gram(reinterpret_cast<const float*>(P->M), P->ldm,
-                                     reinterpret_cast<const float*>(P->N), P->ldn, P->m, P->p, off_dev,
-                                     P->K, blkprod_sq, gws, s));
+        HIP_TRY(h, launch_block_gram(P->in_dtype, P->M, P->ldm, P->N, P->ldn, P->m, P->p, off_dev, P->K, wmax,
+                                     blkprod_sq, gws, s));
       } else {
         HIP_TRY(h, launch_fill_f64(blkprod_sq, P->K, 0.0, s));
       }
     }
     blkprod_sq = nullptr;   // the product kernel below needs no block bookkeeping
+  }
+  if (P->in_dtype == SBMM_BF16 && blkprod_sq) {
+    // wide blocks of a bf16 problem: the float32 product with per-block sums
+    // over exact float32 copies of M and N
+    sbmm_problem Q = *P;
+    float* M32 = ar.take<float>((size_t)P->m * P->n);
+    float* N32 = ar.take<float>((size_t)P->n * P->p);
+    if (ar.base) {
+      HIP_TRY(h, launch_bf16_to_f32(reinterpret_cast<const uint16_t*>(P->M), P->m, P->n, P->ldm, M32, P->n, s));
+      HIP_TRY(h, launch_bf16_to_f32(reinterpret_cast<const uint16_t*>(P->N), P->n, P->p, P->ldn, N32, P->p, s));
+    }
+    Q.in_dtype = SBMM_F32;
+    Q.M = M32; Q.ldm = P->n; Q.N = N32; Q.ldn = P->p;
+    return do_exact(h, &Q, off_dev, MN, ldmn, Y, ldy, blkprod_sq, out2, ar, s);
   }
   const bool bn = blkprod_sq != nullptr;
   const int64_t tiles = gemm_tiles(P->in_dtype, P->m, P->p, bn);

@@ -21,19 +21,43 @@ namespace {
 constexpr int kThreads = 256;
 
 // One workgroup: per-atom counts and offsets, and the draws of each atom in
-// ascending draw order.
+// ascending draw order. The ranks come from one thread walking the draws in
+// order (chunks of the draw list staged in LDS), or for at most kParRank
+// draws from every thread counting the equal draws before its own; with up
+// to kLdsAtoms atoms the counts live in LDS.
+constexpr int kLdsAtoms = 8192, kIdxChunk = 2048, kParRank = 512;
+
 __global__ __launch_bounds__(kThreads) void draw_lists_kernel(const int32_t* __restrict__ idx, int64_t c,
                                                               int64_t A, int32_t* __restrict__ cnt,
                                                               int32_t* __restrict__ rank,
                                                               int64_t* __restrict__ aoff,
                                                               int32_t* __restrict__ list) {
   __shared__ int64_t sm[kThreads];
-  for (int64_t a = threadIdx.x; a < A; a += kThreads) cnt[a] = 0;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int64_t t = 0; t < c; ++t) {
-      const int32_t a = idx[t];
-      rank[t] = a >= 0 ? cnt[a]++ : -1;
+  __shared__ int32_t scnt[kLdsAtoms];
+  __shared__ int32_t sidx[kIdxChunk];
+  const bool lds = A <= kLdsAtoms;
+  int32_t* cn = lds ? scnt : cnt;
+  for (int64_t a = threadIdx.x; a < A; a += kThreads) cn[a] = 0;
+  for (int64_t c0 = 0; c0 < c; c0 += kIdxChunk) {
+    const int64_t nc = min((int64_t)kIdxChunk, c - c0);
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < nc; t += kThreads) sidx[t] = idx[c0 + t];
+    __syncthreads();
+    if (c <= kParRank) {
+      // few draws: each thread ranks its draws by counting the equal earlier
+      // ones (broadcast LDS reads), and the counts come from LDS atomics
+      for (int64_t t = threadIdx.x; t < nc; t += kThreads) {
+        const int32_t a = sidx[t];
+        int32_t r = 0;
+        for (int64_t u = 0; u < t; ++u) r += sidx[u] == a;
+        rank[t] = a >= 0 ? r : -1;
+        if (a >= 0) atomicAdd(&cn[a], 1);
+      }
+    } else if (threadIdx.x == 0) {
+      for (int64_t t = 0; t < nc; ++t) {
+        const int32_t a = sidx[t];
+        rank[c0 + t] = a >= 0 ? cn[a]++ : -1;
+      }
     }
   }
   __syncthreads();
@@ -41,7 +65,7 @@ __global__ __launch_bounds__(kThreads) void draw_lists_kernel(const int32_t* __r
   const int64_t per = (A + kThreads - 1) / kThreads;
   const int64_t b0 = (int64_t)threadIdx.x * per, b1 = min(A, b0 + per);
   int64_t local = 0;
-  for (int64_t a = b0; a < b1; ++a) local += cnt[a];
+  for (int64_t a = b0; a < b1; ++a) local += cn[a];
   sm[threadIdx.x] = local;
   __syncthreads();
   for (int o = 1; o < kThreads; o <<= 1) {
@@ -53,7 +77,8 @@ __global__ __launch_bounds__(kThreads) void draw_lists_kernel(const int32_t* __r
   int64_t run = sm[threadIdx.x] - local;
   for (int64_t a = b0; a < b1; ++a) {
     aoff[a] = run;
-    run += cnt[a];
+    run += cn[a];
+    if (lds) cnt[a] = cn[a];
   }
   if (threadIdx.x == kThreads - 1) aoff[A] = sm[kThreads - 1];
   __syncthreads();
@@ -162,6 +187,16 @@ __global__ __launch_bounds__(kThreads) void gemm_strided_kernel(const T* __restr
     __syncthreads();
   }
   if (i < M && j < Nc) C[i * ldc + j] = (T)acc;
+}
+
+__global__ void bf16_to_f32_kernel(const uint16_t* __restrict__ x, int64_t rows, int64_t cols, int64_t ldx,
+                                   float* __restrict__ y, int64_t ldy) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / cols, c = e % cols;
+    y[r * ldy + c] = __uint_as_float((uint32_t)x[r * ldx + c] << 16);
+  }
 }
 
 __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t rows, int64_t cols, int64_t ldx,
@@ -298,75 +333,127 @@ template <> __device__ __forceinline__ uint16_t to_bf16<uint16_t>(uint16_t x) { 
 template <> __device__ __forceinline__ uint16_t to_bf16<float>(float x) { return float_to_bf16_bits(x); }
 
 // NU[j, :] = bf16(N[ucol[j], :]) for the live compact rows j < *lu, zero in
-// the columns p .. ld - 1: one wave per row, 8 elements per lane and step.
+// the columns p .. ld - 1: one wave per row, 8 elements per lane and step
+// (16-byte loads and stores where the source row allows: vec).
+template <typename T>
+__device__ __forceinline__ uint4 load8_bf16(const T* src, int64_t f, int64_t p, bool vec) {
+  uint16_t e[8];
+  if (vec && f + 8 <= p) {
+    if constexpr (sizeof(T) == 2) return *reinterpret_cast<const uint4*>(src + f);
+    const float4 x0 = *reinterpret_cast<const float4*>(src + f);
+    const float4 x1 = *reinterpret_cast<const float4*>(src + f + 4);
+    e[0] = to_bf16<float>(x0.x); e[1] = to_bf16<float>(x0.y); e[2] = to_bf16<float>(x0.z); e[3] = to_bf16<float>(x0.w);
+    e[4] = to_bf16<float>(x1.x); e[5] = to_bf16<float>(x1.y); e[6] = to_bf16<float>(x1.z); e[7] = to_bf16<float>(x1.w);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = f + q < p ? to_bf16<T>(src[f + q]) : (uint16_t)0;
+  }
+  return make_uint4(e[0] | (uint32_t)e[1] << 16, e[2] | (uint32_t)e[3] << 16, e[4] | (uint32_t)e[5] << 16,
+                    e[6] | (uint32_t)e[7] << 16);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void gather_rows_bf16_kernel(const T* __restrict__ N, int64_t ldn, int64_t p,
                                                                     const int32_t* __restrict__ ucol,
                                                                     const int64_t* __restrict__ lu, int64_t L_max,
-                                                                    uint16_t* __restrict__ out, int64_t ld) {
+                                                                    uint16_t* __restrict__ out, int64_t ld, int vec) {
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (j >= min(*lu, L_max)) return;
   const T* src = N + (int64_t)ucol[j] * ldn;
   uint16_t* dst = out + j * ld;
-  for (int64_t f = 8 * (int64_t)lane; f < ld; f += 512) {
-    uint32_t w[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint16_t lo = f + 2 * e < p ? to_bf16<T>(src[f + 2 * e]) : 0;
-      const uint16_t hi = f + 2 * e + 1 < p ? to_bf16<T>(src[f + 2 * e + 1]) : 0;
-      w[e] = lo | (uint32_t)hi << 16;
-    }
-    *reinterpret_cast<uint4*>(dst + f) = make_uint4(w[0], w[1], w[2], w[3]);
-  }
+  for (int64_t f = 8 * (int64_t)lane; f < ld; f += 512)
+    *reinterpret_cast<uint4*>(dst + f) = load8_bf16<T>(src, f, p, vec != 0);
 }
 
 // MUt[j, h] = bf16(M[h, ucol[j]]) for j < *lu, zero for m <= h < ld:
-// 64 x 64 tiles through LDS, reads along j (the drawn columns of a row, runs
-// of whole atoms), writes along h.
+// 64 x 64 tiles through LDS. A thread reads 8 consecutive compact columns of
+// a row (one 16-byte load when they are 8 consecutive, aligned columns of M:
+// runs inside an atom) and writes 8 consecutive h of an output row.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void gather_cols_t_bf16_kernel(const T* __restrict__ M, int64_t ldm, int64_t m,
                                                                       const int32_t* __restrict__ ucol,
                                                                       const int64_t* __restrict__ lu, int64_t L_max,
                                                                       int64_t h_tiles, uint16_t* __restrict__ out,
-                                                                      int64_t ld) {
-  __shared__ uint16_t t[64][66];
+                                                                      int64_t ld, int vec) {
+  __shared__ uint16_t t[64][72];
   const int64_t j0 = (int64_t)(blockIdx.x / h_tiles) * 64, h0 = (int64_t)(blockIdx.x % h_tiles) * 64;
   const int64_t L = min(*lu, L_max);
   if (j0 >= L) return;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int64_t jr = j0 + tx;
-  const int64_t col = jr < L ? (int64_t)ucol[jr] : -1;
-  for (int i = ty; i < 64; i += 4) {
+  const int tid = threadIdx.x;
+  const int jg = 8 * (tid & 7);
+  int64_t col[8];
+  bool run = vec != 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    col[q] = j0 + jg + q < L ? (int64_t)ucol[j0 + jg + q] : -1;
+    run = run && col[q] == col[0] + q;
+  }
+  run = run && col[0] >= 0 && col[0] % 8 == 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int i = (tid >> 3) + 32 * pass;
     const int64_t h = h0 + i;
-    t[i][tx] = (col >= 0 && h < m) ? to_bf16<T>(M[h * ldm + col]) : (uint16_t)0;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (h < m) {
+      const T* row = M + h * ldm;
+      if (run) {
+        v = load8_bf16<T>(row, col[0], col[0] + 8, true);
+      } else {
+        uint16_t e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = col[q] >= 0 ? to_bf16<T>(row[col[q]]) : (uint16_t)0;
+        v = make_uint4(e[0] | (uint32_t)e[1] << 16, e[2] | (uint32_t)e[3] << 16, e[4] | (uint32_t)e[5] << 16,
+                       e[6] | (uint32_t)e[7] << 16);
+      }
+    }
+    *reinterpret_cast<uint4*>(&t[i][jg]) = v;
   }
   __syncthreads();
-  for (int i = ty; i < 64; i += 4) {
-    const int64_t j = j0 + i, h = h0 + tx;
-    if (j < L && h < ld) out[j * ld + h] = t[tx][i];
+  const int hg = 8 * (tid & 7);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int jj = (tid >> 3) + 32 * pass;
+    const int64_t j = j0 + jj, h = h0 + hg;
+    if (j >= L || h >= ld) continue;
+    uint16_t e[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = t[hg + q][jj];
+    *reinterpret_cast<uint4*>(out + j * ld + h) =
+        make_uint4(e[0] | (uint32_t)e[1] << 16, e[2] | (uint32_t)e[3] << 16, e[4] | (uint32_t)e[5] << 16,
+                   e[6] | (uint32_t)e[7] << 16);
   }
 }
 
 // G16 (m x ldp, bf16 of G, zero in columns p .. ldp - 1) and G16t (p x ldm,
 // bf16 of G^T, zero in columns m .. ldm - 1) from one read of G (m x p
-// float32), 64 x 64 tiles through LDS.
+// float32), 64 x 64 tiles through LDS; a thread converts 8 consecutive
+// elements of a row (two 16-byte loads where aligned: vec) and writes 8
+// consecutive elements of a G16t row.
 __global__ __launch_bounds__(kThreads) void g_prep_kernel(const float* __restrict__ G, int64_t ldg, int64_t m,
                                                           int64_t p, int64_t c_tiles, uint16_t* __restrict__ G16,
-                                                          int64_t ldp, uint16_t* __restrict__ G16t, int64_t ldm) {
-  __shared__ uint16_t t[64][66];
+                                                          int64_t ldp, uint16_t* __restrict__ G16t, int64_t ldm,
+                                                          int vec) {
+  __shared__ uint16_t t[64][72];
   const int64_t r0 = (int64_t)(blockIdx.x / c_tiles) * 64, c0 = (int64_t)(blockIdx.x % c_tiles) * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int i = ty; i < 64; i += 4) {
-    const int64_t r = r0 + i, c = c0 + tx;
-    const uint16_t v = (r < m && c < p) ? float_to_bf16_bits(G[r * ldg + c]) : (uint16_t)0;
-    t[i][tx] = v;
-    if (r < m && c < ldp) G16[r * ldp + c] = v;
+  const int tid = threadIdx.x;
+  const int cg = 8 * (tid & 7);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int i = (tid >> 3) + 32 * pass;
+    const int64_t r = r0 + i, c = c0 + cg;
+    const uint4 v = r < m ? load8_bf16<float>(G + r * ldg, c, p, vec != 0) : make_uint4(0, 0, 0, 0);
+    *reinterpret_cast<uint4*>(&t[i][cg]) = v;
+    if (r < m && c < ldp) *reinterpret_cast<uint4*>(G16 + r * ldp + c) = v;
   }
   __syncthreads();
-  for (int i = ty; i < 64; i += 4) {
-    const int64_t c = c0 + i, r = r0 + tx;
-    if (c < p && r < ldm) G16t[c * ldm + r] = t[tx][i];
+  for (int pass = 0; pass < 2; ++pass) {
+    const int cc = (tid >> 3) + 32 * pass;
+    const int64_t c = c0 + cc, r = r0 + cg;
+    if (c >= p || r >= ldm) continue;
+    uint16_t e[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = t[cg + q][cc];
+    *reinterpret_cast<uint4*>(G16t + c * ldm + r) =
+        make_uint4(e[0] | (uint32_t)e[1] << 16, e[2] | (uint32_t)e[3] << 16, e[4] | (uint32_t)e[5] << 16,
+                   e[6] | (uint32_t)e[7] << 16);
   }
 }
 
@@ -447,6 +534,14 @@ hipError_t launch_to_bf16(const float* x, int64_t rows, int64_t cols, int64_t ld
   return hipGetLastError();
 }
 
+hipError_t launch_bf16_to_f32(const uint16_t* x, int64_t rows, int64_t cols, int64_t ldx, float* y, int64_t ldy,
+                              hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t nb = std::min<int64_t>(ceil_div(rows * cols, 256), 16384);
+  hipLaunchKernelGGL(bf16_to_f32_kernel, dim3((unsigned)nb), dim3(256), 0, s, x, rows, cols, ldx, y, ldy);
+  return hipGetLastError();
+}
+
 hipError_t launch_draw_lists(const int32_t* idx, int64_t c, int64_t A, int32_t* cnt, int32_t* rank,
                              int64_t* aoff, int32_t* list, hipStream_t s) {
   hipLaunchKernelGGL(draw_lists_kernel, dim3(1), dim3(kThreads), 0, s, idx, c, A, cnt, rank, aoff, list);
@@ -520,16 +615,20 @@ hipError_t launch_gather_compact(sbmm_dtype in_dt, const void* N, int64_t ldn, i
   const dim3 gr((unsigned)ceil_div(L_max, 4));
   const int64_t ht = ceil_div(ldmu, 64);
   const dim3 gc((unsigned)(ceil_div(L_max, 64) * ht));
+  const int64_t es = in_dt == SBMM_BF16 ? 2 : 4;
+  // 16-byte loads of 8 elements: rows of N / M start on 16-byte boundaries
+  const int vn = (uintptr_t)N % 16 == 0 && (ldn * es) % 16 == 0;
+  const int vm = (uintptr_t)M % 16 == 0 && (ldm * es) % 16 == 0;
   if (in_dt == SBMM_BF16) {
     hipLaunchKernelGGL(gather_rows_bf16_kernel<uint16_t>, gr, dim3(kThreads), 0, s, (const uint16_t*)N, ldn, p, ucol,
-                       lu, L_max, NU, ldnu);
+                       lu, L_max, NU, ldnu, vn);
     hipLaunchKernelGGL(gather_cols_t_bf16_kernel<uint16_t>, gc, dim3(kThreads), 0, s, (const uint16_t*)M, ldm, m,
-                       ucol, lu, L_max, ht, MUt, ldmu);
+                       ucol, lu, L_max, ht, MUt, ldmu, vm);
   } else if (in_dt == SBMM_F32) {
     hipLaunchKernelGGL(gather_rows_bf16_kernel<float>, gr, dim3(kThreads), 0, s, (const float*)N, ldn, p, ucol, lu,
-                       L_max, NU, ldnu);
+                       L_max, NU, ldnu, vn);
     hipLaunchKernelGGL(gather_cols_t_bf16_kernel<float>, gc, dim3(kThreads), 0, s, (const float*)M, ldm, m, ucol,
-                       lu, L_max, ht, MUt, ldmu);
+                       lu, L_max, ht, MUt, ldmu, vm);
   } else {
     return hipErrorInvalidValue;
   }
@@ -541,8 +640,9 @@ hipError_t launch_g_prep(const float* G, int64_t ldg, int64_t m, int64_t p, uint
   if (m <= 0 || p <= 0) return hipSuccess;
   // tiles cover the padded extents, so every padding element is written
   const int64_t ct = ceil_div(std::max(p, ldp), 64), rt = ceil_div(std::max(m, ldm), 64);
+  const int vec = (uintptr_t)G % 16 == 0 && (ldg * 4) % 16 == 0;
   hipLaunchKernelGGL(g_prep_kernel, dim3((unsigned)(rt * ct)), dim3(kThreads), 0, s, G, ldg, m, p, ct, G16, ldp, G16t,
-                     ldm);
+                     ldm, vec);
   return hipGetLastError();
 }
 

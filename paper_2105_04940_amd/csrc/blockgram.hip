@@ -23,6 +23,8 @@
 // a second kernel forms the inner product in float64 in a fixed order.
 // Splitting the two operands over workgroups halves the accumulators a
 // workgroup holds and doubles the workgroups streaming the inputs.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -34,19 +36,31 @@ constexpr int kT = 128;          // Gram tile (max block width)
 constexpr int kTiles = kT / 16;  // index tiles of 16
 
 struct GramArgs {
-  const float* M; int64_t ldm;
-  const float* N; int64_t ldn;
+  const void* M; int64_t ldm;   // float32 or bf16 (raw bits), the kernels' template type
+  const void* N; int64_t ldn;
   int64_t m, p;
   const int64_t* off;
   double* out;     // [K]
 };
 
+// The Gram tiles of every block: [K][2][tiles][tiles][4 values][64 lanes],
+// tiles = ceil(widest block / 16) <= kTiles, tiles ti <= tj written.
 struct GramWs {
-  float* g;        // [K][2][kTiles][kTiles][4 values][64 lanes], tiles ti <= tj written
+  float* g;
+  int tiles;
 };
 
 constexpr int64_t kTileVals = 4 * 64;
-constexpr int64_t kGramPerOperand = (int64_t)kTiles * kTiles * kTileVals;
+__device__ __forceinline__ int64_t gram_per_operand(int tiles) { return (int64_t)tiles * tiles * kTileVals; }
+
+// element loads through a buffer resource, promoted exactly to float32
+template <typename T> __device__ __forceinline__ float gram_load(__amdgpu_buffer_rsrc_t rs, uint32_t vo, int so);
+template <> __device__ __forceinline__ float gram_load<float>(__amdgpu_buffer_rsrc_t rs, uint32_t vo, int so) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+}
+template <> __device__ __forceinline__ float gram_load<uint16_t>(__amdgpu_buffer_rsrc_t rs, uint32_t vo, int so) {
+  return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, vo, so, 0) << 16);
+}
 
 // A stage holds kStage floats: R = kStage / W contraction rows of W block
 // columns, W = 32, 64 or 128 the smallest multiple of 32 (a power of two)
@@ -65,7 +79,7 @@ __device__ __forceinline__ int lds_pos(int W, int kk, int i) {
 }
 
 // Buffer resource over `bytes` bytes from `base` (fields made wave-uniform).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t gram_rsrc(const float* base, int64_t bytes) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t gram_rsrc(const void* base, int64_t bytes) {
   const uint64_t u = reinterpret_cast<uint64_t>(base);
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
@@ -124,9 +138,12 @@ __device__ __forceinline__ void gram_step(const float* xs, int lane, f32x4 (&acc
 // The stage loop of one workgroup for stage width W (uniform over the
 // block): loads of the next stage into registers, the matrix-core work of
 // the current one, stores into the other LDS buffer, one barrier per stage.
-template <int W>
+template <typename ET, int W>
 __device__ __forceinline__ void gram_loop(const GramArgs& a, float (*Xs)[kStage], int phase, int64_t lo, int nk,
                                           int code, f32x4 (&acc)[kSlots]) {
+  constexpr int ES = sizeof(ET);
+  const ET* Mp = reinterpret_cast<const ET*>(a.M);
+  const ET* Np = reinterpret_cast<const ET*>(a.N);
   constexpr int R = kStage / W;                   // contraction rows per stage
   constexpr int kPasses = kStage / kThreads;
   constexpr int PR0 = kThreads / W, PR1 = kThreads / R;   // rows per pass (phase 0: of M, 1: of N_k)
@@ -149,21 +166,19 @@ __device__ __forceinline__ void gram_loop(const GramArgs& a, float (*Xs)[kStage]
     const int64_t s0 = st * R;
     const int64_t live = min((int64_t)R, ext - s0);   // valid contraction rows of the step
     if (phase == 0) {
-      const int64_t bytes = ((live - 1) * a.ldm + nk) * 4;
-      const __amdgpu_buffer_rsrc_t rs = gram_rsrc(a.M + s0 * a.ldm + lo, bytes);
-      const uint32_t vo = p_in < nk ? (uint32_t)((p_lo * a.ldm + p_in) * 4) : kOut;
-      const int pass = (int)(PR0 * a.ldm * 4);
+      const int64_t bytes = ((live - 1) * a.ldm + nk) * ES;
+      const __amdgpu_buffer_rsrc_t rs = gram_rsrc(Mp + s0 * a.ldm + lo, bytes);
+      const uint32_t vo = p_in < nk ? (uint32_t)((p_lo * a.ldm + p_in) * ES) : kOut;
+      const int pass = (int)(PR0 * a.ldm * ES);
 #pragma unroll
-      for (int q = 0; q < kPasses; ++q)
-        r[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, q * pass, 0));
+      for (int q = 0; q < kPasses; ++q) r[q] = gram_load<ET>(rs, vo, q * pass);
     } else {
-      const int64_t bytes = nk > 0 ? ((nk - 1) * a.ldn + live) * 4 : 0;
-      const __amdgpu_buffer_rsrc_t rs = gram_rsrc(a.N + lo * a.ldn + s0, bytes);
-      const uint32_t vo = p_in < live ? (uint32_t)((p_lo * a.ldn + p_in) * 4) : kOut;
-      const int pass = (int)(PR1 * a.ldn * 4);
+      const int64_t bytes = nk > 0 ? ((nk - 1) * a.ldn + live) * ES : 0;
+      const __amdgpu_buffer_rsrc_t rs = gram_rsrc(Np + lo * a.ldn + s0, bytes);
+      const uint32_t vo = p_in < live ? (uint32_t)((p_lo * a.ldn + p_in) * ES) : kOut;
+      const int pass = (int)(PR1 * a.ldn * ES);
 #pragma unroll
-      for (int q = 0; q < kPasses; ++q)
-        r[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, q * pass, 0));
+      for (int q = 0; q < kPasses; ++q) r[q] = gram_load<ET>(rs, vo, q * pass);
     }
   };
   auto store = [&](int buf) {
@@ -197,6 +212,7 @@ __device__ __forceinline__ void gram_loop(const GramArgs& a, float (*Xs)[kStage]
   }
 }
 
+template <typename ET>
 __global__ __launch_bounds__(kThreads, 4) void block_gram_half_kernel(GramArgs a, GramWs w) {
   __shared__ float Xs[2][kStage];
   const int k = blockIdx.x;
@@ -213,17 +229,17 @@ __global__ __launch_bounds__(kThreads, 4) void block_gram_half_kernel(GramArgs a
 #pragma unroll
   for (int j = 0; j < kSlots; ++j) acc[j] = f32x4{};
   const int W = stage_width(T);
-  if (W == 32) gram_loop<32>(a, Xs, phase, lo, nk, code, acc);
-  else if (W == 64) gram_loop<64>(a, Xs, phase, lo, nk, code, acc);
-  else gram_loop<128>(a, Xs, phase, lo, nk, code, acc);
+  if (W == 32) gram_loop<ET, 32>(a, Xs, phase, lo, nk, code, acc);
+  else if (W == 64) gram_loop<ET, 64>(a, Xs, phase, lo, nk, code, acc);
+  else gram_loop<ET, 128>(a, Xs, phase, lo, nk, code, acc);
   if (!active) return;
-  float* out = w.g + ((int64_t)k * 2 + phase) * kGramPerOperand + lane;
+  float* out = w.g + ((int64_t)k * 2 + phase) * gram_per_operand(w.tiles) + lane;
   const int na = T - ra, nb = rb > ra ? T - rb : 0;
 #pragma unroll
   for (int j = 0; j < kSlots; ++j) {
     int tile = -1;
-    if (j < na) tile = ra * kTiles + ra + j;
-    else if (j < na + nb) tile = rb * kTiles + rb + (j - na);
+    if (j < na) tile = ra * w.tiles + ra + j;
+    else if (j < na + nb) tile = rb * w.tiles + rb + (j - na);
     if (tile >= 0) {
       float* o = out + tile * kTileVals;
 #pragma unroll
@@ -242,14 +258,14 @@ __global__ __launch_bounds__(kThreads) void block_gram_dot_kernel(GramArgs a, Gr
   const int nk = (int)(a.off[k + 1] - a.off[k]);
   const int T = (nk + 15) >> 4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const float* gm = w.g + (int64_t)k * 2 * kGramPerOperand + lane;
-  const float* gn = gm + kGramPerOperand;
+  const float* gm = w.g + (int64_t)k * 2 * gram_per_operand(w.tiles) + lane;
+  const float* gn = gm + gram_per_operand(w.tiles);
   double dot = 0.0;
   int e = 0;
   for (int ti = 0; ti < T; ++ti) {
     for (int tj = ti; tj < T; ++tj, ++e) {
       if ((e & 3) != wave) continue;
-      const int64_t base = (ti * kTiles + tj) * kTileVals;
+      const int64_t base = (ti * w.tiles + tj) * kTileVals;
       double ts = 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) ts = fma((double)gm[base + v * 64], (double)gn[base + v * 64], ts);
@@ -264,14 +280,28 @@ __global__ __launch_bounds__(kThreads) void block_gram_dot_kernel(GramArgs a, Gr
 
 }  // namespace
 
-size_t block_gram_ws_bytes(int32_t K) { return sizeof(float) * (size_t)K * 2 * kGramPerOperand; }
+namespace {
+int gram_tiles(int64_t max_width) { return (int)std::max<int64_t>(1, (max_width + 15) / 16); }
+}  // namespace
 
-hipError_t launch_block_gram(const float* M, int64_t ldm, const float* N, int64_t ldn, int64_t m, int64_t p,
-                             const int64_t* off_dev, int32_t K, double* out, void* ws, hipStream_t s) {
+size_t block_gram_ws_bytes(int32_t K, int64_t max_width) {
+  const size_t t = (size_t)gram_tiles(max_width);
+  return sizeof(float) * (size_t)K * 2 * t * t * kTileVals;
+}
+
+hipError_t launch_block_gram(sbmm_dtype dt, const void* M, int64_t ldm, const void* N, int64_t ldn, int64_t m,
+                             int64_t p, const int64_t* off_dev, int32_t K, int64_t max_width, double* out, void* ws,
+                             hipStream_t s) {
   if (K <= 0) return hipSuccess;
+  if (max_width > kT) return hipErrorInvalidValue;
   GramArgs a{M, ldm, N, ldn, m, p, off_dev, out};
-  GramWs w{reinterpret_cast<float*>(ws)};
-  hipLaunchKernelGGL(block_gram_half_kernel, dim3((unsigned)K, 2), dim3(kThreads), 0, s, a, w);
+  GramWs w{reinterpret_cast<float*>(ws), gram_tiles(max_width)};
+  if (dt == SBMM_F32)
+    hipLaunchKernelGGL(block_gram_half_kernel<float>, dim3((unsigned)K, 2), dim3(kThreads), 0, s, a, w);
+  else if (dt == SBMM_BF16)
+    hipLaunchKernelGGL(block_gram_half_kernel<uint16_t>, dim3((unsigned)K, 2), dim3(kThreads), 0, s, a, w);
+  else
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(block_gram_dot_kernel, dim3((unsigned)K), dim3(kThreads), 0, s, a, w);
   return hipGetLastError();
 }

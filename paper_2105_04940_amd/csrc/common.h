@@ -239,12 +239,18 @@ hipError_t launch_grouped_reduce(const double* sk_part, int64_t sk_nparts, const
 hipError_t launch_hgemm(const GemmLaunch& a, hipStream_t s);
 void hgemm_tile_shape(int64_t* bm, int64_t* bn);
 
-// ||M^k N_k||_F^2 per block through the Gram matrices (float32 inputs,
-// blocks at most block_gram_max_width() wide), one workgroup per block.
-// workspace of launch_block_gram: the two Gram matrices of every block
-size_t block_gram_ws_bytes(int32_t K);
-hipError_t launch_block_gram(const float* M, int64_t ldm, const float* N, int64_t ldn, int64_t m, int64_t p,
-                             const int64_t* off_dev, int32_t K, double* out, void* ws, hipStream_t s);
+// ||M^k N_k||_F^2 per block through the Gram matrices (float32 or bf16
+// inputs, promoted exactly; blocks at most block_gram_max_width() wide), one
+// workgroup per block and operand.
+// workspace of launch_block_gram: the two Gram matrices of every block, in
+// tiles of 16 up to the widest block
+size_t block_gram_ws_bytes(int32_t K, int64_t max_width);
+hipError_t launch_block_gram(sbmm_dtype dt, const void* M, int64_t ldm, const void* N, int64_t ldn, int64_t m,
+                             int64_t p, const int64_t* off_dev, int32_t K, int64_t max_width, double* out, void* ws,
+                             hipStream_t s);
+// y (rows x cols, leading dimension ldy) = float32 of the bf16 x (ldx)
+hipError_t launch_bf16_to_f32(const uint16_t* x, int64_t rows, int64_t cols, int64_t ldx, float* y, int64_t ldy,
+                              hipStream_t s);
 int64_t block_gram_max_width();
 // the row strides (elements) the Gram kernel's 32-bit buffer offsets cover
 bool block_gram_strides_ok(int64_t ldm, int64_t ldn);

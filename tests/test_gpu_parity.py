@@ -671,6 +671,55 @@ def test_backward_bf16_linear_layer(h):
     print("bf16 sampled dX vs exact-product gradient:", rel(host64(Xd.grad), exact))
 
 
+# bf16 block norms ||M^k N_k||_F^2: the Gram path (blocks up to 128 wide,
+# ragged widths, a block of 1) and the float32 product over promoted copies
+# (a block wider than 128)
+BF16_BLOCKNORM = [
+    dict(m=300, n=2000, p=260, off=None, K=30),
+    dict(m=77, n=500, p=45, off=[0, 1, 129, 200, 328, 400, 500], K=None),
+    dict(m=64, n=1000, p=96, off=[0, 100, 400, 1000], K=None),
+]
+
+
+@pytest.mark.parametrize("d", BF16_BLOCKNORM)
+def test_bf16_block_norms_match_oracle(h, d):
+    M, N, off = wl.random_problem(d["m"], d["n"], d["p"], d["K"] or 3, seed=50, skew=1.0)
+    if d["off"] is not None:
+        off = d["off"]
+    Md, Nd = to_dev(M, torch.bfloat16), to_dev(N, torch.bfloat16)
+    Mq, Nq = host64(Md), host64(Nd)
+    MN, bp, mn_sq = h.exact(pk.Problem(Md, Nd, off, 4), store=True, blocknorm=True)
+    ref = om.block_product_sq(Mq, Nq, off)
+    got = bp.cpu().numpy()
+    # float32 accumulation of exact products of bf16 values
+    assert np.all(np.abs(got - ref) <= 2e-5 * ref + 1e-30), float(np.max(np.abs(got - ref) / ref))
+    omn = Mq @ Nq
+    assert rel(host64(MN), omn) < 1e-5
+    assert abs(mn_sq.item() - np.sum(omn * omn)) <= 1e-5 * np.sum(omn * omn)
+
+
+def test_sampled_matmul_exact_rule_bf16(h):
+    # rule (1.2) on the linear layer's dtype: the forward's draws equal the
+    # oracle's for the same block norms
+    X, W, G = wl.linear_layer(512, 2048, 384, seed=51)
+    off = wl.equal_blocks(2048, 64)
+    Xd = to_dev(X, torch.bfloat16).requires_grad_(True)
+    Wd = to_dev(W, torch.bfloat16).requires_grad_(True)
+    Y = pk.SampledMatmul.apply(Xd, Wd, off, 24, 3, 0, "exact", None, None)
+    bp = Y.grad_fn.problem.blkprod_sq.cpu().numpy()
+    Xh, Wh = host64(Xd), host64(Wd)
+    ref = om.block_product_sq(Xh, Wh, off)
+    assert np.all(np.abs(bp - ref) <= 2e-5 * ref)
+    o = om.run(Xh, Wh, off, 24, seed=3, prob="exact", blkprod_sq=bp)
+    assert np.array_equal(Y.grad_fn.plan.idx.cpu().numpy(), o.draws.atom)
+    # the bf16 sketched product: float32 accumulation of the bf16-rounded sketch
+    Cq, Dq = _bf16_round(o.C), _bf16_round(o.D)
+    assert rel(host64(Y), Cq @ Dq) < 1e-5
+    Y.backward(to_dev(G, torch.float32))
+    dX, dW = om.backward(Xh, Wh, o.draws, _bf16_round(G))
+    assert rel(host64(Xd.grad), dX) < 4e-3 and rel(host64(Wd.grad), dW) < 4e-3
+
+
 # ragged extents (m, p not multiples of 8, uneven blocks), many duplicate
 # draws (c above K), stratified mode, float32 and bf16 inputs
 BF16_BACKWARD = [
