@@ -57,6 +57,10 @@ def parse():
                     help="the probability error bounds of Thms 3.3, 4.2, 4.4 at the Section 4 sizes")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 512-problem batched leg")
+    ap.add_argument("--no-section4-sweeps", action="store_true",
+                    help="skip the compact Table 1 sweep record of the default run")
+    ap.add_argument("--no-bound-checks", action="store_true",
+                    help="skip the compact bound-check record of the default run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -233,24 +237,104 @@ def cpu_baseline(M, N, off, target_s):
             flops += 2.0 * r * r * draws.L
             Ls.append(draws.L)
     dt = time.perf_counter() - t0
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
     return {
         "value": flops / dt / 1e12,
         "unit": "TFLOP/s",
         "cores": int(threads),
-        "cpu_model": model,
+        "cpu_model": cpu_model_string(),
         "host_cpus": os.cpu_count(),
+        "tiny_workload": tiny_oracle_seconds(),
         "kind": "oracle",
         "sample": (f"one whole step of the oracle in float64 (norms, exact MN, per-block "
                    f"norms, 9 x (design, draws, sketch, CD, error), L = {Ls}) on M[:{r}, :] "
                    f"(x{n}) and N[:, :{r}]; {dt:.1f} s"),
         "seconds": dt,
     }
+
+
+def cpu_model_string():
+    """The host CPU as /proc/cpuinfo names it, with its family / model /
+    stepping numbers and clock (a virtualized host may report only a short
+    model name)."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ":" in ln:
+                    k, v = ln.split(":", 1)
+                    info.setdefault(k.strip(), v.strip())
+    except OSError:
+        return ""
+    parts = [info.get("model name", "")]
+    ids = [f"{k} {info[k]}" for k in ("vendor_id", "cpu family", "model", "stepping") if k in info]
+    if ids:
+        parts.append("(" + ", ".join(ids) + ")")
+    if "cpu MHz" in info:
+        parts.append(f"{float(info['cpu MHz']):.0f} MHz")
+    if "cache size" in info:
+        parts.append(f"cache {info['cache size']}")
+    return " ".join(x for x in parts if x)
+
+
+def tiny_oracle_seconds(reps=5):
+    """The oracle on the tiny workload (M 256x1024, N 1024x256 float64, 64
+    blocks of 16, c = 16, rule (1.4)), whole run (norms, design, draws,
+    sketch, CD, exact MN, error): median seconds with every BLAS thread and
+    with one."""
+    import workloads as wl
+    from oracle import method as om
+    M, N, off = wl.tiny(0)
+
+    def timeit():
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            om.run(M, N, off, 16, seed=0, prob="norm")
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    out = {"all_threads_s": timeit()}
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            out["single_thread_s"] = timeit()
+    except Exception as e:   # threadpoolctl missing: report that, not a number
+        out["single_thread_s"] = None
+        out["single_thread_note"] = f"threadpoolctl unavailable: {e}"
+    return out
+
+
+def section4_sweeps_compact(r):
+    """The Table 1 sweep reduced to the mean relative error per (case,
+    experiment, point, method), 4 significant digits, and the paper's
+    findings on Case II."""
+    out = {"replications": r["replications"], "ssm_budget": r["ssm_budget"],
+           "experiments": "vary_c: Exps 1/3 (K=10, c0=5000); vary_K: Exps 2/4 (c=5e4, c0=5000); "
+                          "vary_c0: Exp 5 (c=5e4, K=10)"}
+    for case in ("caseI", "caseII"):
+        out[case] = {exp: {pt: {meth: float(f"{v['rel_mean']:.4g}") for meth, v in pts.items()}
+                           for pt, pts in pts_all.items()}
+                     for exp, pts_all in r[case].items()}
+    out["paper_findings_case_II"] = r["paper_findings_case_II"]
+    return out
+
+
+def bound_checks_compact(r):
+    """Per case and method: theta's, beta, the variance bound against the
+    design's expected squared error, and per delta the exceedance fraction;
+    the checks and whether all hold."""
+    out = {"replications": r["replications"], "deltas": r["deltas"]}
+    for case in ("caseI", "caseII"):
+        out[case] = {}
+        for name, v in r[case].items():
+            out[case][name] = {"theta1": v["theta1"], "theta2": v["theta2"], "beta": v["beta"],
+                               "expected_over_var_bound": v["expected_over_var_bound"],
+                               "sq_err_mean_over_expected": v["sq_err_mean_over_expected"],
+                               "exceed_frac": {d: x["exceed_frac"] for d, x in v["per_delta"].items()}}
+    out["checks_failed"] = [k for k, ok in r["checks"].items() if not ok]
+    out["checks_total"] = len(r["checks"])
+    out["all_hold"] = r["all_hold"]
+    return out
 
 
 def stream_copy_GBps(torch, nbytes=1 << 30, reps=10):
@@ -563,6 +647,7 @@ def section4_sweeps(h, pk, wl, torch, reps=100):
         del M, N
         MN, _, mn_sq = h.exact(pk.Problem(Md, Nd, [0, Md.shape[1]], 1), store=True)
         mn2 = mn_sq.item()
+        print(f"section 4 sweeps: case {case}", file=sys.stderr, flush=True)
         cs = [50000, 100000, 200000, 350000, 500000]
         Ks = [10, 50, 100, 250, 500]
         c0s = [500, 1000, 5000, 20000, 50000]
@@ -618,6 +703,7 @@ def bound_checks(h, pk, wl, torch, reps=100, deltas=(0.5, 0.1, 0.01)):
            "replications": reps, "deltas": list(deltas)}
     checks = {}
     for case in (1, 2):
+        print(f"bound checks: case {case}", file=sys.stderr, flush=True)
         M, N = wl.case_data(case)
         off = wl.equal_blocks(M.shape[1], K)
         Md = torch.from_numpy(M).to(dev)
@@ -938,6 +1024,12 @@ def main():
     if not args.no_section4:
         print("section 4 leg", file=sys.stderr, flush=True)
         out["section4"] = section4_leg(h, pk, wl, torch)
+    if not args.no_section4_sweeps:
+        print("section 4 sweeps", file=sys.stderr, flush=True)
+        out["section4_sweeps"] = section4_sweeps_compact(section4_sweeps(h, pk, wl, torch))
+    if not args.no_bound_checks:
+        print("bound checks", file=sys.stderr, flush=True)
+        out["bound_checks"] = bound_checks_compact(bound_checks(h, pk, wl, torch))
     if not args.no_batched:
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(h, pk, wl, torch, max(2, args.steps // 2), 1)
