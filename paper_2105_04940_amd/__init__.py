@@ -15,7 +15,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsbmm.so")
+# SBMM_LIB names another build of the same library (the host-sanitized one
+# of the CPU tests); the default is the in-tree libsbmm.so
+LIB_PATH = os.environ.get("SBMM_LIB") or os.path.join(_HERE, "libsbmm.so")
 
 SBMM_OK, SBMM_E_ARG, SBMM_E_BUDGET, SBMM_E_NONFINITE, SBMM_E_UNSUPPORTED, \
     SBMM_E_NOMEM, SBMM_E_HIP, SBMM_E_STATE = range(8)

@@ -70,6 +70,53 @@ def build(verbose=False, jobs=None):
     return LIB_PATH
 
 
+SAN_LIB_PATH = os.path.join(HERE, "libsbmm_san.so")
+
+
+def build_sanitized(verbose=False):
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    on the host code only (argument validation, workspace sizing, the arena,
+    status handling); device code is built as usual. For CPU tests of the
+    host paths: load it with the sanitizer runtime preloaded (see
+    tests/test_host_sanitized.py)."""
+    objdir = os.path.join(HERE, "_build_san")
+    os.makedirs(objdir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    common = [
+        f"--offload-arch={ARCH}", "-O1", "-g", "-fPIC", "-std=c++17",
+        "-I", os.path.join(ROOT, "include"),
+        "-I", os.path.join(HERE, "csrc"),
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-Wno-unused-result", *san,
+    ]
+    cc = hipcc()
+    procs, objs = [], []
+    for src in sources():
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmd = [cc, *common, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    failed = []
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            failed.append(src)
+            sys.stderr.write(out.decode(errors="replace"))
+    if failed:
+        raise RuntimeError("sanitized HIP compile failed: " + ", ".join(os.path.basename(f) for f in failed))
+    tmp = SAN_LIB_PATH + ".tmp"
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SAN_LIB_PATH)
+    return SAN_LIB_PATH
+
+
 WORKLOAD_SRC = os.path.join(ROOT, "workloads", "gen.hip")
 WORKLOAD_LIB = os.path.join(ROOT, "workloads", "libsbmm_workload.so")
 

@@ -43,13 +43,17 @@ sbmm_status ensure_ws(sbmm_handle h, size_t bytes) {
   hipError_t e = hipMalloc(&h->ws, want);
   if (e != hipSuccess) {
     h->ws = nullptr;
+    (void)hipGetLastError();   // the failed allocation must not surface at the next launch check
     return fail(h, SBMM_E_NOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
   }
   h->ws_bytes = want;
   return SBMM_OK;
 }
 
-bool dtype_in_ok(sbmm_dtype t) { return t == SBMM_F64 || t == SBMM_F32 || t == SBMM_BF16; }
+bool dtype_in_ok(const sbmm_dtype& t) {
+  const int v = enum_raw(t);
+  return v == SBMM_F64 || v == SBMM_F32 || v == SBMM_BF16;
+}
 
 // Host-side validation of a problem; fills the derived sizes.
 sbmm_status validate(sbmm_handle h, const sbmm_problem* P, sbmm_sizes* sz, bool blkprod_internal = false) {
@@ -58,7 +62,10 @@ sbmm_status validate(sbmm_handle h, const sbmm_problem* P, sbmm_sizes* sz, bool 
     return fail(h, SBMM_E_ARG, "shape m=%lld n=%lld p=%lld (need n >= 1, m, p >= 0)",
                 (long long)P->m, (long long)P->n, (long long)P->p);
   if (P->n > INT32_MAX) return fail(h, SBMM_E_ARG, "n exceeds 2^31 - 1");
-  if (!dtype_in_ok(P->in_dtype)) return fail(h, SBMM_E_ARG, "input dtype %d not supported", (int)P->in_dtype);
+  if (!dtype_in_ok(P->in_dtype)) return fail(h, SBMM_E_ARG, "input dtype %d not supported", enum_raw(P->in_dtype));
+  const uintptr_t es = (uintptr_t)dtype_size(P->in_dtype);
+  if ((P->m > 0 && (uintptr_t)P->M % es) || (P->p > 0 && (uintptr_t)P->N % es))
+    return fail(h, SBMM_E_ARG, "M or N is not aligned to its %d-byte elements", (int)es);
   if (P->m > 0 && (!P->M || P->ldm < P->n))
     return fail(h, SBMM_E_ARG, "M is NULL or ldm < n");
   if (P->p > 0 && (!P->N || P->ldn < P->p))
@@ -73,17 +80,17 @@ sbmm_status validate(sbmm_handle h, const sbmm_problem* P, sbmm_sizes* sz, bool 
     maxw = std::max(maxw, w);
   }
   if (P->c < 1 || P->c > INT32_MAX) return fail(h, SBMM_E_ARG, "c = %lld out of range", (long long)P->c);
-  if (P->mode != SBMM_MODE_BLOCK && P->mode != SBMM_MODE_STRATIFIED)
-    return fail(h, SBMM_E_ARG, "unknown mode %d", (int)P->mode);
-  if (P->prob < SBMM_P_UNIFORM || P->prob > SBMM_P_USER)
-    return fail(h, SBMM_E_ARG, "unknown probability rule %d", (int)P->prob);
+  if (enum_raw(P->mode) != SBMM_MODE_BLOCK && enum_raw(P->mode) != SBMM_MODE_STRATIFIED)
+    return fail(h, SBMM_E_ARG, "unknown mode %d", enum_raw(P->mode));
+  if (enum_raw(P->prob) < SBMM_P_UNIFORM || enum_raw(P->prob) > SBMM_P_USER)
+    return fail(h, SBMM_E_ARG, "unknown probability rule %d", enum_raw(P->prob));
   if (P->prob == SBMM_P_USER && !P->user_w) return fail(h, SBMM_E_ARG, "rule USER needs user_w");
   if (P->mode == SBMM_MODE_BLOCK) {
     if (P->prob == SBMM_P_EXACT && !P->blkprod_sq && !blkprod_internal)
       return fail(h, SBMM_E_ARG, "rule EXACT needs blkprod_sq (from sbmm_exact)");
   } else {
-    if (P->alloc < SBMM_ALLOC_UNIFORM || P->alloc > SBMM_ALLOC_TWO_STEP)
-      return fail(h, SBMM_E_ARG, "unknown allocation rule %d", (int)P->alloc);
+    if (enum_raw(P->alloc) < SBMM_ALLOC_UNIFORM || enum_raw(P->alloc) > SBMM_ALLOC_TWO_STEP)
+      return fail(h, SBMM_E_ARG, "unknown allocation rule %d", enum_raw(P->alloc));
     if (P->alloc == SBMM_ALLOC_OPT && !P->blkprod_sq && !blkprod_internal)
       return fail(h, SBMM_E_ARG, "allocation OPT needs blkprod_sq (from sbmm_exact)");
     if (P->alloc == SBMM_ALLOC_TWO_STEP && !P->pilot_sq && !blkprod_internal)
@@ -115,7 +122,7 @@ sbmm_status validate_pilot(sbmm_handle h, const sbmm_problem* P) {
   if (P->mode != SBMM_MODE_STRATIFIED) return fail(h, SBMM_E_ARG, "the pilot needs stratified mode");
   if (P->c0 < P->K || P->c0 > INT32_MAX)
     return fail(h, SBMM_E_ARG, "c0 = %lld must be at least K = %d (and below 2^31)", (long long)P->c0, P->K);
-  if (P->pilot_prob != SBMM_P_UNIFORM && P->pilot_prob != SBMM_P_NORM)
+  if (enum_raw(P->pilot_prob) != SBMM_P_UNIFORM && enum_raw(P->pilot_prob) != SBMM_P_NORM)
     return fail(h, SBMM_E_ARG, "pilot probabilities must be UNIFORM or NORM");
   return SBMM_OK;
 }
@@ -158,6 +165,7 @@ sbmm_status upload_offsets(sbmm_handle h, const sbmm_problem* P, Arena& ar, int6
     hipError_t e = hipMalloc(&h->off_dev, sizeof(int64_t) * cap);
     if (e != hipSuccess) {
       h->off_dev = nullptr;
+      (void)hipGetLastError();
       return fail(h, SBMM_E_NOMEM, "block offsets: %s", hipGetErrorString(e));
     }
     h->off_cap = cap;
@@ -290,7 +298,9 @@ sbmm_status do_plan(sbmm_handle h, const sbmm_problem* P, const sbmm_sizes& sz, 
   if (draw_off_out) *draw_off_out = L.draw_off;
   if (!ar.base) return SBMM_OK;
   if (uck) HIP_TRY(h, hipMemcpyAsync(user_ck_dev, P->user_ck, sizeof(int64_t) * P->K, hipMemcpyHostToDevice, s));
-  L.mode = P->mode; L.prob = eff_prob(P); L.alloc = P->alloc;
+  // alloc is read only in stratified mode (a block problem may leave it unset)
+  L.mode = P->mode; L.prob = eff_prob(P);
+  L.alloc = P->mode == SBMM_MODE_STRATIFIED ? P->alloc : SBMM_ALLOC_UNIFORM;
   L.n = P->n; L.K = P->K; L.c = P->c; L.A = sz.atoms; L.S = sz.strata;
   L.off_dev = off_dev; L.col_sq = col_sq; L.row_sq = row_sq; L.blk = blk;
   L.user_w = P->user_w; L.user_ck_dev = user_ck_dev; L.blkprod_sq = P->blkprod_sq;
@@ -307,9 +317,10 @@ bool plan_out_ok(const sbmm_plan_out* o) {
   return o && o->idx && o->scale && o->col_off && o->ck && o->colmap && o->colscale;
 }
 
-bool sketch_dtype_ok(sbmm_dtype in, sbmm_dtype out) {
-  if (in == SBMM_F64) return out == SBMM_F64;
-  return out == SBMM_F32 || out == SBMM_BF16;
+bool sketch_dtype_ok(const sbmm_dtype& in, const sbmm_dtype& out) {
+  const int i = enum_raw(in), o = enum_raw(out);
+  if (i == SBMM_F64) return o == SBMM_F64;
+  return (i == SBMM_F32 || i == SBMM_BF16) && (o == SBMM_F32 || o == SBMM_BF16);
 }
 
 // Alg. 3 step 1: the pilot plan ([c0/K] draws per block, tag 2), its sketch
@@ -411,7 +422,7 @@ sbmm_status bind_scratch(sbmm_handle h) {
 extern "C" {
 
 const char* sbmm_status_string(sbmm_status s) {
-  switch (s) {
+  switch (enum_raw(s)) {
     case SBMM_OK: return "ok";
     case SBMM_E_ARG: return "invalid argument";
     case SBMM_E_BUDGET: return "sample budget too small";
@@ -643,8 +654,8 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   sbmm_status st = check_handle(h);
   if (st) return st;
   if (m < 0 || p < 0 || L_pad_max < 0 || !L_dev) return fail(h, SBMM_E_ARG, "bad sizes or L_dev");
-  if (dtype != SBMM_F64 && dtype != SBMM_F32 && dtype != SBMM_BF16)
-    return fail(h, SBMM_E_UNSUPPORTED, "sketched product in dtype %d is not built", (int)dtype);
+  if (enum_raw(dtype) != SBMM_F64 && enum_raw(dtype) != SBMM_F32 && enum_raw(dtype) != SBMM_BF16)
+    return fail(h, SBMM_E_UNSUPPORTED, "sketched product in dtype %d is not built", enum_raw(dtype));
   if (m > 0 && p > 0 && L_pad_max > 0 && (!C || !D)) return fail(h, SBMM_E_ARG, "C and D are required");
   if (ldc < L_pad_max || ldd < p) return fail(h, SBMM_E_ARG, "ldc < L_pad_max or ldd < p");
   if (CD && ldcd < p) return fail(h, SBMM_E_ARG, "ldcd < p");
@@ -769,7 +780,7 @@ sbmm_status sbmm_error(sbmm_handle h, int64_t m, int64_t p, sbmm_dtype dtype, co
   sbmm_status st = check_handle(h);
   if (st) return st;
   if (m < 0 || p < 0 || !out2) return fail(h, SBMM_E_ARG, "bad sizes or out2");
-  if (dtype != SBMM_F64 && dtype != SBMM_F32) return fail(h, SBMM_E_ARG, "dtype must be F64 or F32");
+  if (enum_raw(dtype) != SBMM_F64 && enum_raw(dtype) != SBMM_F32) return fail(h, SBMM_E_ARG, "dtype must be F64 or F32");
   if (m > 0 && p > 0 && (!X || !Y || ldx < p || ldy < p)) return fail(h, SBMM_E_ARG, "X/Y missing or ld < p");
   hipStream_t s = (hipStream_t)stream;
   if (m == 0 || p == 0) {
@@ -800,8 +811,8 @@ sbmm_status run_impl(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
   if ((st = validate(h, P, &sz, true))) return st;
   if (!plan_out_ok(plan)) return fail(h, SBMM_E_ARG, "plan output buffers missing");
   if (!sketch_dtype_ok(P->in_dtype, compute)) return fail(h, SBMM_E_ARG, "compute dtype not allowed for the input dtype");
-  if (compute != SBMM_F64 && compute != SBMM_F32 && compute != SBMM_BF16)
-    return fail(h, SBMM_E_UNSUPPORTED, "sketched product in dtype %d is not built", (int)compute);
+  if (enum_raw(compute) != SBMM_F64 && enum_raw(compute) != SBMM_F32 && enum_raw(compute) != SBMM_BF16)
+    return fail(h, SBMM_E_UNSUPPORTED, "sketched product in dtype %d is not built", enum_raw(compute));
   if ((P->m > 0 && P->p > 0 && !CD) || ldcd < P->p) return fail(h, SBMM_E_ARG, "CD is required with ldcd >= p");
   if (C && ldc < sz.L_pad_max) return fail(h, SBMM_E_ARG, "ldc < L_pad_max");
   if (D && ldd < P->p) return fail(h, SBMM_E_ARG, "ldd < p");
@@ -1001,7 +1012,7 @@ sbmm_status sbmm_exact_error(sbmm_handle h, const sbmm_problem* P, const void* C
   sbmm_sizes sz;
   if ((st = validate(h, P, &sz, true))) return st;
   if (!err2_and_mn2) return fail(h, SBMM_E_ARG, "err2_and_mn2 is required");
-  if (cd_dtype != product_dtype(P->in_dtype))
+  if (enum_raw(cd_dtype) != (int)product_dtype(P->in_dtype))
     return fail(h, SBMM_E_ARG, "CD must be in the product dtype (F64 for F64 inputs, else F32)");
   if ((P->m > 0 && P->p > 0 && !CD) || ldcd < P->p) return fail(h, SBMM_E_ARG, "CD is required with ldcd >= p");
   if (MN && ldmn < P->p) return fail(h, SBMM_E_ARG, "ldmn < p");
@@ -1021,9 +1032,7 @@ sbmm_status sbmm_workspace_size(const sbmm_problem* P, sbmm_dtype compute, size_
   sbmm_sizes sz;
   sbmm_status st = validate(nullptr, P, &sz, true);
   if (st) return st;
-  if (!sketch_dtype_ok(P->in_dtype, compute) ||
-      (compute != SBMM_F64 && compute != SBMM_F32 && compute != SBMM_BF16))
-    return SBMM_E_ARG;
+  if (!sketch_dtype_ok(P->in_dtype, compute)) return SBMM_E_ARG;
   // placeholders: never dereferenced by a measuring pass
   char* const ph = reinterpret_cast<char*>((uintptr_t)256);
   sbmm_plan_out pl{};

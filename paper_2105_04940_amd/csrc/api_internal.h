@@ -3,6 +3,7 @@
 #pragma once
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -22,6 +23,17 @@ struct sbmm_handle_s {
 };
 
 namespace {
+
+// A caller's enum argument or field as the int it stored. In C any int fits
+// an enum object; in C++ reading a value outside the enumeration's range
+// through the enum type is undefined, so caller-supplied enums are checked
+// through their object representation before they are used as enums.
+template <typename E> inline int enum_raw(const E& e) {
+  static_assert(sizeof(E) == sizeof(int), "C enums of this ABI are int-sized");
+  int v;
+  std::memcpy(&v, &e, sizeof v);
+  return v;
+}
 
 sbmm_status fail(sbmm_handle h, sbmm_status st, const char* fmt, ...) {
   if (h) {

@@ -105,7 +105,7 @@ sbmm_status validate_item(sbmm_handle h, int32_t t, const sbmm_batch_item& it) {
     if (it.block_off[k + 1] - it.block_off[k] < 1)
       return fail(h, SBMM_E_ARG, "problem %d: block %d is empty", t, k);
   if (it.c < 1 || it.c > INT32_MAX) return fail(h, SBMM_E_ARG, "problem %d: c = %lld out of range", t, (long long)it.c);
-  if (it.prob != SBMM_P_UNIFORM && it.prob != SBMM_P_NORM)
+  if (enum_raw(it.prob) != SBMM_P_UNIFORM && enum_raw(it.prob) != SBMM_P_NORM)
     return fail(h, SBMM_E_ARG, "problem %d: batches take the UNIFORM or NORM rule", t);
   return SBMM_OK;
 }

@@ -127,3 +127,63 @@ def test_null_handle_is_state_error():
     assert lib.sbmm_destroy(None) == pk.SBMM_E_STATE
     assert lib.sbmm_sync(None, None) == pk.SBMM_E_STATE
     assert lib.sbmm_reserve(None, 16) == pk.SBMM_E_STATE
+
+
+def _struct_status(s):
+    out = pk.Sizes_t()
+    return pk.lib().sbmm_query_sizes(ctypes.byref(s), ctypes.byref(out))
+
+
+def test_misaligned_and_short_leading_dimensions():
+    import torch
+    # a float32 M one byte off its element boundary, a float64 N four bytes off
+    M = FakeTensor(8, 10, torch.float32, ptr=0x1001)
+    N = FakeTensor(10, 6, torch.float32)
+    assert _status(pk.Problem(M, N, [0, 10], 2))[0] == pk.SBMM_E_ARG
+    M = FakeTensor(8, 10, torch.float64)
+    N = FakeTensor(10, 6, torch.float64, ptr=0x2004)
+    assert _status(pk.Problem(M, N, [0, 10], 2))[0] == pk.SBMM_E_ARG
+    # bf16 needs two-byte alignment only; float32 at a 4-byte (not 16-byte) boundary is valid
+    M = FakeTensor(8, 10, torch.bfloat16, ptr=0x1002)
+    N = FakeTensor(10, 6, torch.bfloat16, ptr=0x2006)
+    assert _status(pk.Problem(M, N, [0, 10], 2))[0] == pk.SBMM_OK
+    M = FakeTensor(8, 10, torch.float32, ptr=0x1004)
+    assert _status(pk.Problem(M, FakeTensor(10, 6, torch.float32), [0, 10], 2))[0] == pk.SBMM_OK
+    # leading dimensions below the row length
+    s = _problem().struct()
+    s.ldm = s.n - 1
+    assert _struct_status(s) == pk.SBMM_E_ARG
+    s = _problem().struct()
+    s.ldn = s.p - 1
+    assert _struct_status(s) == pk.SBMM_E_ARG
+
+
+@pytest.mark.parametrize("field,value,extra", [
+    ("prob", 99, {}), ("prob", -1, {}), ("in_dtype", 4, {}), ("in_dtype", -7, {}),
+    ("mode", 2, {}), ("alloc", 99, dict(mode="stratified")),
+    ("pilot_prob", 2, dict(mode="stratified", alloc="two_step", c0=4)),
+    ("pilot_prob", 99, dict(mode="stratified", alloc="two_step", c0=4)),
+])
+def test_enum_values_outside_their_range(field, value, extra):
+    s = _problem(**extra).struct()
+    setattr(s, field, value)
+    if field == "pilot_prob":
+        s.pilot_sq = 0x3000     # present, so the pilot's own checks run
+        st = pk.lib().sbmm_workspace_size(ctypes.byref(s), pk.SBMM_F32, ctypes.byref(ctypes.c_size_t()), None)
+    else:
+        st = _struct_status(s)
+    assert st == pk.SBMM_E_ARG
+
+
+def test_workspace_size_rejects_unknown_compute_dtype():
+    s = _problem().struct()
+    n = ctypes.c_size_t()
+    for bad in (pk.SBMM_F8E4M3, 17, -1):
+        assert pk.lib().sbmm_workspace_size(ctypes.byref(s), bad, ctypes.byref(n), None) == pk.SBMM_E_ARG
+    assert pk.lib().sbmm_workspace_size(ctypes.byref(s), pk.SBMM_F32, ctypes.byref(n), None) == pk.SBMM_OK
+
+
+def test_status_string_of_any_int():
+    lib = pk.lib()
+    for v in (-1, 8, 99, 2**31 - 1):
+        assert lib.sbmm_status_string(v) == b"unknown status"
