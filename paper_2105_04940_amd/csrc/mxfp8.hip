@@ -329,10 +329,27 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t mx_panel_rsrc(const uint8_t* b
 // eight waves (two per SIMD), each 128 x 64 of the tile
 constexpr int kMxWaves = 8;
 
+// The two tile stages and the two scale stages are separate LDS objects: the
+// loads into one and the reads of the other are then provably disjoint, so
+// the compiler's wait for the loads stays at the step boundary instead of
+// before every fragment read.
+struct MxStage {
+  uint4 A[MxTile::BM * MxTile::KC];
+  uint4 B[MxTile::BN * MxTile::KC];
+};
+// E8M0 scale words of four k-steps for the 256 rows of A and the 256 columns
+// of B: [row][k-step % 4], rows of B after those of A
+struct MxScales {
+  uint32_t w[2 * MxTile::BM * 4];
+};
+
 __global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g) {
-  __shared__ MxTile sh;
+  __shared__ MxStage st0, st1;
+  __shared__ MxScales sc0, sc1;
+  __shared__ double red[16];
   constexpr int BK = MxTile::BK, NW = kMxWaves, CB = 16 / NW;
   constexpr int INSTS = MxTile::BM / 8 / NW;   // load instructions per wave per operand and step
+  static_assert(2 * MxTile::BM == 64 * NW, "one scale row per lane of the workgroup");
   int64_t tm, tn;
   mx_tile_coords(g, tm, tn);
   const int64_t m0 = tm * MxTile::BM, n0 = tn * MxTile::BN;
@@ -351,7 +368,7 @@ __global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g)
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[b][c] = f32x16{};
 
-  auto issue = [&](int64_t kt, int buf) {
+  auto issue = [&](int64_t kt, MxStage& dst) {
     const int64_t k0 = kt * BK;
     const unsigned sk = (unsigned)k0;
 #pragma unroll
@@ -362,32 +379,27 @@ __global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g)
       const unsigned oa = live ? (unsigned)(row * g.lda + chunk * 16) : kOut;
       const unsigned ob = live ? (unsigned)(row * g.ldb + chunk * 16) : kOut;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(INSTS * wave + j) * 64], 16, oa, sk, 0, 0);
+          ra, (__attribute__((address_space(3))) void*)&dst.A[(INSTS * wave + j) * 64], 16, oa, sk, 0, 0);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rb, (__attribute__((address_space(3))) void*)&sh.Bs[buf][(INSTS * wave + j) * 64], 16, ob, sk, 0, 0);
+          rb, (__attribute__((address_space(3))) void*)&dst.B[(INSTS * wave + j) * 64], 16, ob, sk, 0, 0);
     }
   };
-  // the four E8M0 scales of a k-step for this lane's rows / columns (one
-  // 32-bit word per 32 x 32 block; 127 = 1 outside the matrix)
-  // through buffer resources over the scale arrays, so that a lane keeps one
-  // 32-bit offset per row and the step is a scalar offset; rows past the
-  // matrix read 0 (scale 2^-127 on zero codes)
+  // The scale words of k-steps 4q .. 4q + 3 (16 bytes of a scale row) for
+  // every row of the tile, one row per lane of the workgroup, straight into
+  // LDS: one instruction per wave every four k-steps, instead of one 4-byte
+  // load per row, block and k-step. Rows past the matrix lie outside the
+  // buffer's range and read 0 (scale 2^-127 on zero codes); words past a
+  // row's scale blocks belong to k-steps that are never computed.
+  const int srow = 64 * wave + lane;           // 0 .. 511: A rows, then B rows
+  const bool sis_a = srow < MxTile::BM;
   const __amdgpu_buffer_rsrc_t rsa = mx_panel_rsrc(g.As, g.m, g.ldas);
   const __amdgpu_buffer_rsrc_t rsb = mx_panel_rsrc(g.Bs, g.p, g.ldbs);
-  int voa[4], vob[CB];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) voa[b] = (int)((m0 + wm0 + 32 * b + lr) * g.ldas);
-#pragma unroll
-  for (int c = 0; c < CB; ++c) vob[c] = (int)((n0 + wn0 + 32 * c + lr) * g.ldbs);
-  uint32_t sa[4], sb[CB];
-  auto load_scales = [&](int64_t kt, uint32_t* xa, uint32_t* xb) {
-    const int so = (int)(4 * kt);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) xa[b] = __builtin_amdgcn_raw_buffer_load_b32(rsa, voa[b], so, 0);
-#pragma unroll
-    for (int c = 0; c < CB; ++c) xb[c] = __builtin_amdgcn_raw_buffer_load_b32(rsb, vob[c], so, 0);
+  const unsigned svo = sis_a ? (unsigned)((m0 + srow) * g.ldas) : (unsigned)((n0 + srow - MxTile::BM) * g.ldbs);
+  auto issue_scales = [&](int64_t q, MxScales& dst) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(sis_a ? rsa : rsb,
+        (__attribute__((address_space(3))) void*)&dst.w[64 * wave * 4], 16, svo, (unsigned)(16 * q), 0, 0);
   };
-  auto compute = [&](int buf) {
+  auto compute = [&](const MxStage& src, const uint32_t* sa, const uint32_t* sb) {
 #pragma unroll 1
     for (int s = 0; s < BK / 64; ++s) {
       i32x8 av[4], bv[CB];
@@ -395,13 +407,13 @@ __global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int row = wm0 + 32 * b + lr;
-        const uint4 u0 = sh.As[buf][mx_lds_slot(row, c0)], u1 = sh.As[buf][mx_lds_slot(row, c0 + 2)];
+        const uint4 u0 = src.A[mx_lds_slot(row, c0)], u1 = src.A[mx_lds_slot(row, c0 + 2)];
         av[b] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w, (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
       }
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
         const int row = wn0 + 32 * c + lr;
-        const uint4 u0 = sh.Bs[buf][mx_lds_slot(row, c0)], u1 = sh.Bs[buf][mx_lds_slot(row, c0 + 2)];
+        const uint4 u0 = src.B[mx_lds_slot(row, c0)], u1 = src.B[mx_lds_slot(row, c0 + 2)];
         bv[c] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w, (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
       }
       const int sh_bits = 8 * (2 * s + lh);
@@ -414,30 +426,42 @@ __global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g)
               (int)((sb[c] >> sh_bits) & 0xffu));
     }
   };
-
+  // One k-step: the next step's tile (and, before a group of four, the next
+  // group's scales) is issued into the other stage, this step's tile is
+  // consumed, then everything lands.
   const int64_t nkt = (K + BK - 1) / BK;
+  auto step = [&](int64_t kt, const MxStage& cur, MxStage& nxt, const MxScales& scur, MxScales& snxt) {
+    if (kt + 1 < nkt) {
+      if ((kt & 3) == 3) issue_scales((kt + 1) >> 2, snxt);
+      issue(kt + 1, nxt);
+    }
+    uint32_t sa[4], sb[CB];
+    const int kq = (int)(kt & 3);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) sa[b] = scur.w[(wm0 + 32 * b + lr) * 4 + kq];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) sb[c] = scur.w[(MxTile::BM + wn0 + 32 * c + lr) * 4 + kq];
+    compute(cur, sa, sb);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
   if (nkt > 0) {
-    load_scales(0, sa, sb);
-    issue(0, 0);
+    issue_scales(0, sc0);
+    issue(0, st0);
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  for (int64_t kt = 0; kt < nkt; ++kt) {
-    const int cur = (int)(kt & 1);
-    uint32_t na[4], nb[CB];
-    if (kt + 1 < nkt) {
-      load_scales(kt + 1, na, nb);
-      issue(kt + 1, cur ^ 1);
-    }
-    compute(cur);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (kt + 1 < nkt) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sa[i] = na[i];
-#pragma unroll
-      for (int i = 0; i < CB; ++i) sb[i] = nb[i];
-    }
+  // eight steps per trip: the tile stages alternate every step, the scale
+  // stages every four, each at a fixed LDS object
+  for (int64_t kt = 0; kt < nkt; kt += 8) {
+    step(kt, st0, st1, sc0, sc1);
+    if (kt + 1 < nkt) step(kt + 1, st1, st0, sc0, sc1);
+    if (kt + 2 < nkt) step(kt + 2, st0, st1, sc0, sc1);
+    if (kt + 3 < nkt) step(kt + 3, st1, st0, sc0, sc1);
+    if (kt + 4 < nkt) step(kt + 4, st0, st1, sc1, sc0);
+    if (kt + 5 < nkt) step(kt + 5, st1, st0, sc1, sc0);
+    if (kt + 6 < nkt) step(kt + 6, st0, st1, sc1, sc0);
+    if (kt + 7 < nkt) step(kt + 7, st1, st0, sc1, sc0);
   }
 
   double e2 = 0.0, n2 = 0.0;
@@ -465,14 +489,14 @@ __global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g)
   if (g.tile_part) {
     e2 = warp_sum_f64(e2);
     n2 = warp_sum_f64(n2);
-    if (lane == 0) { sh.red[wave] = e2; sh.red[NW + wave] = n2; }
+    if (lane == 0) { red[wave] = e2; red[NW + wave] = n2; }
     __syncthreads();
     if (threadIdx.x == 0) {
       const int64_t tiles = g.tiles_m * g.tiles_n;
       double a = 0.0, b = 0.0;
       for (int w = 0; w < NW; ++w) {
-        a += sh.red[w];
-        b += sh.red[NW + w];
+        a += red[w];
+        b += red[NW + w];
       }
       g.tile_part[blockIdx.x] = a;
       g.tile_part[tiles + blockIdx.x] = b;
