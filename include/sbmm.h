@@ -433,23 +433,26 @@ typedef struct sbmm_batch_s* sbmm_batch;
 /* Tile configuration of the two grouped products (exact MN, sketched CD)
  * and whether their work lists start with the longest inner extents. A tile
  * configuration is one of 128x128, 64x128, 128x64, 64x64 (0..3, a
- * register-staged kernel) and 256x256 (4, LDS-direct loads, eight waves per
- * workgroup). The sketched product has two forms: cfg 0..3 read the drawn
- * columns of M and rows of N in place (the gather fused into the product's
- * loads), cfg 5..9 are tile configurations 0..4 over sketches C, D first
- * gathered into a workspace the batch owns (at most 32 GiB, or one problem's
- * sketches if larger, filled by groups of problems, one gather and one
- * product launch per group); 5..9 exist when that workspace could be
- * allocated at sbmm_batch_create, and exact cfg 4 when every problem's M and
- * N rows start on 16-byte boundaries. Configurations 0..3 and their
- * materialized forms give the same bits; the 256x256 tiles sum in another
- * order and agree with them to float32 rounding. The timings are filled by
- * sbmm_batch_tune: ms[g][2 cfg + lpt] for product g (0 exact, 1 sketch), -1
- * where not measured. */
+ * register-staged kernel), 256x256 (4, LDS-direct loads, eight waves per
+ * workgroup) and 128x128 (5, LDS-direct loads, four waves per workgroup, two
+ * workgroups per compute unit). The sketched product has two forms: cfg 0..3
+ * read the drawn columns of M and rows of N in place (the gather fused into
+ * the product's loads), cfg 6..11 are tile configurations 0..5 over sketches
+ * C, D first gathered into a workspace the batch owns (at most 32 GiB, or one
+ * problem's sketches if larger, filled by groups of problems, one gather and
+ * one product launch per group); 6..11 exist when that workspace could be
+ * allocated at sbmm_batch_create. The LDS-direct configurations (exact 4 and
+ * 5, materialized 10 and 11) need every problem's rows to start on 16-byte
+ * boundaries and its panels to fit 32-bit offsets. Configurations 0..3 and
+ * their materialized forms give the same bits; the LDS-direct tiles sum in
+ * another order and agree with them to float32 rounding. The timings are
+ * filled by sbmm_batch_tune: ms[g][2 cfg + lpt] for product g (0 exact, 1
+ * sketch), -1 where not measured. */
+enum { SBMM_BATCH_TUNING_SLOTS = 24 };
 typedef struct {
   int32_t cfg[2];
   int32_t lpt[2];
-  float ms[2][20];
+  float ms[2][SBMM_BATCH_TUNING_SLOTS];
 } sbmm_batch_tuning;
 
 /* Validate T problems, allocate the batch's device memory (owned by the

@@ -44,7 +44,7 @@ NOALLOC_SCRATCH_BYTES = 16 << 20   # SBMM_NOALLOC_SCRATCH_BYTES
 BOUND_FIELDS = ("theta1", "theta2", "theta1_hat", "theta2_hat", "beta", "mn", "phi",
                 "var_bound", "expected")
 BOUND_MAX_DELTA = 8
-BATCH_TILES = ((128, 128), (64, 128), (128, 64), (64, 64), (256, 256))
+BATCH_TILES = ((128, 128), (64, 128), (128, 64), (64, 64), (256, 256), (128, 128))
 
 
 class SbmmError(RuntimeError):
@@ -99,9 +99,12 @@ class BatchOutputs_t(ctypes.Structure):
     _fields_ = [("err2_mn2", ctypes.c_void_p), ("L", ctypes.c_void_p), ("idx", ctypes.c_void_p)]
 
 
+BATCH_TUNING_SLOTS = 24   # SBMM_BATCH_TUNING_SLOTS
+
+
 class BatchTuning_t(ctypes.Structure):
     _fields_ = [("cfg", ctypes.c_int32 * 2), ("lpt", ctypes.c_int32 * 2),
-                ("ms", (ctypes.c_float * 20) * 2)]
+                ("ms", (ctypes.c_float * BATCH_TUNING_SLOTS) * 2)]
 
 
 def load_library(path=LIB_PATH):
@@ -625,8 +628,8 @@ class Batch:
         for g in range(2):
             t.cfg[g] = d["cfg"][g]
             t.lpt[g] = d["lpt"][g]
-            for i in range(20):
-                t.ms[g][i] = d.get("ms", [[-1.0] * 20] * 2)[g][i]
+            for i in range(BATCH_TUNING_SLOTS):
+                t.ms[g][i] = d.get("ms", [[-1.0] * BATCH_TUNING_SLOTS] * 2)[g][i]
         self.handle._check(self._lib.sbmm_batch_set_tuning(self.handle.h, self.b, ctypes.byref(t)))
 
     @staticmethod
@@ -635,7 +638,7 @@ class Batch:
         return {"cfg": [t.cfg[0], t.cfg[1]], "lpt": [t.lpt[0], t.lpt[1]],
                 "tiles": [list(BATCH_TILES[t.cfg[0] % n]), list(BATCH_TILES[t.cfg[1] % n])],
                 "sketch_materialized": t.cfg[1] >= n,
-                "ms": [[t.ms[g][i] for i in range(20)] for g in range(2)]}
+                "ms": [[t.ms[g][i] for i in range(BATCH_TUNING_SLOTS)] for g in range(2)]}
 
     def draws(self, t):
         """The drawn blocks of problem t (device tensor view)."""

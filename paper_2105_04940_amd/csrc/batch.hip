@@ -150,14 +150,14 @@ int product_cfgs(const sbmm_batch b, int g) {
 
 bool materialized(const sbmm_batch b, int g, int cfg) { return g == 1 && cfg >= grouped_cfg_count(); }
 
-// Whether configuration cfg of product g can run: the 256 x 256 tiles
-// (tile configuration 4) take no fused gather, and for the exact product need
-// every problem's rows 16-byte aligned.
+// Whether configuration cfg of product g can run: the LDS-direct tiles
+// (tile configurations 4 and 5) take no fused gather, and need every
+// problem's rows 16-byte aligned and its panels within 32-bit offsets.
 bool cfg_ok(const sbmm_batch b, int g, int cfg) {
   if (cfg < 0 || cfg >= product_cfgs(b, g)) return false;
   const bool mat = materialized(b, g, cfg);
   const int tile = mat ? cfg - grouped_cfg_count() : cfg;
-  if (tile != 4) return true;
+  if (tile != 4 && tile != 5) return true;
   if (g == 0) return b->exact_lds;
   return mat && b->sketch_lds;
 }
@@ -516,7 +516,7 @@ sbmm_status sbmm_batch_create(sbmm_handle h, int32_t T, const sbmm_batch_item* i
   b->exact_lds = true;
   for (int32_t t = 0; t < T; ++t) b->exact_lds = b->exact_lds && grouped_lds_ok(b->launches[0][t]);
   for (int g = 0; g < kProducts; ++g) {
-    for (int i = 0; i < 20; ++i) b->tuning.ms[g][i] = -1.0f;
+    for (int i = 0; i < SBMM_BATCH_TUNING_SLOTS; ++i) b->tuning.ms[g][i] = -1.0f;
     if ((st = apply_product(b, g, 0, 1)) != SBMM_OK) {
       sbmm_batch_destroy(b);
       return st;
@@ -632,7 +632,7 @@ sbmm_status sbmm_batch_set_tuning(sbmm_handle h, sbmm_batch b, const sbmm_batch_
   for (int g = 0; g < kProducts; ++g)
     if ((st = apply_product(b, g, t->cfg[g], t->lpt[g])) != SBMM_OK) return st;
   for (int g = 0; g < kProducts; ++g)
-    for (int i = 0; i < 20; ++i) b->tuning.ms[g][i] = t->ms[g][i];
+    for (int i = 0; i < SBMM_BATCH_TUNING_SLOTS; ++i) b->tuning.ms[g][i] = t->ms[g][i];
   return SBMM_OK;
 }
 

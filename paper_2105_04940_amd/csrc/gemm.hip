@@ -859,9 +859,12 @@ __global__ __launch_bounds__(kThreads, WG_PER_CU) void sgemm_grouped_kernel(Grou
   using T = SgemmTile<WMB, WNB, BK>;
   __shared__ T sh;
   const int64_t it = blockIdx.x;
-  const int32_t pi = ga.item_prob[it];
-  const int64_t local = ga.item_tile[it];
-  const GemmArgs& g = ga.probs[pi];
+  const int32_t pi = __builtin_amdgcn_readfirstlane(ga.item_prob[it]);
+  const int64_t local = __builtin_amdgcn_readfirstlane(ga.item_tile[it]);
+  // a copy of the problem's arguments: read once into scalar registers (through
+  // a reference the compiler reloads them inside the k loop, since the
+  // kernel's stores might alias them)
+  const GemmArgs g = ga.probs[pi];
   const int64_t m0 = (local / g.tiles_n) * T::BM, n0 = (local % g.tiles_n) * T::BN;
   const int64_t K = inner_extent(g);
   const bool interior = (GATHER || g.vec_a) && g.vec_b && m0 + T::BM <= g.m && n0 + T::BN <= g.p;
@@ -878,10 +881,208 @@ template <int NW>
 __global__ __launch_bounds__(NW * 64, 1) void sgemm_grouped_lds_kernel(GroupedArgs ga) {
   __shared__ SgemmLdsTile sh;
   const int64_t it = blockIdx.x;
-  const int32_t pi = ga.item_prob[it];
-  const int64_t local = ga.item_tile[it];
-  const GemmArgs& g = ga.probs[pi];
+  const int32_t pi = __builtin_amdgcn_readfirstlane(ga.item_prob[it]);
+  const int64_t local = __builtin_amdgcn_readfirstlane(ga.item_tile[it]);
+  const GemmArgs g = ga.probs[pi];   // by value, as in the kernel above
   sgemm_lds_body<NW, true>(g, sh, local / g.tiles_n, local % g.tiles_n, it, ga.part_base[pi] + local, ga.nparts);
+}
+
+// ============================================================================
+// Grouped float32 products on 128 x 128 tiles with LDS-direct loads, two
+// workgroups per CU, four waves of 64 x 64 (2 x 2 blocks of
+// v_mfma_f32_32x32x2_f32). For the many small products of a batch, where
+// 256 x 256 tiles waste their ragged edges and the register-staged 128 x 128
+// kernel spends its issue slots on staging. A step covers 32 k as in the
+// 256 x 256 kernel (A rows as XOR-swizzled 16-byte chunks of 4 k, B rows as
+// loaded); a B load instruction fills two 128-float rows (one per half-wave),
+// so B rows are stored in pairs padded by 16 floats, which puts rows four
+// apart (the two half-waves of a fragment read) 32 banks apart. The two
+// stages are separate LDS objects over a two-step loop, so the loads into
+// one never look like they alias the reads of the other. Staging slot (fold
+// every 4096 k) and error partials per work item, as the other grouped
+// kernels keep them.
+// ============================================================================
+constexpr int kL128Pair = 2 * 128 + 16;   // floats per stored pair of B rows
+
+struct Lds128Stage {
+  uint4 A[128 * 8];
+  float B[16 * kL128Pair];
+};
+
+__global__ __launch_bounds__(256, 2) void sgemm_grouped_lds128_kernel(GroupedArgs ga) {
+  __shared__ Lds128Stage st0, st1;
+  __shared__ double red[2][4];
+  constexpr int BK = 32, FOLD_STEPS = 4096 / BK;
+  const int64_t it = blockIdx.x;
+  const int32_t pi = __builtin_amdgcn_readfirstlane(ga.item_prob[it]);
+  const int64_t local = __builtin_amdgcn_readfirstlane(ga.item_tile[it]);
+  const GemmArgs g = ga.probs[pi];   // by value, as in the kernels above
+  const int64_t m0 = (local / g.tiles_n) * 128, n0 = (local % g.tiles_n) * 128;
+  const int64_t K = inner_extent(g);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 31, lh = lane >> 5;
+  const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
+  const float* A = reinterpret_cast<const float*>(g.A) + m0 * g.lda;
+  const float* B = reinterpret_cast<const float*>(g.B);
+  // A records end at the last row's K-th entry (the range check is per
+  // dword): a chunk straddling K reads zeros past K in the last row and the
+  // row's next entries elsewhere, which the last step clears in LDS
+  const int64_t arows = min((int64_t)128, g.m - m0);
+  const __amdgpu_buffer_rsrc_t ra = f32_rsrc(A, arows > 0 ? ((arows - 1) * g.lda + K) * 4 : 0);
+  constexpr unsigned kOut = 0x80000000u;
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[b][c] = f32x16{};
+
+  auto issue = [&](int64_t kt, Lds128Stage& dst) {
+    const int64_t k0 = kt * BK;
+    const unsigned sk = (unsigned)(k0 * 4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = (4 * wave + j) * 8 + (lane >> 3);
+      const int chunk = (lane & 7) ^ ((row >> 1) & 7);
+      const bool live = k0 + 4 * chunk < K;
+      const unsigned oa = live ? (unsigned)(row * g.lda * 4 + chunk * 16) : kOut;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          ra, (__attribute__((address_space(3))) void*)&dst.A[(4 * wave + j) * 64], 16, oa, sk, 0, 0);
+    }
+    // B rows k0 .. k0 + 31 of columns n0 .. n0 + 127: a row past K, or an
+    // entry past p in the step's last row, lies past the record count and
+    // reads 0; entries past p in other rows only feed columns not stored
+    const int64_t brows = min((int64_t)BK, K - k0);
+    const int64_t bbytes = brows > 0 ? ((brows - 1) * g.ldb + (g.p - n0)) * 4 : 0;
+    const __amdgpu_buffer_rsrc_t rb = f32_rsrc(B + k0 * g.ldb + n0, bbytes);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = 4 * wave + j;                 // rows 2q (lanes 0..31) and 2q + 1 (32..63)
+      const unsigned ob = (unsigned)((2 * q + lh) * g.ldb * 4 + lr * 16);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (__attribute__((address_space(3))) void*)&dst.B[q * kL128Pair],
+                                               16, ob, 0, 0, 0);
+    }
+  };
+  auto brow = [](const Lds128Stage& st, int r, int col) { return st.B[(r >> 1) * kL128Pair + (r & 1) * 128 + col]; };
+  // half-wave h takes k = 8u + 4h + q in MFMA q of super-step u; the next
+  // super-step's fragments are read while the current MFMAs run
+  auto compute = [&](const Lds128Stage& src) {
+    f32x4 av[2][2];
+    float bv[2][2][4];
+    auto frag = [&](int u, int r) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        av[r][b] = __builtin_bit_cast(f32x4, src.A[lds_a_slot(wm0 + 32 * b + lr, 2 * u + lh)]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) bv[r][c][q] = brow(src, 8 * u + 4 * lh + q, wn0 + 32 * c + lr);
+    };
+    frag(0, 0);
+#pragma unroll
+    for (int u = 0; u < BK / 8; ++u) {
+      if (u + 1 < BK / 8) frag(u + 1, (u + 1) & 1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u & 1][b][q], bv[u & 1][c][q], acc[b][c], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  // this wave's quarter of the item's staging slot, [accumulator][lane]
+  const __amdgpu_buffer_rsrc_t rs = f32_rsrc(g.stage + it * (128 * 128) + wave * (64 * 64), 64 * 64 * 4);
+  const int vo = lane * 4;
+  int folds = 0;
+  auto fold = [&]() {
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int so = ((b * 2 + c) * 16 + v) * 256;
+          float x = acc[b][c][v];
+          if (folds) x += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, vo, so, 0);
+        }
+        acc[b][c] = f32x16{};
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    ++folds;
+  };
+
+  const int64_t nkt = (K + BK - 1) / BK;
+  auto step = [&](int64_t kt, Lds128Stage& cur, Lds128Stage& nxt) {
+    if (kt + 1 < nkt) {
+      issue(kt + 1, nxt);
+    } else if (K & 3) {
+      // the inner extent ends inside a chunk: clear the A entries past K of
+      // that chunk in every row (B rows past K already read zero)
+      const int kz = (int)(K - kt * BK), cs = kz >> 2, e0 = kz & 3;
+      if (tid < 128) {
+        float* q = reinterpret_cast<float*>(&cur.A[lds_a_slot(tid, cs)]);
+        for (int e = e0; e < 4; ++e) q[e] = 0.0f;
+      }
+      __syncthreads();
+    }
+    compute(cur);
+    if ((kt + 1) % FOLD_STEPS == 0 && kt + 1 < nkt) fold();
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+  };
+  if (nkt > 0) issue(0, st0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int64_t kt = 0; kt < nkt; kt += 2) {
+    step(kt, st0, st1);
+    if (kt + 1 < nkt) step(kt + 1, st1, st0);
+  }
+
+  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
+  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
+  double e2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
+      if (row >= g.m) continue;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int64_t col = n0 + wn0 + 32 * c + lr;
+        if (col >= g.p) continue;
+        float val = acc[b][c][v];
+        if (folds) val += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, ((b * 2 + c) * 16 + v) * 256, 0));
+        if (Cout) Cout[row * g.ldc + col] = val;
+        const double dv = (double)val;
+        if (Y) {
+          const double d = dv - (double)Y[row * g.ldy + col];
+          e2 = fma(d, d, e2);
+        }
+        n2 = fma(dv, dv, n2);
+      }
+      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  if (g.tile_part) {
+    // the four waves' sums added in wave order
+    e2 = warp_sum_f64(e2);
+    n2 = warp_sum_f64(n2);
+    if (lane == 0) {
+      red[0][wave] = e2;
+      red[1][wave] = n2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int64_t part = ga.part_base[pi] + local;
+      g.tile_part[part] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+      g.tile_part[ga.nparts + part] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+  }
 }
 
 // Per problem t: out[2t] = sum of the error partials of its sketched tiles,
@@ -1226,9 +1427,10 @@ hipError_t launch_gemm(const GemmLaunch& L, hipStream_t s) {
 // ----------------------------------------------------------------------------
 namespace {
 struct GroupedCfg { int bm, bn, wg_per_cu; };
-// 0..3: the register-staged kernel; 4: 256 x 256 tiles with LDS-direct loads
-// (no fused gather, 16-byte aligned rows)
-constexpr GroupedCfg kGroupedCfgs[] = {{128, 128, 2}, {64, 128, 2}, {128, 64, 2}, {64, 64, 4}, {256, 256, 1}};
+// 0..3: the register-staged kernel; 4: 256 x 256 and 5: 128 x 128 tiles with
+// LDS-direct loads (no fused gather, 16-byte aligned rows)
+constexpr GroupedCfg kGroupedCfgs[] = {{128, 128, 2}, {64, 128, 2}, {128, 64, 2}, {64, 64, 4}, {256, 256, 1},
+                                       {128, 128, 2}};
 constexpr int kGroupedCfgCount = sizeof(kGroupedCfgs) / sizeof(kGroupedCfgs[0]);
 
 template <bool GATHER>
@@ -1239,9 +1441,12 @@ void launch_grouped_cfg(int cfg, dim3 grid, const GroupedArgs& ga, hipStream_t s
     case 1: hipLaunchKernelGGL((sgemm_grouped_kernel<1, 2, F32_BK, 2, GATHER>), grid, block, 0, s, ga); break;
     case 2: hipLaunchKernelGGL((sgemm_grouped_kernel<2, 1, F32_BK, 2, GATHER>), grid, block, 0, s, ga); break;
     case 3: hipLaunchKernelGGL((sgemm_grouped_kernel<1, 1, F32_BK, 4, GATHER>), grid, block, 0, s, ga); break;
-    default:
+    case 4:
       if constexpr (!GATHER)
         hipLaunchKernelGGL(sgemm_grouped_lds_kernel<kLdsWaves>, grid, dim3(kLdsWaves * 64), 0, s, ga);
+      break;
+    default:
+      if constexpr (!GATHER) hipLaunchKernelGGL(sgemm_grouped_lds128_kernel, grid, dim3(256), 0, s, ga);
       break;
   }
 }
@@ -1274,7 +1479,7 @@ bool grouped_lds_ok(const GemmLaunch& L) {
 hipError_t launch_grouped_gemm(const GroupedLaunch& L, hipStream_t s) {
   if (L.items <= 0) return hipSuccess;
   if (L.stage == nullptr) return hipErrorInvalidValue;
-  if (L.gather && L.cfg >= 4) return hipErrorInvalidValue;   // no fused gather on the 256 x 256 tiles
+  if (L.gather && L.cfg >= 4) return hipErrorInvalidValue;   // no fused gather on the LDS-direct tiles
   GroupedArgs ga{reinterpret_cast<const GemmArgs*>(L.probs), L.item_prob, L.item_tile, L.part_base,
                  L.items, L.nparts};
   const dim3 grid((unsigned)L.items);

@@ -186,9 +186,9 @@ def test_results_do_not_depend_on_tiles_or_order(small_batch):
     b.run()
     ref = _snapshot(b)
     # tile configurations 0..3 of the register-staged kernel; sketch
-    # configurations 5..8: the same tiles over materialized sketches
+    # configurations 6..9: the same tiles over materialized sketches
     for cfg_ex in range(4):
-        for cfg_sk in (0, 1, 2, 3, 5, 6, 7, 8):
+        for cfg_sk in (0, 1, 2, 3, 6, 7, 8, 9):
             for lpt in (0, 1):
                 _clear(b)
                 b.set_tuning({"cfg": [cfg_ex, cfg_sk], "lpt": [lpt, 1 - lpt]})
@@ -202,14 +202,15 @@ def test_tuner_picks_a_measured_configuration(small_batch):
     t = b.tune(reps=2)
     # this batch has rows that are not 16-byte aligned: the exact product
     # runs on tile configurations 0..3 (x 2 orders); the sketch fused on 0..3
-    # and materialized on 0..4 (configurations 5..9)
-    expect = {0: set(range(0, 8)), 1: set(range(0, 8)) | set(range(10, 20))}
+    # and materialized on 0..5 (configurations 6..11, the workspace's rows
+    # being aligned)
+    expect = {0: set(range(0, 8)), 1: set(range(0, 8)) | set(range(12, 24))}
     for g in range(2):
         ms = t["ms"][g]
         assert {i for i, v in enumerate(ms) if v > 0} == expect[g]
-        assert all(ms[i] == -1.0 for i in range(20) if i not in expect[g])
+        assert all(ms[i] == -1.0 for i in range(pk.BATCH_TUNING_SLOTS) if i not in expect[g])
         assert ms[2 * t["cfg"][g] + t["lpt"][g]] == min(ms[i] for i in expect[g])
-    assert t["sketch_materialized"] == (t["cfg"][1] >= 5)
+    assert t["sketch_materialized"] == (t["cfg"][1] >= 6)
     _clear(b)
     b.run()
     torch.cuda.synchronize()
@@ -242,10 +243,10 @@ def test_graph_replays_match_eager(small_batch, sk):
 
 
 def test_tuning_out_of_range(small_batch):
-    # exact 4: rows not 16-byte aligned in this batch; sketch 4: no fused
-    # gather on the 256 x 256 tiles; 10: past the materialized forms
+    # exact 4, 5: rows not 16-byte aligned in this batch; sketch 4, 5: no
+    # fused gather on the LDS-direct tiles; 12: past the materialized forms
     b, *_ = small_batch
-    for cfg in ([4, 0], [0, 4], [0, 10], [-1, 0]):
+    for cfg in ([4, 0], [5, 0], [0, 4], [0, 5], [0, 12], [-1, 0]):
         with pytest.raises(pk.SbmmError):
             b.set_tuning({"cfg": cfg, "lpt": [1, 1]})
     b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
@@ -262,9 +263,10 @@ ALIGNED = [
 
 
 def test_wide_tiles_in_batches(h):
-    # tile configuration 4 (256 x 256, LDS-direct loads) for the exact product
-    # and the materialized sketch: the same draws, products within float32
-    # rounding of configuration 0 and of the oracle, graph replays included
+    # tile configurations 4 (256 x 256) and 5 (128 x 128) with LDS-direct
+    # loads for the exact product and the materialized sketch: the same draws,
+    # products within float32 rounding of configuration 0 and of the oracle,
+    # graph replays included
     probs, host = [], []
     for t, d in enumerate(ALIGNED):
         g = wl.rng(200 + t)
@@ -283,7 +285,7 @@ def test_wide_tiles_in_batches(h):
         b.run()
         torch.cuda.synchronize()
         ref = _snapshot(b)
-        for cfg in ([4, 9], [4, 0], [0, 9]):
+        for cfg in ([4, 10], [5, 11], [4, 0], [5, 0], [0, 10], [0, 11]):
             _clear(b)
             b.set_tuning({"cfg": cfg, "lpt": [1, 1]})
             b.run()
@@ -303,7 +305,8 @@ def test_wide_tiles_in_batches(h):
             torch.cuda.synchronize()
             assert _same(snap, _snapshot(b)), rep_
         t = b.tune(reps=1)
-        assert t["ms"][0][8] > 0 and t["ms"][1][18] > 0 and t["ms"][1][8] == -1.0
+        assert t["ms"][0][8] > 0 and t["ms"][0][10] > 0 and t["ms"][1][20] > 0 and t["ms"][1][22] > 0
+        assert t["ms"][1][8] == -1.0 and t["ms"][1][10] == -1.0
     finally:
         b.close()
 
@@ -311,8 +314,8 @@ def test_wide_tiles_in_batches(h):
 def test_wide_sketch_rules_out_wide_tiles(h):
     # one block of 16384 columns drawn 128 times: the materialized sketch C has
     # a leading dimension of 2^21 floats, past the 32-bit panel offsets of the
-    # 256 x 256 tiles, so the materialized configuration 9 is refused and not
-    # timed, and the other configurations still give the oracle's result
+    # LDS-direct tiles, so the materialized configurations 10 and 11 are
+    # refused and not timed, and the others still give the oracle's result
     n, m, p = 16384, 2, 4
     g = wl.rng(300)
     M = g.standard_normal((m, n)).astype(np.float32)
@@ -321,10 +324,12 @@ def test_wide_sketch_rules_out_wide_tiles(h):
     b = pk.Batch(h, probs)
     try:
         with pytest.raises(pk.SbmmError):
-            b.set_tuning({"cfg": [0, 9], "lpt": [1, 1]})
+            b.set_tuning({"cfg": [0, 10], "lpt": [1, 1]})
+        with pytest.raises(pk.SbmmError):
+            b.set_tuning({"cfg": [0, 11], "lpt": [1, 1]})
         t = b.tune(reps=1)
-        assert t["ms"][1][18] == -1.0 and t["ms"][1][19] == -1.0
-        assert t["cfg"][1] != 9
+        assert all(t["ms"][1][i] == -1.0 for i in (20, 21, 22, 23))
+        assert t["cfg"][1] not in (10, 11)
         b.run()
         torch.cuda.synchronize()
         o = oracle_problem(M, N, [0, n], 128, "norm", 0)
@@ -433,19 +438,19 @@ def test_full_batched_workload_sampled(h):
     # both forms of the sketched product (gather fused; sketches materialized
     # group by group, about 80 GB of them in 32 GiB groups) give the same bits
     # on the register-staged tiles, and agree to float32 rounding on the
-    # 256 x 256 tiles, for every problem
+    # LDS-direct tiles, for every problem
     b.set_tuning({"cfg": [0, 0], "lpt": [1, 1]})
     b.run()
     torch.cuda.synchronize()
     ref = [x.clone() for x in b.CD]
-    for sk in (2, 6, 9):
+    for sk in (2, 7, 10, 11):
         for x in b.CD:
             x.fill_(float("nan"))
         b.set_tuning({"cfg": [0, sk], "lpt": [1, 1]})
         b.run()
         torch.cuda.synchronize()
         for t in range(len(items)):
-            if sk == 9:
+            if sk >= 10:
                 d = ((b.CD[t].double() - ref[t].double()).norm() / ref[t].double().norm()).item()
                 assert d < 1e-5, (sk, t)
             else:
