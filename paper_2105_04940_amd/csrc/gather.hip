@@ -167,7 +167,8 @@ __global__ __launch_bounds__(kThreads) void batch_gather_kernel(const GatherArgs
                                                                 int32_t count) {
   const int64_t bid = blockIdx.x;
   const int32_t t = find_item(wg_off, count, bid);
-  gather_body<float, float>(args[t], bid - wg_off[t]);
+  const GatherArgs a = args[t];   // a copy: read once, not reloaded behind the kernel's stores
+  gather_body<float, float>(a, bid - wg_off[t]);
 }
 
 template <typename Tin>

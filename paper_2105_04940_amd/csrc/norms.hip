@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void batch_norms_kernel(const NormArgs* _
   __shared__ double sm[4 * 64 * (16 / sizeof(T))];
   const int64_t bid = blockIdx.x;
   const int32_t t = find_problem(wg_off, count, bid);
-  const NormArgs& a = args[t];
+  const NormArgs a = args[t];   // a copy: read once, not reloaded behind the kernel's stores
   const int64_t local = bid - wg_off[t];
   if (local < a.nblocks_m)
     colsq_part<T>(a, local, sm);
@@ -318,7 +318,8 @@ __global__ __launch_bounds__(kThreads) void batch_stats_kernel(const StatsArgs* 
                                                                const int64_t* __restrict__ blk_off, int32_t count) {
   const int64_t bid = blockIdx.x;
   const int32_t t = find_problem(blk_off, count, bid);
-  block_stats_body(args[t], (int)(bid - blk_off[t]), 0);
+  const StatsArgs a = args[t];
+  block_stats_body(a, (int)(bid - blk_off[t]), 0);
 }
 
 int elems_per_vec(sbmm_dtype dt) { return 16 / (int)dtype_size(dt); }

@@ -610,7 +610,7 @@ __global__ __launch_bounds__(kThreads) void colmap_kernel(PlanLaunch a) {
 // problem blockIdx.x (design, allocation, draws, offsets, column map), with
 // workgroup barriers between the steps.
 __global__ __launch_bounds__(kThreads) void batch_plan_kernel(const PlanLaunch* __restrict__ plans) {
-  const PlanLaunch& a = plans[blockIdx.x];
+  const PlanLaunch a = plans[blockIdx.x];   // a copy: read once, not reloaded behind the kernel's stores
   design_body(a, 0);
   __syncthreads();
   alloc_block_body(a);
