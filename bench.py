@@ -768,7 +768,7 @@ def main():
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1],
                     "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d <dir> -o run -- "
                     "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-linear-layer --no-batched "
-                    "--no-section4 --calibration-copy")
+                    "--no-section4 --no-section4-sweeps --no-bound-checks --calibration-copy")
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the path "
