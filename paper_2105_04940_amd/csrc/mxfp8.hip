@@ -430,17 +430,28 @@ __global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g)
   // group's scales) is issued into the other stage, this step's tile is
   // consumed, then everything lands.
   const int64_t nkt = (K + BK - 1) / BK;
-  auto step = [&](int64_t kt, const MxStage& cur, MxStage& nxt, const MxScales& scur, MxScales& snxt) {
+  // the scale words of the current group of four steps for this lane's four
+  // rows of A and two columns of B, read from LDS once per group (16 bytes a
+  // row: conflict-free, where one word per step at a 16-byte stride is not)
+  uint4 sa4[4], sb4[CB];
+  auto step = [&](int64_t kt, int kq, const MxStage& cur, MxStage& nxt, const MxScales& scur, MxScales& snxt) {
+    if (kq == 0) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) sa4[b] = *reinterpret_cast<const uint4*>(&scur.w[(wm0 + 32 * b + lr) * 4]);
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        sb4[c] = *reinterpret_cast<const uint4*>(&scur.w[(MxTile::BM + wn0 + 32 * c + lr) * 4]);
+    }
     if (kt + 1 < nkt) {
-      if ((kt & 3) == 3) issue_scales((kt + 1) >> 2, snxt);
+      if (kq == 3) issue_scales((kt + 1) >> 2, snxt);
       issue(kt + 1, nxt);
     }
+    auto word = [kq](const uint4& v) { return kq == 0 ? v.x : kq == 1 ? v.y : kq == 2 ? v.z : v.w; };
     uint32_t sa[4], sb[CB];
-    const int kq = (int)(kt & 3);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) sa[b] = scur.w[(wm0 + 32 * b + lr) * 4 + kq];
+    for (int b = 0; b < 4; ++b) sa[b] = word(sa4[b]);
 #pragma unroll
-    for (int c = 0; c < CB; ++c) sb[c] = scur.w[(MxTile::BM + wn0 + 32 * c + lr) * 4 + kq];
+    for (int c = 0; c < CB; ++c) sb[c] = word(sb4[c]);
     compute(cur, sa, sb);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -452,16 +463,17 @@ __global__ __launch_bounds__(kMxWaves * 64, 1) void mx_gemm_lds_kernel(MxArgs g)
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   // eight steps per trip: the tile stages alternate every step, the scale
-  // stages every four, each at a fixed LDS object
+  // stages every four, each at a fixed LDS object (kt is a multiple of 8, so
+  // each call's step within its group of four is a constant)
   for (int64_t kt = 0; kt < nkt; kt += 8) {
-    step(kt, st0, st1, sc0, sc1);
-    if (kt + 1 < nkt) step(kt + 1, st1, st0, sc0, sc1);
-    if (kt + 2 < nkt) step(kt + 2, st0, st1, sc0, sc1);
-    if (kt + 3 < nkt) step(kt + 3, st1, st0, sc0, sc1);
-    if (kt + 4 < nkt) step(kt + 4, st0, st1, sc1, sc0);
-    if (kt + 5 < nkt) step(kt + 5, st1, st0, sc1, sc0);
-    if (kt + 6 < nkt) step(kt + 6, st0, st1, sc1, sc0);
-    if (kt + 7 < nkt) step(kt + 7, st1, st0, sc1, sc0);
+    step(kt, 0, st0, st1, sc0, sc1);
+    if (kt + 1 < nkt) step(kt + 1, 1, st1, st0, sc0, sc1);
+    if (kt + 2 < nkt) step(kt + 2, 2, st0, st1, sc0, sc1);
+    if (kt + 3 < nkt) step(kt + 3, 3, st1, st0, sc0, sc1);
+    if (kt + 4 < nkt) step(kt + 4, 0, st0, st1, sc1, sc0);
+    if (kt + 5 < nkt) step(kt + 5, 1, st1, st0, sc1, sc0);
+    if (kt + 6 < nkt) step(kt + 6, 2, st0, st1, sc1, sc0);
+    if (kt + 7 < nkt) step(kt + 7, 3, st1, st0, sc1, sc0);
   }
 
   double e2 = 0.0, n2 = 0.0;
