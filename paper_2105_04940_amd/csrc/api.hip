@@ -248,7 +248,11 @@ sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
     return do_exact(h, &Q, off_dev, MN, ldmn, Y, ldy, blkprod_sq, out2, ar, s);
   }
   const bool bn = blkprod_sq != nullptr;
-  const int64_t tiles = gemm_tiles(P->in_dtype, P->m, P->p, bn);
+  GemmLaunch G{};
+  G.dt = P->in_dtype; G.A = P->M; G.lda = P->ldm; G.B = P->N; G.ldb = P->ldn;
+  G.m = P->m; G.p = P->p; G.K_host = P->n; G.K_dev = nullptr;
+  // bf16 products never carry block sums here (handled above)
+  const int64_t tiles = P->in_dtype == SBMM_BF16 ? hgemm_tiles(G) : gemm_tiles(P->in_dtype, P->m, P->p, bn);
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
   double* blk_part = bn ? ar.take<double>((size_t)P->K * std::max<int64_t>(tiles, 1) * 4) : nullptr;
   float* stage = ar.take<float>(gemm_stage_bytes(P->in_dtype, P->m, P->p) / sizeof(float));
@@ -260,9 +264,6 @@ sbmm_status do_exact(sbmm_handle h, const sbmm_problem* P, const int64_t* off_de
     if (bn) HIP_TRY(h, launch_fill_f64(blkprod_sq, P->K, 0.0, s));
     return SBMM_OK;
   }
-  GemmLaunch G{};
-  G.dt = P->in_dtype; G.A = P->M; G.lda = P->ldm; G.B = P->N; G.ldb = P->ldn;
-  G.m = P->m; G.p = P->p; G.K_host = P->n; G.K_dev = nullptr;
   G.Cout = MN; G.ldc = ldmn; G.Y = Y; G.ldy = ldy; G.tile_part = tile_part;
   G.K_blocks = P->K; G.off_dev = off_dev; G.blk_part = blk_part; G.stage = stage;
   G.skinny_ws = skinny; G.skinny_K_max = P->n;
@@ -662,11 +663,16 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   if ((MN != nullptr) != (err_sq != nullptr)) return fail(h, SBMM_E_ARG, "MN and err_sq go together");
   if (MN && ldmn < p) return fail(h, SBMM_E_ARG, "ldmn < p");
   hipStream_t s = (hipStream_t)stream;
-  // bf16 runs in the inner-index-contiguous form: D^T (p x L_pad) first
+  GemmLaunch G{};
+  G.dt = dtype; G.A = C; G.lda = ldc; G.B = D; G.ldb = ldd; G.m = m; G.p = p;
+  G.K_host = 0; G.K_dev = L_dev; G.K_max = L_pad_max; G.Cout = CD; G.ldc = ldcd; G.Y = MN; G.ldy = ldmn;
+  // bf16 reads D as it is where its rows allow (16-byte aligned, 32-bit
+  // offsets), otherwise from a transposed copy D^T (p x L_pad)
   const bool bf = dtype == SBMM_BF16;
+  const bool bf_t = bf && !hgemm_kn_ok(G);
   const int64_t tiles = bf ? gemm_tiles_tn(m, p) : gemm_tiles(dtype, m, p, false);
   const size_t stage_elems = gemm_stage_bytes(dtype, m, p) / sizeof(float);
-  const size_t dt_elems = bf ? (size_t)std::max<int64_t>(p, 1) * std::max<int64_t>(L_pad_max, 1) : 0;
+  const size_t dt_elems = bf_t ? (size_t)std::max<int64_t>(p, 1) * std::max<int64_t>(L_pad_max, 1) : 0;
   const size_t skb = bf ? 0 : gemm_skinny_ws_bytes(dtype, m, p, L_pad_max, 0);
   Arena dry(nullptr);
   dry.take<double>(2 * std::max<int64_t>(tiles, 1));
@@ -685,12 +691,9 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
     if (err_sq) HIP_TRY(h, launch_fill_f64(err_sq, 1, 0.0, s));
     return SBMM_OK;
   }
-  GemmLaunch G{};
-  G.dt = dtype; G.A = C; G.lda = ldc; G.B = D; G.ldb = ldd; G.m = m; G.p = p;
-  G.K_host = 0; G.K_dev = L_dev; G.Cout = CD; G.ldc = ldcd; G.Y = MN; G.ldy = ldmn;
   G.tile_part = err_sq ? tile_part : nullptr;
   G.stage = stage;
-  if (bf) {
+  if (bf_t) {
     HIP_TRY(h, launch_transpose_bf16(SBMM_BF16, D, L_pad_max, p, ldd, L_dev, Dt, L_pad_max, s));
     G.B = Dt; G.ldb = L_pad_max; G.b_trans = true;
   }
@@ -842,7 +845,10 @@ sbmm_status run_impl(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
     const int64_t lddw = D ? ldd : P->p;
     void* MNw = MN ? MN : (bp ? ar.take<char>(pes * (size_t)std::max<int64_t>(P->m, 1) * std::max<int64_t>(P->p, 1)) : nullptr);
     const int64_t ldmnw = MN ? ldmn : P->p;
-    const int64_t tiles_s = gemm_tiles(compute, P->m, P->p, false);
+    GemmLaunch Gs{};   // the sketched product (step 5)
+    Gs.dt = compute; Gs.A = Cw; Gs.lda = ldcw; Gs.B = Dw; Gs.ldb = lddw; Gs.m = P->m; Gs.p = P->p;
+    Gs.K_host = 0; Gs.K_dev = plan->col_off + P->c; Gs.K_max = sz.L_pad_max;
+    const int64_t tiles_s = compute == SBMM_BF16 ? hgemm_tiles(Gs) : gemm_tiles(compute, P->m, P->p, false);
     double* sk_part = ar.take<double>(2 * std::max<int64_t>(tiles_s, 1));
     float* sk_stage = ar.take<float>(gemm_stage_bytes(compute, P->m, P->p) / sizeof(float));
     const size_t skb = compute == SBMM_BF16 ? 0 : gemm_skinny_ws_bytes(compute, P->m, P->p, sz.L_pad_max, 0);
@@ -910,9 +916,8 @@ sbmm_status run_impl(sbmm_handle h, const sbmm_problem* P, sbmm_dtype compute, v
     }
     // 5. sketched product (with the error when MN is already there)
     if (tiles_s > 0) {
-      GemmLaunch G{};
-      G.dt = compute; G.A = Cw; G.lda = ldcw; G.B = Dw; G.ldb = lddw; G.m = P->m; G.p = P->p;
-      G.K_host = 0; G.K_dev = plan->col_off + P->c; G.Cout = CD; G.ldc = ldcd;
+      GemmLaunch G = Gs;
+      G.Cout = CD; G.ldc = ldcd;
       G.Y = bp ? MNw : nullptr; G.ldy = ldmnw; G.tile_part = bp ? sk_part : nullptr;
       G.stage = sk_stage;
       G.skinny_ws = sk_skinny; G.skinny_K_max = sz.L_pad_max;

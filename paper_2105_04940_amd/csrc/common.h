@@ -191,6 +191,9 @@ struct GemmLaunch {
   // (SC_ROWS), as bf16 or (sc_f32) float32, leading dimension sc_ld
   const int64_t* m_dev; const int64_t* p_dev;
   int sc_mode; void* sc_out; int64_t sc_ld; int sc_f32; const int32_t* sc_map; const double* sc_w;
+  // upper bound of the device inner extent (0: unknown); the bf16 product
+  // with B as K x p rows needs it to bound its 32-bit offsets
+  int64_t K_max;
 };
 enum { SC_NONE = 0, SC_COLS = 1, SC_ROWS = 2 };
 // Workspace of the split-K path for an m x p product with inner extent up to
@@ -237,6 +240,13 @@ hipError_t launch_grouped_reduce(const double* sk_part, int64_t sk_nparts, const
                                  hipStream_t s);
 // bf16 products (launch_gemm forwards SBMM_BF16 here) and their tile shape
 hipError_t launch_hgemm(const GemmLaunch& a, hipStream_t s);
+// The bf16 product takes A (m x K) and B (K x p) as they are, both row-major
+// (no transposed copy of B): 16-byte aligned rows and 32-bit offsets over the
+// K_max (or K_host) rows of B.
+bool hgemm_kn_ok(const GemmLaunch& a);
+// Workgroup tiles (error-partial slots) of the bf16 product launch_gemm runs
+// for these operands (256 x 256 tiles for the forms above, else 128 x 128).
+int64_t hgemm_tiles(const GemmLaunch& a);
 void hgemm_tile_shape(int64_t* bm, int64_t* bn);
 
 // ||M^k N_k||_F^2 per block through the Gram matrices (float32 or bf16

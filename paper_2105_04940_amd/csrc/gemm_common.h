@@ -34,6 +34,48 @@ struct GemmArgs {
   int sc_mode; void* sc_out; int64_t sc_ld; int sc_f32; const int32_t* sc_map; const double* sc_w;
 };
 
+// Words of a raw buffer resource (base address, range in bytes, the flags of
+// an untyped buffer), each made wave-uniform so the quad sits in scalar
+// registers. Offsets at or past `bytes` read as zero.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ i32x4 buffer_words(const void* base, int bytes) {
+  const uint64_t u = reinterpret_cast<uint64_t>(base);
+  i32x4 r;
+  r.x = (int)__builtin_amdgcn_readfirstlane((uint32_t)u);
+  r.y = (int)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  r.z = __builtin_amdgcn_readfirstlane(bytes);
+  r.w = 0x00020000;
+  return r;
+}
+
+// LDS address of a __shared__ object.
+__device__ __forceinline__ uint32_t lds_offset(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// One LDS-DMA load of 16 bytes a lane: lane l's bytes at voff + soff of the
+// buffer land at LDS address lds + 16 l (lds wave-uniform). Written as inline
+// asm rather than the load-to-LDS builtin on purpose: with the builtin the
+// compiler sinks the loads to the end of the matrix-instruction sequence that
+// follows (leaving them a fraction of a k-step to land) and adds its own
+// conservative waits before reads of the other stage. Here the load issues
+// where it is written, nothing else waits for it, and the "memory" clobber
+// keeps LDS reads from moving across it. The caller waits with
+// wait_loads_barrier before any wave reads the destination.
+__device__ __forceinline__ void lds_dma16(i32x4 rs, uint32_t lds, uint32_t voff, uint32_t soff) {
+  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+               :: "s"(lds), "v"(voff), "s"(rs), "s"(soff) : "memory", "m0");
+}
+
+// Wait until at most N of this wave's vector-memory loads are outstanding
+// (they complete in order), then barrier: every wave's loads older than its
+// newest N have landed in LDS. One statement, so no LDS read moves above it;
+// a bare barrier, since __syncthreads() adds a fence that waits for all loads.
+template <int N>
+__device__ __forceinline__ void wait_loads_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" :: "n"(N) : "memory");
+}
+
 __device__ inline __attribute__((always_inline)) int64_t inner_extent(const GemmArgs& g) {
   if (g.K_dev) {
     const int64_t L = *g.K_dev;

@@ -18,6 +18,8 @@ using namespace gemm_detail;
 // operand rounding (2^-9) dominates the error, so there is no fold.
 // ============================================================================
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
 
 template <int WMB, int WNB, int BK>
 struct HgemmTile {
@@ -384,8 +386,8 @@ __global__ __launch_bounds__(kThreads, 1) void hgemm_tn_kernel(GemmArgs g) {
 // the buffer's record count and chunks past the inner extent get an
 // out-of-range offset: both read as zero, so edge tiles need no separate
 // path, and a live chunk of a valid row never reads past that row's first K
-// elements. Per k-step: issue the next tile's loads, run the 64 matrix
-// instructions on the current tile, wait for the loads, barrier.
+// elements. Per k-step: wait for the step's loads and barrier, issue the
+// next step's loads, run the 64 matrix instructions on the current tile.
 // ============================================================================
 template <int BK_, int STAGES_>
 struct TnLdsTile {
@@ -405,23 +407,28 @@ __device__ __forceinline__ int tn_lds_slot(int row, int chunk) {
   else return row * 4 + (chunk ^ ((row >> 2) & 3));
 }
 
-// Buffer resource of a panel of `rows` rows; every field is made explicitly
-// wave-uniform (scalar registers), so the loads need no per-lane loop.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const uint16_t* base, int64_t rows, int64_t ld) {
-  const uint64_t u = reinterpret_cast<uint64_t>(base);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-  const int bytes = __builtin_amdgcn_readfirstlane((int)(rows > 0 ? rows * ld * 2 : 0));
-  void* p = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
-  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
-}
-
 // NW waves per workgroup: 4 (one per SIMD, 128 x 128 each) or 8 (two per
 // SIMD, 128 x 64 each). EPI: SC_NONE stores the float32 product (and the
 // error partials); SC_COLS / SC_ROWS scatter the weighted product into the
 // columns / rows of another matrix (the backward's dM, dN).
-template <int BK, int STAGES, int NW, int EPI>
+//
+// BKN: B is given as K x p rows (the sketch's D as gathered) instead of p x K.
+// A k-step's B tile is then its 64 k-rows of 256 columns (512 bytes each, two
+// rows per wave instruction: lane l fills slot 32 (l >> 5) + (l & 31) of the
+// instruction's pair of rows), chunk c of row r at slot c ^ 4 (r & 3). The
+// matrix instruction wants, in lane l, the 8 k-values of column l & 31 at k
+// 8 (l >> 5) .. + 7: two transposing LDS reads (ds_read_b64_tr_b16) give
+// them. In such a read lane i of each 16-lane group names 8 bytes (4 columns)
+// of one row and receives the element of its own column from the 4 rows the
+// group named (a one-wave probe of the instruction: element e of lane i
+// comes from the 8 bytes lane 4 e + (i >> 2) named, position i & 3), so the
+// group names rows k0 + (i >> 2), columns n0 + 4 (i & 3). The four rows of a
+// group differ in r & 3, so the swizzle spreads their 32-byte pieces over
+// distinct banks.
+template <int BK, int STAGES, int NW, int EPI, bool BKN = false>
 __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
+  static_assert(STAGES == 2, "a ring of two stages");
+  static_assert(!BKN || (BK == 64 && NW == 8), "the k-row B form: k-step 64, 8 waves");
   using Tile = TnLdsTile<BK, STAGES>;
   constexpr int KC = Tile::KC;
   constexpr int CB = 16 / NW;                          // 32-column blocks per wave
@@ -443,9 +450,12 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   const int lr = lane & 31, lh = lane >> 5;
   const int wm0 = (wave & 1) * 128, wn0 = (wave >> 1) * 32 * CB;
   const uint16_t* A = reinterpret_cast<const uint16_t*>(g.A) + m0 * g.lda;
-  const uint16_t* B = reinterpret_cast<const uint16_t*>(g.B) + n0 * g.ldb;
-  const __amdgpu_buffer_rsrc_t ra = panel_rsrc(A, min((int64_t)Tile::BM, g.m - m0), g.lda);
-  const __amdgpu_buffer_rsrc_t rb = panel_rsrc(B, min((int64_t)Tile::BN, g.p - n0), g.ldb);
+  // BKN: B's columns from n0 on, to the end of its K rows (rows at or past K
+  // read as zero, as do chunks at or past column p)
+  const uint16_t* B = reinterpret_cast<const uint16_t*>(g.B) + (BKN ? n0 : n0 * g.ldb);
+  const i32x4 ra = buffer_words(A, (int)(min((int64_t)Tile::BM, g.m - m0) * g.lda * 2));
+  const i32x4 rb = buffer_words(B, BKN ? (int)((K * g.ldb - n0) * 2)
+                                       : (int)(min((int64_t)Tile::BN, g.p - n0) * g.ldb * 2));
   constexpr unsigned kOut = 0x80000000u;   // past any record count
 
   f32x16 acc[4][CB];
@@ -468,10 +478,44 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       const bool live = k0 + 8 * chunk < K;   // the inner tail reads zero
       const unsigned oa = live ? (unsigned)(row * g.lda * 2 + chunk * 16) : kOut;
       const unsigned ob = live ? (unsigned)(row * g.ldb * 2 + chunk * 16) : kOut;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(INSTS * wave + j) * 64], 16, oa, sk, 0, 0);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rb, (__attribute__((address_space(3))) void*)&sh.Bs[buf][(INSTS * wave + j) * 64], 16, ob, sk, 0, 0);
+      lds_dma16(ra, lds_offset(&sh.As[buf][(INSTS * wave + j) * 64]), oa, sk);
+      if constexpr (!BKN) lds_dma16(rb, lds_offset(&sh.Bs[buf][(INSTS * wave + j) * 64]), ob, sk);
+    }
+    if constexpr (BKN) {
+      constexpr int BINSTS = BK / 2 / NW;   // two k-rows per instruction
+      const unsigned skb = (unsigned)(k0 * g.ldb * 2);
+#pragma unroll
+      for (int j = 0; j < BINSTS; ++j) {
+        const int r = 2 * (BINSTS * wave + j) + (lane >> 5);
+        const int c = (lane & 31) ^ (4 * (r & 3));
+        const unsigned ob = n0 + 8 * c < g.p ? (unsigned)(r * g.ldb * 2 + c * 16) : kOut;
+        lds_dma16(rb, lds_offset(&sh.Bs[buf][(BINSTS * wave + j) * 64]), ob, skb);
+      }
+    }
+  };
+  // BKN: byte offset in a B stage of this lane's first transposing read for
+  // column block c (k-row 8 (l >> 5) + ((l & 15) >> 2), column wn0 + 32 c +
+  // 16 ((l >> 4) & 1) + 4 (l & 3)); other sub-steps (16 rows on) and the
+  // second read (4 rows on) keep r & 3, so they add constants
+  int bkn_off[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int i = lane & 15, G = lane >> 4;
+    const int r = 8 * (G >> 1) + (i >> 2);
+    const int n = wn0 + 32 * c + 16 * (G & 1) + 4 * (i & 3);
+    bkn_off[c] = r * 512 + (((n >> 3) ^ (4 * (r & 3))) << 4) + ((n >> 2) & 1) * 8;
+  }
+  auto b_frag = [&](int buf, int s, int c) -> bf16x8 {
+    if constexpr (BKN) {
+      const char* base = reinterpret_cast<const char*>(&sh.Bs[buf][0]) + bkn_off[c] + 16 * s * 512;
+      const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+          (__attribute__((address_space(3))) i16x4*)(base));
+      const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+          (__attribute__((address_space(3))) i16x4*)(base + 4 * 512));
+      const i16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+      return __builtin_bit_cast(bf16x8, v);
+    } else {
+      return __builtin_bit_cast(bf16x8, sh.Bs[buf][tn_lds_slot<KC>(wn0 + 32 * c + lr, 2 * s + lh)]);
     }
   };
   auto compute = [&](int buf) {
@@ -482,8 +526,7 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       for (int b = 0; b < 4; ++b)
         av[b] = __builtin_bit_cast(bf16x8, sh.As[buf][tn_lds_slot<KC>(wm0 + 32 * b + lr, 2 * s + lh)]);
 #pragma unroll
-      for (int c = 0; c < CB; ++c)
-        bv[c] = __builtin_bit_cast(bf16x8, sh.Bs[buf][tn_lds_slot<KC>(wn0 + 32 * c + lr, 2 * s + lh)]);
+      for (int c = 0; c < CB; ++c) bv[c] = b_frag(buf, s, c);
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -492,26 +535,19 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
     }
   };
 
-  // a ring of STAGES tiles, loads issued STAGES - 1 steps ahead; before step
-  // kt computes, the loads of every step up to kt have landed (memory reads
-  // of a wave complete in order, so at most the STAGES - 2 newer steps' loads
-  // may still be outstanding) and the barrier publishes them to all waves
+  // two stages: at the top of step kt every wave's loads of step kt have
+  // landed (vmcnt(0), barrier); the loads of step kt + 1 then go into the
+  // stage step kt - 1 read, and overlap the matrix instructions of step kt
   const int64_t nkt = (K + BK - 1) / BK;
-#pragma unroll
-  for (int st = 0; st < STAGES - 1; ++st)
-    if (st < nkt) issue(st, st);
-  for (int64_t kt = 0; kt < nkt; ++kt) {
-    const int64_t ahead = nkt - 1 - kt;   // steps issued after kt (capped below)
-    if (STAGES == 2 || ahead <= 0) {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    } else if (ahead == 1) {
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * INSTS) : "memory");
-    } else {
-      asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * INSTS * (STAGES - 2)) : "memory");
-    }
-    __syncthreads();
-    if (kt + STAGES - 1 < nkt) issue(kt + STAGES - 1, (int)((kt + STAGES - 1) % STAGES));
-    compute((int)(kt % STAGES));
+  auto step = [&](int64_t kt, int buf) {
+    wait_loads_barrier<0>();
+    if (kt + 1 < nkt) issue(kt + 1, buf ^ 1);
+    compute(buf);
+  };
+  if (nkt > 0) issue(0, 0);
+  for (int64_t kt = 0; kt < nkt; kt += 2) {
+    step(kt, 0);
+    if (kt + 1 < nkt) step(kt + 1, 1);
   }
 
   if constexpr (EPI != SC_NONE) {
@@ -611,8 +647,39 @@ void hgemm_tn_tile_shape(int64_t* bm, int64_t* bn) { *bm = TnTile::BM; *bn = TnT
 
 int64_t gemm_tiles_tn(int64_t m, int64_t p) { return ceil_div(m, TnTile::BM) * ceil_div(p, TnTile::BN); }
 
+bool hgemm_kn_ok(const GemmLaunch& L);
+
+int64_t hgemm_tiles(const GemmLaunch& L) {
+  int64_t bm, bn;
+  if (hgemm_kn_ok(L) || (L.b_trans && !L.a_trans)) hgemm_tn_tile_shape(&bm, &bn);
+  else hgemm_tile_shape(&bm, &bn);
+  return ceil_div(L.m, bm) * ceil_div(L.p, bn);
+}
+
+bool hgemm_kn_ok(const GemmLaunch& L) {
+  const int64_t K_max = L.K_dev ? L.K_max : L.K_host;
+  const bool rows16 = (uintptr_t)L.A % 16 == 0 && (L.lda * 2) % 16 == 0 && (uintptr_t)L.B % 16 == 0 &&
+                      (L.ldb * 2) % 16 == 0;
+  // whole 8-element chunks of A along k (a device extent is a multiple of
+  // 32), 32-bit offsets over A's 256-row panels and all of B's rows
+  const bool chunks = L.K_dev != nullptr || L.K_host % 8 == 0;
+  const bool fits = 257 * L.lda * 2 < ((int64_t)1 << 31) && (K_max + 1) * L.ldb * 2 < ((int64_t)1 << 31);
+  return L.dt == SBMM_BF16 && !L.a_trans && !L.b_trans && L.sc_mode == SC_NONE && !L.m_dev && !L.p_dev &&
+         K_max > 0 && rows16 && chunks && fits;
+}
+
 hipError_t launch_hgemm(const GemmLaunch& L, hipStream_t s) {
   int64_t bm, bn;
+  if (hgemm_kn_ok(L)) {
+    // B as K x p rows: the 256 x 256 kernel with transposing reads of B
+    hgemm_tn_tile_shape(&bm, &bn);
+    const GemmArgs g = make_gemm_args(L, bm, bn);
+    const int64_t tiles = g.tiles_m * g.tiles_n;
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((hgemm_tn_lds_kernel<TN_BK, TN_STAGES, TN_WAVES, SC_NONE, true>), dim3((unsigned)tiles),
+                       dim3(TN_WAVES * 64), 0, s, g);
+    return hipGetLastError();
+  }
   if (L.b_trans && !L.a_trans) {
     // both operands inner-index contiguous: the 256 x 256 kernels
     hgemm_tn_tile_shape(&bm, &bn);

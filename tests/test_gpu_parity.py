@@ -582,6 +582,43 @@ def test_bf16_sketch(h, in_dtype, shape):
     assert arith < 2e-2
 
 
+# p a multiple of 8: D's rows are 16-byte aligned and the product reads D as
+# gathered (K x p rows, transposing LDS reads of B); ragged row and column
+# tiles (m, p not multiples of 256) and, with equal blocks of 50 and c = 45,
+# an inner extent L_pad = 2272 that ends half way through a 64-wide k-step
+@pytest.mark.parametrize("m,p,n,K,c", [(300, 264, 3000, 60, 45), (257, 520, 5000, 100, 64), (64, 8, 800, 16, 9)])
+def test_bf16_sketch_product_reads_d_rows(h, m, p, n, K, c):
+    M, N, _ = wl.random_problem(m, n, p, K, seed=m + p, skew=1.0)
+    off = np.arange(0, n + 1, n // K, dtype=np.int64)
+    Md, Nd = to_dev(M, torch.float32), to_dev(N, torch.float32)
+    prob = pk.Problem(Md, Nd, off, c, prob="uniform", seed=4)
+    col, row, blk = h.norms(prob)
+    pl = h.plan(prob, col, row, blk)
+    C, D = h.sketch(prob, pl, out_dtype=torch.bfloat16)
+    o = om.run(host64(Md), host64(Nd), off, c, prob="uniform", seed=4)
+    assert np.array_equal(pl.idx.cpu().numpy(), o.draws.atom)
+    L = o.draws.L
+    Cq, Dq = _bf16_round(o.C), _bf16_round(o.D)
+    assert np.array_equal(host64(C)[:, :L], Cq) and np.array_equal(host64(D)[:L], Dq)
+    MN = torch.from_numpy(o.MN.astype(np.float32)).to(Md.device)
+    CD, err = h.sketch_gemm(C, D, pl, MN=MN)
+    ref = Cq @ Dq
+    assert rel(host64(CD), ref) < 1e-5
+    e_ref = float(np.sum((o.MN.astype(np.float32).astype(np.float64) - ref) ** 2))
+    assert abs(err.item() - e_ref) <= 1e-4 * e_ref
+
+
+# the exact product of bf16 inputs with row-major N read as it is (aligned rows)
+@pytest.mark.parametrize("m,n,p", [(300, 1000, 264), (257, 4104, 520)])
+def test_bf16_exact_product_reads_n_rows(h, m, n, p):
+    M, N, off = wl.random_problem(m, n, p, 20, seed=n + p, skew=1.0)
+    Md, Nd = to_dev(M, torch.bfloat16), to_dev(N, torch.bfloat16)
+    MN, _, mn_sq = h.exact(pk.Problem(Md, Nd, off, 4), store=True)
+    omn = host64(Md) @ host64(Nd)
+    assert rel(host64(MN), omn) < 1e-5
+    assert abs(mn_sq.item() - np.sum(omn * omn)) <= 1e-5 * np.sum(omn * omn)
+
+
 def test_plan_rejects_missing_block_norms(h):
     M, N, off = wl.random_problem(10, 60, 8, 3, seed=40)
     for kw in (dict(prob="exact"), dict(mode="stratified", alloc="opt")):
