@@ -63,6 +63,11 @@ __device__ __forceinline__ uint32_t lds_offset(const void* p) {
 // keeps LDS reads from moving across it. The caller waits with
 // wait_loads_barrier before any wave reads the destination.
 __device__ __forceinline__ void lds_dma16(i32x4 rs, uint32_t lds, uint32_t voff, uint32_t soff) {
+  // the scalar operands are uniform by contract; readfirstlane makes that
+  // visible where the compiler cannot prove it (free where it can)
+  rs.x = __builtin_amdgcn_readfirstlane(rs.x); rs.y = __builtin_amdgcn_readfirstlane(rs.y);
+  rs.z = __builtin_amdgcn_readfirstlane(rs.z); rs.w = __builtin_amdgcn_readfirstlane(rs.w);
+  lds = __builtin_amdgcn_readfirstlane(lds); soff = __builtin_amdgcn_readfirstlane(soff);
   asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
                :: "s"(lds), "v"(voff), "s"(rs), "s"(soff) : "memory", "m0");
 }

@@ -338,8 +338,11 @@ struct MxStage {
   uint4 B[MxTile::BN * MxTile::KC];
 };
 // E8M0 scale words of four k-steps for the 256 rows of A and the 256 columns
-// of B: [row][k-step % 4], rows of B after those of A
-struct MxScales {
+// of B: [row][k-step % 4], rows of B after those of A. 16-byte aligned, so a
+// row's four words are one ds_read_b128 (with 4-byte alignment the compiler
+// splits it into dword pairs, which at a 16-byte lane stride put rows r and
+// r + 16 in one bank)
+struct alignas(16) MxScales {
   uint32_t w[2 * MxTile::BM * 4];
 };
 
