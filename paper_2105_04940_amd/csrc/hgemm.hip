@@ -590,30 +590,9 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       }
     return;
   }
-  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
-  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
   double e2 = 0.0, n2 = 0.0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
-      if (row >= g.m) continue;
-#pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        const int64_t col = n0 + wn0 + 32 * c + lr;
-        if (col >= g.p) continue;
-        const float val = acc[b][c][v];
-        if (Cout) Cout[row * g.ldc + col] = val;
-        const double dv = (double)val;
-        if (Y) {
-          const double d = dv - (double)Y[row * g.ldy + col];
-          e2 = fma(d, d, e2);
-        }
-        n2 = fma(dv, dv, n2);
-      }
-      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
+  store_tile_with_error<CB>(acc, reinterpret_cast<float*>(g.C), g.ldc, reinterpret_cast<const float*>(g.Y), g.ldy,
+                            g.m, g.p, m0 + wm0 + 4 * lh, n0 + wn0 + lr, e2, n2);
   if (g.tile_part) {
     // NW waves' sums added in wave order
     e2 = warp_sum_f64(e2);
