@@ -721,21 +721,30 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
   const __amdgpu_buffer_rsrc_t rs = f32_rsrc(sbase, inside ? 128 * 32 * CB * 4 : 0);
   const int vo = lane * 4;
   int folds = 0;
+  // slot += acc (acc first), one accumulator block at a time; the slot
+  // values of the next block are requested before the current one is added
   auto fold = [&]() {
+    float nx[2][16];
+    auto ld = [&](int q) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+      for (int v = 0; v < 16; ++v)
+        nx[q & 1][v] = folds ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, (q * 16 + v) * 256, 0))
+                             : 0.0f;
+    };
+    ld(0);
 #pragma unroll
-      for (int c = 0; c < CB; ++c) {
+    for (int q = 0; q < 4 * CB; ++q) {   // accumulator block q = b CB + c
+      if (q + 1 < 4 * CB) ld(q + 1);
+      const int b = q / CB, c = q % CB;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int so = ((b * CB + c) * 16 + v) * 256;
-          float x = acc[b][c][v];
-          if (folds) x += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, vo, so, 0);
-        }
-        acc[b][c] = f32x16{};
-        __builtin_amdgcn_sched_barrier(0);
+      for (int v = 0; v < 16; ++v) {
+        float x = acc[b][c][v];
+        if (folds) x += nx[q & 1][v];
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, vo, (q * 16 + v) * 256, 0);
       }
+      acc[b][c] = f32x16{};
+      __builtin_amdgcn_sched_barrier(0);
+    }
     ++folds;
   };
 
@@ -760,31 +769,12 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
     if ((kt + 1) % T::FOLD_STEPS == 0 && kt + 1 < nkt) fold();
   }
 
-  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
-  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
   double e2 = 0.0, n2 = 0.0;
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
-      if (row >= g.m) continue;
-#pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        const int64_t col = n0 + wn0 + 32 * c + lr;
-        if (col >= g.p) continue;
-        float val = acc[b][c][v];
-        if (folds) val += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, ((b * CB + c) * 16 + v) * 256, 0));
-        if (Cout) Cout[row * g.ldc + col] = val;
-        const double dv = (double)val;
-        if (Y) {
-          const double d = dv - (double)Y[row * g.ldy + col];
-          e2 = fma(d, d, e2);
-        }
-        n2 = fma(dv, dv, n2);
-      }
-      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
+  store_tile_with_error<CB>(
+      acc, reinterpret_cast<float*>(g.C), g.ldc, reinterpret_cast<const float*>(g.Y), g.ldy, g.m, g.p,
+      m0 + wm0 + 4 * lh, n0 + wn0 + lr, e2, n2, folds > 0, [&](int b, int c, int v) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, ((b * CB + c) * 16 + v) * 256, 0));
+      });
   if (g.tile_part && GROUPED) {
     e2 = warp_sum_f64(e2);
     n2 = warp_sum_f64(n2);

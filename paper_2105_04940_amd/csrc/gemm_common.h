@@ -110,26 +110,33 @@ __device__ inline __attribute__((always_inline)) void tile_coords(const GemmArgs
 
 // Epilogue of a wave's 128 x 32 CB accumulator block of a 32x32 matrix
 // instruction layout (acc[b][c][v]: row r0 + 32 b + 8 (v >> 2) + (v & 3),
-// column c0 + 32 c): stores the float32 values into C (if given) and adds
-// the float64 squared differences to Y (if given) and squared values into
-// e2 / n2, in the order b, v, c. The 64 rows go in 16 groups of 4; the Y
-// values of group g + 2 are requested before group g is consumed, so three
-// groups' loads overlap instead of each waiting out a full memory latency
-// (the scheduling barrier between groups keeps the register use bounded).
-template <int CB>
+// column c0 + 32 c): the value is acc, plus extra(b, c, v) when has_extra (a
+// float32 add, acc first: the staged partial sums of a long inner extent);
+// it goes to C (if given), and the float64 squared difference to Y (if
+// given) and the squared value are added into e2 / n2, in the order b, v, c.
+// The 64 rows go in 16 groups of 4; the Y and extra values of group g + 2
+// are requested before group g is consumed, so three groups' loads overlap
+// instead of each waiting out a full memory latency (the scheduling barrier
+// between groups keeps the register use bounded).
+struct NoExtra {
+  __device__ float operator()(int, int, int) const { return 0.0f; }
+};
+template <int CB, typename Extra = NoExtra>
 __device__ __forceinline__ void store_tile_with_error(const f32x16 (&acc)[4][CB], float* __restrict__ C,
                                                       int64_t ldc, const float* __restrict__ Y, int64_t ldy,
                                                       int64_t m, int64_t p, int64_t r0, int64_t c0, double& e2,
-                                                      double& n2) {
+                                                      double& n2, bool has_extra = false, Extra extra = Extra()) {
   constexpr int NG = 16, AHEAD = 2;
-  float y[AHEAD + 1][4][CB];
+  float y[AHEAD + 1][4][CB], x[AHEAD + 1][4][CB];
   auto load = [&](int gi) {
 #pragma unroll
     for (int vv = 0; vv < 4; ++vv)
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
         const int64_t row = r0 + 32 * (gi >> 2) + 8 * (gi & 3) + vv, col = c0 + 32 * c;
-        y[gi % (AHEAD + 1)][vv][c] = (Y && row < m && col < p) ? Y[row * ldy + col] : 0.0f;
+        const bool in = row < m && col < p;
+        y[gi % (AHEAD + 1)][vv][c] = (Y && in) ? Y[row * ldy + col] : 0.0f;
+        x[gi % (AHEAD + 1)][vv][c] = (has_extra && in) ? extra(gi >> 2, c, 4 * (gi & 3) + vv) : 0.0f;
       }
   };
 #pragma unroll
@@ -146,7 +153,8 @@ __device__ __forceinline__ void store_tile_with_error(const f32x16 (&acc)[4][CB]
       for (int c = 0; c < CB; ++c) {
         const int64_t col = c0 + 32 * c;
         if (col >= p) continue;
-        const float val = acc[gi >> 2][c][v];
+        float val = acc[gi >> 2][c][v];
+        if (has_extra) val += x[gi % (AHEAD + 1)][vv][c];
         if (C) C[row * ldc + col] = val;
         const double dv = (double)val;
         if (Y) {
