@@ -988,21 +988,30 @@ __global__ __launch_bounds__(256, 2) void sgemm_grouped_lds128_kernel(GroupedArg
   const __amdgpu_buffer_rsrc_t rs = f32_rsrc(g.stage + it * (128 * 128) + wave * (64 * 64), 64 * 64 * 4);
   const int vo = lane * 4;
   int folds = 0;
+  // slot += acc (acc first) one accumulator block at a time, the next
+  // block's slot values requested before the current one is added
   auto fold = [&]() {
+    float nx[2][16];
+    auto ld = [&](int q) {
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int v = 0; v < 16; ++v)
+        nx[q & 1][v] = folds ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, (q * 16 + v) * 256, 0))
+                             : 0.0f;
+    };
+    ld(0);
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
+    for (int q = 0; q < 4; ++q) {   // accumulator block q = 2 b + c
+      if (q + 1 < 4) ld(q + 1);
+      const int b = q / 2, c = q % 2;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int so = ((b * 2 + c) * 16 + v) * 256;
-          float x = acc[b][c][v];
-          if (folds) x += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, vo, so, 0);
-        }
-        acc[b][c] = f32x16{};
-        __builtin_amdgcn_sched_barrier(0);
+      for (int v = 0; v < 16; ++v) {
+        float x = acc[b][c][v];
+        if (folds) x += nx[q & 1][v];
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), rs, vo, (q * 16 + v) * 256, 0);
       }
+      acc[b][c] = f32x16{};
+      __builtin_amdgcn_sched_barrier(0);
+    }
     ++folds;
   };
 
