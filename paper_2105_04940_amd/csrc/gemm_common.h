@@ -68,8 +68,10 @@ __device__ __forceinline__ void lds_dma16(i32x4 rs, uint32_t lds, uint32_t voff,
   rs.x = __builtin_amdgcn_readfirstlane(rs.x); rs.y = __builtin_amdgcn_readfirstlane(rs.y);
   rs.z = __builtin_amdgcn_readfirstlane(rs.z); rs.w = __builtin_amdgcn_readfirstlane(rs.w);
   lds = __builtin_amdgcn_readfirstlane(lds); soff = __builtin_amdgcn_readfirstlane(soff);
-  asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
-               :: "s"(lds), "v"(voff), "s"(rs), "s"(soff) : "memory", "m0");
+  // m0 (the LDS base of the load) is an input operand, so the compiler sets
+  // it and knows its value; nothing is clobbered behind its back
+  asm volatile("buffer_load_dwordx4 %0, %1, %2 offen lds"
+               :: "v"(voff), "s"(rs), "s"(soff), "{m0}"(lds) : "memory");
 }
 
 // Wait until at most N of this wave's vector-memory loads are outstanding
