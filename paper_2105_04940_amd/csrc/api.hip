@@ -676,14 +676,12 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   const size_t skb = bf ? 0 : gemm_skinny_ws_bytes(dtype, m, p, L_pad_max, 0);
   Arena dry(nullptr);
   dry.take<double>(2 * std::max<int64_t>(tiles, 1));
-  dry.take<double>(2);
   dry.take<float>(stage_elems);
   dry.take<uint16_t>(dt_elems);
   dry.take<char>(skb);
   if ((st = ensure_ws(h, dry.off))) return st;
   Arena ar(h->ws);
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
-  double* out2 = ar.take<double>(2);
   float* stage = ar.take<float>(stage_elems);
   uint16_t* Dt = ar.take<uint16_t>(dt_elems);
   void* skinny = skb ? ar.take<char>(skb) : nullptr;
@@ -700,8 +698,9 @@ sbmm_status sbmm_sketch_gemm(sbmm_handle h, int64_t m, int64_t p, int64_t L_pad_
   G.skinny_ws = skinny; G.skinny_K_max = L_pad_max;
   HIP_TRY(h, run_product(G, s));
   if (err_sq) {
-    HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
-    HIP_TRY(h, hipMemcpyAsync(err_sq, out2, sizeof(double), hipMemcpyDeviceToDevice, s));
+    // the squared-error partials (row 0 of tile_part) summed straight into
+    // err_sq: one small kernel, no device-to-device copy behind it
+    HIP_TRY(h, launch_reduce_cols(tile_part, 1, tiles, err_sq, s));
   }
   return SBMM_OK;
 }
@@ -757,10 +756,9 @@ sbmm_status sbmm_sketch_gemm_mx(sbmm_handle h, int64_t m, int64_t p, int64_t L_p
   if (MN && ldmn < p) return fail(h, SBMM_E_ARG, "ldmn < p");
   hipStream_t s = (hipStream_t)stream;
   const int64_t tiles = mx_gemm_tiles(m, p);
-  if ((st = ensure_ws(h, 512 + sizeof(double) * (2 * std::max<int64_t>(tiles, 1) + 2)))) return st;
+  if ((st = ensure_ws(h, 512 + sizeof(double) * 2 * std::max<int64_t>(tiles, 1)))) return st;
   Arena ar(h->ws);
   double* tile_part = ar.take<double>(2 * std::max<int64_t>(tiles, 1));
-  double* out2 = ar.take<double>(2);
   if (tiles == 0) {
     if (err_sq) HIP_TRY(h, launch_fill_f64(err_sq, 1, 0.0, s));
     return SBMM_OK;
@@ -772,8 +770,9 @@ sbmm_status sbmm_sketch_gemm_mx(sbmm_handle h, int64_t m, int64_t p, int64_t L_p
   G.tile_part = err_sq ? tile_part : nullptr;
   HIP_TRY(h, launch_mx_gemm(G, s));
   if (err_sq) {
-    HIP_TRY(h, launch_reduce_cols(tile_part, 2, tiles, out2, s));
-    HIP_TRY(h, hipMemcpyAsync(err_sq, out2, sizeof(double), hipMemcpyDeviceToDevice, s));
+    // the squared-error partials (row 0 of tile_part) summed straight into
+    // err_sq: one small kernel, no device-to-device copy behind it
+    HIP_TRY(h, launch_reduce_cols(tile_part, 1, tiles, err_sq, s));
   }
   return SBMM_OK;
 }

@@ -117,17 +117,18 @@ __device__ inline __attribute__((always_inline)) void tile_coords(const GemmArgs
 // it goes to C (if given), and the float64 squared difference to Y (if
 // given) and the squared value are added into e2 / n2, in the order b, v, c.
 // The 64 rows go in 16 groups of 4; the Y and extra values of group g + 2
-// are requested before group g is consumed, so three groups' loads overlap
-// instead of each waiting out a full memory latency (the scheduling barrier
-// between groups keeps the register use bounded).
+// are requested before group g is consumed, so three groups' loads overlap.
+// The loads are unconditional (an element outside the output reads Y[0], and
+// extra must be safe to call for any (b, c, v)) and their values are only
+// looked at later: a load under a per-element condition becomes a branch
+// that waits for it on the spot, one full memory latency per element.
 struct NoExtra {
   __device__ float operator()(int, int, int) const { return 0.0f; }
 };
-template <int CB, typename Extra = NoExtra>
-__device__ __forceinline__ void store_tile_with_error(const f32x16 (&acc)[4][CB], float* __restrict__ C,
-                                                      int64_t ldc, const float* __restrict__ Y, int64_t ldy,
-                                                      int64_t m, int64_t p, int64_t r0, int64_t c0, double& e2,
-                                                      double& n2, bool has_extra = false, Extra extra = Extra()) {
+template <int CB, bool HAS_Y, bool HAS_X, typename Extra>
+__device__ __forceinline__ void store_tile_impl(const f32x16 (&acc)[4][CB], float* __restrict__ C, int64_t ldc,
+                                                const float* __restrict__ Y, int64_t ldy, int64_t m, int64_t p,
+                                                int64_t r0, int64_t c0, double& e2, double& n2, Extra& extra) {
   constexpr int NG = 16, AHEAD = 2;
   float y[AHEAD + 1][4][CB], x[AHEAD + 1][4][CB];
   auto load = [&](int gi) {
@@ -136,9 +137,8 @@ __device__ __forceinline__ void store_tile_with_error(const f32x16 (&acc)[4][CB]
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
         const int64_t row = r0 + 32 * (gi >> 2) + 8 * (gi & 3) + vv, col = c0 + 32 * c;
-        const bool in = row < m && col < p;
-        y[gi % (AHEAD + 1)][vv][c] = (Y && in) ? Y[row * ldy + col] : 0.0f;
-        x[gi % (AHEAD + 1)][vv][c] = (has_extra && in) ? extra(gi >> 2, c, 4 * (gi & 3) + vv) : 0.0f;
+        if constexpr (HAS_Y) y[gi % (AHEAD + 1)][vv][c] = Y[row < m && col < p ? row * ldy + col : 0];
+        if constexpr (HAS_X) x[gi % (AHEAD + 1)][vv][c] = extra(gi >> 2, c, 4 * (gi & 3) + vv);
       }
   };
 #pragma unroll
@@ -156,10 +156,10 @@ __device__ __forceinline__ void store_tile_with_error(const f32x16 (&acc)[4][CB]
         const int64_t col = c0 + 32 * c;
         if (col >= p) continue;
         float val = acc[gi >> 2][c][v];
-        if (has_extra) val += x[gi % (AHEAD + 1)][vv][c];
+        if constexpr (HAS_X) val += x[gi % (AHEAD + 1)][vv][c];
         if (C) C[row * ldc + col] = val;
         const double dv = (double)val;
-        if (Y) {
+        if constexpr (HAS_Y) {
           const double d = dv - (double)y[gi % (AHEAD + 1)][vv][c];
           e2 = fma(d, d, e2);
         }
@@ -167,6 +167,20 @@ __device__ __forceinline__ void store_tile_with_error(const f32x16 (&acc)[4][CB]
       }
     }
     __builtin_amdgcn_sched_barrier(0);
+  }
+}
+template <int CB, typename Extra = NoExtra>
+__device__ __forceinline__ void store_tile_with_error(const f32x16 (&acc)[4][CB], float* __restrict__ C,
+                                                      int64_t ldc, const float* __restrict__ Y, int64_t ldy,
+                                                      int64_t m, int64_t p, int64_t r0, int64_t c0, double& e2,
+                                                      double& n2, bool has_extra = false, Extra extra = Extra()) {
+  // both conditions are uniform over the workgroup
+  if (Y) {
+    if (has_extra) store_tile_impl<CB, true, true>(acc, C, ldc, Y, ldy, m, p, r0, c0, e2, n2, extra);
+    else store_tile_impl<CB, true, false>(acc, C, ldc, Y, ldy, m, p, r0, c0, e2, n2, extra);
+  } else {
+    if (has_extra) store_tile_impl<CB, false, true>(acc, C, ldc, Y, ldy, m, p, r0, c0, e2, n2, extra);
+    else store_tile_impl<CB, false, false>(acc, C, ldc, Y, ldy, m, p, r0, c0, e2, n2, extra);
   }
 }
 
