@@ -525,31 +525,13 @@ __device__ __forceinline__ void sgemm_body(const GemmArgs& g, SgemmTile<WMB, WNB
     }
   }
 
-  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
-  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
   double e2 = 0.0, n2 = 0.0;
-#pragma unroll
-  for (int b = 0; b < WMB; ++b)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = m0 + wave_m0 + WMB * (8 * (v >> 2) + 4 * lh + (v & 3)) + b;
-      if (EDGE && row >= g.m) continue;
-#pragma unroll
-      for (int c = 0; c < WNB; ++c) {
-        const int64_t col = n0 + wave_n0 + WNB * lr + c;
-        if (EDGE && col >= g.p) continue;
-        float val = acc[b][c][v];
-        if (folds) val += stg[((b * WNB + c) * 16 + v) * 64];
-        if (Cout) Cout[row * g.ldc + col] = val;
-        const double dv = (double)val;
-        if (Y) {
-          const double d = dv - (double)Y[row * g.ldy + col];
-          e2 = fma(d, d, e2);
-        }
-        n2 = fma(dv, dv, n2);
-      }
-      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
-    }
+  // one group ahead: these register-staged tiles have less room
+  store_block_with_error<WMB, WNB, 1>(
+      acc, [=](int b, int v) { return m0 + wave_m0 + WMB * (8 * (v >> 2) + 4 * lh + (v & 3)) + b; },
+      [=](int c) { return n0 + wave_n0 + WNB * lr + c; }, reinterpret_cast<float*>(g.C), g.ldc,
+      reinterpret_cast<const float*>(g.Y), g.ldy, g.m, g.p, e2, n2, folds > 0,
+      [&](int b, int c, int v) { return stg[((b * WNB + c) * 16 + v) * 64]; });
   if (g.tile_part) write_tile_partials_at(g, e2, n2, sh.red, part, nparts);
 }
 
@@ -1042,31 +1024,13 @@ __global__ __launch_bounds__(256, 2) void sgemm_grouped_lds128_kernel(GroupedArg
     if (kt + 1 < nkt) step(kt + 1, st1, st0);
   }
 
-  float* __restrict__ Cout = reinterpret_cast<float*>(g.C);
-  const float* __restrict__ Y = reinterpret_cast<const float*>(g.Y);
   double e2 = 0.0, n2 = 0.0;
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t row = m0 + wm0 + 32 * b + 8 * (v >> 2) + 4 * lh + (v & 3);
-      if (row >= g.m) continue;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int64_t col = n0 + wn0 + 32 * c + lr;
-        if (col >= g.p) continue;
-        float val = acc[b][c][v];
-        if (folds) val += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, ((b * 2 + c) * 16 + v) * 256, 0));
-        if (Cout) Cout[row * g.ldc + col] = val;
-        const double dv = (double)val;
-        if (Y) {
-          const double d = dv - (double)Y[row * g.ldy + col];
-          e2 = fma(d, d, e2);
-        }
-        n2 = fma(dv, dv, n2);
-      }
-      if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
+  store_block_with_error<2, 2>(
+      acc, [=](int b, int v) { return m0 + wm0 + 4 * lh + 32 * b + 8 * (v >> 2) + (v & 3); },
+      [=](int c) { return n0 + wn0 + lr + 32 * c; }, reinterpret_cast<float*>(g.C), g.ldc,
+      reinterpret_cast<const float*>(g.Y), g.ldy, g.m, g.p, e2, n2, folds > 0, [&](int b, int c, int v) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, vo, ((b * 2 + c) * 16 + v) * 256, 0));
+      });
   if (g.tile_part) {
     // the four waves' sums added in wave order
     e2 = warp_sum_f64(e2);

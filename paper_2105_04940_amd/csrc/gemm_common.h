@@ -110,52 +110,54 @@ __device__ inline __attribute__((always_inline)) void tile_coords(const GemmArgs
   tn = r / gm;
 }
 
-// Epilogue of a wave's 128 x 32 CB accumulator block of a 32x32 matrix
-// instruction layout (acc[b][c][v]: row r0 + 32 b + 8 (v >> 2) + (v & 3),
-// column c0 + 32 c): the value is acc, plus extra(b, c, v) when has_extra (a
-// float32 add, acc first: the staged partial sums of a long inner extent);
-// it goes to C (if given), and the float64 squared difference to Y (if
-// given) and the squared value are added into e2 / n2, in the order b, v, c.
-// The 64 rows go in 16 groups of 4; the Y and extra values of group g + 2
-// are requested before group g is consumed, so three groups' loads overlap.
-// The loads are unconditional (an element outside the output reads Y[0], and
-// extra must be safe to call for any (b, c, v)) and their values are only
-// looked at later: a load under a per-element condition becomes a branch
-// that waits for it on the spot, one full memory latency per element.
+// Epilogue of a wave's RB x CB blocks of 32x32 matrix-instruction
+// accumulators: acc[b][c][v] is output element (rowf(b, v), colf(c)). The
+// value is acc, plus extra(b, c, v) when has_extra (a float32 add, acc
+// first: the staged partial sums of a long inner extent); it goes to C (if
+// given), and the float64 squared difference to Y (if given) and the squared
+// value are added into e2 / n2, in the order b, v, c. The elements go in
+// groups of 4 v; the Y and extra values of group g + AHEAD are requested
+// before group g is consumed, so several groups' loads overlap. The loads
+// are unconditional (an element outside the output reads Y[0], and extra
+// must be safe to call for any (b, c, v)) and their values are only looked
+// at later: a load under a per-element condition becomes a branch that waits
+// for it on the spot, one full memory latency per element.
 struct NoExtra {
   __device__ float operator()(int, int, int) const { return 0.0f; }
 };
-template <int CB, bool HAS_Y, bool HAS_X, typename Extra>
-__device__ __forceinline__ void store_tile_impl(const f32x16 (&acc)[4][CB], float* __restrict__ C, int64_t ldc,
-                                                const float* __restrict__ Y, int64_t ldy, int64_t m, int64_t p,
-                                                int64_t r0, int64_t c0, double& e2, double& n2, Extra& extra) {
-  constexpr int NG = 16, AHEAD = 2;
+template <int RB, int CB, int AHEAD, bool HAS_Y, bool HAS_X, typename RowF, typename ColF, typename Extra>
+__device__ __forceinline__ void store_block_impl(const f32x16 (&acc)[RB][CB], RowF& rowf, ColF& colf,
+                                                 float* __restrict__ C, int64_t ldc, const float* __restrict__ Y,
+                                                 int64_t ldy, int64_t m, int64_t p, double& e2, double& n2,
+                                                 Extra& extra) {
+  constexpr int NG = 4 * RB;
   float y[AHEAD + 1][4][CB], x[AHEAD + 1][4][CB];
   auto load = [&](int gi) {
 #pragma unroll
     for (int vv = 0; vv < 4; ++vv)
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
-        const int64_t row = r0 + 32 * (gi >> 2) + 8 * (gi & 3) + vv, col = c0 + 32 * c;
+        const int b = gi >> 2, v = 4 * (gi & 3) + vv;
+        const int64_t row = rowf(b, v), col = colf(c);
         if constexpr (HAS_Y) y[gi % (AHEAD + 1)][vv][c] = Y[row < m && col < p ? row * ldy + col : 0];
-        if constexpr (HAS_X) x[gi % (AHEAD + 1)][vv][c] = extra(gi >> 2, c, 4 * (gi & 3) + vv);
+        if constexpr (HAS_X) x[gi % (AHEAD + 1)][vv][c] = extra(b, c, v);
       }
   };
 #pragma unroll
-  for (int gi = 0; gi < AHEAD; ++gi) load(gi);
+  for (int gi = 0; gi < AHEAD && gi < NG; ++gi) load(gi);
 #pragma unroll
   for (int gi = 0; gi < NG; ++gi) {
     if (gi + AHEAD < NG) load(gi + AHEAD);
 #pragma unroll
     for (int vv = 0; vv < 4; ++vv) {
-      const int v = 4 * (gi & 3) + vv;
-      const int64_t row = r0 + 32 * (gi >> 2) + 8 * (gi & 3) + vv;
+      const int b = gi >> 2, v = 4 * (gi & 3) + vv;
+      const int64_t row = rowf(b, v);
       if (row >= m) continue;
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
-        const int64_t col = c0 + 32 * c;
+        const int64_t col = colf(c);
         if (col >= p) continue;
-        float val = acc[gi >> 2][c][v];
+        float val = acc[b][c][v];
         if constexpr (HAS_X) val += x[gi % (AHEAD + 1)][vv][c];
         if (C) C[row * ldc + col] = val;
         const double dv = (double)val;
@@ -169,19 +171,31 @@ __device__ __forceinline__ void store_tile_impl(const f32x16 (&acc)[4][CB], floa
     __builtin_amdgcn_sched_barrier(0);
   }
 }
+template <int RB, int CB, int AHEAD = 2, typename RowF, typename ColF, typename Extra = NoExtra>
+__device__ __forceinline__ void store_block_with_error(const f32x16 (&acc)[RB][CB], RowF rowf, ColF colf,
+                                                       float* __restrict__ C, int64_t ldc,
+                                                       const float* __restrict__ Y, int64_t ldy, int64_t m,
+                                                       int64_t p, double& e2, double& n2, bool has_extra = false,
+                                                       Extra extra = Extra()) {
+  // both conditions are uniform over the workgroup
+  if (Y) {
+    if (has_extra) store_block_impl<RB, CB, AHEAD, true, true>(acc, rowf, colf, C, ldc, Y, ldy, m, p, e2, n2, extra);
+    else store_block_impl<RB, CB, AHEAD, true, false>(acc, rowf, colf, C, ldc, Y, ldy, m, p, e2, n2, extra);
+  } else {
+    if (has_extra) store_block_impl<RB, CB, AHEAD, false, true>(acc, rowf, colf, C, ldc, Y, ldy, m, p, e2, n2, extra);
+    else store_block_impl<RB, CB, AHEAD, false, false>(acc, rowf, colf, C, ldc, Y, ldy, m, p, e2, n2, extra);
+  }
+}
+// The 128 x 32 CB block of a wave in the 256 x 256 tile kernels: row
+// r0 + 32 b + 8 (v >> 2) + (v & 3), column c0 + 32 c.
 template <int CB, typename Extra = NoExtra>
 __device__ __forceinline__ void store_tile_with_error(const f32x16 (&acc)[4][CB], float* __restrict__ C,
                                                       int64_t ldc, const float* __restrict__ Y, int64_t ldy,
                                                       int64_t m, int64_t p, int64_t r0, int64_t c0, double& e2,
                                                       double& n2, bool has_extra = false, Extra extra = Extra()) {
-  // both conditions are uniform over the workgroup
-  if (Y) {
-    if (has_extra) store_tile_impl<CB, true, true>(acc, C, ldc, Y, ldy, m, p, r0, c0, e2, n2, extra);
-    else store_tile_impl<CB, true, false>(acc, C, ldc, Y, ldy, m, p, r0, c0, e2, n2, extra);
-  } else {
-    if (has_extra) store_tile_impl<CB, false, true>(acc, C, ldc, Y, ldy, m, p, r0, c0, e2, n2, extra);
-    else store_tile_impl<CB, false, false>(acc, C, ldc, Y, ldy, m, p, r0, c0, e2, n2, extra);
-  }
+  store_block_with_error<4, CB>(
+      acc, [=](int b, int v) { return r0 + 32 * b + 8 * (v >> 2) + (v & 3); }, [=](int c) { return c0 + 32 * c; },
+      C, ldc, Y, ldy, m, p, e2, n2, has_extra, extra);
 }
 
 // Reduce the epilogue partial sums of the workgroup in a fixed order into
