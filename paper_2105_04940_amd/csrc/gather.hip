@@ -36,9 +36,9 @@ template <> __device__ __forceinline__ double from_d<double>(double v) { return 
 template <> __device__ __forceinline__ float from_d<float>(double v) { return (float)v; }
 template <> __device__ __forceinline__ uint16_t from_d<uint16_t>(double v) { return float_to_bf16_bits((float)v); }
 
-template <typename T> __device__ __forceinline__ void load4(const T* p, double* v) {
+template <typename T> __device__ __forceinline__ void load4_raw(const T* p, T* v) {
   const typename Vec4<T>::type x = *reinterpret_cast<const typename Vec4<T>::type*>(p);
-  v[0] = to_d<T>(x[0]); v[1] = to_d<T>(x[1]); v[2] = to_d<T>(x[2]); v[3] = to_d<T>(x[3]);
+  v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
 }
 template <typename T> __device__ __forceinline__ void store4(T* p, const double* v) {
   typename Vec4<T>::type x;
@@ -85,25 +85,32 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int64_t bid) {
     Tout* C = reinterpret_cast<Tout*>(a.C);
     const int64_t h1 = min(a.m, (hb + 1) * kRowsC);
     // rows in groups of kBatch: every load of a group is issued before its
-    // stores (C may not alias M, which the compiler cannot know)
+    // stores (C may not alias M, which the compiler cannot know), in one
+    // branch per group with the raw values converted after it (a load whose
+    // value is used inside its own branch is waited for there, one latency
+    // each); a padding column reads column 0 and is zeroed afterwards
+    int32_t jc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) jc[q] = j[q] >= 0 ? j[q] : 0;
     for (int64_t hg = hb * kRowsC; hg < h1; hg += kBatch) {
-      double v[kBatch][4];
+      Tin raw[kBatch][4];
+      if (run) {
 #pragma unroll
-      for (int r = 0; r < kBatch; ++r) {
-        const int64_t h = min(hg + r, h1 - 1);   // a short last group re-reads its last row
-        if (run) {
-          load4<Tin>(M + h * a.ldm + j[0], v[r]);
-        } else {
+        for (int r = 0; r < kBatch; ++r)   // a short last group re-reads its last row
+          load4_raw<Tin>(M + min(hg + r, h1 - 1) * a.ldm + j[0], raw[r]);
+      } else {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) v[r][q] = j[q] >= 0 ? to_d<Tin>(M[h * a.ldm + j[q]]) : 0.0;
-        }
+        for (int r = 0; r < kBatch; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) raw[r][q] = M[min(hg + r, h1 - 1) * a.ldm + jc[q]];
       }
+      double v[kBatch][4];
 #pragma unroll
       for (int r = 0; r < kBatch; ++r) {
         const int64_t h = hg + r;
         if (h >= h1) break;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[r][q] = j[q] >= 0 ? v[r][q] * sc[q] : 0.0;
+        for (int q = 0; q < 4; ++q) v[r][q] = j[q] >= 0 ? to_d<Tin>(raw[r][q]) * sc[q] : 0.0;
         if (vst) {
           store4<Tout>(C + h * a.ldc + l0, v[r]);
         } else {
@@ -123,21 +130,24 @@ __device__ __forceinline__ void gather_body(const GatherArgs& a, int64_t bid) {
     Tout* dst = reinterpret_cast<Tout*>(a.D) + l * a.ldd;
     const bool vst = (a.ldd % 4 == 0) && ((uintptr_t)a.D % (4 * sizeof(Tout)) == 0);
     const int64_t p4 = vst ? a.p / 4 * 4 : 0;   // elements written four at a time
+    // the loads unconditional (a lane past p4 re-reads the row's start, a
+    // padding row reads row 0; both are zeroed), their values used only
+    // after all of them are issued
     for (int64_t f0 = 4 * (int64_t)lane; f0 < p4; f0 += 256 * kBatch) {
-      double v[kBatch][4];
+      Tin raw[kBatch][4];
 #pragma unroll
       for (int r = 0; r < kBatch; ++r) {
         const int64_t f = f0 + 256 * r;
-        if (j >= 0 && f < p4) load4<Tin>(src + f, v[r]);
-        else v[r][0] = v[r][1] = v[r][2] = v[r][3] = 0.0;
+        load4_raw<Tin>(src + (f < p4 ? f : 0), raw[r]);
       }
 #pragma unroll
       for (int r = 0; r < kBatch; ++r) {
         const int64_t f = f0 + 256 * r;
         if (f >= p4) break;
+        double v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[r][q] *= sc;
-        store4<Tout>(dst + f, v[r]);
+        for (int q = 0; q < 4; ++q) v[q] = j >= 0 ? to_d<Tin>(raw[r][q]) * sc : 0.0;
+        store4<Tout>(dst + f, v);
       }
     }
     for (int64_t f = p4 + lane; f < a.p; f += 64)
