@@ -76,12 +76,19 @@ __global__ __launch_bounds__(256) void mx_gather_kernel(MxGatherArgs a) {
       if (kb < (nblk + 3) / 4 * 4) a.Cs[i * a.ldcs + kb] = 127;
       return;
     }
+    // all 32 loads issued before any value is used (a padding column reads
+    // column 0 and is zeroed): a load under its own condition would be
+    // waited for on the spot
+    int32_t jj[kBlk];
+    float raw[kBlk];
+#pragma unroll
+    for (int e = 0; e < kBlk; ++e) jj[e] = a.colmap[kb * kBlk + e];
+#pragma unroll
+    for (int e = 0; e < kBlk; ++e) raw[e] = a.M[i * a.ldm + (jj[e] >= 0 ? jj[e] : 0)];
     float amax = 0.0f;
 #pragma unroll
     for (int e = 0; e < kBlk; ++e) {
-      const int64_t l = kb * kBlk + e;
-      const int32_t j = a.colmap[l];
-      x[e] = j >= 0 ? (float)((double)a.M[i * a.ldm + j] * a.colscale[l]) : 0.0f;
+      x[e] = jj[e] >= 0 ? (float)((double)raw[e] * a.colscale[kb * kBlk + e]) : 0.0f;
       amax = fmaxf(amax, fabsf(x[e]));
     }
     uint8_t eb;
@@ -105,12 +112,17 @@ __global__ __launch_bounds__(256) void mx_gather_kernel(MxGatherArgs a) {
       if (kb < (nblk + 3) / 4 * 4) a.Ds[j * a.ldds + kb] = 127;
       return;
     }
+    // as above: the 32 loads first, a padding row reads row 0
+    int32_t rr[kBlk];
+    float raw[kBlk];
+#pragma unroll
+    for (int e = 0; e < kBlk; ++e) rr[e] = a.colmap[kb * kBlk + e];
+#pragma unroll
+    for (int e = 0; e < kBlk; ++e) raw[e] = a.N[(int64_t)(rr[e] >= 0 ? rr[e] : 0) * a.ldn + j];
     float amax = 0.0f;
 #pragma unroll
     for (int e = 0; e < kBlk; ++e) {
-      const int64_t l = kb * kBlk + e;
-      const int32_t r = a.colmap[l];
-      x[e] = r >= 0 ? (float)((double)a.N[(int64_t)r * a.ldn + j] * a.colscale[l]) : 0.0f;
+      x[e] = rr[e] >= 0 ? (float)((double)raw[e] * a.colscale[kb * kBlk + e]) : 0.0f;
       amax = fmaxf(amax, fabsf(x[e]));
     }
     uint8_t eb;
