@@ -55,10 +55,18 @@ struct MxGatherArgs {
   const int32_t* colmap; const double* colscale;
   uint8_t* C; int64_t ldc; uint8_t* Cs; int64_t ldcs;     // m x L_pad, m x L_pad/32
   uint8_t* Dt; int64_t lddt; uint8_t* Ds; int64_t ldds;   // p x L_pad, p x L_pad/32
+  int64_t cchunks;                  // workgroups per row of C (64 blocks each)
   int64_t cgroups;                  // workgroups on the C part
 };
 
-// C part: workgroup (row i, group of 256 blocks), one block per thread.
+constexpr int kMxCBlocksPerWave = 16;   // C part: blocks of one row per wave
+
+// C part: workgroup (row i, chunk of 64 blocks), 16 blocks per wave, two at
+// a time: lane l holds sketch column 32 kb + (l & 31) of block kb = base + 2t
+// + (l >> 5), so a wave reads 64 consecutive sketch columns of the row (runs
+// of M's row inside drawn blocks), a block's absolute maximum comes from a
+// reduction over its 32 lanes, and every fourth lane packs its own and the
+// next three lanes' codes into one word.
 // Dt part: workgroup (256 columns j, block kb), one column per thread (the
 // reads of one sketch row are coalesced across the threads).
 __global__ __launch_bounds__(256) void mx_gather_kernel(MxGatherArgs a) {
@@ -67,41 +75,46 @@ __global__ __launch_bounds__(256) void mx_gather_kernel(MxGatherArgs a) {
   const int64_t bid = blockIdx.x;
   float x[kBlk];
   if (bid < a.cgroups) {
-    const int64_t per_row = (a.nblk_max + 255) / 256;
-    const int64_t i = bid / per_row;
-    const int64_t kb = (bid % per_row) * 256 + threadIdx.x;
-    if (kb >= nblk) {
-      // the product reads scales in words of 4 blocks: the rest of the last
-      // word is 1 (127), its data is never read
-      if (kb < (nblk + 3) / 4 * 4) a.Cs[i * a.ldcs + kb] = 127;
-      return;
+    const int64_t i = bid / a.cchunks;
+    const int lane = threadIdx.x & 63, e = lane & 31;
+    const int64_t kb0 = ((bid % a.cchunks) * 4 + (threadIdx.x >> 6)) * kMxCBlocksPerWave + (lane >> 5);
+    constexpr int T = kMxCBlocksPerWave / 2;
+    // every load first (a block past the sketch reads entry 0, a padding
+    // column column 0; their values are not used)
+    int32_t jj[T];
+    double scl[T];
+    float raw[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int64_t kb = kb0 + 2 * t;
+      const int64_t l = kb < nblk ? kb * kBlk + e : 0;
+      jj[t] = a.colmap[l];
+      scl[t] = a.colscale[l];
     }
-    // all 32 loads issued before any value is used (a padding column reads
-    // column 0 and is zeroed): a load under its own condition would be
-    // waited for on the spot
-    int32_t jj[kBlk];
-    float raw[kBlk];
 #pragma unroll
-    for (int e = 0; e < kBlk; ++e) jj[e] = a.colmap[kb * kBlk + e];
+    for (int t = 0; t < T; ++t) raw[t] = a.M[i * a.ldm + (jj[t] >= 0 ? jj[t] : 0)];
 #pragma unroll
-    for (int e = 0; e < kBlk; ++e) raw[e] = a.M[i * a.ldm + (jj[e] >= 0 ? jj[e] : 0)];
-    float amax = 0.0f;
+    for (int t = 0; t < T; ++t) {
+      const int64_t kb = kb0 + 2 * t;
+      const float x = jj[t] >= 0 ? (float)((double)raw[t] * scl[t]) : 0.0f;
+      float amax = fabsf(x);
 #pragma unroll
-    for (int e = 0; e < kBlk; ++e) {
-      x[e] = jj[e] >= 0 ? (float)((double)raw[e] * a.colscale[kb * kBlk + e]) : 0.0f;
-      amax = fmaxf(amax, fabsf(x[e]));
+      for (int o = 16; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+      uint8_t eb;
+      float down;
+      mx_block_scale(amax, &eb, &down);
+      const float y = x * down;
+      const float y1 = __shfl_down(y, 1, 64), y2 = __shfl_down(y, 2, 64), y3 = __shfl_down(y, 3, 64);
+      if (kb < nblk) {
+        if ((e & 3) == 0)
+          *reinterpret_cast<uint32_t*>(a.C + i * a.ldc + kb * kBlk + e) = pack4_e4m3(y, y1, y2, y3);
+        if (e == 0) a.Cs[i * a.ldcs + kb] = eb;
+      } else if (e == 0 && kb < (nblk + 3) / 4 * 4) {
+        // the product reads scales in words of 4 blocks: the rest of the
+        // last word is 1 (127), its data is never read
+        a.Cs[i * a.ldcs + kb] = 127;
+      }
     }
-    uint8_t eb;
-    float down;
-    mx_block_scale(amax, &eb, &down);
-    uint32_t w[kBlk / 4];
-#pragma unroll
-    for (int q = 0; q < kBlk / 4; ++q)
-      w[q] = pack4_e4m3(x[4 * q] * down, x[4 * q + 1] * down, x[4 * q + 2] * down, x[4 * q + 3] * down);
-    uint4* dst = reinterpret_cast<uint4*>(a.C + i * a.ldc + kb * kBlk);
-    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
-    a.Cs[i * a.ldcs + kb] = eb;
   } else {
     const int64_t b = bid - a.cgroups;
     const int64_t jgroups = (a.p + 255) / 256;
@@ -523,8 +536,8 @@ hipError_t launch_mx_gather(const MxGatherLaunch& L, hipStream_t s) {
   // blocks up to the next multiple of 4 (their scales are written as 1)
   const int64_t nblk_w = round_up(a.nblk_max, 4);
   a.nblk_max = nblk_w;
-  const int64_t per_row = ceil_div(nblk_w, 256);
-  a.cgroups = (L.C && L.m > 0) ? L.m * per_row : 0;
+  a.cchunks = ceil_div(nblk_w, 4 * kMxCBlocksPerWave);
+  a.cgroups = (L.C && L.m > 0) ? L.m * a.cchunks : 0;
   const int64_t dgroups = (L.Dt && L.p > 0) ? nblk_w * ceil_div(L.p, 256) : 0;
   const int64_t total = a.cgroups + dgroups;
   if (total == 0) return hipSuccess;
