@@ -56,9 +56,10 @@ __device__ __forceinline__ uint32_t lds_offset(const void* p) {
 // One LDS-DMA load of 16 bytes a lane: lane l's bytes at voff + soff of the
 // buffer land at LDS address lds + 16 l (lds wave-uniform). Written as inline
 // asm rather than the load-to-LDS builtin on purpose: with the builtin the
-// compiler sinks the loads to the end of the matrix-instruction sequence that
-// follows (leaving them a fraction of a k-step to land) and adds its own
-// conservative waits before reads of the other stage. Here the load issues
+// compiler may sink the loads to the end of the matrix-instruction sequence
+// that follows (leaving them a fraction of a k-step to land; a timing probe
+// showed it) and adds its own conservative waits before reads of the other
+// stage. Here the load issues
 // where it is written, nothing else waits for it, and the "memory" clobber
 // keeps LDS reads from moving across it. The caller waits with
 // wait_loads_barrier before any wave reads the destination.
