@@ -207,6 +207,18 @@ sbmm_status sbmm_plan(sbmm_handle h, const sbmm_problem* prob,
                       const double* blk, const sbmm_plan_out* out,
                       int64_t* L_host, sbmm_stream stream);
 
+/* Matrix-core throughput of this device for one operand type, measured (a
+ * reference beside the specification's peaks, which assume a clock that the
+ * power limit holds lower under matrix work; not part of the method). Four
+ * workgroups of four waves per compute unit each run eight independent
+ * chains of the dtype's 32x32 matrix instruction on operands held in
+ * registers: F32 v_mfma_f32_32x32x2_f32, BF16 v_mfma_f32_32x32x16_bf16,
+ * F8E4M3 the block-scaled v_mfma_scale_f32_32x32x64_f8f6f4 of the MX
+ * product. One warm-up launch, then one timed with events; *tflops (host)
+ * receives the instructions' 2 m n k flops over the elapsed time. Synchronous:
+ * waits for the handle's device. SBMM_E_UNSUPPORTED for F64. */
+sbmm_status sbmm_peak_probe(sbmm_handle h, sbmm_dtype dtype, double* tflops);
+
 /* sbmm_plan for callers that cannot allocate device memory (code under HIP
  * graph capture, serving loops, harnesses that forbid hipMalloc): the same
  * kernels, arguments, outputs and status reporting as sbmm_plan, but every

@@ -36,7 +36,7 @@ EXPORTS = (
     "sbmm_batch_create", "sbmm_batch_destroy", "sbmm_batch_run", "sbmm_batch_capture",
     "sbmm_batch_replay", "sbmm_batch_tune", "sbmm_batch_set_tuning",
     "sbmm_sketch_mx", "sbmm_sketch_gemm_mx", "sbmm_pilot", "sbmm_bound",
-    "sbmm_workspace_size", "sbmm_exact_error", "sbmm_plan_noalloc",
+    "sbmm_workspace_size", "sbmm_exact_error", "sbmm_plan_noalloc", "sbmm_peak_probe",
 )
 NOALLOC_SCRATCH_BYTES = 16 << 20   # SBMM_NOALLOC_SCRATCH_BYTES
 # Layout of sbmm_bound's output (SBMM_BOUND_* in the header), then eta_j and
@@ -135,6 +135,7 @@ def load_library(path=LIB_PATH):
         "sbmm_sketch_gemm": (st, [vp, i64, i64, i64, vp, st, vp, i64, vp, i64, vp, i64,
                                   vp, i64, vp, vp]),
         "sbmm_error": (st, [vp, i64, i64, st, vp, i64, vp, i64, vp, vp]),
+        "sbmm_peak_probe": (st, [vp, st, P(ctypes.c_double)]),
         "sbmm_run": (st, [vp, P(Problem_t), st, vp, i64, vp, i64, vp, i64, vp, i64,
                           P(PlanOut_t), P(ctypes.c_double), P(ctypes.c_double), P(i64), vp]),
         "sbmm_backward": (st, [vp, P(Problem_t), P(PlanOut_t), i64, st, vp, i64, vp, i64, vp, i64,
@@ -488,6 +489,14 @@ class Handle:
             Dt.stride(0), _ptr(Ds), Ds.stride(0), _ptr(CD), p, _ptr(MN), p if MN is not None else 0,
             _ptr(err), _stream()))
         return CD, err
+
+    def peak_probe(self, dtype):
+        """sbmm_peak_probe: the device's measured matrix-core TFLOP/s for
+        "f32", "bf16" or "f8e4m3" (register operands, no memory traffic)."""
+        codes = {"f32": SBMM_F32, "bf16": SBMM_BF16, "f8e4m3": SBMM_F8E4M3}
+        out = ctypes.c_double()
+        self._check(self._lib.sbmm_peak_probe(self.h, codes[dtype], ctypes.byref(out)))
+        return out.value
 
     def error(self, X, Y):
         torch = _torch()

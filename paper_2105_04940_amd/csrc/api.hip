@@ -777,6 +777,42 @@ sbmm_status sbmm_sketch_gemm_mx(sbmm_handle h, int64_t m, int64_t p, int64_t L_p
   return SBMM_OK;
 }
 
+sbmm_status sbmm_peak_probe(sbmm_handle h, sbmm_dtype dtype, double* tflops) {
+  sbmm_status st = check_handle(h);
+  if (st) return st;
+  if (!tflops) return fail(h, SBMM_E_ARG, "tflops is NULL");
+  const int dt = enum_raw(dtype);
+  if (dt != SBMM_F32 && dt != SBMM_BF16 && dt != SBMM_F8E4M3)
+    return fail(h, SBMM_E_UNSUPPORTED, "no matrix-core probe for dtype %d", dt);
+  HIP_TRY(h, hipSetDevice(h->device));
+  int cus = 0;
+  HIP_TRY(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+  const int grid = 4 * std::max(cus, 1);
+  // about 5-10 ms per launch at these instructions' rates
+  const int64_t iters = dt == SBMM_BF16 ? 16384 : 8192;
+  if ((st = ensure_ws(h, sizeof(float) * (size_t)grid * 256))) return st;
+  float* out = reinterpret_cast<float*>(h->ws);
+  struct Events {   // destroyed on every return path
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIP_TRY(h, hipEventCreate(&ev.a));
+  HIP_TRY(h, hipEventCreate(&ev.b));
+  int64_t count = 0;
+  HIP_TRY(h, launch_mfma_peak(dtype, grid, iters, out, &count, nullptr));   // warm-up (clock ramp)
+  HIP_TRY(h, hipEventRecord(ev.a, nullptr));
+  HIP_TRY(h, launch_mfma_peak(dtype, grid, iters, out, &count, nullptr));
+  HIP_TRY(h, hipEventRecord(ev.b, nullptr));
+  HIP_TRY(h, hipEventSynchronize(ev.b));
+  float ms = 0.0f;
+  HIP_TRY(h, hipEventElapsedTime(&ms, ev.a, ev.b));
+  *tflops = ms > 0.0f ? (double)count * (double)mfma_peak_flops_per_instruction(dtype) / ((double)ms * 1e9) : 0.0;
+  return SBMM_OK;
+}
+
 sbmm_status sbmm_error(sbmm_handle h, int64_t m, int64_t p, sbmm_dtype dtype, const void* X, int64_t ldx,
                        const void* Y, int64_t ldy, double* out2, sbmm_stream stream) {
   sbmm_status st = check_handle(h);

@@ -240,6 +240,13 @@ hipError_t launch_grouped_reduce(const double* sk_part, int64_t sk_nparts, const
                                  hipStream_t s);
 // bf16 products (launch_gemm forwards SBMM_BF16 here) and their tile shape
 hipError_t launch_hgemm(const GemmLaunch& a, hipStream_t s);
+// Measured matrix-core throughput (peak.hip): `grid` workgroups of four
+// waves, each wave running independent chains of the dtype's 32x32
+// instruction `iters` times; *instructions receives their total count. out
+// holds one float per thread (grid x 256).
+hipError_t launch_mfma_peak(sbmm_dtype dt, int grid, int64_t iters, float* out, int64_t* instructions,
+                            hipStream_t s);
+int64_t mfma_peak_flops_per_instruction(sbmm_dtype dt);
 // The bf16 product takes A (m x K) and B (K x p) as they are, both row-major
 // (no transposed copy of B): 16-byte aligned rows and 32-bit offsets over the
 // K_max (or K_host) rows of B.

@@ -127,6 +127,8 @@ def test_null_handle_is_state_error():
     assert lib.sbmm_destroy(None) == pk.SBMM_E_STATE
     assert lib.sbmm_sync(None, None) == pk.SBMM_E_STATE
     assert lib.sbmm_reserve(None, 16) == pk.SBMM_E_STATE
+    out = ctypes.c_double()
+    assert lib.sbmm_peak_probe(None, pk.SBMM_F32, ctypes.byref(out)) == pk.SBMM_E_STATE
 
 
 def _struct_status(s):

@@ -57,3 +57,19 @@ def test_device_entry_points_reject_bad_arguments(h):
                                 None, None) == pk.SBMM_E_UNSUPPORTED
     assert lib.sbmm_error(h.h, 4, 4, 9, None, 4, None, 4, col.data_ptr(), None) == pk.SBMM_E_ARG
     torch.cuda.synchronize()
+
+
+def test_peak_probe_rates_are_ordered(h):
+    # the measured matrix-core rates: positive, below the specification's
+    # 2.4 GHz peaks (157.3 / 2500 / 5000 TFLOP/s, a little margin for the
+    # clock), and in the order of the instructions' widths
+    f32, bf16, f8 = h.peak_probe("f32"), h.peak_probe("bf16"), h.peak_probe("f8e4m3")
+    print(f"measured matrix-core TFLOP/s: f32 {f32:.1f}, bf16 {bf16:.1f}, f8e4m3 {f8:.1f}")
+    assert 0.3 * 157.3 < f32 < 1.05 * 157.3
+    assert 0.3 * 2500.0 < bf16 < 1.05 * 2500.0
+    assert 0.3 * 5000.0 < f8 < 1.05 * 5000.0
+    assert f32 < bf16 < f8
+    out = ctypes.c_double()
+    assert pk.lib().sbmm_peak_probe(h.h, pk.SBMM_F64, ctypes.byref(out)) == pk.SBMM_E_UNSUPPORTED
+    assert pk.lib().sbmm_peak_probe(h.h, 17, ctypes.byref(out)) == pk.SBMM_E_UNSUPPORTED
+    assert pk.lib().sbmm_peak_probe(h.h, pk.SBMM_F32, None) == pk.SBMM_E_ARG
