@@ -2,10 +2,12 @@
 4096 float32, 1024 uneven blocks of 16..112, lognormal(0, 1.5) column / row
 factors), in the launch configuration the benchmark times.
 
-The oracle computes the norms, design and draws at full size, and CD and MN
-on a seeded sample of entries (one by one, from their definitions); the
-norms are compared in full. Indices must be identical; float32 outputs must
-be within 1e-5 (relative Frobenius over the sampled entries).
+The oracle computes the norms, design and draws at full size, CD and MN on a
+seeded sample of entries (one by one, from their definitions), and CD and MN
+in full (float64 products of its own sketch, and of M and N; about 3 TFLOP on
+the host); the norms are compared in full. Indices must be identical; float32
+outputs must be within 1e-5 (relative Frobenius over the sampled entries and
+over all entries), and every entry within 1e-5 of the largest in magnitude.
 """
 import numpy as np
 import pytest
@@ -55,13 +57,19 @@ def test_paper_scale_norms(h, paper_inputs):
 
 
 @pytest.fixture(scope="module")
+def paper_mn(paper_inputs):
+    M, N, *_ = paper_inputs
+    return om.exact_product(M, N)
+
+
+@pytest.fixture(scope="module")
 def paper_blkprod(paper_inputs):
     M, N, off, *_ = paper_inputs
     return om.block_product_sq(M, N, off)
 
 
 @pytest.mark.parametrize("c,prob", [(256, "norm"), (64, "uniform"), (128, "exact")])
-def test_paper_scale_run(h, paper_inputs, paper_blkprod, c, prob):
+def test_paper_scale_run(h, paper_inputs, paper_blkprod, paper_mn, c, prob):
     M, N, off, Md, Nd, col, row = paper_inputs
     bp = None
     if prob == "exact":
@@ -91,6 +99,13 @@ def test_paper_scale_run(h, paper_inputs, paper_blkprod, c, prob):
     MN = r["MN"].cpu().numpy()
     assert rel(CD[rows, cols], cd_o) < 1e-5
     assert rel(MN[rows, cols], mn_o) < 1e-5
+    # every entry: the oracle's float64 MN, and CD from its own sketch
+    C_o, D_o = om.sketch(M, N, draws)
+    CD_o = om.sketch_product(C_o, D_o)
+    del C_o, D_o
+    for got, ref in ((CD, CD_o), (MN, paper_mn)):
+        assert rel(got, ref) < 1e-5
+        assert float(np.max(np.abs(got - ref))) <= 1e-5 * float(np.max(np.abs(ref)))
     # the fused error equals the standalone error kernel on the same outputs
     e2 = h.error(r["CD"], r["MN"]).cpu().numpy()
     assert abs(r["err"] ** 2 - e2[0]) <= 1e-12 * e2[0]
