@@ -2,10 +2,13 @@
 8192 in bf16 (X ~ N(0,1), W ~ N(0, 0.01^2)), 512 blocks of 32, c = 128,
 upstream gradient G 8192 x 8192 ~ N(0,1), through SampledMatmul.
 
-The oracle draws from its own norms; the gradients are checked on a seeded
-sample of columns of dX and rows of dW against float64 products of the bf16
-operands (X, W and G rounded to bf16) with each block's draws merged (the sum
-of scale^2), and every untouched column / row must be exactly zero."""
+The oracle draws from its own norms. The forward output is checked in full
+against the float64 product of the oracle's sketch rounded as the gather
+rounds it (to float32, then bf16); the gradients in every drawn column of dX
+and row of dW (and, separately, on a seeded sample of them) against float64
+products of the bf16 operands (X, W and G rounded to bf16) with each block's
+draws merged (the sum of scale^2); every untouched column / row must be
+exactly zero."""
 import numpy as np
 import pytest
 
@@ -38,6 +41,7 @@ def test_linear_layer_full_size():
     Gd = torch.from_numpy(G).to(DEV)
     Y = pk.SampledMatmul.apply(Xd, Wd, off, 128, 11, 0, "norm", None, None)
     gpu_idx = Y.grad_fn.plan.idx.cpu().numpy()
+    Yh = Y.detach().float().cpu().numpy().astype(np.float64)
     Y.backward(Gd)
     torch.cuda.synchronize()
     Xh = Xd.detach().float().cpu().numpy().astype(np.float64)
@@ -69,3 +73,21 @@ def test_linear_layer_full_size():
     # bf16 outputs: within the bf16 rounding of the float64 reference
     assert rel(np.array(got_x), np.array(ref_x)) < 4e-3
     assert rel(np.array(got_w), np.array(ref_w)) < 4e-3
+    # every drawn column of dX and row of dW
+    fac = np.zeros(X.shape[1])
+    for t in range(len(draws.atom)):
+        fac[draws.lo[t]:draws.lo[t] + draws.width[t]] += draws.scale[t] ** 2
+    hi = np.nonzero(hit)[0]
+    ref_dx = (Gq @ Wh[hi, :].T) * fac[hi][None, :]
+    assert rel(dX[:, hi], ref_dx) < 4e-3
+    del ref_dx
+    ref_dw = (Xh[:, hi].T @ Gq) * fac[hi][:, None]
+    assert rel(dW[hi], ref_dw) < 4e-3
+    del ref_dw
+    # the forward output in full: the sketch rounded to float32 then bf16, the
+    # product of those values (float32 accumulation on the device)
+    C_o, D_o = om.sketch(Xh, Wh, draws)
+    y_ref = bf16_round(C_o) @ bf16_round(D_o)
+    del C_o, D_o
+    tol = 1e-5 if Y.dtype == torch.float32 else 4e-3
+    assert rel(Yh, y_ref) < tol, (rel(Yh, y_ref), Y.dtype)
