@@ -156,3 +156,35 @@ def test_mx_zero_problem(h):
     CD, _ = h.sketch_gemm_mx(C8, Cs, Dt8, Ds, plan)
     torch.cuda.synchronize()
     assert plan.L == 0 and torch.count_nonzero(CD).item() == 0
+
+
+def test_mx_paper_scale(h):
+    # the paper-scale block workload at c = 256, rule (1.4): every code and
+    # scale byte of C and D^T against the oracle's quantization of its own
+    # sketch, and the product on a 128 x 128 block of sampled entries within
+    # the instruction bound (the full bound would take hours on the host)
+    M, N, off = wl.paper_scale()
+    Md = torch.from_numpy(M).to(DEV)
+    Nd = torch.from_numpy(N).to(DEV)
+    prob = pk.Problem(Md, Nd, off, 256, prob="norm", seed=0)
+    col, row, blk = h.norms(prob)
+    plan = h.plan(prob, col, row, blk, sync=True)
+    C8, Cs, Dt8, Ds = h.sketch_mx(prob, plan)
+    CD, _ = h.sketch_gemm_mx(C8, Cs, Dt8, Ds, plan)
+    torch.cuda.synchronize()
+    draws, Lp, Cq, Ec, Dq, Ed = oracle_mx(M.astype(np.float64), N.astype(np.float64), off, 256, "norm", 0)
+    assert np.array_equal(plan.idx.cpu().numpy(), draws.atom)
+    assert plan.L == draws.L
+    Cg, Ecg = decode(C8.cpu().numpy(), Cs.cpu().numpy(), Lp)
+    assert np.array_equal(Ecg, Ec) and np.array_equal(Cg, Cq)
+    del Cg
+    Dg, Edg = decode(Dt8.cpu().numpy(), Ds.cpu().numpy(), Lp)
+    assert np.array_equal(Edg, Ed) and np.array_equal(Dg, Dq)
+    del Dg
+    g = wl.rng(77)
+    rows = np.sort(g.choice(M.shape[0], size=128, replace=False))
+    cols = np.sort(g.choice(N.shape[1], size=128, replace=False))
+    ref = Cq[rows] @ Dq[cols].T
+    bound = instruction_bound(Cq[rows], Ec[rows], Dq[cols], Ed[cols], Lp)
+    gpu = CD.double().cpu().numpy()[np.ix_(rows, cols)]
+    assert np.all(np.abs(gpu - ref) <= bound), float(np.max(np.abs(gpu - ref) / np.maximum(bound, 1e-300)))
