@@ -110,3 +110,36 @@ def test_paper_scale_run(h, paper_inputs, paper_blkprod, paper_mn, c, prob):
     e2 = h.error(r["CD"], r["MN"]).cpu().numpy()
     assert abs(r["err"] ** 2 - e2[0]) <= 1e-12 * e2[0]
     assert abs(r["rel"] - np.sqrt(e2[0] / e2[1])) <= 1e-12 * r["rel"]
+
+
+def _bf16_round(x):
+    """float64 -> float32 -> bf16 (nearest even each time) -> float64: the
+    rounding the gather applies to the scaled sketch."""
+    return torch.from_numpy(np.asarray(x, np.float64)).to(torch.float32).to(torch.bfloat16).to(
+        torch.float64).numpy()
+
+
+def test_paper_scale_bf16_sketch(h, paper_inputs):
+    # the bf16 sketch the benchmark times (D's rows read as gathered): C and D
+    # bit-exact against the oracle's sketch rounded the gather's way, CD in
+    # every entry against the float64 product of those values
+    M, N, off, Md, Nd, col, row = paper_inputs
+    prob = pk.Problem(Md, Nd, off, 256, prob="norm", seed=0, trial=0)
+    gcol, grow, gblk = h.norms(prob)
+    pl = h.plan(prob, gcol, grow, gblk)
+    C, D = h.sketch(prob, pl, out_dtype=torch.bfloat16)
+    CD, _ = h.sketch_gemm(C, D, pl)
+    torch.cuda.synchronize()
+    design, *_ = om.plan(M, N, off, 256, prob="norm", col_row=(col, row))
+    draws = om.sample(design, 0, 0)
+    assert np.array_equal(pl.idx.cpu().numpy(), draws.atom)
+    L = draws.L
+    C_o, D_o = om.sketch(M, N, draws)
+    Cq, Dq = _bf16_round(C_o), _bf16_round(D_o)
+    del C_o, D_o
+    assert np.array_equal(C[:, :L].double().cpu().numpy(), Cq)
+    assert np.array_equal(D[:L].double().cpu().numpy(), Dq)
+    ref = Cq @ Dq
+    got = CD.double().cpu().numpy()
+    assert rel(got, ref) < 1e-5
+    assert float(np.max(np.abs(got - ref))) <= 1e-5 * float(np.max(np.abs(ref)))
