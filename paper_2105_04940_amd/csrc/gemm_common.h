@@ -84,6 +84,14 @@ __device__ __forceinline__ void wait_loads_barrier() {
   asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" :: "n"(N) : "memory");
 }
 
+// As wait_loads_barrier, and this wave's LDS reads have returned too: for a
+// barrier after which other waves overwrite what those reads fetched, while
+// the values read are still to be used.
+template <int N>
+__device__ __forceinline__ void wait_loads_reads_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" :: "n"(N) : "memory");
+}
+
 __device__ inline __attribute__((always_inline)) int64_t inner_extent(const GemmArgs& g) {
   if (g.K_dev) {
     const int64_t L = *g.K_dev;

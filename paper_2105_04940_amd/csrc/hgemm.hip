@@ -518,36 +518,73 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       return __builtin_bit_cast(bf16x8, sh.Bs[buf][tn_lds_slot<KC>(wn0 + 32 * c + lr, 2 * s + lh)]);
     }
   };
-  auto compute = [&](int buf) {
+  auto frags = [&](int buf, int s, bf16x8 (&av)[4], bf16x8 (&bv)[CB]) {
 #pragma unroll
-    for (int s = 0; s < BK / 16; ++s) {
-      bf16x8 av[4], bv[CB];
+    for (int b = 0; b < 4; ++b)
+      av[b] = __builtin_bit_cast(bf16x8, sh.As[buf][tn_lds_slot<KC>(wm0 + 32 * b + lr, 2 * s + lh)]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        av[b] = __builtin_bit_cast(bf16x8, sh.As[buf][tn_lds_slot<KC>(wm0 + 32 * b + lr, 2 * s + lh)]);
+    for (int c = 0; c < CB; ++c) bv[c] = b_frag(buf, s, c);
+  };
+  // The fragments of sub-step s + 1 are read while the matrix instructions
+  // of sub-step s run (one LDS read between two matrix instructions, an
+  // order the scheduling-group barriers impose: left alone, the compiler
+  // issues each sub-step's reads just before their use and waits on them).
+  // Fragment sets alternate by sub-step; four sub-steps a step, so sub-step 0
+  // of every step uses set 0.
+  constexpr int READS = 4 + (BKN ? 2 : 1) * CB;   // LDS read instructions per sub-step
+  constexpr int NS = BK / 16;
+  static_assert(NS % 2 == 0, "sub-step 0 of every step in fragment set 0");
+  bf16x8 av[2][4], bv[2][CB];
+  auto mfmas = [&](int set) {
 #pragma unroll
-      for (int c = 0; c < CB; ++c) bv[c] = b_frag(buf, s, c);
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < CB; ++c)
+        acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[set][b], bv[set][c], acc[b][c], 0, 0, 0);
+  };
+  auto interleave = [&]() {
 #pragma unroll
-        for (int c = 0; c < CB; ++c)
-          acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[b], bv[c], acc[b][c], 0, 0, 0);
+    for (int i = 0; i < 4 * CB; ++i) {
+      if (i < READS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     }
+    __builtin_amdgcn_sched_barrier(0);
   };
 
-  // two stages: at the top of step kt every wave's loads of step kt have
-  // landed (vmcnt(0), barrier); the loads of step kt + 1 then go into the
-  // stage step kt - 1 read, and overlap the matrix instructions of step kt
+  // Two stages. Step kt's loads were issued one step ahead into stage
+  // kt & 1. A step runs sub-steps 0 .. NS - 2, each reading the next
+  // sub-step's fragments; then every wave waits for its own LDS reads and
+  // for step kt + 1's loads, and barriers: step kt + 1's stage is complete
+  // and no wave reads stage kt & 1 any more, so step kt + 2's loads go there.
+  // The last sub-step's matrix instructions then run while the first
+  // fragments of step kt + 1 are read, so the barrier and that first read
+  // overlap matrix work instead of following it.
   const int64_t nkt = (K + BK - 1) / BK;
-  auto step = [&](int64_t kt, int buf) {
-    wait_loads_barrier<0>();
-    if (kt + 1 < nkt) issue(kt + 1, buf ^ 1);
-    compute(buf);
+  auto body = [&](int64_t kt, int buf) {
+#pragma unroll
+    for (int s = 0; s + 1 < NS; ++s) {
+      frags(buf, s + 1, av[(s + 1) & 1], bv[(s + 1) & 1]);
+      mfmas(s & 1);
+      interleave();
+    }
+    // (after the last step the barrier is uniform and the reads of the
+    // other stage, in bounds, go unused: one path for every step)
+    wait_loads_reads_barrier<0>();
+    if (kt + 2 < nkt) issue(kt + 2, buf);
+    frags(buf ^ 1, 0, av[0], bv[0]);
+    mfmas(1);
+    interleave();
   };
-  if (nkt > 0) issue(0, 0);
+  if (nkt > 0) {
+    issue(0, 0);
+    wait_loads_barrier<0>();
+    if (nkt > 1) issue(1, 1);
+    frags(0, 0, av[0], bv[0]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   for (int64_t kt = 0; kt < nkt; kt += 2) {
-    step(kt, 0);
-    if (kt + 1 < nkt) step(kt + 1, 1);
+    body(kt, 0);
+    if (kt + 1 < nkt) body(kt + 1, 1);
   }
 
   if constexpr (EPI != SC_NONE) {
