@@ -389,12 +389,11 @@ __global__ __launch_bounds__(kThreads, 1) void hgemm_tn_kernel(GemmArgs g) {
 // elements. Per k-step: wait for the step's loads and barrier, issue the
 // next step's loads, run the 64 matrix instructions on the current tile.
 // ============================================================================
-template <int BK_, int STAGES_>
+template <int BK_, int SA_, int SB_>
 struct TnLdsTile {
-  static constexpr int BM = 256, BN = 256, BK = BK_, KC = BK / 8, STAGES = STAGES_;
-  uint4 As[STAGES][BM * KC];
-  uint4 Bs[STAGES][BN * KC];
-  double red[16];
+  static constexpr int BM = 256, BN = 256, BK = BK_, KC = BK / 8, SA = SA_, SB = SB_;
+  uint4 As[SA][BM * KC];   // after the main loop, the first stage holds the error partials
+  uint4 Bs[SB][BN * KC];
 };
 
 // LDS slot of 16-byte chunk `chunk` of tile row `row`: a row holds KC chunks
@@ -429,7 +428,10 @@ template <int BK, int STAGES, int NW, int EPI, bool BKN = false>
 __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   static_assert(STAGES == 2, "a ring of two stages");
   static_assert(!BKN || (BK == 64 && NW == 8), "the k-row B form: k-step 64, 8 waves");
-  using Tile = TnLdsTile<BK, STAGES>;
+  // the k-row B form keeps A in a ring of three stages (A tiles two steps
+  // ahead) beside B in a ring of two: 96 + 64 KB, all of LDS
+  constexpr int SA = BKN ? 3 : 2, SB = 2;
+  using Tile = TnLdsTile<BK, SA, SB>;
   constexpr int KC = Tile::KC;
   constexpr int CB = 16 / NW;                          // 32-column blocks per wave
   constexpr int ROWS_PER_INST = 64 / KC;               // tile rows one wave instruction fills
@@ -467,7 +469,9 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   // instruction j of wave w fills slots [(INSTS w + j) 64, +64): lane l holds
   // slot P = (INSTS w + j) 64 + l, i.e. tile row P / KC and the chunk whose
   // swizzled slot is P % KC
-  auto issue = [&](int64_t kt, int buf) {
+  // A's tile of step kt into A stage buf (and, in the p x K form, B's into B
+  // stage buf: the same rows and chunks)
+  auto issue_a = [&](int64_t kt, int buf) {
     const int64_t k0 = kt * BK;
     const unsigned sk = (unsigned)(k0 * 2);
 #pragma unroll
@@ -481,9 +485,12 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       lds_dma16(ra, lds_offset(&sh.As[buf][(INSTS * wave + j) * 64]), oa, sk);
       if constexpr (!BKN) lds_dma16(rb, lds_offset(&sh.Bs[buf][(INSTS * wave + j) * 64]), ob, sk);
     }
+  };
+  // BKN: B's tile of step kt (its 64 k-rows) into B stage buf
+  auto issue_b = [&](int64_t kt, int buf) {
     if constexpr (BKN) {
       constexpr int BINSTS = BK / 2 / NW;   // two k-rows per instruction
-      const unsigned skb = (unsigned)(k0 * g.ldb * 2);
+      const unsigned skb = (unsigned)(kt * BK * g.ldb * 2);
 #pragma unroll
       for (int j = 0; j < BINSTS; ++j) {
         const int r = 2 * (BINSTS * wave + j) + (lane >> 5);
@@ -518,12 +525,12 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       return __builtin_bit_cast(bf16x8, sh.Bs[buf][tn_lds_slot<KC>(wn0 + 32 * c + lr, 2 * s + lh)]);
     }
   };
-  auto frags = [&](int buf, int s, bf16x8 (&av)[4], bf16x8 (&bv)[CB]) {
+  auto frags = [&](int sa, int sb, int s, bf16x8 (&av)[4], bf16x8 (&bv)[CB]) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      av[b] = __builtin_bit_cast(bf16x8, sh.As[buf][tn_lds_slot<KC>(wm0 + 32 * b + lr, 2 * s + lh)]);
+      av[b] = __builtin_bit_cast(bf16x8, sh.As[sa][tn_lds_slot<KC>(wm0 + 32 * b + lr, 2 * s + lh)]);
 #pragma unroll
-    for (int c = 0; c < CB; ++c) bv[c] = b_frag(buf, s, c);
+    for (int c = 0; c < CB; ++c) bv[c] = b_frag(sb, s, c);
   };
   // The fragments of sub-step s + 1 are read while the matrix instructions
   // of sub-step s run (one LDS read between two matrix instructions, an
@@ -551,40 +558,83 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
     __builtin_amdgcn_sched_barrier(0);
   };
 
-  // Two stages. Step kt's loads were issued one step ahead into stage
-  // kt & 1. A step runs sub-steps 0 .. NS - 2, each reading the next
-  // sub-step's fragments; then every wave waits for its own LDS reads and
-  // for step kt + 1's loads, and barriers: step kt + 1's stage is complete
-  // and no wave reads stage kt & 1 any more, so step kt + 2's loads go there.
-  // The last sub-step's matrix instructions then run while the first
-  // fragments of step kt + 1 are read, so the barrier and that first read
-  // overlap matrix work instead of following it.
+  // Step kt reads A stage kt % SA and B stage kt % 2. A step runs sub-steps
+  // 0 .. NS - 2, each reading the next sub-step's fragments; then every wave
+  // waits for its own LDS reads and for step kt + 1's tiles, and barriers:
+  // step kt + 1's stages are complete and no wave reads step kt's any more,
+  // so the tiles of the steps that take them over are issued there. The
+  // last sub-step's matrix instructions then run while the first fragments
+  // of step kt + 1 are read, so the barrier and that first read overlap
+  // matrix work instead of following it. Two A stages: step kt + 2's tiles,
+  // one step ahead. Three A stages: B of step kt + 2, then A of step kt + 3,
+  // two steps ahead (in the 8 x 4 tile block of an XCD every A panel is
+  // shared by 4 tiles and every B panel by 8, so A misses the L2 twice as
+  // often; timing-only copies of the kernel ran 9 % faster with A's loads
+  // all hitting L2, 3 % with B's). Loads complete in issue order, so at the
+  // barrier of step kt the newest A tile (step kt + 2) may still be in
+  // flight while everything older has landed.
   const int64_t nkt = (K + BK - 1) / BK;
-  auto body = [&](int64_t kt, int buf) {
+  constexpr int AINSTS = INSTS;   // load instructions per wave in one A tile
+  static_assert(!BKN || BK / 2 / NW == INSTS, "A and B tiles take the same number of loads");
+  auto body = [&](int64_t kt, int sa, int sb) {
 #pragma unroll
     for (int s = 0; s + 1 < NS; ++s) {
-      frags(buf, s + 1, av[(s + 1) & 1], bv[(s + 1) & 1]);
+      frags(sa, sb, s + 1, av[(s + 1) & 1], bv[(s + 1) & 1]);
       mfmas(s & 1);
       interleave();
     }
     // (after the last step the barrier is uniform and the reads of the
-    // other stage, in bounds, go unused: one path for every step)
-    wait_loads_reads_barrier<0>();
-    if (kt + 2 < nkt) issue(kt + 2, buf);
-    frags(buf ^ 1, 0, av[0], bv[0]);
+    // next stages, in bounds, go unused: one path for every step)
+    if constexpr (SA == 3) {
+      if (kt + 2 < nkt) wait_loads_reads_barrier<AINSTS>();
+      else wait_loads_reads_barrier<0>();
+      if (kt + 2 < nkt) issue_b(kt + 2, sb);
+      if (kt + 3 < nkt) issue_a(kt + 3, sa);
+    } else {
+      wait_loads_reads_barrier<0>();
+      if (kt + 2 < nkt) {
+        issue_a(kt + 2, sa);
+        issue_b(kt + 2, sb);
+      }
+    }
+    frags(sa + 1 < SA ? sa + 1 : 0, sb ^ 1, 0, av[0], bv[0]);
     mfmas(1);
     interleave();
   };
   if (nkt > 0) {
-    issue(0, 0);
-    wait_loads_barrier<0>();
-    if (nkt > 1) issue(1, 1);
-    frags(0, 0, av[0], bv[0]);
+    issue_a(0, 0);
+    issue_b(0, 0);
+    if (nkt > 1) {
+      issue_a(1, 1);
+      issue_b(1, 1);
+    }
+    if constexpr (SA == 3) {
+      if (nkt > 2) issue_a(2, 2);
+      // step 0's tiles landed; those issued after them may still be in flight
+      if (nkt > 2) wait_loads_barrier<3 * AINSTS>();
+      else if (nkt > 1) wait_loads_barrier<2 * AINSTS>();
+      else wait_loads_barrier<0>();
+    } else {
+      if (nkt > 1) wait_loads_barrier<2 * AINSTS>();
+      else wait_loads_barrier<0>();
+    }
+    frags(0, 0, 0, av[0], bv[0]);
     __builtin_amdgcn_sched_barrier(0);
   }
-  for (int64_t kt = 0; kt < nkt; kt += 2) {
-    body(kt, 0);
-    if (kt + 1 < nkt) body(kt + 1, 1);
+  if constexpr (SA == 3) {
+    for (int64_t kt = 0; kt < nkt; kt += 6) {
+      body(kt, 0, 0);
+      if (kt + 1 < nkt) body(kt + 1, 1, 1);
+      if (kt + 2 < nkt) body(kt + 2, 2, 0);
+      if (kt + 3 < nkt) body(kt + 3, 0, 1);
+      if (kt + 4 < nkt) body(kt + 4, 1, 0);
+      if (kt + 5 < nkt) body(kt + 5, 2, 1);
+    }
+  } else {
+    for (int64_t kt = 0; kt < nkt; kt += 2) {
+      body(kt, 0, 0);
+      if (kt + 1 < nkt) body(kt + 1, 1, 1);
+    }
   }
 
   if constexpr (EPI != SC_NONE) {
@@ -631,19 +681,23 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
   store_tile_with_error<CB>(acc, reinterpret_cast<float*>(g.C), g.ldc, reinterpret_cast<const float*>(g.Y), g.ldy,
                             g.m, g.p, m0 + wm0 + 4 * lh, n0 + wn0 + lr, e2, n2);
   if (g.tile_part) {
-    // NW waves' sums added in wave order
+    // NW waves' sums added in wave order, through the first A stage once
+    // every wave is past its last LDS read (no tile load is in flight: the
+    // last step's barrier waited for all of them)
+    double* red = reinterpret_cast<double*>(&sh.As[0][0]);
     e2 = warp_sum_f64(e2);
     n2 = warp_sum_f64(n2);
+    __syncthreads();
     if (lane == 0) {
-      sh.red[wave] = e2;
-      sh.red[NW + wave] = n2;
+      red[wave] = e2;
+      red[NW + wave] = n2;
     }
     __syncthreads();
     if (tid == 0) {
       double a = 0.0, b = 0.0;
       for (int w = 0; w < NW; ++w) {
-        a += sh.red[w];
-        b += sh.red[NW + w];
+        a += red[w];
+        b += red[NW + w];
       }
       g.tile_part[blockIdx.x] = a;
       g.tile_part[g.tiles_m * g.tiles_n + blockIdx.x] = b;

@@ -608,6 +608,38 @@ def test_bf16_sketch_product_reads_d_rows(h, m, p, n, K, c):
     assert abs(err.item() - e_ref) <= 1e-4 * e_ref
 
 
+class _Extent:
+    """Stands in for a plan where a product reads only the sketch width."""
+
+    def __init__(self, L):
+        self.L_dev = torch.tensor([L], dtype=torch.int64, device="cuda:0")
+
+
+# the k-row bf16 product over inner extents of one to eight 64-wide k-steps
+# (its A tiles come two steps ahead through a ring of three stages, B one
+# step ahead through two, so the first steps and the ring's turns are the edge
+# cases), some ending half way through a step; ragged 300 x 264 tiles; NaN past
+# the extent must not reach the product
+@pytest.mark.parametrize("L", [17, 64, 96, 160, 192, 250, 320, 352, 416, 480])
+def test_bf16_kn_product_short_extents(h, L):
+    m, p, Lp = 300, 264, 512
+    K = (L + 31) // 32 * 32
+    g = np.random.default_rng(L)
+    C = torch.from_numpy(g.standard_normal((m, Lp)).astype(np.float32)).to(torch.bfloat16)
+    D = torch.from_numpy(g.standard_normal((Lp, p)).astype(np.float32)).to(torch.bfloat16)
+    C[:, L:K] = 0
+    D[L:K] = 0
+    C[:, K:] = float("nan")
+    D[K:] = float("nan")
+    Cd, Dd = C.to("cuda:0"), D.to("cuda:0")
+    MN = torch.from_numpy(g.standard_normal((m, p)).astype(np.float32)).to("cuda:0")
+    CD, err = h.sketch_gemm(Cd, Dd, _Extent(L), MN=MN)
+    ref = C[:, :L].double().numpy() @ D[:L].double().numpy()
+    assert rel(host64(CD), ref) < 1e-5
+    e_ref = float(np.sum((host64(MN) - ref) ** 2))
+    assert abs(err.item() - e_ref) <= 1e-4 * e_ref
+
+
 # the exact product of bf16 inputs with row-major N read as it is (aligned rows)
 @pytest.mark.parametrize("m,n,p", [(300, 1000, 264), (257, 4104, 520)])
 def test_bf16_exact_product_reads_n_rows(h, m, n, p):
