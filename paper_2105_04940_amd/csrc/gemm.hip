@@ -622,7 +622,7 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
   // last row reads zeros past K; in the other rows it reads the row's next
   // entries, which the last step clears in LDS (below)
   const int64_t arows = min((int64_t)T::BM, g.m - m0);
-  const __amdgpu_buffer_rsrc_t ra = f32_rsrc(A, arows > 0 ? ((arows - 1) * g.lda + K) * 4 : 0);
+  const i32x4 ra = buffer_words(A, arows > 0 ? (int)(((arows - 1) * g.lda + K) * 4) : 0);
   constexpr unsigned kOut = 0x80000000u;   // past any record count
 
   f32x16 acc[4][CB];
@@ -640,8 +640,7 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
       const int chunk = (lane % KC) ^ ((row >> 1) & 7);
       const bool live = k0 + 4 * chunk < K;
       const unsigned oa = live ? (unsigned)(row * g.lda * 4 + chunk * 16) : kOut;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          ra, (__attribute__((address_space(3))) void*)&sh.As[buf][(AINSTS * wave + j) * 64], 16, oa, sk, 0, 0);
+      lds_dma16(ra, lds_offset(&sh.As[buf][(AINSTS * wave + j) * 64]), oa, sk);
     }
     // B: rows k0 .. k0 + 31 of columns n0 .. n0 + 255; a row past K, or an
     // entry past p in the stage's last row, lies past the record count and
@@ -649,43 +648,38 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
     // only feed output columns that are not stored
     const int64_t brows = min((int64_t)BK, K - k0);
     const int64_t bbytes = brows > 0 ? ((brows - 1) * g.ldb + (g.p - n0)) * 4 : 0;
-    const __amdgpu_buffer_rsrc_t rb = f32_rsrc(B + k0 * g.ldb + n0, bbytes);
+    const i32x4 rb = buffer_words(B + k0 * g.ldb + n0, (int)bbytes);
 #pragma unroll
     for (int j = 0; j < BINSTS; ++j) {
       const int r = BINSTS * wave + j;
       const unsigned ob = (unsigned)(r * g.ldb * 4 + lane * 16);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (__attribute__((address_space(3))) void*)&sh.Bs[buf][r][0], 16,
-                                               ob, 0, 0, 0);
+      lds_dma16(rb, lds_offset(&sh.Bs[buf][r][0]), ob, 0u);
     }
   };
   // the fragments of super-step u + 1 are read from LDS while the MFMAs of
-  // super-step u run (two register sets)
-  auto compute = [&](int buf) {
-    f32x4 av[2][4];
-    float bv[2][CB][4];
-    auto frag = [&](int u, int r) {
+  // super-step u run (two register sets; four super-steps a step, so
+  // super-step 0 of every step uses set 0)
+  constexpr int NU = BK / 8;
+  static_assert(NU % 2 == 0, "super-step 0 of every step in register set 0");
+  f32x4 av[2][4];
+  float bv[2][CB][4];
+  auto frag = [&](int buf, int u, int r) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      av[r][b] = __builtin_bit_cast(f32x4, sh.As[buf][lds_a_slot(wm0 + 32 * b + lr, 2 * u + lh)]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) bv[r][c][q] = sh.Bs[buf][8 * u + 4 * lh + q][wn0 + 32 * c + lr];
+  };
+  auto mfmas = [&](int r) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        av[r][b] = __builtin_bit_cast(f32x4, sh.As[buf][lds_a_slot(wm0 + 32 * b + lr, 2 * u + lh)]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < CB; ++c) bv[r][c][q] = sh.Bs[buf][8 * u + 4 * lh + q][wn0 + 32 * c + lr];
-    };
-    frag(0, 0);
-#pragma unroll
-    for (int u = 0; u < BK / 8; ++u) {
-      if (u + 1 < BK / 8) frag(u + 1, (u + 1) & 1);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-          for (int c = 0; c < CB; ++c)
-            acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u & 1][b][q], bv[u & 1][c][q], acc[b][c], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
-    }
+        for (int c = 0; c < CB; ++c)
+          acc[b][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[r][b][q], bv[r][c][q], acc[b][c], 0, 0, 0);
   };
 
   // the 128 x 128 tile of the 128 x 128 tiling this wave's part lies in
@@ -730,16 +724,11 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
     ++folds;
   };
 
-  const int64_t nkt = (K + BK - 1) / BK;
-  if (nkt > 0) issue(0, 0);
-  for (int64_t kt = 0; kt < nkt; ++kt) {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (kt + 1 < nkt) {
-      issue(kt + 1, (int)((kt + 1) & 1));
-    } else if (K & 3) {
-      // the inner extent ends inside a chunk: clear the A entries past K
-      // of that chunk in every row (B rows past K already read zero)
+  // The inner extent ends inside a chunk of the last step kt: clear the A
+  // entries past K of that chunk in every row (B rows past K already read
+  // zero), once the step's tile has landed and before any wave reads it.
+  auto clear_tail = [&](int64_t kt) {
+    if (K & 3) {
       const int kz = (int)(K - kt * BK), cs = kz >> 2, e0 = kz & 3;
       if (tid < T::BM) {
         float* q = reinterpret_cast<float*>(&sh.As[kt & 1][lds_a_slot(tid, cs)]);
@@ -747,8 +736,45 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
       }
       __syncthreads();
     }
-    compute((int)(kt & 1));
+  };
+  // Step kt's tile was issued one step ahead into stage kt & 1. A step runs
+  // super-steps 0 .. NU - 2; then every wave waits for its own LDS reads and
+  // for step kt + 1's tile, and barriers: step kt + 1's stage is complete and
+  // no wave reads stage kt & 1 any more, so step kt + 2's tile goes there.
+  // The last super-step's matrix instructions then run after the first
+  // fragments of step kt + 1 are requested, so the barrier, the loads' issue
+  // and that first read no longer stand between two steps' matrix work.
+  const int64_t nkt = (K + BK - 1) / BK;
+  auto body = [&](int64_t kt, int buf) {
+#pragma unroll
+    for (int u = 0; u + 1 < NU; ++u) {
+      frag(buf, u + 1, (u + 1) & 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas(u & 1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // (after the last step the barrier is uniform and the reads of the
+    // other stage, in bounds, go unused: one path for every step)
+    wait_loads_reads_barrier<0>();
+    if (kt + 2 < nkt) issue(kt + 2, buf);
+    if (kt + 2 == nkt) clear_tail(kt + 1);
+    frag(buf ^ 1, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    mfmas((NU - 1) & 1);
+    __builtin_amdgcn_sched_barrier(0);
     if ((kt + 1) % T::FOLD_STEPS == 0 && kt + 1 < nkt) fold();
+  };
+  if (nkt > 0) {
+    issue(0, 0);
+    wait_loads_barrier<0>();
+    if (nkt > 1) issue(1, 1);
+    else clear_tail(0);
+    frag(0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  for (int64_t kt = 0; kt < nkt; kt += 2) {
+    body(kt, 0);
+    if (kt + 1 < nkt) body(kt + 1, 1);
   }
 
   double e2 = 0.0, n2 = 0.0;
