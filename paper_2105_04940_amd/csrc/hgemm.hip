@@ -386,8 +386,9 @@ __global__ __launch_bounds__(kThreads, 1) void hgemm_tn_kernel(GemmArgs g) {
 // the buffer's record count and chunks past the inner extent get an
 // out-of-range offset: both read as zero, so edge tiles need no separate
 // path, and a live chunk of a valid row never reads past that row's first K
-// elements. Per k-step: wait for the step's loads and barrier, issue the
-// next step's loads, run the 64 matrix instructions on the current tile.
+// elements. The k-step loop (below, at the kernel's main loop) overlaps the
+// loads of later steps, the step barrier and the fragment reads with the
+// matrix instructions.
 // ============================================================================
 template <int BK_, int SA_, int SB_>
 struct TnLdsTile {
