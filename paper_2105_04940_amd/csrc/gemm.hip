@@ -631,6 +631,12 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[b][c] = f32x16{};
 
+  // the parts of B's per-step record count, made scalar once: computed next
+  // to the loads from the vector copies the compiler keeps for the lane
+  // offsets, they came back through a readfirstlane right before a load
+  // (whose resource then needs five wait states)
+  const int ldb_bytes = __builtin_amdgcn_readfirstlane((int)(g.ldb * 4));
+  const int btail_bytes = __builtin_amdgcn_readfirstlane((int)((g.p - n0) * 4));
   auto issue = [&](int64_t kt, int buf) {
     const int64_t k0 = kt * BK;
     const unsigned sk = (unsigned)(k0 * 4);
@@ -646,9 +652,8 @@ __device__ __forceinline__ void sgemm_lds_body(const GemmArgs& g, SgemmLdsTile& 
     // entry past p in the stage's last row, lies past the record count and
     // reads 0 (the check is per dword); entries past p in the other rows
     // only feed output columns that are not stored
-    const int64_t brows = min((int64_t)BK, K - k0);
-    const int64_t bbytes = brows > 0 ? ((brows - 1) * g.ldb + (g.p - n0)) * 4 : 0;
-    const i32x4 rb = buffer_words(B + k0 * g.ldb + n0, (int)bbytes);
+    const int brows = (int)min((int64_t)BK, K - k0);
+    const i32x4 rb = buffer_words(B + k0 * g.ldb + n0, brows > 0 ? (brows - 1) * ldb_bytes + btail_bytes : 0);
 #pragma unroll
     for (int j = 0; j < BINSTS; ++j) {
       const int r = BINSTS * wave + j;

@@ -59,10 +59,19 @@ __device__ __forceinline__ uint32_t lds_offset(const void* p) {
 // compiler may sink the loads to the end of the matrix-instruction sequence
 // that follows (leaving them a fraction of a k-step to land; a timing probe
 // showed it) and adds its own conservative waits before reads of the other
-// stage. Here the load issues
-// where it is written, nothing else waits for it, and the "memory" clobber
-// keeps LDS reads from moving across it. The caller waits with
-// wait_loads_barrier before any wave reads the destination.
+// stage. Here the load issues where it is written, nothing else waits for
+// it, and the "memory" clobber keeps LDS reads from moving across it. The
+// caller waits with wait_loads_barrier before any wave reads the
+// destination.
+//
+// The compiler's hazard checks do not look inside inline asm, so the wait
+// states the load needs after its operands are written are in the asm: one
+// after m0 is written (always, the compiler sets m0 just before), and
+// WAIT + 1 in all. A vector instruction that writes an SGPR the load reads
+// (a readfirstlane below, when an operand lives in vector registers) needs
+// five, WAIT = 4; operands computed from scalars need none of those, and
+// the build's tests check the compiled kernels for that pattern.
+template <int WAIT = 0>
 __device__ __forceinline__ void lds_dma16(i32x4 rs, uint32_t lds, uint32_t voff, uint32_t soff) {
   // the scalar operands are uniform by contract; readfirstlane makes that
   // visible where the compiler cannot prove it (free where it can)
@@ -71,8 +80,8 @@ __device__ __forceinline__ void lds_dma16(i32x4 rs, uint32_t lds, uint32_t voff,
   lds = __builtin_amdgcn_readfirstlane(lds); soff = __builtin_amdgcn_readfirstlane(soff);
   // m0 (the LDS base of the load) is an input operand, so the compiler sets
   // it and knows its value; nothing is clobbered behind its back
-  asm volatile("buffer_load_dwordx4 %0, %1, %2 offen lds"
-               :: "v"(voff), "s"(rs), "s"(soff), "{m0}"(lds) : "memory");
+  asm volatile("s_nop %4\n\tbuffer_load_dwordx4 %0, %1, %2 offen lds"
+               :: "v"(voff), "s"(rs), "s"(soff), "{m0}"(lds), "n"(WAIT) : "memory");
 }
 
 // Wait until at most N of this wave's vector-memory loads are outstanding

@@ -487,11 +487,16 @@ __global__ __launch_bounds__(NW * 64, 1) void hgemm_tn_lds_kernel(GemmArgs g) {
       if constexpr (!BKN) lds_dma16(rb, lds_offset(&sh.Bs[buf][(INSTS * wave + j) * 64]), ob, sk);
     }
   };
-  // BKN: B's tile of step kt (its 64 k-rows) into B stage buf
+  // BKN: B's tile of step kt (its 64 k-rows) into B stage buf. The byte
+  // stride of a k-step is made scalar here, once: computed next to the loads
+  // from the vector copy of ldb the compiler keeps for the lane offsets, it
+  // came back through a readfirstlane right before a load (the load's
+  // soffset then needs five wait states)
+  const unsigned kstep_b = __builtin_amdgcn_readfirstlane((unsigned)(BK * g.ldb * 2));
   auto issue_b = [&](int64_t kt, int buf) {
     if constexpr (BKN) {
       constexpr int BINSTS = BK / 2 / NW;   // two k-rows per instruction
-      const unsigned skb = (unsigned)(kt * BK * g.ldb * 2);
+      const unsigned skb = (unsigned)kt * kstep_b;
 #pragma unroll
       for (int j = 0; j < BINSTS; ++j) {
         const int r = 2 * (BINSTS * wave + j) + (lane >> 5);
