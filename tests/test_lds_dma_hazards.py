@@ -94,11 +94,12 @@ def assembly(tmp_path_factory):
     return texts
 
 
-@pytest.mark.parametrize("src", SOURCES)
-def test_lds_dma_loads_have_their_wait_states(src, assembly):
-    tagged = _instructions(assembly[src])
+def check(asm):
+    """Problems of the inline-asm LDS-DMA loads in an assembly text (empty
+    when every load has its wait states) and the number of such loads."""
+    tagged = _instructions(asm)
     ins = [t for t, _ in tagged]
-    loads = 0
+    problems, loads = [], 0
     for i, (t, in_asm) in enumerate(tagged):
         m = LOAD.fullmatch(t)
         if not m or not in_asm:
@@ -106,14 +107,53 @@ def test_lds_dma_loads_have_their_wait_states(src, assembly):
         loads += 1
         used = _sgprs(m.group(1)) | _sgprs(m.group(2))
         # the asm's own s_nop comes right before the load
-        assert i > 0 and ins[i - 1].startswith("s_nop"), f"{src}: LDS-DMA load without its s_nop: {t}"
+        if i == 0 or not ins[i - 1].startswith("s_nop"):
+            problems.append(f"load without its s_nop: {t}")
+            continue
         waits = int(ins[i - 1].split()[1]) + 1
         j = i - 2
         while waits < 5 and j >= 0:
             prev = ins[j]
             hit = _valu_sgpr_dest(prev) & used
-            assert not hit, f"{src}: '{prev}' writes s{sorted(hit)} {waits} wait states before '{t}'"
+            if hit:
+                problems.append(f"'{prev}' writes s{sorted(hit)} {waits} wait states before '{t}'")
             m2 = re.fullmatch(r"s_nop (\d+)", prev)
             waits += int(m2.group(1)) + 1 if m2 else 1
             j -= 1
+    return problems, loads
+
+
+@pytest.mark.parametrize("src", SOURCES)
+def test_lds_dma_loads_have_their_wait_states(src, assembly):
+    problems, loads = check(assembly[src])
     assert loads > 0, f"{src}: no LDS-DMA loads found"
+    assert not problems, f"{src}: " + "; ".join(problems[:5])
+
+
+def _asm_load(pre, nop=0):
+    """A synthetic instruction sequence ending in one inline-asm load that
+    reads s[8:11] and s4."""
+    body = "\n".join(f"\t{x}" for x in pre)
+    return (f"{body}\n\t;;#ASMSTART\n\ts_nop {nop}\n"
+            "\tbuffer_load_dwordx4 v1, s[8:11], s4 offen lds\n\t;;#ASMEND\n")
+
+
+def test_checker_flags_planted_hazards():
+    # a readfirstlane into the resource right before the load
+    assert check(_asm_load(["v_readfirstlane_b32 s10, v2", "s_mov_b32 m0, s3"]))[0]
+    # into the soffset, three instructions before
+    assert check(_asm_load(["v_readfirstlane_b32 s4, v2", "s_add_u32 s5, s5, 1", "s_mov_b32 m0, s3"]))[0]
+    # a compare into an SGPR pair the resource uses
+    assert check(_asm_load(["v_cmp_eq_u32_e64 s[8:9], v1, v2", "s_mov_b32 m0, s3"]))[0]
+    # a load without its own s_nop
+    assert check("\t;;#ASMSTART\n\tbuffer_load_dwordx4 v1, s[8:11], s4 offen lds\n\t;;#ASMEND\n")[0]
+
+
+def test_checker_accepts_settled_operands():
+    # the same writes, but five wait states before the load (the asm's own
+    # s_nop 4), or far enough back, or to SGPRs the load does not read
+    assert not check(_asm_load(["v_readfirstlane_b32 s10, v2", "s_mov_b32 m0, s3"], nop=4))[0]
+    assert not check(_asm_load(["v_readfirstlane_b32 s10, v2"] + ["s_add_u32 s5, s5, 1"] * 4 + ["s_mov_b32 m0, s3"]))[0]
+    assert not check(_asm_load(["v_readfirstlane_b32 s12, v2", "s_mov_b32 m0, s3"]))[0]
+    # a load the compiler emits itself (no inline-asm markers) is its own business
+    assert check("\tv_readfirstlane_b32 s10, v2\n\tbuffer_load_dwordx4 v1, s[8:11], s4 offen lds\n") == ([], 0)
